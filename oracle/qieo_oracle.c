@@ -1,0 +1,335 @@
+/*
+ * QIEO oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded (optionally row-threaded) CPU implementation
+ * of one generation of quantum-inspired evolutionary optimization on the
+ * 0/1 knapsack problem, written from the paper "Evaluation of portability and
+ * performance of an OpenMP5 offloaded Quantum-Inspired Evolutionary
+ * Optimization Across the GPU Ecosystem" (Srikanth et al.):
+ *   - the qubit gene and its norm constraint (Sec. I, Introduction),
+ *   - the knapsack fitness, eq. (1) (Sec. III-A, Formulation),
+ *   - the four steps QIP -> Evaluation -> DetermineElite -> CIP and their
+ *     order (Sec. III-B, Methodology, and Fig. 1).
+ * Where the paper is silent, the readings below are the ones the GPU library
+ * implements as well (they are its specification, not borrowed code):
+ *   R1  allele 1 is observed iff u < beta^2, u a 24-bit uniform in [0,1).
+ *   R2  QIP only reads the amplitudes; CIP (rotation + renormalisation) is
+ *       their only writer.
+ *   R3  CIP rotates gene i of chromosome c only when f(c) < f(elite) and
+ *       x[c][i] != b[i] (b = elite string), by |dtheta| = 0.01*pi, with the
+ *       sign chosen from the quadrant of (alpha, beta) so that beta^2 moves
+ *       toward b[i]; a zero product takes the fixed rule in cip_gene().
+ *   R4  the rotation is followed by one Newton step toward unit norm,
+ *       g = 1.5 - 0.5*n, using only +, -, * (bit-reproducible everywhere).
+ *   R5  the elite is the generation best; ties go to the lowest index.
+ *   R6  FP32 amplitudes initialised to fl32(1/sqrt 2); exact integer fitness.
+ *   R7  uniform draws come from Philox4x32-10 (Salmon et al., SC'11) with
+ *       counter {i/4, c, t, 0} and key {seed_lo, seed_hi}; gene i uses word
+ *       i mod 4 of its call.
+ *
+ * Every floating-point operation below is one IEEE-754 binary32 operation
+ * rounded to nearest (build with -ffp-contract=off, no fast-math, SSE).
+ *
+ * Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
+ * load this code.  The GPU library shares nothing with it.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror,       */
+/* Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds   */
+/* of two 32x32->64 multiplies with a Weyl-sequence key schedule.           */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                          uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ x1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ x3 ^ k1;
+        uint32_t n3 = lo0;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The four 32-bit draws of genes 4k..4k+3 of chromosome c at generation t
+ * (reading R7). */
+static void draws4(uint64_t seed, int64_t t, int64_t c, int64_t k, uint32_t r[4])
+{
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)c, (uint32_t)t, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, r);
+}
+
+/* 24-bit uniform in [0, 1 - 2^-24], exact in binary32 (reading R1). */
+static float uniform24(uint32_t r)
+{
+    return (float)(r >> 8) * 0x1p-24f;
+}
+
+float oracle_uniform(uint64_t seed, int64_t t, int64_t c, int64_t i)
+{
+    uint32_t r[4];
+    draws4(seed, t, c, i / 4, r);
+    return uniform24(r[i % 4]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rotation gate constants (reading R3): binary32 roundings of cos(0.01 pi), */
+/* sin(0.01 pi) and 1/sqrt(2), written as exact hex literals.               */
+/* ------------------------------------------------------------------------ */
+#define ROT_C  0x1.ffbf52p-1f
+#define ROT_S  0x1.015122p-5f
+#define AMP0   0x1.6a09e6p-1f
+
+/* CIP on one gene (readings R3, R4).  tgt is the elite's allele b[i].
+ * Returns 1 if the gene was rotated, 0 if the zero-product rule skipped it. */
+int oracle_cip_gene(float *alpha, float *beta, int tgt)
+{
+    float a = *alpha, b = *beta;
+    float p = a * b;
+    float sd;
+    if (p > 0.0f) {
+        /* d(beta^2)/dtheta = 2 alpha beta > 0: positive angle raises beta^2 */
+        sd = tgt ? ROT_S : -ROT_S;
+    } else if (p < 0.0f) {
+        sd = tgt ? -ROT_S : ROT_S;
+    } else {
+        /* on an axis: nothing to do if already at the target pole */
+        if ((tgt && a == 0.0f) || (!tgt && b == 0.0f))
+            return 0;
+        sd = ROT_S;
+    }
+    float a1 = ROT_C * a - sd * b;
+    float b1 = sd * a + ROT_C * b;
+    float n = a1 * a1 + b1 * b1;
+    float g = 1.5f - 0.5f * n;
+    *alpha = a1 * g;
+    *beta = b1 * g;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* State.                                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct oracle {
+    int32_t ng, np;
+    int64_t cap;        /* knapsack capacity W of eq. (1) */
+    int64_t lambda;     /* penalty factor of eq. (1), > 0 */
+    uint64_t seed;
+    int32_t *v, *w;     /* item values and weights, length ng */
+    float *alpha, *beta;/* np x ng, chromosome-major */
+    uint8_t *x;         /* observed alleles of the current generation */
+    int64_t *P, *W, *fit;
+    int64_t t;          /* index of the next generation to run */
+    int64_t elite;      /* elite of the last completed generation, -1 none */
+    int has_best;
+    int64_t best_f, best_P, best_W, best_gen, best_chrom;
+    uint8_t *best_x;
+    int threads;
+} oracle;
+
+void oracle_free(oracle *s)
+{
+    if (!s) return;
+    free(s->v); free(s->w); free(s->alpha); free(s->beta); free(s->x);
+    free(s->P); free(s->W); free(s->fit); free(s->best_x);
+    free(s);
+}
+
+/* Creates the initial population (every amplitude fl32(1/sqrt 2), reading
+ * R6).  Returns NULL on bad sizes or allocation failure. */
+oracle *oracle_new(int32_t ng, int32_t np, const int32_t *v, const int32_t *w,
+                   int64_t cap, uint64_t seed, int64_t lambda)
+{
+    if (ng < 1 || np < 1 || lambda < 1) return NULL;
+    oracle *s = (oracle *)calloc(1, sizeof(oracle));
+    if (!s) return NULL;
+    size_t n = (size_t)ng * (size_t)np;
+    s->ng = ng; s->np = np; s->cap = cap; s->seed = seed; s->lambda = lambda;
+    s->v = (int32_t *)malloc(sizeof(int32_t) * ng);
+    s->w = (int32_t *)malloc(sizeof(int32_t) * ng);
+    s->alpha = (float *)malloc(sizeof(float) * n);
+    s->beta = (float *)malloc(sizeof(float) * n);
+    s->x = (uint8_t *)calloc(n, 1);
+    s->P = (int64_t *)calloc(np, sizeof(int64_t));
+    s->W = (int64_t *)calloc(np, sizeof(int64_t));
+    s->fit = (int64_t *)calloc(np, sizeof(int64_t));
+    s->best_x = (uint8_t *)calloc(ng, 1);
+    if (!s->v || !s->w || !s->alpha || !s->beta || !s->x || !s->P || !s->W ||
+        !s->fit || !s->best_x) {
+        oracle_free(s);
+        return NULL;
+    }
+    memcpy(s->v, v, sizeof(int32_t) * ng);
+    memcpy(s->w, w, sizeof(int32_t) * ng);
+    for (size_t k = 0; k < n; ++k) { s->alpha[k] = AMP0; s->beta[k] = AMP0; }
+    s->t = 0;
+    s->elite = -1;
+    s->has_best = 0;
+    s->threads = 1;
+    return s;
+}
+
+void oracle_set_threads(oracle *s, int threads) { s->threads = threads < 1 ? 1 : threads; }
+
+/* QIP (Sec. III-B): observe every qubit of every chromosome (reading R1, R2). */
+void oracle_qip(oracle *s)
+{
+    const int64_t ng = s->ng;
+    const int64_t nk = (ng + 3) / 4;
+#pragma omp parallel for num_threads(s->threads) schedule(static)
+    for (int64_t c = 0; c < s->np; ++c) {
+        for (int64_t k = 0; k < nk; ++k) {
+            uint32_t r[4];
+            draws4(s->seed, s->t, c, k, r);
+            for (int j = 0; j < 4; ++j) {
+                int64_t i = 4 * k + j;
+                if (i >= ng) break;
+                float b = s->beta[c * ng + i];
+                float b2 = b * b;
+                s->x[c * ng + i] = (uniform24(r[j]) < b2) ? 1 : 0;
+            }
+        }
+    }
+}
+
+/* Evaluation, eq. (1): profit and weight sums, then the capacity test; an
+ * infeasible chromosome scores -lambda times its excess weight. */
+void oracle_fe(oracle *s)
+{
+    const int64_t ng = s->ng;
+#pragma omp parallel for num_threads(s->threads) schedule(static)
+    for (int64_t c = 0; c < s->np; ++c) {
+        int64_t P = 0, W = 0;
+        for (int64_t i = 0; i < ng; ++i) {
+            P += (int64_t)s->v[i] * s->x[c * ng + i];
+            W += (int64_t)s->w[i] * s->x[c * ng + i];
+        }
+        s->P[c] = P;
+        s->W[c] = W;
+        s->fit[c] = (W <= s->cap) ? P : -s->lambda * (W - s->cap);
+    }
+}
+
+/* DetermineElite (Sec. III-B): the generation-best chromosome, lowest index
+ * on ties (reading R5); the best-so-far record changes only on a strictly
+ * larger fitness. */
+void oracle_de(oracle *s)
+{
+    int64_t e = 0;
+    for (int64_t c = 1; c < s->np; ++c)
+        if (s->fit[c] > s->fit[e]) e = c;
+    s->elite = e;
+    if (!s->has_best || s->fit[e] > s->best_f) {
+        s->has_best = 1;
+        s->best_f = s->fit[e];
+        s->best_P = s->P[e];
+        s->best_W = s->W[e];
+        s->best_gen = s->t;
+        s->best_chrom = e;
+        memcpy(s->best_x, s->x + e * (int64_t)s->ng, (size_t)s->ng);
+    }
+}
+
+/* CIP (Sec. III-B): rotate every qubit of every chromosome that scores below
+ * the elite toward the elite's allele where the two differ (reading R3). */
+void oracle_cip(oracle *s)
+{
+    const int64_t ng = s->ng;
+    const int64_t e = s->elite;
+    const int64_t fe = s->fit[e];
+    const uint8_t *b = s->x + e * ng;
+#pragma omp parallel for num_threads(s->threads) schedule(static)
+    for (int64_t c = 0; c < s->np; ++c) {
+        if (!(s->fit[c] < fe)) continue;
+        for (int64_t i = 0; i < ng; ++i) {
+            if (s->x[c * ng + i] == b[i]) continue;
+            oracle_cip_gene(&s->alpha[c * ng + i], &s->beta[c * ng + i], b[i]);
+        }
+    }
+}
+
+/* One generation, in the order of Fig. 1. */
+void oracle_generation(oracle *s)
+{
+    oracle_qip(s);
+    oracle_fe(s);
+    oracle_de(s);
+    oracle_cip(s);
+    s->t += 1;
+}
+
+void oracle_run(oracle *s, int64_t n)
+{
+    for (int64_t g = 0; g < n; ++g) oracle_generation(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors (copies into caller-owned buffers; any pointer may be NULL).   */
+/* ------------------------------------------------------------------------ */
+void oracle_get_amplitudes(const oracle *s, float *alpha, float *beta)
+{
+    size_t n = (size_t)s->ng * (size_t)s->np;
+    if (alpha) memcpy(alpha, s->alpha, n * sizeof(float));
+    if (beta) memcpy(beta, s->beta, n * sizeof(float));
+}
+
+void oracle_set_amplitudes(oracle *s, const float *alpha, const float *beta)
+{
+    size_t n = (size_t)s->ng * (size_t)s->np;
+    if (alpha) memcpy(s->alpha, alpha, n * sizeof(float));
+    if (beta) memcpy(s->beta, beta, n * sizeof(float));
+}
+
+void oracle_get_alleles(const oracle *s, uint8_t *x)
+{
+    memcpy(x, s->x, (size_t)s->ng * (size_t)s->np);
+}
+
+void oracle_set_alleles(oracle *s, const uint8_t *x)
+{
+    memcpy(s->x, x, (size_t)s->ng * (size_t)s->np);
+}
+
+void oracle_get_fitness(const oracle *s, int64_t *fit, int64_t *P, int64_t *W)
+{
+    if (fit) memcpy(fit, s->fit, sizeof(int64_t) * s->np);
+    if (P) memcpy(P, s->P, sizeof(int64_t) * s->np);
+    if (W) memcpy(W, s->W, sizeof(int64_t) * s->np);
+}
+
+void oracle_set_fitness(oracle *s, const int64_t *fit)
+{
+    memcpy(s->fit, fit, sizeof(int64_t) * s->np);
+}
+
+int64_t oracle_generation_index(const oracle *s) { return s->t; }
+int64_t oracle_elite(const oracle *s) { return s->elite; }
+
+/* best: {has_best, f, P, W, generation, chromosome}; bits: ng bytes or NULL */
+void oracle_get_best(const oracle *s, int64_t out[6], uint8_t *bits)
+{
+    out[0] = s->has_best; out[1] = s->best_f; out[2] = s->best_P;
+    out[3] = s->best_W; out[4] = s->best_gen; out[5] = s->best_chrom;
+    if (bits) memcpy(bits, s->best_x, (size_t)s->ng);
+}

@@ -1,0 +1,170 @@
+/*
+ * libqieo -- quantum-inspired evolutionary optimization (QIEO) of the 0/1
+ * knapsack problem on one AMD Instinct MI355X (gfx950).
+ *
+ * The library runs the per-generation loop of the paper (Srikanth et al.,
+ * "Evaluation of portability and performance of an OpenMP5 offloaded
+ * Quantum-Inspired Evolutionary Optimization Across the GPU Ecosystem"):
+ * QIP observes every qubit gene, Evaluation scores every chromosome with the
+ * knapsack fitness of eq. (1), DetermineElite picks the generation best, and
+ * CIP rotates every qubit toward that elite (Sec. III-B, Fig. 1).  All four
+ * steps run on the GPU; the population stays resident in device memory.
+ *
+ * Conventions for every call:
+ *   - Return value 0 (QIEO_OK) on success, a negative QIEO_E* code otherwise;
+ *     qieo_last_error() then holds a thread-local message.  No C++ exception
+ *     crosses this interface.
+ *   - Every input array is host memory and is copied; the caller keeps
+ *     ownership.  Every output array is caller-owned host memory of the stated
+ *     length.  Handles are owned by the caller until the matching destroy.
+ *   - One thread at a time per handle; distinct handles are independent.
+ *   - A run is deterministic: the state after qieo_step(h, a) followed by
+ *     qieo_step(h, b) equals the state after qieo_step(h, a + b), and equals
+ *     the same instance run alone, in a batch, or inside the server.
+ *
+ * Readings of points the paper leaves open (the CPU oracle implements the
+ * same ones):
+ *   - allele 1 is observed iff u < beta^2, with u the 24-bit uniform
+ *     (r >> 8) * 2^-24 of the 32-bit Philox4x32-10 word r drawn with counter
+ *     {gene/4, chromosome, generation, 0} and key {seed lo, seed hi}; gene i
+ *     takes word i mod 4;
+ *   - amplitudes are binary32, initialised to fl32(1/sqrt 2); fitness is exact
+ *     int32 with penalty factor lambda = 1 (any lambda > 0 gives the same run);
+ *   - the elite is the generation best, lowest index on ties; chromosome c
+ *     rotates gene i only when f(c) < f(elite) and x[c][i] differs from the
+ *     elite's allele, by 0.01*pi toward it, then one Newton step
+ *     g = 1.5 - 0.5*(a^2 + b^2) rescales (a, b) toward unit norm.
+ */
+#ifndef QIEO_H
+#define QIEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define QIEO_OK         0
+#define QIEO_EINVAL    -1   /* bad argument: sizes, null pointers, ranges      */
+#define QIEO_EOVERFLOW -2   /* sum of values or weights exceeds INT32_MAX      */
+#define QIEO_ENOMEM    -3   /* device (or host) allocation failed / no room    */
+#define QIEO_EDEVICE   -4   /* HIP runtime error or no usable gfx950 device    */
+#define QIEO_EAGAIN    -5   /* result not ready yet (server poll)              */
+#define QIEO_ESTATE    -6   /* call not valid in the object's current state   */
+
+/* ---- problem description (Sec. III-A) ----------------------------------- */
+/* Item i of the knapsack: value v_i (profit) and weight w_i, both >= 0. */
+typedef struct qieo_item {
+    int32_t profit;
+    int32_t weight;
+} qieo_item;
+
+/* Best chromosome found so far (the best generation elite).  fitness follows
+ * eq. (1) with lambda = 1: the profit when weight <= capacity, otherwise
+ * -(weight - capacity).  generation is the index (from 0) of the generation
+ * that first produced it, chromosome its row in that generation.
+ * generation = -1 when no generation has run yet. */
+typedef struct qieo_result {
+    int32_t fitness;
+    int32_t profit;
+    int32_t weight;
+    int32_t feasible;
+    int64_t generation;
+    int64_t chromosome;
+} qieo_result;
+
+/* Optional device context.  alloc/free replace hipMalloc/hipFree for the
+ * instance's device memory (both NULL: hipMalloc/hipFree); alloc returns NULL
+ * on failure.  stream is a hipStream_t on which all work is ordered (NULL:
+ * the library creates and owns one stream per handle). */
+typedef struct qieo_dev_ctx {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+    void *stream;
+} qieo_dev_ctx;
+
+typedef struct qieo_inst qieo_inst;
+
+/* ---- single instance ----------------------------------------------------- */
+
+/* Creates one population of n_pop chromosomes of n_items qubit genes for the
+ * knapsack (items, capacity) (Sec. III-A) and initialises every amplitude pair
+ * on the device.  Requires n_items >= 1, n_pop >= 1, capacity >= 0, every
+ * profit and weight >= 0 (QIEO_EINVAL), and sum(profit), sum(weight) <=
+ * INT32_MAX (QIEO_EOVERFLOW).  seed keys the Philox draws.  On success *out
+ * receives the handle; on failure nothing is allocated. */
+int qieo_create(const qieo_item *items, int32_t n_items, int32_t capacity,
+                int32_t n_pop, uint64_t seed, qieo_inst **out);
+
+/* As qieo_create, with an optional device context (NULL = defaults). */
+int qieo_create_ex(const qieo_item *items, int32_t n_items, int32_t capacity,
+                   int32_t n_pop, uint64_t seed, const qieo_dev_ctx *ctx,
+                   qieo_inst **out);
+
+/* Runs n_generations full generations (QIP, Evaluation, DetermineElite, CIP;
+ * Sec. III-B, Fig. 1) and waits for them.  n_generations >= 0. */
+int qieo_step(qieo_inst *h, int32_t n_generations);
+
+/* As qieo_step, without waiting: the work is queued on the handle's stream.
+ * Host-side reads of the handle (qieo_best, export) wait by themselves. */
+int qieo_step_async(qieo_inst *h, int32_t n_generations);
+
+/* Waits for all queued work of the handle. */
+int qieo_sync(qieo_inst *h);
+
+/* Best-so-far chromosome.  bits_or_null, if not NULL, receives the allele
+ * string packed little-endian (item i is bit i%32 of word i/32); n_words must
+ * be >= ceil(n_items/32) (QIEO_EINVAL otherwise). */
+int qieo_best(qieo_inst *h, qieo_result *out, uint32_t *bits_or_null,
+              size_t n_words);
+
+/* Number of generations run so far. */
+int qieo_generations(qieo_inst *h, int64_t *out);
+
+/* Copies rows [row0, row0 + n_rows) of the population state after the last
+ * completed generation t-1, with that generation's CIP applied, to host
+ * arrays (row-major, n_items per row): alpha, beta (binary32 amplitudes),
+ * alleles (0/1 bytes observed at t-1), and for each row fitness, profit and
+ * weight at t-1.  Any pointer may be NULL.  elite (may be NULL) receives the
+ * elite index of generation t-1, or -1 when no generation has run.  The
+ * device state is not modified.  Requires 0 <= row0, n_rows >= 0,
+ * row0 + n_rows <= n_pop. */
+int qieo_export_rows(qieo_inst *h, int32_t row0, int32_t n_rows,
+                     float *alpha, float *beta, uint8_t *alleles,
+                     int32_t *fitness, int32_t *profit, int32_t *weight,
+                     int32_t *elite);
+
+/* Releases the handle and all its device memory (NULL is ignored). */
+void qieo_destroy(qieo_inst *h);
+
+/* Work shape of the generation kernel for this handle: rows_per_block in
+ * {1, 2, 4} chromosomes per workgroup, waves_per_block in [1, 16] wavefronts
+ * splitting each chromosome's genes.  0 for either keeps the library's
+ * choice.  The shape changes speed only, never results.  Out-of-range values
+ * give QIEO_EINVAL. */
+int qieo_set_tile(qieo_inst *h, int32_t rows_per_block, int32_t waves_per_block);
+/* Current work shape. */
+int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_block);
+
+/* ---- errors and introspection ------------------------------------------- */
+const char *qieo_strerror(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char *qieo_last_error(void);
+/* Library version string. */
+const char *qieo_version(void);
+
+/* Kernel timing, for measurement.  When enabled, the library records HIP
+ * events on the handle's stream around every generation kernel it launches;
+ * qieo_kernel_time returns the number of such launches and their summed
+ * duration in milliseconds since the last reset, and resets on request.
+ * Timing adds two event records per generation. */
+int qieo_set_timing(qieo_inst *h, int enabled);
+int qieo_kernel_time(qieo_inst *h, int64_t *launches, double *total_ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QIEO_H */

@@ -1,0 +1,164 @@
+// Device building blocks of the QIEO generation for gfx950 (CDNA4, wave64).
+//
+// Everything here is per-lane arithmetic; the layout and control flow live in
+// qieo_kernels.hip.  Floating-point expressions are written one IEEE binary32
+// operation at a time and the library is compiled with -ffp-contract=off, so
+// no multiply is fused into an add.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qieo {
+
+// ---------------------------------------------------------------------------
+// Rotation-gate constants: binary32 roundings of cos(0.01 pi), sin(0.01 pi)
+// and the initial amplitude 1/sqrt(2).
+// ---------------------------------------------------------------------------
+constexpr float kCos = 0x1.ffbf52p-1f;
+constexpr float kSin = 0x1.015122p-5f;
+constexpr float kAmp0 = 0x1.6a09e6p-1f;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform (it is the
+// instance seed) and so is every round's key; counter word 0 is the only
+// per-lane input, words 1-3 (chromosome, generation, stream 0) are uniform.
+// The 32x32->64 products are plain 64-bit multiplies, which the compiler
+// lowers to v_mad_u64_u32 for per-lane operands and to scalar multiplies for
+// uniform ones.
+// ---------------------------------------------------------------------------
+struct Draw4 {
+    uint32_t r0, r1, r2, r3;
+};
+
+__device__ __forceinline__ void philox_round(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                             uint32_t& x3, uint32_t k0, uint32_t k1)
+{
+    const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+    const uint32_t y1 = (uint32_t)pb;
+    const uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+    const uint32_t y3 = (uint32_t)pa;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+}
+
+__device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c0, c1, c2, c3, k0, k1);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Draw4{c0, c1, c2, c3};
+}
+
+// Observation of one qubit: 1 iff the 24-bit uniform of r lies below beta^2.
+__device__ __forceinline__ bool observe(uint32_t r, float beta)
+{
+    const float u = (float)(r >> 8) * 0x1p-24f;
+    const float b2 = beta * beta;
+    return u < b2;
+}
+
+// ---------------------------------------------------------------------------
+// Lane-mask helpers.  A wave-uniform 64-bit mask m holds one bit per lane;
+// sel(m, f, t) returns t on lanes whose bit is set and f elsewhere, in a
+// single v_cndmask_b32 with m as the SGPR-pair condition.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t uniform_mask(uint64_t m)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)m);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(m >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ float sel(uint64_t m, float if0, float if1)
+{
+    float r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(if0), "v"(if1), "s"(uniform_mask(m)));
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Memory helpers.  Streams of the amplitude planes use global (address space
+// 1) vector loads/stores from a wave-uniform row base plus a 32-bit per-lane
+// index; wave-uniform reads of allele words use the constant address space
+// so they become scalar loads into SGPRs.  The kernels never write memory they
+// read through the scalar path within the same launch.
+// ---------------------------------------------------------------------------
+#define QIEO_AS_GLOBAL __attribute__((address_space(1)))
+#define QIEO_AS_CONST __attribute__((address_space(4)))
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* base, uint32_t idx)
+{
+    return ((const QIEO_AS_GLOBAL T*)base)[idx];
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(T* base, uint32_t idx, T v)
+{
+    ((QIEO_AS_GLOBAL T*)base)[idx] = v;
+}
+
+template <typename T>
+__device__ __forceinline__ T sload(const T* p)
+{
+    return *(const QIEO_AS_CONST T*)p;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p)
+{
+    return __ballot(p);
+}
+
+// Loads a 64-bit lane mask that every lane reads from the same address and
+// pins it to scalar registers.
+__device__ __forceinline__ uint64_t load_mask(const uint64_t* p)
+{
+    return sload(p);
+}
+
+// ---------------------------------------------------------------------------
+// CIP on one gene, given as lane masks: rot = lanes whose gene must move
+// toward the elite, tgt = lanes whose elite allele is 1.  Direction: positive
+// angle raises beta^2 when alpha*beta > 0, so the sign of the step is
+// sign(alpha*beta) for target 1 and its opposite for target 0; a zero product
+// steps by +0.01 pi unless the gene already sits on the target pole.  The
+// Newton factor g = 1.5 - 0.5 n pulls the norm back to 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cip_gene(float& a, float& b, uint64_t rot, uint64_t tgt)
+{
+    const float p = a * b;
+    const float sdp = sel(tgt, -kSin, kSin);          // step for p > 0
+    const float sdn = sel(tgt, kSin, -kSin);          // step for p < 0
+    float sd = (p > 0.0f) ? sdp : kSin;
+    sd = (p < 0.0f) ? sdn : sd;
+    // already on the target pole: target 1 with alpha == 0, target 0 with beta == 0
+    const float pole = sel(tgt, b, a);
+    const uint64_t skip = ballot(pole == 0.0f);
+    const uint64_t mv = rot & ~skip;
+    const float ca = kCos * a;
+    const float sb = sd * b;
+    const float a1 = ca - sb;
+    const float sa = sd * a;
+    const float cb = kCos * b;
+    const float b1 = sa + cb;
+    const float aa = a1 * a1;
+    const float bb = b1 * b1;
+    const float n = aa + bb;
+    const float hn = 0.5f * n;
+    const float g = 1.5f - hn;
+    const float a2 = a1 * g;
+    const float b2 = b1 * g;
+    a = sel(mv, a, a2);
+    b = sel(mv, b, b2);
+}
+
+}  // namespace qieo

@@ -1,0 +1,36 @@
+// Host-side helpers shared by the single-instance, batch and server runtimes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/qieo.h"
+#include "qieo_kernels.hpp"
+
+namespace qieo {
+
+// Byte offsets of every plane inside one instance's device arena.
+struct ArenaLayout {
+    int32_t pitch, nchunk;
+    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase;
+    size_t zero_from;
+    size_t total;
+};
+
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L);
+InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
+                   uint64_t seed);
+int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop);
+int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
+                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging);
+int check_device();
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S);
+
+}  // namespace qieo

@@ -1,0 +1,399 @@
+// QIEO generation kernels for gfx950 (CDNA4, wave64).
+//
+// One launch runs one whole generation t of every tile it is given, fused as
+//     CIP(t-1)  ->  QIP(t)  ->  Evaluation(t)  ->  DetermineElite(t)
+// (Sec. III-B and Fig. 1 of the paper give the order QIP, Evaluation,
+// DetermineElite, CIP; the rotation of generation t-1 is deferred into the
+// next launch, where it shares one read and one write of the amplitude planes
+// with the observation of generation t).  The kernel boundary is the only
+// grid-wide barrier a generation needs: the elite of t-1 is final when the
+// launch of t starts.
+//
+// Work decomposition.  A workgroup owns R whole chromosomes (rows); its S
+// wavefronts split each row into 256-gene chunks (wave w takes chunks w, w+S,
+// ...), so Evaluation's gene-axis reduction (eq. (1)) closes inside the
+// workgroup: wave shuffles, then LDS across the S waves, then one 64-bit
+// atomicMax per row for DetermineElite.  No cross-workgroup partial sums, no
+// tickets, no memory fences.
+//
+// Per lane and chunk: 4 consecutive genes = one float4 of beta (and alpha
+// when the row rotates) = one Philox4x32-10 call.  The observed alleles of a
+// chunk are the four wave ballots of the comparisons: they are stored as
+// eight 32-bit words and re-read as wave-uniform lane masks, so CIP's
+// per-gene tests (own allele vs elite allele, target) are scalar mask logic
+// and v_cndmask selects.
+#include "qieo_device.hpp"
+#include "qieo_kernels.hpp"
+
+namespace qieo {
+
+namespace {
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int32_t key_fitness(unsigned long long key)
+{
+    return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
+}
+
+__device__ __forceinline__ int32_t key_row(unsigned long long key)
+{
+    return (int32_t)(~(uint32_t)key);
+}
+
+__device__ __forceinline__ unsigned long long make_key(int32_t f, int32_t row)
+{
+    return ((unsigned long long)((uint32_t)f ^ 0x80000000u) << 32) |
+           (unsigned long long)(~(uint32_t)row);
+}
+
+// Best-so-far update for generation tg whose elite is (e, fe).  Executed by
+// one whole wavefront (the only writer of the record in this launch), after
+// the generation tg launch has completed.
+__device__ void best_update(const InstDev& I, int64_t tg, int32_t e, int32_t fe,
+                            const uint32_t* __restrict__ xg, int lane)
+{
+    const int has = I.best[0];
+    const int32_t bf = I.best[1];
+    if (has && !(fe > bf)) return;
+    const int wpr = I.nchunk * kWordsPerChunk;
+    const uint32_t* src = xg + (size_t)e * wpr;
+    for (int i = lane; i < wpr; i += 64) I.best_bits[i] = src[i];
+    if (lane == 0) {
+        const int slot = (int)(tg & 1) * I.np + e;
+        I.best[1] = fe;
+        I.best[2] = I.prof[slot];
+        I.best[3] = I.wt[slot];
+        I.best[4] = (int32_t)(uint32_t)(uint64_t)tg;
+        I.best[5] = (int32_t)(uint32_t)((uint64_t)tg >> 32);
+        I.best[6] = e;
+        I.best[0] = 1;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Initial state: every real gene (alpha, beta) = (1/sqrt2, 1/sqrt2); padding
+// genes (1, 0).
+// ---------------------------------------------------------------------------
+__global__ void init_kernel(InstDev I)
+{
+    const size_t n = (size_t)I.np * I.pitch;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (size_t)gridDim.x * blockDim.x) {
+        const int g = (int)(k % (size_t)I.pitch);
+        const bool real = g < I.ng;
+        I.alpha[k] = real ? kAmp0 : 1.0f;
+        I.beta[k] = real ? kAmp0 : 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused generation.  k is this launch's offset inside the current call:
+// the generation index is t = *tbase + k, and an instance whose call asked
+// for fewer than k+1 generations skips the launch.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
+                                                         const Tile* __restrict__ tiles, int k,
+                                                         const int32_t* __restrict__ gens_arr,
+                                                         int gens_all)
+{
+    uint32_t inst = 0, row0;
+    if (tiles != nullptr) {
+        const Tile tt = tiles[blockIdx.x];
+        inst = tt.inst;
+        row0 = tt.row0;
+    } else {
+        row0 = blockIdx.x * R;
+    }
+    const InstDev I = insts[inst];
+    const int gens = gens_arr ? sload(gens_arr + inst) : gens_all;
+    if (k >= gens) return;
+
+    // Values this launch reads but never writes go through the scalar path:
+    // the generation counter, the elite key of t-1 and the fitness of t-1.
+    const int64_t t = sload(I.tbase) + k;
+    const int par = (int)(t & 1);
+    const int np = I.np;
+    const int wpr = I.nchunk * kWordsPerChunk;
+    const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
+    uint32_t* __restrict__ xcur = I.xbits + (size_t)par * np * wpr;
+
+    const int lane = threadIdx.x & 63;
+    // wave index is uniform across the wavefront; say so to the compiler so the
+    // chunk loop, its addresses and its allele-mask loads stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int S = blockDim.x >> 6;
+
+    const bool pending = t > 0;
+    int32_t e_prev = 0, fe_prev = 0;
+    if (pending) {
+        const unsigned long long key = sload(I.ekey + (t - 1) % 3);
+        e_prev = key_row(key);
+        fe_prev = key_fitness(key);
+    }
+
+    if (row0 == 0 && wave == 0) {
+        if (lane == 0) I.ekey[(t + 1) % 3] = 0ull;
+        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+    }
+
+    const int nrows = min(R, np - (int)row0);
+    bool rot[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rot[r] = pending && r < nrows && sload(I.fit + (par ^ 1) * np + row0 + r) < fe_prev;
+
+    uint32_t accP[R], accW[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { accP[r] = 0u; accW[r] = 0u; }
+
+    const uint32_t* __restrict__ brow = xprev + (size_t)e_prev * wpr;
+
+    for (int ch = wave; ch < I.nchunk; ch += S) {
+        const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
+        // Lanes past the row end (only in a row's last chunk) load from the
+        // slack that follows every plane and the next row; their alleles are
+        // masked to 0 and their stores are skipped.
+        const bool act = g0 < (uint32_t)I.pitch;
+        const uint32_t q = g0 >> 2;          // float4 / int4 index in a row
+        const i32x4 v4 = gload((const i32x4*)I.v, q);
+        const i32x4 w4 = gload((const i32x4*)I.w, q);
+        uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0;
+        if (pending) {
+            const uint64_t* bw = reinterpret_cast<const uint64_t*>(brow + ch * kWordsPerChunk);
+            bm0 = load_mask(bw); bm1 = load_mask(bw + 1);
+            bm2 = load_mask(bw + 2); bm3 = load_mask(bw + 3);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nrows) break;
+            const int c = (int)row0 + r;
+            const f32x4* arow = (const f32x4*)(I.alpha + (size_t)c * I.pitch);
+            const f32x4* brow4 = (const f32x4*)(I.beta + (size_t)c * I.pitch);
+            f32x4 b4 = gload(brow4, q);
+            f32x4 a4;
+            if (rot[r]) {
+                a4 = gload(arow, q);
+                const uint64_t* xw =
+                    reinterpret_cast<const uint64_t*>(xprev + (size_t)c * wpr + ch * kWordsPerChunk);
+                const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
+                const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
+                float a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
+                float b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
+                cip_gene(a0, b0, xm0 ^ bm0, bm0);
+                cip_gene(a1, b1, xm1 ^ bm1, bm1);
+                cip_gene(a2, b2, xm2 ^ bm2, bm2);
+                cip_gene(a3, b3, xm3 ^ bm3, bm3);
+                a4 = f32x4{a0, a1, a2, a3};
+                b4 = f32x4{b0, b1, b2, b3};
+            }
+            const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+            const bool x0 = act && observe(d.r0, b4.x);
+            const bool x1 = act && observe(d.r1, b4.y);
+            const bool x2 = act && observe(d.r2, b4.z);
+            const bool x3 = act && observe(d.r3, b4.w);
+            const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
+            if (lane < kWordsPerChunk) {
+                const int j = lane >> 1;
+                const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
+                const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
+                gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+            }
+            accP[r] += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
+                       (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
+            accW[r] += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
+                       (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+            if (rot[r] && act) {
+                gstore((f32x4*)arow, q, a4);
+                gstore((f32x4*)brow4, q, b4);
+            }
+        }
+    }
+
+    // Evaluation: close the gene-axis sums of eq. (1) inside the workgroup.
+    __shared__ uint32_t red[16][R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t p = wave_sum(accP[r]);
+        const uint32_t w = wave_sum(accW[r]);
+        if (lane == 0) { red[wave][r][0] = p; red[wave][r][1] = w; }
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)nrows) {
+        const int r = threadIdx.x;
+        uint32_t P = 0u, W = 0u;
+        for (int s = 0; s < S; ++s) { P += red[s][r][0]; W += red[s][r][1]; }
+        const int c = (int)row0 + r;
+        const int32_t Pi = (int32_t)P, Wi = (int32_t)W;
+        const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
+        const int slot = par * np + c;
+        I.fit[slot] = f;
+        I.prof[slot] = Pi;
+        I.wt[slot] = Wi;
+        // DetermineElite: the largest key is the largest fitness, lowest row.
+        atomicMax(&I.ekey[t % 3], make_key(f, c));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// End of a call: best-so-far update for the last generation of the call and
+// advance of the generation counter.  One workgroup (one wave) per instance.
+// ---------------------------------------------------------------------------
+__global__ void finish_kernel(const InstDev* __restrict__ insts,
+                              const int32_t* __restrict__ gens_arr, int gens_all)
+{
+    const InstDev I = insts[blockIdx.x];
+    const int gens = gens_arr ? gens_arr[blockIdx.x] : gens_all;
+    if (gens <= 0) return;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const int64_t tl = *I.tbase + gens - 1;
+        const unsigned long long key = I.ekey[tl % 3];
+        const uint32_t* xg = I.xbits + (size_t)(tl & 1) * I.np * I.nchunk * kWordsPerChunk;
+        best_update(I, tl, key_row(key), key_fitness(key), xg, lane);
+        if (lane == 0) *I.tbase = tl + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Export of rows [row0, row0+n) after the last completed generation t-1:
+// amplitudes with CIP(t-1) applied (state untouched), alleles and fitness of
+// t-1.  Block = 256 threads = 4 waves, one gene per thread.
+// ---------------------------------------------------------------------------
+__global__ void export_kernel(const InstDev* __restrict__ insts, int row0, float* alpha,
+                              float* beta, uint8_t* alleles)
+{
+    const InstDev I = insts[0];
+    const int64_t t = *I.tbase;
+    const int c = row0 + blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = g < I.ng;
+    const int wpr = I.nchunk * kWordsPerChunk;
+    const size_t src = (size_t)c * I.pitch + (act ? g : 0);
+    float a = act ? I.alpha[src] : 1.0f;
+    float b = act ? I.beta[src] : 0.0f;
+    bool x = false, bel = false, rot = false;
+    if (t > 0 && act) {
+        const int par = (int)((t - 1) & 1);
+        const uint32_t* xg = I.xbits + (size_t)par * I.np * wpr;
+        const unsigned long long key = I.ekey[(t - 1) % 3];
+        const int e = key_row(key);
+        const int32_t fe = key_fitness(key);
+        const int ch = g / kChunk, q = g % kChunk, L = q >> 2, j = q & 3;
+        const int word = ch * kWordsPerChunk + 2 * j + (L >> 5);
+        const int bit = L & 31;
+        x = (xg[(size_t)c * wpr + word] >> bit) & 1u;
+        bel = (xg[(size_t)e * wpr + word] >> bit) & 1u;
+        rot = (I.fit[par * I.np + c] < fe) && (x != bel);
+    }
+    const uint64_t rm = ballot(rot), tm = ballot(bel);
+    cip_gene(a, b, rm, tm);
+    if (act) {
+        const size_t dst = (size_t)blockIdx.y * I.ng + g;
+        if (alpha) alpha[dst] = a;
+        if (beta) beta[dst] = b;
+        if (alleles) alleles[dst] = x ? 1 : 0;
+    }
+}
+
+__global__ void export_rows_kernel(const InstDev* __restrict__ insts, int row0, int n_rows,
+                                   int32_t* fit, int32_t* prof, int32_t* wt)
+{
+    const InstDev I = insts[0];
+    const int64_t t = *I.tbase;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int slot = (int)((t - 1) & 1) * I.np + row0 + r;
+    const bool any = t > 0;
+    if (fit) fit[r] = any ? I.fit[slot] : 0;
+    if (prof) prof[r] = any ? I.prof[slot] : 0;
+    if (wt) wt[r] = any ? I.wt[slot] : 0;
+}
+
+// Chunked-ballot allele words -> plain packed bits (gene i = bit i%32 of word i/32).
+__global__ void bits_unpack_kernel(const uint32_t* __restrict__ src, int ng, uint32_t* dst)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = (ng + 31) / 32;
+    if (q >= nw) return;
+    uint32_t out = 0u;
+    for (int b = 0; b < 32; ++b) {
+        const int g = 32 * q + b;
+        if (g >= ng) break;
+        const int ch = g / kChunk, r = g % kChunk, L = r >> 2, j = r & 3;
+        const uint32_t w = src[ch * kWordsPerChunk + 2 * j + (L >> 5)];
+        out |= ((w >> (L & 31)) & 1u) << b;
+    }
+    dst[q] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_init(const InstDev& I, hipStream_t s)
+{
+    const size_t n = (size_t)I.np * I.pitch;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(init_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I);
+    return hipGetLastError();
+}
+
+hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
+                             int rows_per_block, int waves_per_block, int k,
+                             const int32_t* gens_arr, int gens_all, hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
+    switch (rows_per_block) {
+    case 1: hipLaunchKernelGGL(generation_kernel<1>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
+    case 2: hipLaunchKernelGGL(generation_kernel<2>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
+    case 4: hipLaunchKernelGGL(generation_kernel<4>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
+                         hipStream_t s)
+{
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finish_kernel, dim3((unsigned)n_inst), dim3(64), 0, s, dI, gens_arr,
+                       gens_all);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng, float* alpha,
+                         float* beta, uint8_t* alleles, int32_t* fit, int32_t* prof,
+                         int32_t* wt, hipStream_t s)
+{
+    if (n_rows <= 0) return hipSuccess;
+    if (alpha || beta || alleles) {
+        const dim3 grid((unsigned)((ng + 255) / 256), (unsigned)n_rows);
+        hipLaunchKernelGGL(export_kernel, grid, dim3(256), 0, s, dI, row0, alpha, beta, alleles);
+    }
+    if (fit || prof || wt)
+        hipLaunchKernelGGL(export_rows_kernel, dim3((unsigned)((n_rows + 255) / 256)), dim3(256),
+                           0, s, dI, row0, n_rows, fit, prof, wt);
+    return hipGetLastError();
+}
+
+hipError_t launch_bits_unpack(const uint32_t* src_words, int ng, uint32_t* dst_words,
+                              hipStream_t s)
+{
+    const int nw = (ng + 31) / 32;
+    hipLaunchKernelGGL(bits_unpack_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
+                       src_words, ng, dst_words);
+    return hipGetLastError();
+}
+
+}  // namespace qieo

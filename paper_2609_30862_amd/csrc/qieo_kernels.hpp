@@ -1,0 +1,76 @@
+// Shared declarations between the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qieo {
+
+// Genes handled by one wavefront per step: 64 lanes x 4 consecutive genes,
+// i.e. one Philox call (four 32-bit words) per lane.
+constexpr int kChunk = 256;
+// Allele words per chunk: four 64-bit lane masks (one per gene slot j of the
+// lanes), stored as eight 32-bit words.
+constexpr int kWordsPerChunk = 8;
+
+// Device-side description of one resident population.  All arrays live in
+// device memory; the struct itself is read by the kernels from a device copy.
+//
+// Layout (pitch = genes per row rounded up to 64, nchunk = ceil(pitch/256)):
+//   alpha, beta : float[np][pitch]        SoA amplitude planes, gene-fastest
+//   xbits       : uint32[2][np][nchunk*8] alleles of generation t in slot t&1;
+//                 word 2j+h of chunk k holds, at bit b, gene 256k + 4(32h+b) + j
+//   v, w        : int32[pitch]            item values / weights (0 in padding)
+//   fit,prof,wt : int32[2][np]            eq. (1) fitness, profit, weight of t
+//                                         in slot t&1
+//   ekey        : uint64[3]               elite key of generation t in slot t%3:
+//                 ((uint32)f ^ 0x80000000) << 32 | ~row  (max = best, lowest row)
+//   best        : int32[8]                {has, f, profit, weight, gen lo, gen hi,
+//                                          row, 0}
+//   best_bits   : uint32[nchunk*8]        alleles of the best, in xbits layout
+//   tbase       : int64[1]                number of generations completed
+// Padding genes (ng <= i < pitch) hold alpha = 1, beta = 0, v = w = 0: they
+// are never observed as 1 and never rotate.  Each amplitude plane is followed
+// by kChunk floats of zeroed slack and v, w hold nchunk*kChunk entries, so a
+// wavefront may read a whole chunk past the end of any row.
+struct InstDev {
+    float* alpha;
+    float* beta;
+    uint32_t* xbits;
+    const int32_t* v;
+    const int32_t* w;
+    int32_t* fit;
+    int32_t* prof;
+    int32_t* wt;
+    unsigned long long* ekey;
+    int32_t* best;
+    uint32_t* best_bits;
+    int64_t* tbase;
+    int32_t np, ng, pitch, nchunk;
+    int32_t capacity;
+    uint32_t seed_lo, seed_hi;
+};
+
+// One work tile of a batched launch: instance index and first row.
+struct Tile {
+    uint32_t inst;
+    uint32_t row0;
+};
+
+// Host-side launchers (qieo_kernels.hip).
+hipError_t launch_init(const InstDev& I, hipStream_t s);
+// gens_arr (device, one entry per instance) or, when NULL, gens_all gives the
+// number of generations each instance runs in the current call; launch k
+// (0-based) skips instances with gens <= k.
+hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
+                             int rows_per_block, int waves_per_block, int k,
+                             const int32_t* gens_arr, int gens_all, hipStream_t s);
+hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
+                         hipStream_t s);
+hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng,
+                         float* alpha, float* beta, uint8_t* alleles,
+                         int32_t* fit, int32_t* prof, int32_t* wt, hipStream_t s);
+hipError_t launch_bits_unpack(const uint32_t* src_words, int ng, uint32_t* dst_words,
+                              hipStream_t s);
+
+}  // namespace qieo

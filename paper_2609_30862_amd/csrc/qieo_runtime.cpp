@@ -1,0 +1,566 @@
+// libqieo host runtime: C ABI, validation, device memory, streams, timing.
+//
+// One instance owns one device arena (a single allocation, carved into the
+// planes described in qieo_kernels.hpp) and one stream.  qieo_step enqueues
+// one fused generation launch per generation plus one finishing launch, all
+// on that stream; nothing crosses back to the host inside the loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qieo.h"
+#include "qieo_internal.hpp"
+#include "qieo_kernels.hpp"
+
+using namespace qieo;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+namespace qieo {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return set_error(QIEO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ---------------------------------------------------------------------------
+// Device arena
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L)
+{
+    const int32_t pitch = (int32_t)align_up((size_t)ng, 64);
+    const int32_t nchunk = (pitch + kChunk - 1) / kChunk;
+    const size_t wpr = (size_t)nchunk * kWordsPerChunk;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L->pitch = pitch;
+    L->nchunk = nchunk;
+    L->alpha = take(((size_t)np * pitch + kChunk) * sizeof(float));
+    L->beta = take(((size_t)np * pitch + kChunk) * sizeof(float));
+    L->xbits = take(2 * (size_t)np * wpr * sizeof(uint32_t));
+    L->v = take((size_t)nchunk * kChunk * sizeof(int32_t));
+    L->w = take((size_t)nchunk * kChunk * sizeof(int32_t));
+    L->fit = take(2 * (size_t)np * sizeof(int32_t));
+    L->prof = take(2 * (size_t)np * sizeof(int32_t));
+    L->wt = take(2 * (size_t)np * sizeof(int32_t));
+    L->ekey = take(3 * sizeof(unsigned long long));
+    L->best = take(8 * sizeof(int32_t));
+    L->best_bits = take(wpr * sizeof(uint32_t));
+    L->tbase = take(sizeof(int64_t));
+    L->total = off;
+    // everything except the amplitude planes themselves is zero-initialised
+    L->zero_from = 0;
+    return off;
+}
+
+InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
+                   uint64_t seed)
+{
+    InstDev d{};
+    d.alpha = reinterpret_cast<float*>(base + L.alpha);
+    d.beta = reinterpret_cast<float*>(base + L.beta);
+    d.xbits = reinterpret_cast<uint32_t*>(base + L.xbits);
+    d.v = reinterpret_cast<const int32_t*>(base + L.v);
+    d.w = reinterpret_cast<const int32_t*>(base + L.w);
+    d.fit = reinterpret_cast<int32_t*>(base + L.fit);
+    d.prof = reinterpret_cast<int32_t*>(base + L.prof);
+    d.wt = reinterpret_cast<int32_t*>(base + L.wt);
+    d.ekey = reinterpret_cast<unsigned long long*>(base + L.ekey);
+    d.best = reinterpret_cast<int32_t*>(base + L.best);
+    d.best_bits = reinterpret_cast<uint32_t*>(base + L.best_bits);
+    d.tbase = reinterpret_cast<int64_t*>(base + L.tbase);
+    d.np = np;
+    d.ng = ng;
+    d.pitch = L.pitch;
+    d.nchunk = L.nchunk;
+    d.capacity = cap;
+    d.seed_lo = (uint32_t)seed;
+    d.seed_hi = (uint32_t)(seed >> 32);
+    return d;
+}
+
+int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop)
+{
+    if (!items) return set_error(QIEO_EINVAL, "items is NULL");
+    if (n_items < 1) return set_error(QIEO_EINVAL, "n_items must be >= 1 (got %d)", n_items);
+    if (n_pop < 1) return set_error(QIEO_EINVAL, "n_pop must be >= 1 (got %d)", n_pop);
+    if (capacity < 0) return set_error(QIEO_EINVAL, "capacity must be >= 0 (got %d)", capacity);
+    if (n_items > (1 << 30) - 256)
+        return set_error(QIEO_EINVAL, "n_items too large (%d)", n_items);
+    int64_t sv = 0, sw = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        if (items[i].profit < 0 || items[i].weight < 0)
+            return set_error(QIEO_EINVAL, "item %d has a negative profit or weight", i);
+        sv += items[i].profit;
+        sw += items[i].weight;
+    }
+    if (sv > INT32_MAX || sw > INT32_MAX)
+        return set_error(QIEO_EOVERFLOW,
+                         "sum of profits (%lld) or weights (%lld) exceeds INT32_MAX",
+                         (long long)sv, (long long)sw);
+    return QIEO_OK;
+}
+
+// Upload item tables (zero-padded to pitch) and initialise the state.
+int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
+                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging)
+{
+    const size_t pitch = (size_t)d.nchunk * kChunk;   // v, w are zero-padded to whole chunks
+    staging.assign(2 * pitch, 0);
+    for (int32_t i = 0; i < d.ng; ++i) {
+        staging[i] = items[i].profit;
+        staging[pitch + i] = items[i].weight;
+    }
+    hipError_t e;
+    if ((e = hipMemsetAsync(base + L.zero_from, 0, L.total - L.zero_from, s)) != hipSuccess)
+        return hip_fail(e, "hipMemsetAsync");
+    if ((e = hipMemcpyAsync(base + L.v, staging.data(), pitch * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(v)");
+    if ((e = hipMemcpyAsync(base + L.w, staging.data() + pitch, pitch * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(w)");
+    if ((e = launch_init(d, s)) != hipSuccess) return hip_fail(e, "init kernel");
+    return QIEO_OK;
+}
+
+int check_device()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t p;
+    if ((e = hipGetDeviceProperties(&p, dev)) != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
+        return set_error(QIEO_EDEVICE, "device %d is %s, libqieo is built for gfx950", dev,
+                         p.gcnArchName);
+    return QIEO_OK;
+}
+
+// Tile shape for a single instance: rows per workgroup R and waves per
+// workgroup S.  Whole rows stay in one workgroup (Evaluation closes in LDS);
+// S splits the gene axis.  The choice keeps >= ~8 waves per CU resident.
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S)
+{
+    int s = 8;
+    if (nchunk < s) s = std::max(1, nchunk);
+    int r = 1;
+    if (np >= 2048 && nchunk >= 64) r = 2;
+    *R = r;
+    *S = s;
+}
+
+}  // namespace qieo
+
+// ---------------------------------------------------------------------------
+// Single instance
+// ---------------------------------------------------------------------------
+struct qieo_inst {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    qieo_dev_ctx ctx{};
+    bool has_alloc = false;
+    char* arena = nullptr;
+    ArenaLayout L{};
+    InstDev d{};
+    InstDev* d_desc = nullptr;   // device copy of the descriptor (inside its own alloc)
+    InstDev* h_desc = nullptr;   // pinned host staging of the descriptor
+    int32_t ng = 0, np = 0, capacity = 0;
+    uint64_t seed = 0;
+    int64_t t = 0;               // generations enqueued so far
+    int R = 1, S = 1;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop) per timed launch
+    size_t ev_used = 0;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+static void* dev_alloc(qieo_inst* h, size_t bytes)
+{
+    if (h->has_alloc) return h->ctx.alloc(bytes, h->ctx.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+static void dev_free(qieo_inst* h, void* p)
+{
+    if (!p) return;
+    if (h->has_alloc) h->ctx.free(p, h->ctx.user);
+    else (void)hipFree(p);
+}
+
+static void inst_release(qieo_inst* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    dev_free(h, h->arena);
+    dev_free(h, h->d_desc);
+    if (h->h_desc) (void)hipHostFree(h->h_desc);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t capacity,
+                              int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx,
+                              qieo_inst** out)
+{
+    clear_error();
+    if (!out) return set_error(QIEO_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_problem(items, n_items, capacity, n_pop);
+    if (rc) return rc;
+    if (ctx && ((ctx->alloc == nullptr) != (ctx->free == nullptr)))
+        return set_error(QIEO_EINVAL, "ctx->alloc and ctx->free must be both set or both NULL");
+    if ((rc = check_device())) return rc;
+
+    qieo_inst* h = new (std::nothrow) qieo_inst();
+    if (!h) return set_error(QIEO_ENOMEM, "host allocation failed");
+    (void)hipGetDevice(&h->device);
+    if (ctx) {
+        h->ctx = *ctx;
+        h->has_alloc = ctx->alloc != nullptr;
+    }
+    hipError_t e;
+    if (ctx && ctx->stream) {
+        h->stream = (hipStream_t)ctx->stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess) {
+            rc = hip_fail(e, "hipStreamCreate");
+            inst_release(h);
+            return rc;
+        }
+        h->own_stream = true;
+    }
+    h->ng = n_items;
+    h->np = n_pop;
+    h->capacity = capacity;
+    h->seed = seed;
+    arena_layout(n_items, n_pop, &h->L);
+    h->arena = (char*)dev_alloc(h, h->L.total);
+    h->d_desc = (InstDev*)dev_alloc(h, sizeof(InstDev));
+    if (!h->arena || !h->d_desc) {
+        inst_release(h);
+        return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", h->L.total);
+    }
+    if ((e = hipHostMalloc((void**)&h->h_desc, sizeof(InstDev), hipHostMallocDefault)) !=
+        hipSuccess) {
+        rc = hip_fail(e, "hipHostMalloc");
+        inst_release(h);
+        return rc;
+    }
+    h->d = bind_arena(h->arena, h->L, n_items, n_pop, capacity, seed);
+    std::vector<int32_t> staging;
+    if ((rc = upload_and_init(h->d, items, h->stream, h->L, h->arena, staging))) {
+        inst_release(h);
+        return rc;
+    }
+    *h->h_desc = h->d;
+    if ((e = hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(InstDev), hipMemcpyHostToDevice,
+                            h->stream)) != hipSuccess) {
+        rc = hip_fail(e, "hipMemcpyAsync(descriptor)");
+        inst_release(h);
+        return rc;
+    }
+    pick_tile(n_pop, h->L.nchunk, &h->R, &h->S);
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+        rc = hip_fail(e, "hipStreamSynchronize");
+        inst_release(h);
+        return rc;
+    }
+    *out = h;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_create(const qieo_item* items, int32_t n_items, int32_t capacity,
+                           int32_t n_pop, uint64_t seed, qieo_inst** out)
+{
+    return qieo_create_ex(items, n_items, capacity, n_pop, seed, nullptr, out);
+}
+
+static int timed_event_pair(qieo_inst* h, hipEvent_t* a, hipEvent_t* b)
+{
+    while (h->ev.size() < 2 * (h->ev_used + 1)) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+        h->ev.push_back(e);
+    }
+    *a = h->ev[2 * h->ev_used];
+    *b = h->ev[2 * h->ev_used + 1];
+    h->ev_used++;
+    return QIEO_OK;
+}
+
+static int collect_timing(qieo_inst* h)
+{
+    if (h->ev_used == 0) return QIEO_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (size_t k = 0; k < h->ev_used; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        h->total_ms += ms;
+        h->launches++;
+    }
+    h->ev_used = 0;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (n < 0) return set_error(QIEO_EINVAL, "n_generations must be >= 0 (got %d)", n);
+    if (n == 0) return QIEO_OK;
+    if (h->t + n > (int64_t)INT32_MAX)
+        return set_error(QIEO_EINVAL, "generation index would exceed 2^31-1");
+    hipError_t e;
+    const int blocks = (h->np + h->R - 1) / h->R;
+    for (int32_t k = 0; k < n; ++k) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (h->timing) {
+            int rc = timed_event_pair(h, &a, &b);
+            if (rc) return rc;
+            (void)hipEventRecord(a, h->stream);
+        }
+        if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, k, nullptr, n,
+                                   h->stream)) != hipSuccess)
+            return hip_fail(e, "generation kernel");
+        if (h->timing) (void)hipEventRecord(b, h->stream);
+    }
+    if ((e = launch_finish(h->d_desc, 1, nullptr, n, h->stream)) != hipSuccess)
+        return hip_fail(e, "finish kernel");
+    h->t += n;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_sync(qieo_inst* h)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (h->timing) return collect_timing(h);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_step(qieo_inst* h, int32_t n)
+{
+    int rc = qieo_step_async(h, n);
+    if (rc) return rc;
+    return qieo_sync(h);
+}
+
+extern "C" int qieo_generations(qieo_inst* h, int64_t* out)
+{
+    clear_error();
+    if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
+    *out = h->t;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_best(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t n_words)
+{
+    clear_error();
+    if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
+    const size_t need = ((size_t)h->ng + 31) / 32;
+    if (bits && n_words < need)
+        return set_error(QIEO_EINVAL, "bits buffer has %zu words, needs %zu", n_words, need);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int32_t rec[8];
+    if ((e = hipMemcpy(rec, h->d.best, sizeof rec, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(best)");
+    if (!rec[0]) {
+        *out = qieo_result{0, 0, 0, 0, -1, -1};
+        if (bits) std::memset(bits, 0, need * sizeof(uint32_t));
+        return QIEO_OK;
+    }
+    out->fitness = rec[1];
+    out->profit = rec[2];
+    out->weight = rec[3];
+    out->feasible = rec[3] <= h->capacity ? 1 : 0;
+    out->generation = (int64_t)(((uint64_t)(uint32_t)rec[5] << 32) | (uint32_t)rec[4]);
+    out->chromosome = rec[6];
+    if (bits) {
+        uint32_t* tmp = (uint32_t*)dev_alloc(h, need * sizeof(uint32_t));
+        if (!tmp) return set_error(QIEO_ENOMEM, "device allocation failed");
+        int rc = QIEO_OK;
+        if ((e = launch_bits_unpack(h->d.best_bits, h->ng, tmp, h->stream)) != hipSuccess)
+            rc = hip_fail(e, "bits unpack kernel");
+        else if ((e = hipMemcpyAsync(bits, tmp, need * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                     h->stream)) != hipSuccess)
+            rc = hip_fail(e, "hipMemcpyAsync(bits)");
+        else if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            rc = hip_fail(e, "hipStreamSynchronize");
+        dev_free(h, tmp);
+        return rc;
+    }
+    return QIEO_OK;
+}
+
+extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, float* alpha,
+                                float* beta, uint8_t* alleles, int32_t* fitness,
+                                int32_t* profit, int32_t* weight, int32_t* elite)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (row0 < 0 || n_rows < 0 || (int64_t)row0 + n_rows > h->np)
+        return set_error(QIEO_EINVAL, "rows [%d, %d) outside [0, %d)", row0, row0 + n_rows,
+                         h->np);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (elite) {
+        if (h->t == 0) {
+            *elite = -1;
+        } else {
+            unsigned long long key = 0;
+            if ((e = hipMemcpyAsync(&key, h->d.ekey + (h->t - 1) % 3, sizeof key,
+                                    hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(elite)");
+            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+                return hip_fail(e, "hipStreamSynchronize");
+            *elite = (int32_t)(~(uint32_t)key);
+        }
+    }
+    if (n_rows == 0) return QIEO_OK;
+    const size_t per = (size_t)n_rows * h->ng;
+    const size_t bytes = per * (2 * sizeof(float) + 1) + 3 * (size_t)n_rows * sizeof(int32_t) + 64;
+    char* tmp = (char*)dev_alloc(h, bytes);
+    if (!tmp) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    float* da = (float*)tmp;
+    float* db = da + per;
+    int32_t* dfit = (int32_t*)(db + per);
+    int32_t* dprof = dfit + n_rows;
+    int32_t* dwt = dprof + n_rows;
+    uint8_t* dx = (uint8_t*)(dwt + n_rows);
+    int rc = QIEO_OK;
+    if ((e = launch_export(h->d_desc, row0, n_rows, h->ng, da, db, dx, dfit, dprof, dwt,
+                           h->stream)) != hipSuccess) {
+        rc = hip_fail(e, "export kernel");
+    } else {
+        struct { void* dst; const void* src; size_t n; } cp[] = {
+            {alpha, da, per * sizeof(float)}, {beta, db, per * sizeof(float)},
+            {alleles, dx, per}, {fitness, dfit, n_rows * sizeof(int32_t)},
+            {profit, dprof, n_rows * sizeof(int32_t)}, {weight, dwt, n_rows * sizeof(int32_t)}};
+        for (auto& c : cp) {
+            if (!c.dst) continue;
+            if ((e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToHost, h->stream)) !=
+                hipSuccess) {
+                rc = hip_fail(e, "hipMemcpyAsync(export)");
+                break;
+            }
+        }
+        if (rc == QIEO_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    (void)hipStreamSynchronize(h->stream);
+    dev_free(h, tmp);
+    return rc;
+}
+
+extern "C" void qieo_destroy(qieo_inst* h) { inst_release(h); }
+
+extern "C" int qieo_set_tile(qieo_inst* h, int32_t rows_per_block, int32_t waves_per_block)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (rows_per_block != 0 && rows_per_block != 1 && rows_per_block != 2 && rows_per_block != 4)
+        return set_error(QIEO_EINVAL, "rows_per_block must be 1, 2 or 4 (got %d)",
+                         rows_per_block);
+    if (waves_per_block < 0 || waves_per_block > 16)
+        return set_error(QIEO_EINVAL, "waves_per_block must be in [1, 16] (got %d)",
+                         waves_per_block);
+    int R, S;
+    pick_tile(h->np, h->L.nchunk, &R, &S);
+    h->R = rows_per_block ? rows_per_block : R;
+    h->S = waves_per_block ? waves_per_block : S;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_get_tile(qieo_inst* h, int32_t* rows_per_block, int32_t* waves_per_block)
+{
+    clear_error();
+    if (!h || !rows_per_block || !waves_per_block) return set_error(QIEO_EINVAL, "NULL argument");
+    *rows_per_block = h->R;
+    *waves_per_block = h->S;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_set_timing(qieo_inst* h, int enabled)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    h->timing = enabled != 0;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_kernel_time(qieo_inst* h, int64_t* launches, double* total_ms, int reset)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    int rc = collect_timing(h);
+    if (rc) return rc;
+    if (launches) *launches = h->launches;
+    if (total_ms) *total_ms = h->total_ms;
+    if (reset) {
+        h->launches = 0;
+        h->total_ms = 0.0;
+    }
+    return QIEO_OK;
+}
+
+extern "C" const char* qieo_strerror(int code)
+{
+    switch (code) {
+    case QIEO_OK: return "success";
+    case QIEO_EINVAL: return "invalid argument";
+    case QIEO_EOVERFLOW: return "sum of profits or weights exceeds INT32_MAX";
+    case QIEO_ENOMEM: return "out of memory";
+    case QIEO_EDEVICE: return "device or HIP runtime error";
+    case QIEO_EAGAIN: return "not ready";
+    case QIEO_ESTATE: return "invalid state";
+    default: return "unknown error";
+    }
+}
+
+extern "C" const char* qieo_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* qieo_version(void) { return "libqieo 0.1 (gfx950)"; }

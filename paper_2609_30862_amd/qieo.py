@@ -1,0 +1,284 @@
+"""ctypes binding of libqieo (include/qieo.h).
+
+Argument marshalling only: every step of the QIEO generation runs in the HIP
+kernels of libqieo.so.  The functions keep the C names; ``Instance`` is a
+small owner object around a handle.  There is no CPU fallback: if the shared
+library is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqieo.so")
+
+QIEO_OK = 0
+QIEO_EINVAL = -1
+QIEO_EOVERFLOW = -2
+QIEO_ENOMEM = -3
+QIEO_EDEVICE = -4
+QIEO_EAGAIN = -5
+QIEO_ESTATE = -6
+
+
+class QieoError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed (%d, %s): %s" % (where, code, _strerror(code), detail))
+        self.code = code
+
+
+class qieo_item(ctypes.Structure):
+    _fields_ = [("profit", ctypes.c_int32), ("weight", ctypes.c_int32)]
+
+
+class qieo_result(ctypes.Structure):
+    _fields_ = [("fitness", ctypes.c_int32), ("profit", ctypes.c_int32),
+                ("weight", ctypes.c_int32), ("feasible", ctypes.c_int32),
+                ("generation", ctypes.c_int64), ("chromosome", ctypes.c_int64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class qieo_dev_ctx(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqieo.so is not built (expected at %s); run "
+                          "__graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    H = ctypes.c_void_p
+    L.qieo_create.restype = ctypes.c_int
+    L.qieo_create.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(H)]
+    L.qieo_create_ex.restype = ctypes.c_int
+    L.qieo_create_ex.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(qieo_dev_ctx),
+                                 ctypes.POINTER(H)]
+    for n in ("qieo_step", "qieo_step_async"):
+        getattr(L, n).restype = ctypes.c_int
+        getattr(L, n).argtypes = [H, i32]
+    L.qieo_sync.restype = ctypes.c_int
+    L.qieo_sync.argtypes = [H]
+    L.qieo_best.restype = ctypes.c_int
+    L.qieo_best.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
+    L.qieo_generations.restype = ctypes.c_int
+    L.qieo_generations.argtypes = [H, ctypes.POINTER(i64)]
+    L.qieo_export_rows.restype = ctypes.c_int
+    L.qieo_export_rows.argtypes = [H, i32, i32, P, P, P, P, P, P, ctypes.POINTER(i32)]
+    L.qieo_destroy.restype = None
+    L.qieo_destroy.argtypes = [H]
+    L.qieo_strerror.restype = ctypes.c_char_p
+    L.qieo_strerror.argtypes = [ctypes.c_int]
+    L.qieo_last_error.restype = ctypes.c_char_p
+    L.qieo_last_error.argtypes = []
+    L.qieo_version.restype = ctypes.c_char_p
+    L.qieo_version.argtypes = []
+    L.qieo_set_tile.restype = ctypes.c_int
+    L.qieo_set_tile.argtypes = [H, i32, i32]
+    L.qieo_get_tile.restype = ctypes.c_int
+    L.qieo_get_tile.argtypes = [H, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.qieo_set_timing.restype = ctypes.c_int
+    L.qieo_set_timing.argtypes = [H, ctypes.c_int]
+    L.qieo_kernel_time.restype = ctypes.c_int
+    L.qieo_kernel_time.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_int]
+    return L
+
+
+lib = _load()
+
+
+def _strerror(code: int) -> str:
+    return lib.qieo_strerror(code).decode()
+
+
+def qieo_last_error() -> str:
+    return lib.qieo_last_error().decode()
+
+
+def qieo_version() -> str:
+    return lib.qieo_version().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != QIEO_OK:
+        raise QieoError(rc, where, qieo_last_error())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def items_array(values, weights):
+    v = np.ascontiguousarray(values, dtype=np.int64)
+    w = np.ascontiguousarray(weights, dtype=np.int64)
+    if v.shape != w.shape or v.ndim != 1:
+        raise ValueError("values and weights must be 1-D arrays of equal length")
+    if v.size and (v.min() < np.iinfo(np.int32).min or v.max() > np.iinfo(np.int32).max or
+                   w.min() < np.iinfo(np.int32).min or w.max() > np.iinfo(np.int32).max):
+        raise ValueError("values and weights must fit in int32")
+    arr = np.empty((v.size, 2), dtype=np.int32)
+    arr[:, 0] = v
+    arr[:, 1] = w
+    return arr
+
+
+# --- C-named entry points ---------------------------------------------------
+
+def qieo_create(items: np.ndarray, n_items: int, capacity: int, n_pop: int, seed: int,
+                stream: int | None = None):
+    """items: int32 array [n_items, 2] of (profit, weight).  Returns a handle."""
+    h = ctypes.c_void_p()
+    if stream is None:
+        rc = lib.qieo_create(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1),
+                             ctypes.byref(h))
+    else:
+        ctx = qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None, ctypes.c_void_p(stream))
+        rc = lib.qieo_create_ex(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1),
+                                ctypes.byref(ctx), ctypes.byref(h))
+    _check(rc, "qieo_create")
+    return h
+
+
+def qieo_step(h, n_generations: int):
+    _check(lib.qieo_step(h, int(n_generations)), "qieo_step")
+
+
+def qieo_step_async(h, n_generations: int):
+    _check(lib.qieo_step_async(h, int(n_generations)), "qieo_step_async")
+
+
+def qieo_sync(h):
+    _check(lib.qieo_sync(h), "qieo_sync")
+
+
+def qieo_best(h, n_items: int | None = None):
+    r = qieo_result()
+    bits = None
+    if n_items is not None:
+        bits = np.zeros((n_items + 31) // 32, dtype=np.uint32)
+    _check(lib.qieo_best(h, ctypes.byref(r), _ptr(bits), 0 if bits is None else bits.size),
+           "qieo_best")
+    return r, bits
+
+
+def qieo_generations(h) -> int:
+    t = ctypes.c_int64()
+    _check(lib.qieo_generations(h, ctypes.byref(t)), "qieo_generations")
+    return int(t.value)
+
+
+def qieo_destroy(h):
+    if h:
+        lib.qieo_destroy(h)
+
+
+@dataclass
+class Result:
+    fitness: int
+    profit: int
+    weight: int
+    feasible: bool
+    generation: int
+    chromosome: int
+    bits: np.ndarray | None = None
+
+    def alleles(self, n_items: int) -> np.ndarray:
+        """The best string as 0/1 bytes."""
+        b = np.unpackbits(self.bits.view(np.uint8), bitorder="little")
+        return b[:n_items].astype(np.uint8)
+
+
+class Instance:
+    """One resident QIEO population (owner of a libqieo handle)."""
+
+    def __init__(self, values, weights, capacity: int, n_pop: int, seed: int,
+                 stream: int | None = None):
+        self.items = items_array(values, weights)
+        self.n_items = int(self.items.shape[0])
+        self.n_pop = int(n_pop)
+        self.capacity = int(capacity)
+        self.seed = int(seed)
+        self._h = qieo_create(self.items, self.n_items, self.capacity, self.n_pop, self.seed,
+                              stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            qieo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, n: int):
+        qieo_step(self._h, n)
+
+    def step_async(self, n: int):
+        qieo_step_async(self._h, n)
+
+    def sync(self):
+        qieo_sync(self._h)
+
+    @property
+    def generations(self) -> int:
+        return qieo_generations(self._h)
+
+    def best(self) -> Result:
+        r, bits = qieo_best(self._h, self.n_items)
+        return Result(r.fitness, r.profit, r.weight, bool(r.feasible), r.generation,
+                      r.chromosome, bits)
+
+    def export_rows(self, row0: int = 0, n_rows: int | None = None, amplitudes: bool = True,
+                    alleles: bool = True):
+        """State after the last completed generation (its CIP applied) for
+        rows [row0, row0 + n_rows): dict of numpy arrays plus the elite."""
+        if n_rows is None:
+            n_rows = self.n_pop - row0
+        ng = self.n_items
+        a = np.empty((n_rows, ng), np.float32) if amplitudes else None
+        b = np.empty((n_rows, ng), np.float32) if amplitudes else None
+        x = np.empty((n_rows, ng), np.uint8) if alleles else None
+        f = np.empty(n_rows, np.int32)
+        p = np.empty(n_rows, np.int32)
+        w = np.empty(n_rows, np.int32)
+        e = ctypes.c_int32()
+        _check(lib.qieo_export_rows(self._h, row0, n_rows, _ptr(a), _ptr(b), _ptr(x), _ptr(f),
+                                    _ptr(p), _ptr(w), ctypes.byref(e)), "qieo_export_rows")
+        return dict(alpha=a, beta=b, alleles=x, fitness=f, profit=p, weight=w,
+                    elite=int(e.value))
+
+    def set_tile(self, rows_per_block: int = 0, waves_per_block: int = 0):
+        _check(lib.qieo_set_tile(self._h, rows_per_block, waves_per_block), "qieo_set_tile")
+
+    def tile(self):
+        r, s = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.qieo_get_tile(self._h, ctypes.byref(r), ctypes.byref(s)), "qieo_get_tile")
+        return int(r.value), int(s.value)
+
+    def set_timing(self, enabled: bool):
+        _check(lib.qieo_set_timing(self._h, int(bool(enabled))), "qieo_set_timing")
+
+    def kernel_time(self, reset: bool = False):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib.qieo_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms), int(reset)),
+               "qieo_kernel_time")
+        return int(n.value), float(ms.value)

@@ -1,0 +1,77 @@
+"""The C-ABI library loads without a GPU, exports every symbol its header
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(qieo_[a-z_0-9]+)\s*\(", src):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for core in ("qieo_create", "qieo_step", "qieo_best", "qieo_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_30862_amd import qieo
+    lib = ctypes.CDLL(qieo.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_version():
+    from paper_2609_30862_amd import qieo
+    assert "gfx950" in qieo.qieo_version()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert qieo.lib.qieo_strerror(code)
+
+
+@pytest.mark.parametrize("values,weights,cap,n_pop,code", [
+    ([1, -2], [3, 4], 3, 4, -1),           # negative value
+    ([1, 2], [3, -4], 3, 4, -1),           # negative weight
+    ([1, 2], [3, 4], -1, 4, -1),           # negative capacity
+    ([1, 2], [3, 4], 3, 0, -1),            # empty population
+    ([2**31 - 1, 1], [3, 4], 3, 4, -2),    # profit sum overflows int32
+    ([1, 1], [2**31 - 1, 4], 3, 4, -2),    # weight sum overflows int32
+])
+def test_create_validates_before_device(values, weights, cap, n_pop, code):
+    from paper_2609_30862_amd import qieo
+    with pytest.raises(qieo.QieoError) as ei:
+        qieo.Instance(values, weights, cap, n_pop, 0)
+    assert ei.value.code == code
+
+
+def test_create_rejects_empty_items():
+    from paper_2609_30862_amd import qieo
+    h = ctypes.c_void_p()
+    items = np.zeros((1, 2), np.int32)
+    rc = qieo.lib.qieo_create(items.ctypes.data_as(ctypes.c_void_p), 0, 1, 1, 0,
+                              ctypes.byref(h))
+    assert rc == qieo.QIEO_EINVAL and not h.value
+    rc = qieo.lib.qieo_create(None, 3, 1, 1, 0, ctypes.byref(h))
+    assert rc == qieo.QIEO_EINVAL
+
+
+def test_null_handles_are_rejected():
+    from paper_2609_30862_amd import qieo
+    L = qieo.lib
+    assert L.qieo_step(None, 1) == qieo.QIEO_EINVAL
+    assert L.qieo_sync(None) == qieo.QIEO_EINVAL
+    assert L.qieo_set_tile(None, 1, 1) == qieo.QIEO_EINVAL
+    L.qieo_destroy(None)

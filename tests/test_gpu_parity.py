@@ -1,0 +1,129 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for
+bit (amplitudes as binary32 bit patterns, alleles, integer fitness, elite
+index, best-so-far record), generation by generation."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import assert_state_equal, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qieo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2609_30862_amd import qieo as q
+    return q
+
+
+def _pair(qieo, oracle_mod, inst, threads=1, tile=None):
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    if tile is not None:
+        g.set_tile(*tile)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          threads=threads)
+    return g, o
+
+
+def test_initial_state(qieo, oracle_mod):
+    inst = workloads.random_instance(300, 5, seed=1)
+    g, o = _pair(qieo, oracle_mod, inst)
+    st = g.export_rows()
+    a, b = o.amplitudes()
+    assert np.array_equal(st["alpha"], a) and np.array_equal(st["beta"], b)
+    assert st["elite"] == -1
+    r = g.best()
+    assert r.generation == -1
+
+
+def test_small_instance_every_generation(qieo, oracle_mod):
+    """Ng=100, Np=16, 500 generations, seed 0: full state after every one."""
+    inst = workloads.small_instance()
+    say("small instance %s" % inst.name)
+    g, o = _pair(qieo, oracle_mod, inst)
+    for gen in range(inst.generations):
+        g.step(1)
+        o.generation()
+        assert_state_equal(g, o, label="gen %d" % gen)
+    assert g.generations == inst.generations
+
+
+# ragged sizes: genes per row around the 64-gene pitch and 256-gene chunk
+# boundaries, single rows, odd row counts; every work shape
+SHAPES = [
+    (1, 1), (3, 1), (63, 2), (64, 3), (65, 4), (255, 5), (256, 6), (257, 7),
+    (511, 3), (1000, 9), (4097, 5), (20000, 3), (130, 33),
+]
+
+
+@pytest.mark.parametrize("ng,n_pop", SHAPES)
+def test_ragged_shapes_every_generation(qieo, oracle_mod, ng, n_pop):
+    inst = workloads.random_instance(ng, n_pop, seed=ng * 7 + n_pop)
+    say("ragged Ng=%d Np=%d" % (ng, n_pop))
+    g, o = _pair(qieo, oracle_mod, inst)
+    for gen in range(12):
+        g.step(1)
+        o.generation()
+        assert_state_equal(g, o, label="Ng=%d Np=%d gen %d" % (ng, n_pop, gen))
+
+
+@pytest.mark.parametrize("tile", [(1, 1), (1, 3), (2, 2), (2, 16), (4, 1), (4, 5), (4, 16)])
+def test_work_shapes_same_trajectory(qieo, oracle_mod, tile):
+    inst = workloads.random_instance(1500, 23, seed=99)
+    say("tile %s" % (tile,))
+    g, o = _pair(qieo, oracle_mod, inst, tile=tile)
+    assert g.tile() == tile
+    for step in (1, 2, 7):
+        g.step(step)
+        o.run(step)
+        assert_state_equal(g, o, label="tile %s t=%d" % (tile, o.t))
+
+
+def test_split_steps_equal_one_step(qieo, oracle_mod):
+    inst = workloads.random_instance(777, 19, seed=4)
+    a = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    b = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    a.step(30)
+    for n in (1, 4, 0, 10, 15):
+        b.step(n)
+    sa, sb = a.export_rows(), b.export_rows()
+    for k in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sa["elite"] == sb["elite"]
+    assert a.best() .__dict__.keys() == b.best().__dict__.keys()
+    ra, rb = a.best(), b.best()
+    assert (ra.fitness, ra.generation, ra.chromosome) == (rb.fitness, rb.generation, rb.chromosome)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    o.run(30)
+    assert_state_equal(b, o, label="split")
+
+
+def test_async_steps(qieo, oracle_mod):
+    inst = workloads.random_instance(2000, 40, seed=8)
+    g, o = _pair(qieo, oracle_mod, inst)
+    for _ in range(5):
+        g.step_async(3)
+    g.sync()
+    o.run(15)
+    assert_state_equal(g, o, label="async")
+
+
+def test_medium_instance_checkpoints(qieo, oracle_mod):
+    """Ng=10,000, Np=1024, 1000 generations, seed 1: full state at several
+    generations and at the end (oracle row-threaded)."""
+    inst = workloads.medium_instance()
+    threads = min(16, os.cpu_count() or 1)
+    say("medium instance, oracle threads %d" % threads)
+    g, o = _pair(qieo, oracle_mod, inst, threads=threads)
+    done = 0
+    for ck in (1, 2, 10, 100, 400, 1000):
+        g.step(ck - done)
+        o.run(ck - done)
+        done = ck
+        say("  compare at generation %d" % ck)
+        assert_state_equal(g, o, label="medium gen %d" % ck)

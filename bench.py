@@ -23,10 +23,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, 8.0 TB/s
 BYTES_PER_GENE_UPDATE = 16      # binary32 (alpha, beta) read + write
+KERNEL_SOURCES = ["paper_2609_30862_amd/csrc/qieo_kernels.hip",
+                  "paper_2609_30862_amd/csrc/qieo_device.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_kernels.hpp"]
+PROFILE = "profiles/generation_kernel_np4096_ng200000.md"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(n_pop: int, n_items: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on this workload with the current kernel sources; else None."""
+    import hashlib
+    if (n_pop, n_items) != (4096, 200_000):
+        return None
+    try:
+        text = open(os.path.join(ROOT, PROFILE)).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+        if fig.get("kernel_source_sha256") != h.hexdigest():
+            return None
+        return float(fig["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(inst, rows: int, gens: int):
@@ -53,9 +78,12 @@ def main():
     ap.add_argument("--n-pop", type=int, default=4096)
     ap.add_argument("--n-items", type=int, default=200_000)
     ap.add_argument("--tile", type=str, default="", help="R,S work shape override")
+    ap.add_argument("--kernel-flags", type=int, default=-1, help="generation kernel variant")
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -72,12 +100,23 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB x 5" % args.copy_calibration)
+        return
     inst = workloads.large_instance(args.n_pop, args.n_items)
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
     g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
     if args.tile:
         r, s = (int(x) for x in args.tile.split(","))
         g.set_tile(r, s)
+    if args.kernel_flags >= 0:
+        g.set_kernel_flags(args.kernel_flags)
     log("work shape rows/block, waves/block = %s" % (g.tile(),))
     g.step(args.warmup)
 
@@ -123,7 +162,8 @@ def main():
                    "generations_per_step": 1},
         "hbm_frac_algorithmic": value * BYTES_PER_GENE_UPDATE / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(inst.n_pop, inst.n_items),
                      "kernel": "generation_kernel", "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_per_launch},
     }

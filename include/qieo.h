@@ -148,6 +148,10 @@ void qieo_destroy(qieo_inst *h);
 int qieo_set_tile(qieo_inst *h, int32_t rows_per_block, int32_t waves_per_block);
 /* Current work shape. */
 int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_block);
+/* Code variant of the generation kernel: bit 0 prefetches the next chunk's
+ * amplitudes while the current one is computed, bit 1 stores amplitudes with
+ * non-temporal hints.  Variants change speed only, never results. */
+int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 
 /* ---- errors and introspection ------------------------------------------- */
 const char *qieo_strerror(int code);

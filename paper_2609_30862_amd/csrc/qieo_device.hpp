@@ -107,6 +107,13 @@ __device__ __forceinline__ void gstore(T* base, uint32_t idx, T v)
     ((QIEO_AS_GLOBAL T*)base)[idx] = v;
 }
 
+// Streaming store that is not expected to be re-read soon (no L2 retention).
+template <typename T>
+__device__ __forceinline__ void gstore_nt(T* base, uint32_t idx, T v)
+{
+    __builtin_nontemporal_store(v, &((QIEO_AS_GLOBAL T*)base)[idx]);
+}
+
 template <typename T>
 __device__ __forceinline__ T sload(const T* p)
 {

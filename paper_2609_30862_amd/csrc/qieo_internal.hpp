@@ -31,6 +31,6 @@ int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, 
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
                     const ArenaLayout& L, char* base, std::vector<int32_t>& staging);
 int check_device();
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S);
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 
 }  // namespace qieo

@@ -99,7 +99,7 @@ __global__ void init_kernel(InstDev I)
 // the generation index is t = *tbase + k, and an instance whose call asked
 // for fewer than k+1 generations skips the launch.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool PF, bool NT>
 __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
                                                          const Tile* __restrict__ tiles, int k,
                                                          const int32_t* __restrict__ gens_arr,
@@ -122,7 +122,8 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
     const int64_t t = sload(I.tbase) + k;
     const int par = (int)(t & 1);
     const int np = I.np;
-    const int wpr = I.nchunk * kWordsPerChunk;
+    const int nchunk = I.nchunk;
+    const int wpr = nchunk * kWordsPerChunk;
     const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
     uint32_t* __restrict__ xcur = I.xbits + (size_t)par * np * wpr;
 
@@ -147,9 +148,15 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 
     const int nrows = min(R, np - (int)row0);
     bool rot[R];
+    const f32x4* arow[R];
+    const f32x4* brow4[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
         rot[r] = pending && r < nrows && sload(I.fit + (par ^ 1) * np + row0 + r) < fe_prev;
+        const size_t base = (size_t)(row0 + (r < nrows ? r : 0)) * I.pitch;
+        arow[r] = (const f32x4*)(I.alpha + base);
+        brow4[r] = (const f32x4*)(I.beta + base);
+    }
 
     uint32_t accP[R], accW[R];
 #pragma unroll
@@ -157,13 +164,37 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 
     const uint32_t* __restrict__ brow = xprev + (size_t)e_prev * wpr;
 
-    for (int ch = wave; ch < I.nchunk; ch += S) {
+    // Amplitudes of one chunk for the workgroup's rows: beta always (QIP),
+    // alpha only for rows that rotate (CIP).  Lanes past the row end (only in
+    // a row's last chunk) read the slack after the plane or the next row;
+    // their alleles are masked to 0 and their stores skipped.
+    f32x4 nb[R], na[R];
+    auto load_chunk = [&](int chx) {
+        const uint32_t qx = (uint32_t)chx * (kChunk / 4) + lane;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r < nrows) {
+                nb[r] = gload(brow4[r], qx);
+                if (rot[r]) na[r] = gload(arow[r], qx);
+            }
+        }
+    };
+    if (PF && wave < nchunk) load_chunk(wave);
+
+    for (int ch = wave; ch < nchunk; ch += S) {
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
-        // Lanes past the row end (only in a row's last chunk) load from the
-        // slack that follows every plane and the next row; their alleles are
-        // masked to 0 and their stores are skipped.
         const bool act = g0 < (uint32_t)I.pitch;
         const uint32_t q = g0 >> 2;          // float4 / int4 index in a row
+        f32x4 cb[R], ca[R];
+        if (PF) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) { cb[r] = nb[r]; ca[r] = na[r]; }
+            if (ch + S < nchunk) load_chunk(ch + S);   // next chunk in flight during this one
+        } else {
+            load_chunk(ch);
+#pragma unroll
+            for (int r = 0; r < R; ++r) { cb[r] = nb[r]; ca[r] = na[r]; }
+        }
         const i32x4 v4 = gload((const i32x4*)I.v, q);
         const i32x4 w4 = gload((const i32x4*)I.w, q);
         uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0;
@@ -176,12 +207,9 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         for (int r = 0; r < R; ++r) {
             if (r >= nrows) break;
             const int c = (int)row0 + r;
-            const f32x4* arow = (const f32x4*)(I.alpha + (size_t)c * I.pitch);
-            const f32x4* brow4 = (const f32x4*)(I.beta + (size_t)c * I.pitch);
-            f32x4 b4 = gload(brow4, q);
-            f32x4 a4;
+            f32x4 b4 = cb[r];
+            f32x4 a4 = ca[r];
             if (rot[r]) {
-                a4 = gload(arow, q);
                 const uint64_t* xw =
                     reinterpret_cast<const uint64_t*>(xprev + (size_t)c * wpr + ch * kWordsPerChunk);
                 const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
@@ -212,8 +240,13 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
             accW[r] += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
                        (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
             if (rot[r] && act) {
-                gstore((f32x4*)arow, q, a4);
-                gstore((f32x4*)brow4, q, b4);
+                if (NT) {
+                    gstore_nt((f32x4*)arow[r], q, a4);
+                    gstore_nt((f32x4*)brow4[r], q, b4);
+                } else {
+                    gstore((f32x4*)arow[r], q, a4);
+                    gstore((f32x4*)brow4[r], q, b4);
+                }
             }
         }
     }
@@ -348,18 +381,30 @@ hipError_t launch_init(const InstDev& I, hipStream_t s)
 }
 
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
-                             int rows_per_block, int waves_per_block, int k,
+                             int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s)
 {
     if (n_blocks <= 0) return hipSuccess;
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
+#define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
+    hipLaunchKernelGGL((generation_kernel<RR, PFF, NTT>), grid, block, 0, s, dI, tiles, k,      \
+                       gens_arr, gens_all)
+#define QIEO_LAUNCH_R(RR)                                                                      \
+    switch (flags & 3) {                                                                       \
+    case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
+    case 1: QIEO_LAUNCH(RR, true, false); break;                                               \
+    case 2: QIEO_LAUNCH(RR, false, true); break;                                               \
+    default: QIEO_LAUNCH(RR, true, true); break;                                               \
+    }
     switch (rows_per_block) {
-    case 1: hipLaunchKernelGGL(generation_kernel<1>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
-    case 2: hipLaunchKernelGGL(generation_kernel<2>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
-    case 4: hipLaunchKernelGGL(generation_kernel<4>, grid, block, 0, s, dI, tiles, k, gens_arr, gens_all); break;
+    case 1: QIEO_LAUNCH_R(1); break;
+    case 2: QIEO_LAUNCH_R(2); break;
+    case 4: QIEO_LAUNCH_R(4); break;
     default: return hipErrorInvalidValue;
     }
+#undef QIEO_LAUNCH_R
+#undef QIEO_LAUNCH
     return hipGetLastError();
 }
 

@@ -62,8 +62,12 @@ hipError_t launch_init(const InstDev& I, hipStream_t s);
 // gens_arr (device, one entry per instance) or, when NULL, gens_all gives the
 // number of generations each instance runs in the current call; launch k
 // (0-based) skips instances with gens <= k.
+// flags: bit 0 = prefetch the next chunk's amplitudes while computing the
+// current one; bit 1 = non-temporal amplitude stores.
+constexpr int kFlagPrefetch = 1;
+constexpr int kFlagNontemporal = 2;
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
-                             int rows_per_block, int waves_per_block, int k,
+                             int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
                          hipStream_t s);

@@ -166,17 +166,25 @@ int check_device()
     return QIEO_OK;
 }
 
-// Tile shape for a single instance: rows per workgroup R and waves per
-// workgroup S.  Whole rows stay in one workgroup (Evaluation closes in LDS);
-// S splits the gene axis.  The choice keeps >= ~8 waves per CU resident.
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S)
+// Work shape for a single instance: rows per workgroup R, waves per
+// workgroup S and kernel variant flags.  Whole rows stay in one workgroup
+// (Evaluation closes in LDS); S splits the gene axis.  R is the largest of
+// 4, 2, 1 that still leaves >= 32 wavefronts per CU (8192 on 256 CUs), since
+// more rows per workgroup amortise the item-table and elite-mask reads;
+// prefetching pays once a wave walks several chunks.  On the 4096 x 200,000
+// workload this is (4, 8, prefetch | non-temporal), the fastest shape of a
+// full sweep of R in {1,2,4}, S in {4,8,16} and all flags.
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
 {
     int s = 8;
     if (nchunk < s) s = std::max(1, nchunk);
     int r = 1;
-    if (np >= 2048 && nchunk >= 64) r = 2;
+    for (int cand : {4, 2}) {
+        if ((int64_t)((np + cand - 1) / cand) * s >= 8192) { r = cand; break; }
+    }
     *R = r;
     *S = s;
+    *flags = (nchunk >= 2 * s ? kFlagPrefetch : 0) | kFlagNontemporal;
 }
 
 }  // namespace qieo
@@ -198,7 +206,7 @@ struct qieo_inst {
     int32_t ng = 0, np = 0, capacity = 0;
     uint64_t seed = 0;
     int64_t t = 0;               // generations enqueued so far
-    int R = 1, S = 1;
+    int R = 1, S = 1, flags = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) per timed launch
     size_t ev_used = 0;
@@ -297,7 +305,7 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
         inst_release(h);
         return rc;
     }
-    pick_tile(n_pop, h->L.nchunk, &h->R, &h->S);
+    pick_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags);
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         rc = hip_fail(e, "hipStreamSynchronize");
         inst_release(h);
@@ -360,7 +368,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
             if (rc) return rc;
             (void)hipEventRecord(a, h->stream);
         }
-        if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, k, nullptr, n,
+        if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
                                    h->stream)) != hipSuccess)
             return hip_fail(e, "generation kernel");
         if (h->timing) (void)hipEventRecord(b, h->stream);
@@ -462,24 +470,40 @@ extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, floa
     }
     if (n_rows == 0) return QIEO_OK;
     const size_t per = (size_t)n_rows * h->ng;
-    const size_t bytes = per * (2 * sizeof(float) + 1) + 3 * (size_t)n_rows * sizeof(int32_t) + 64;
-    char* tmp = (char*)dev_alloc(h, bytes);
-    if (!tmp) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", bytes);
-    float* da = (float*)tmp;
-    float* db = da + per;
-    int32_t* dfit = (int32_t*)(db + per);
-    int32_t* dprof = dfit + n_rows;
-    int32_t* dwt = dprof + n_rows;
-    uint8_t* dx = (uint8_t*)(dwt + n_rows);
+    // device staging only for the outputs asked for
+    const size_t amp_bytes = per * sizeof(float);
+    const size_t row_bytes = (size_t)n_rows * sizeof(int32_t);
+    size_t off = 0;
+    auto reserve = [&](bool want, size_t n) {
+        if (!want) return (size_t)-1;
+        const size_t o = off;
+        off += (n + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_a = reserve(alpha != nullptr, amp_bytes);
+    const size_t o_b = reserve(beta != nullptr, amp_bytes);
+    const size_t o_x = reserve(alleles != nullptr, per);
+    const size_t o_f = reserve(fitness != nullptr, row_bytes);
+    const size_t o_p = reserve(profit != nullptr, row_bytes);
+    const size_t o_w = reserve(weight != nullptr, row_bytes);
+    if (off == 0) return QIEO_OK;
+    char* tmp = (char*)dev_alloc(h, off);
+    if (!tmp) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", off);
+    auto at = [&](size_t o) { return o == (size_t)-1 ? nullptr : tmp + o; };
+    float* da = (float*)at(o_a);
+    float* db = (float*)at(o_b);
+    uint8_t* dx = (uint8_t*)at(o_x);
+    int32_t* dfit = (int32_t*)at(o_f);
+    int32_t* dprof = (int32_t*)at(o_p);
+    int32_t* dwt = (int32_t*)at(o_w);
     int rc = QIEO_OK;
     if ((e = launch_export(h->d_desc, row0, n_rows, h->ng, da, db, dx, dfit, dprof, dwt,
                            h->stream)) != hipSuccess) {
         rc = hip_fail(e, "export kernel");
     } else {
         struct { void* dst; const void* src; size_t n; } cp[] = {
-            {alpha, da, per * sizeof(float)}, {beta, db, per * sizeof(float)},
-            {alleles, dx, per}, {fitness, dfit, n_rows * sizeof(int32_t)},
-            {profit, dprof, n_rows * sizeof(int32_t)}, {weight, dwt, n_rows * sizeof(int32_t)}};
+            {alpha, da, amp_bytes}, {beta, db, amp_bytes}, {alleles, dx, per},
+            {fitness, dfit, row_bytes}, {profit, dprof, row_bytes}, {weight, dwt, row_bytes}};
         for (auto& c : cp) {
             if (!c.dst) continue;
             if ((e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToHost, h->stream)) !=
@@ -508,10 +532,19 @@ extern "C" int qieo_set_tile(qieo_inst* h, int32_t rows_per_block, int32_t waves
     if (waves_per_block < 0 || waves_per_block > 16)
         return set_error(QIEO_EINVAL, "waves_per_block must be in [1, 16] (got %d)",
                          waves_per_block);
-    int R, S;
-    pick_tile(h->np, h->L.nchunk, &R, &S);
+    int R, S, F;
+    pick_tile(h->np, h->L.nchunk, &R, &S, &F);
     h->R = rows_per_block ? rows_per_block : R;
     h->S = waves_per_block ? waves_per_block : S;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_set_kernel_flags(qieo_inst* h, int32_t flags)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (flags < 0 || flags > 3) return set_error(QIEO_EINVAL, "flags must be in [0, 3] (got %d)", flags);
+    h->flags = flags;
     return QIEO_OK;
 }
 

@@ -83,6 +83,8 @@ def _load():
     L.qieo_version.argtypes = []
     L.qieo_set_tile.restype = ctypes.c_int
     L.qieo_set_tile.argtypes = [H, i32, i32]
+    L.qieo_set_kernel_flags.restype = ctypes.c_int
+    L.qieo_set_kernel_flags.argtypes = [H, i32]
     L.qieo_get_tile.restype = ctypes.c_int
     L.qieo_get_tile.argtypes = [H, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.qieo_set_timing.restype = ctypes.c_int
@@ -211,9 +213,13 @@ class Instance:
                               stream)
 
     def close(self):
-        if getattr(self, "_h", None):
-            qieo_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and lib is not None:
+            try:
+                lib.qieo_destroy(h)
+            except Exception:       # interpreter shutdown: the library may be gone
+                pass
 
     def __del__(self):
         self.close()
@@ -267,6 +273,9 @@ class Instance:
 
     def set_tile(self, rows_per_block: int = 0, waves_per_block: int = 0):
         _check(lib.qieo_set_tile(self._h, rows_per_block, waves_per_block), "qieo_set_tile")
+
+    def set_kernel_flags(self, flags: int):
+        _check(lib.qieo_set_kernel_flags(self._h, int(flags)), "qieo_set_kernel_flags")
 
     def tile(self):
         r, s = ctypes.c_int32(), ctypes.c_int32()

@@ -72,11 +72,13 @@ def test_ragged_shapes_every_generation(qieo, oracle_mod, ng, n_pop):
         assert_state_equal(g, o, label="Ng=%d Np=%d gen %d" % (ng, n_pop, gen))
 
 
-@pytest.mark.parametrize("tile", [(1, 1), (1, 3), (2, 2), (2, 16), (4, 1), (4, 5), (4, 16)])
-def test_work_shapes_same_trajectory(qieo, oracle_mod, tile):
+@pytest.mark.parametrize("tile,flags", [((1, 1), 0), ((1, 3), 1), ((2, 2), 2), ((2, 16), 3),
+                                        ((4, 1), 1), ((4, 5), 3), ((4, 16), 0), ((1, 8), 3)])
+def test_work_shapes_same_trajectory(qieo, oracle_mod, tile, flags):
     inst = workloads.random_instance(1500, 23, seed=99)
-    say("tile %s" % (tile,))
+    say("tile %s flags %d" % (tile, flags))
     g, o = _pair(qieo, oracle_mod, inst, tile=tile)
+    g.set_kernel_flags(flags)
     assert g.tile() == tile
     for step in (1, 2, 7):
         g.step(step)

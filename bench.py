@@ -70,6 +70,138 @@ def cpu_baseline(inst, rows: int, gens: int):
                       "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt)}
 
 
+def bench_batch(args):
+    """512 ragged instances, 500 generations each: one batched call (all
+    instances in the same launches, graph-replayed) against the per-instance
+    loop of qieo_step calls, at identical best-found profit."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2609_30862_amd import qieo
+
+    insts = workloads.batch_instances()
+    gens = insts[0].generations
+    genes = sum(i.genes for i in insts)
+    probs = [(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
+    log("batch: %d instances, %.4g genes per generation, %d generations" % (len(insts), genes, gens))
+    b = qieo.Batch(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(gens)
+    wall_batch = time.perf_counter() - t0
+    best_batch = [b.best(k) for k in range(len(insts))]
+    b.close()
+    log("batched: %.3f s" % wall_batch)
+
+    wall_loop = 0.0
+    same = 0
+    for k, i in enumerate(insts):
+        g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(gens)
+        wall_loop += time.perf_counter() - t0
+        r = g.best()
+        same += int((r.fitness, r.profit, r.generation, r.chromosome) ==
+                    (best_batch[k].fitness, best_batch[k].profit, best_batch[k].generation,
+                     best_batch[k].chromosome))
+        g.close()
+    log("per-instance loop: %.3f s; identical best records %d/%d" % (wall_loop, same, len(insts)))
+    out = {
+        "metric": "gene-updates/s", "value": genes * gens / wall_batch, "unit": "gene-updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "qieo-knapsack batch of %d ragged instances, %d generations"
+                               % (len(insts), gens)},
+        "per_instance_loop": {"value": genes * gens / wall_loop, "seconds": wall_loop},
+        "speedup_vs_loop": wall_loop / wall_batch,
+        "identical_best": "%d/%d" % (same, len(insts)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Open-loop replay of a Poisson request stream through the server: each
+    request is submitted at its arrival time; latency is completion minus
+    submission.  The per-instance loop (qieo_create + qieo_step per request,
+    one after another) runs a sample of the same requests for comparison."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2609_30862_amd import qieo
+
+    reqs = workloads.serving_requests(args.requests, args.rate)
+    work = [r.instance.genes * r.instance.generations for r in reqs]
+    log("serve: %d requests at %.0f/s, %.4g gene-updates, budget %.0f GB, cap %d, G=%d"
+        % (len(reqs), args.rate, sum(work), args.budget_gb, args.max_resident,
+           args.gens_per_iter))
+    srv = qieo.Server(int(args.budget_gb * (1 << 30)), args.max_resident, args.gens_per_iter)
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        delay = t0 + r.arrival_s - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        i = r.instance
+        tickets.append(srv.submit(i.values, i.weights, i.capacity, i.n_pop, i.seed,
+                                  i.generations))
+    t_sub = time.perf_counter() - t0
+    log("submitted in %.2f s; waiting" % t_sub)
+    res, lat = [], []
+    last_log = time.perf_counter()
+    for k, t in enumerate(tickets):
+        out = srv.wait(t)
+        res.append(out[0])
+        lat.append(out[1] * 1e-9)
+        if time.perf_counter() - last_log > 20:
+            st = srv.stats()
+            log("  %d/%d done, resident %d, queued %d" % (k + 1, len(tickets), st["resident"],
+                                                          st["queued"]))
+            last_log = time.perf_counter()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    served = sum(work) / wall
+    log("served: %.2f s, %.4g gene-updates/s, latency p50 %.2f s p99 %.2f s, peak resident %d"
+        % (wall, served, np.percentile(lat, 50), np.percentile(lat, 99), st["peak_resident"]))
+
+    m = min(args.loop_sample, len(reqs))
+    loop_s, same = 0.0, 0
+    for k in range(m):
+        i = reqs[k].instance
+        g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        g.step(i.generations)
+        loop_s += time.perf_counter() - ts
+        r = g.best()
+        same += int((r.fitness, r.generation, r.chromosome) ==
+                    (res[k].fitness, res[k].generation, res[k].chromosome) and
+                    np.array_equal(r.bits, res[k].bits))
+        g.close()
+    loop_rate = sum(work[:m]) / loop_s
+    log("per-instance loop on %d requests: %.2f s, %.4g gene-updates/s, identical %d/%d"
+        % (m, loop_s, loop_rate, same, m))
+    out = {
+        "metric": "gene-updates/s", "value": served, "unit": "gene-updates/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "qieo-knapsack serving, %d Poisson requests at %.0f/s, "
+                               "%.0f GB budget" % (len(reqs), args.rate, args.budget_gb),
+                   "max_resident": args.max_resident, "gens_per_iter": args.gens_per_iter},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "mean": float(lat.mean()), "max": float(lat.max())},
+        "server": {k: st[k] for k in ("iterations", "peak_resident", "peak_pool_used", "failed")},
+        "per_instance_loop": {"requests": m, "value": loop_rate, "seconds": loop_s,
+                              "identical_best": "%d/%d" % (same, m)},
+        "speedup_vs_loop": served / loop_rate,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +214,17 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["large", "batch", "serve"], default="large",
+                    help="large: the single 4096 x 200,000 instance (default); batch: 512 "
+                         "ragged instances x 500 generations vs a per-instance launch loop; "
+                         "serve: Poisson request stream through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=500.0, help="serve: offered requests/s")
+    ap.add_argument("--budget-gb", type=float, default=128.0, help="serve: HBM budget")
+    ap.add_argument("--max-resident", type=int, default=0, help="serve: resident cap (0 = none)")
+    ap.add_argument("--gens-per-iter", type=int, default=25, help="serve: generations/iteration")
+    ap.add_argument("--loop-sample", type=int, default=200,
+                    help="serve: requests re-run one by one for the per-instance loop baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -109,6 +252,10 @@ def main():
         torch.cuda.synchronize()
         log("copied %d MiB x 5" % args.copy_calibration)
         return
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     inst = workloads.large_instance(args.n_pop, args.n_items)
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
     g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)

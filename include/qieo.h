@@ -153,6 +153,98 @@ int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_bloc
  * non-temporal hints.  Variants change speed only, never results. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 
+/* ---- batch: many instances advanced together (one device pool) ---------- */
+
+/* One knapsack problem plus its QIEO parameters (Sec. III-A): items as for
+ * qieo_create, capacity, population size n_pop, Philox seed. */
+typedef struct qieo_problem {
+    const qieo_item *items;
+    int32_t n_items;
+    int32_t capacity;
+    int32_t n_pop;
+    uint64_t seed;
+} qieo_problem;
+
+typedef struct qieo_batch qieo_batch;
+
+/* Creates n >= 1 populations, each exactly as qieo_create would, in one
+ * device pool of the summed size.  Each problem is validated as in
+ * qieo_create (the failing index is named in qieo_last_error()).  Instances
+ * are numbered 0..n-1 in input order. */
+int qieo_batch_create(const qieo_problem *probs, int32_t n, const qieo_dev_ctx *ctx,
+                      qieo_batch **out);
+
+/* Runs n_gen_per_inst[i] >= 0 generations of instance i, for every i (array
+ * of qieo_batch_size entries), all instances in the same launches; waits.
+ * Each instance's state afterwards is bit-identical to running it alone with
+ * qieo_step. */
+int qieo_batch_step(qieo_batch *b, const int32_t *n_gen_per_inst);
+/* As qieo_batch_step without waiting; the counts are copied before return. */
+int qieo_batch_step_async(qieo_batch *b, const int32_t *n_gen_per_inst);
+int qieo_batch_sync(qieo_batch *b);
+int qieo_batch_size(const qieo_batch *b, int32_t *n);
+int qieo_batch_generations(qieo_batch *b, int32_t i, int64_t *out);
+/* Best-so-far of instance i; bits as for qieo_best. */
+int qieo_batch_best(qieo_batch *b, int32_t i, qieo_result *out, uint32_t *bits,
+                    size_t n_words);
+/* Row export of instance i, as qieo_export_rows. */
+int qieo_batch_export_rows(qieo_batch *b, int32_t i, int32_t row0, int32_t n_rows,
+                           float *alpha, float *beta, uint8_t *alleles, int32_t *fitness,
+                           int32_t *profit, int32_t *weight, int32_t *elite);
+/* Work shape for every launch of the batch (rows_per_block = 0 restores the
+ * library's per-class choice); see qieo_set_tile and qieo_set_kernel_flags. */
+int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per_block,
+                        int32_t flags);
+/* 1 (default): each call's launches are captured once into a HIP graph and
+ * replayed; 0: launched one by one. */
+int qieo_batch_set_graph(qieo_batch *b, int32_t enabled);
+void qieo_batch_destroy(qieo_batch *b);
+
+/* ---- server: continuous batching of solve requests ----------------------- */
+
+/* hbm_budget_bytes: size of the device pool that holds resident populations
+ * (one allocation at create; a request is admitted only when its population
+ * fits).  max_resident: cap on concurrently resident requests (0 = none).
+ * gens_per_iter: generations every resident population advances per engine
+ * iteration (0 = 25); admissions and retirements happen between iterations. */
+typedef struct qieo_server_cfg {
+    size_t hbm_budget_bytes;
+    int32_t max_resident;
+    int32_t gens_per_iter;
+} qieo_server_cfg;
+
+typedef struct qieo_server_stats {
+    int64_t queued, resident, admitted, completed, failed, iterations;
+    double gene_updates;          /* sum of Np*Ng*generations run so far */
+    size_t pool_bytes, pool_used;
+    int64_t peak_resident;
+    size_t peak_pool_used;
+    int32_t error;                /* first worker error (0 = none) */
+} qieo_server_stats;
+
+typedef struct qieo_server qieo_server;
+
+/* Creates the server and its worker thread (which owns all GPU work). */
+int qieo_server_create(const qieo_server_cfg *cfg, const qieo_dev_ctx *ctx, qieo_server **out);
+/* Queues a request to run n_gen >= 1 generations of a fresh population for
+ * problem p (copied; validated as in qieo_create).  Thread-safe.  *ticket
+ * identifies it.  Its result is bit-identical to qieo_create + qieo_step(n_gen)
+ * + qieo_best on the same inputs, whatever else is resident. */
+int qieo_server_submit(qieo_server *s, const qieo_problem *p, int32_t n_gen, uint64_t *ticket);
+/* QIEO_EAGAIN while the request is queued or running; otherwise its result
+ * (or its failure code, e.g. QIEO_ENOMEM when its population can never fit
+ * the budget).  latency_ns = completion - submission, steady clock. */
+int qieo_server_poll(qieo_server *s, uint64_t ticket, qieo_result *out, uint32_t *bits,
+                     size_t n_words, int64_t *latency_ns);
+/* As qieo_server_poll, blocking until the request has finished. */
+int qieo_server_wait(qieo_server *s, uint64_t ticket, qieo_result *out, uint32_t *bits,
+                     size_t n_words, int64_t *latency_ns);
+/* Forgets a finished request (its result can no longer be polled). */
+int qieo_server_release(qieo_server *s, uint64_t ticket);
+int qieo_server_get_stats(qieo_server *s, qieo_server_stats *out);
+/* Stops the worker after its current iteration and frees everything. */
+void qieo_server_destroy(qieo_server *s);
+
 /* ---- errors and introspection ------------------------------------------- */
 const char *qieo_strerror(int code);
 /* Message of the last failing call on this thread ("" if none). */

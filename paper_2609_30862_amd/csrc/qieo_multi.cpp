@@ -1,0 +1,519 @@
+// Multi-instance engine and the batch C ABI.
+//
+// A batch keeps every population resident in one device pool and advances
+// all of them with the same generation launches: the tile table of a launch
+// lists (instance, first row) pairs from every instance of one shape class,
+// so a generation of 512 small instances costs a handful of launches instead
+// of 512.  The launches of a whole call (n generations x classes, plus the
+// finishing step) are captured once into a HIP graph and replayed.
+#include "qieo_multi.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "../../include/qieo.h"
+
+namespace qieo {
+
+// ---------------------------------------------------------------------------
+// DevicePool
+// ---------------------------------------------------------------------------
+static size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+DevicePool::~DevicePool()
+{
+    if (!base_) return;
+    if (has_alloc_) ctx_.free(base_, ctx_.user);
+    else (void)hipFree(base_);
+}
+
+int DevicePool::init(size_t bytes, const qieo_dev_ctx* ctx)
+{
+    bytes = round256(std::max<size_t>(bytes, 256));
+    if (ctx && ctx->alloc) {
+        ctx_ = *ctx;
+        has_alloc_ = true;
+        base_ = (char*)ctx->alloc(bytes, ctx->user);
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        base_ = (char*)p;
+    }
+    if (!base_) return set_error(QIEO_ENOMEM, "device pool of %zu bytes could not be allocated", bytes);
+    cap_ = bytes;
+    used_ = 0;
+    free_.clear();
+    busy_.clear();
+    free_[0] = bytes;
+    return QIEO_OK;
+}
+
+char* DevicePool::alloc(size_t bytes)
+{
+    bytes = round256(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        busy_[off] = bytes;
+        used_ += bytes;
+        return base_ + off;
+    }
+    return nullptr;
+}
+
+void DevicePool::release(char* p)
+{
+    if (!p) return;
+    const size_t off = (size_t)(p - base_);
+    auto b = busy_.find(off);
+    if (b == busy_.end()) return;
+    size_t start = off, sz = b->second;
+    busy_.erase(b);
+    used_ -= sz;
+    auto next = free_.lower_bound(start);
+    if (next != free_.end() && start + sz == next->first) {
+        sz += next->second;
+        next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == start) {
+            start = prev->first;
+            sz += prev->second;
+            free_.erase(prev);
+        }
+    }
+    free_[start] = sz;
+}
+
+size_t DevicePool::largest_free() const
+{
+    size_t m = 0;
+    for (auto& f : free_) m = std::max(m, f.second);
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+Engine::~Engine()
+{
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    invalidate_graph();
+    for (auto& c : classes_)
+        if (c.d_tiles) (void)hipFree(c.d_tiles);
+    if (d_desc_) (void)hipFree(d_desc_);
+    if (d_gens_) (void)hipFree(d_gens_);
+    if (h_gens_) (void)hipHostFree(h_gens_);
+}
+
+void Engine::invalidate_graph()
+{
+    if (graph_) (void)hipGraphExecDestroy(graph_);
+    graph_ = nullptr;
+    graph_n_ = -1;
+}
+
+int Engine::add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32_t capacity,
+                int32_t n_pop, uint64_t seed, uint64_t id)
+{
+    int rc = validate_problem(items, n_items, capacity, n_pop);
+    if (rc) return rc;
+    Member m;
+    arena_layout(n_items, n_pop, &m.L);
+    m.arena = pool.alloc(m.L.total);
+    if (!m.arena)
+        return set_error(QIEO_ENOMEM, "no room for %zu bytes in the device pool (%zu of %zu used)",
+                         m.L.total, pool.used(), pool.capacity());
+    m.d = bind_arena(m.arena, m.L, n_items, n_pop, capacity, seed);
+    m.ng = n_items;
+    m.np = n_pop;
+    m.capacity = capacity;
+    m.seed = seed;
+    m.id = id;
+    if ((rc = upload_and_init(m.d, items, stream_, m.L, m.arena, staging_))) {
+        pool.release(m.arena);
+        return rc;
+    }
+    // the pageable staging buffer is reused by the next add
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) {
+        pool.release(m.arena);
+        return hip_fail(e, "hipStreamSynchronize");
+    }
+    members_.push_back(m);
+    dirty_ = true;
+    return QIEO_OK;
+}
+
+void Engine::remove_at(size_t idx, DevicePool& pool)
+{
+    if (idx >= members_.size()) return;
+    pool.release(members_[idx].arena);
+    members_.erase(members_.begin() + idx);
+    dirty_ = true;
+}
+
+void Engine::force_shape(int R, int S, int flags)
+{
+    force_R_ = R;
+    force_S_ = S;
+    force_flags_ = flags;
+    dirty_ = true;
+}
+
+// Shape classes by chunks per row: a workgroup of S waves needs >= S chunks
+// per row to keep its waves busy, so short rows go to narrow workgroups.
+static int class_of(int32_t nchunk)
+{
+    if (nchunk <= 1) return 0;
+    if (nchunk <= 3) return 1;
+    if (nchunk <= 7) return 2;
+    return 3;
+}
+
+int Engine::rebuild()
+{
+    invalidate_graph();
+    for (auto& c : classes_)
+        if (c.d_tiles) (void)hipFree(c.d_tiles);
+    classes_.clear();
+    const size_t n = members_.size();
+    hipError_t e;
+    if (n > desc_cap_) {
+        if (d_desc_) (void)hipFree(d_desc_);
+        if (d_gens_) (void)hipFree(d_gens_);
+        if (h_gens_) (void)hipHostFree(h_gens_);
+        d_desc_ = nullptr;
+        d_gens_ = nullptr;
+        h_gens_ = nullptr;
+        const size_t cap = std::max<size_t>(n, 2 * desc_cap_);
+        if ((e = hipMalloc(&d_desc_, cap * sizeof(InstDev))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(descriptors)");
+        if ((e = hipMalloc(&d_gens_, cap * sizeof(int32_t))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(generation counts)");
+        if ((e = hipHostMalloc((void**)&h_gens_, cap * sizeof(int32_t), hipHostMallocDefault)) !=
+            hipSuccess)
+            return hip_fail(e, "hipHostMalloc");
+        desc_cap_ = gens_cap_ = cap;
+    }
+    if (n == 0) {
+        dirty_ = false;
+        return QIEO_OK;
+    }
+    std::vector<InstDev> desc(n);
+    for (size_t i = 0; i < n; ++i) desc[i] = members_[i].d;
+    if ((e = hipMemcpyAsync(d_desc_, desc.data(), n * sizeof(InstDev), hipMemcpyHostToDevice,
+                            stream_)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(descriptors)");
+
+    // group members by shape class; within a class, longest rows first so the
+    // longest-running workgroups start first
+    std::vector<std::vector<size_t>> groups(4);
+    for (size_t i = 0; i < n; ++i) groups[class_of(members_[i].L.nchunk)].push_back(i);
+    static const int kS[4] = {1, 2, 4, 8};
+    for (int c = 0; c < 4; ++c) {
+        auto& g = groups[c];
+        if (g.empty()) continue;
+        std::sort(g.begin(), g.end(), [&](size_t a, size_t b) {
+            if (members_[a].L.nchunk != members_[b].L.nchunk)
+                return members_[a].L.nchunk > members_[b].L.nchunk;
+            return a < b;
+        });
+        ShapeClass sc;
+        int64_t rows = 0, max_nchunk = 0;
+        for (size_t i : g) {
+            rows += members_[i].np;
+            max_nchunk = std::max<int64_t>(max_nchunk, members_[i].L.nchunk);
+        }
+        sc.S = kS[c];
+        sc.R = 1;
+        for (int cand : {4, 2}) {
+            // blocks of the class at R rows each, times S waves: keep >= 8192 waves
+            int64_t blocks = 0;
+            for (size_t i : g) blocks += (members_[i].np + cand - 1) / cand;
+            if (blocks * sc.S >= 8192) { sc.R = cand; break; }
+        }
+        sc.flags = kFlagNontemporal | (max_nchunk >= 2 * sc.S ? kFlagPrefetch : 0);
+        if (force_R_ > 0) {
+            sc.R = force_R_;
+            sc.S = force_S_;
+            sc.flags = force_flags_;
+        }
+        for (size_t i : g)
+            for (int32_t r0 = 0; r0 < members_[i].np; r0 += sc.R)
+                sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
+        if ((e = hipMalloc(&sc.d_tiles, sc.tiles.size() * sizeof(Tile))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(tiles)");
+        if ((e = hipMemcpyAsync(sc.d_tiles, sc.tiles.data(), sc.tiles.size() * sizeof(Tile),
+                                hipMemcpyHostToDevice, stream_)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(tiles)");
+        classes_.push_back(std::move(sc));
+    }
+    // host vectors above are pageable and local: wait for their copies
+    if ((e = hipStreamSynchronize(stream_)) != hipSuccess)
+        return hip_fail(e, "hipStreamSynchronize");
+    dirty_ = false;
+    return QIEO_OK;
+}
+
+int Engine::enqueue(int nmax)
+{
+    hipError_t e;
+    for (int k = 0; k < nmax; ++k) {
+        for (auto& c : classes_) {
+            if ((e = launch_generation(d_desc_, c.d_tiles, (int)c.tiles.size(), c.R, c.S, c.flags,
+                                       k, d_gens_, 0, stream_)) != hipSuccess)
+                return hip_fail(e, "generation kernel");
+        }
+    }
+    if ((e = launch_finish(d_desc_, (int)members_.size(), d_gens_, 0, stream_)) != hipSuccess)
+        return hip_fail(e, "finish kernel");
+    return QIEO_OK;
+}
+
+int Engine::capture(int nmax)
+{
+    invalidate_graph();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = enqueue(nmax);
+    e = hipStreamEndCapture(stream_, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        graph_ = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    graph_n_ = nmax;
+    return QIEO_OK;
+}
+
+int Engine::run(const int32_t* gens)
+{
+    int rc;
+    if (dirty_ && (rc = rebuild())) return rc;
+    const size_t n = members_.size();
+    if (n == 0) return QIEO_OK;
+    int nmax = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (gens[i] < 0) return set_error(QIEO_EINVAL, "negative generation count for instance %zu", i);
+        if (members_[i].t + gens[i] > (int64_t)INT32_MAX)
+            return set_error(QIEO_EINVAL, "generation index of instance %zu would exceed 2^31-1", i);
+        nmax = std::max(nmax, gens[i]);
+    }
+    if (nmax == 0) return QIEO_OK;
+    // the pinned counts may still feed the previous call's copy
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::memcpy(h_gens_, gens, n * sizeof(int32_t));
+    if ((e = hipMemcpyAsync(d_gens_, h_gens_, n * sizeof(int32_t), hipMemcpyHostToDevice,
+                            stream_)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(generation counts)");
+    if (use_graph_) {
+        if (graph_n_ != nmax && (rc = capture(nmax))) return rc;
+        if ((e = hipGraphLaunch(graph_, stream_)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else if ((rc = enqueue(nmax))) {
+        return rc;
+    }
+    for (size_t i = 0; i < n; ++i) members_[i].t += gens[i];
+    return QIEO_OK;
+}
+
+int Engine::sync()
+{
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return QIEO_OK;
+}
+
+}  // namespace qieo
+
+// ---------------------------------------------------------------------------
+// Batch C ABI
+// ---------------------------------------------------------------------------
+using namespace qieo;
+
+struct qieo_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevicePool pool;
+    Engine* eng = nullptr;
+};
+
+static void batch_release(qieo_batch* b)
+{
+    if (!b) return;
+    delete b->eng;
+    b->eng = nullptr;
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qieo_dev_ctx* ctx,
+                                 qieo_batch** out)
+{
+    clear_error();
+    if (!out) return set_error(QIEO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !probs) return set_error(QIEO_EINVAL, "need n >= 1 problems (got %d)", n);
+    if (ctx && ((ctx->alloc == nullptr) != (ctx->free == nullptr)))
+        return set_error(QIEO_EINVAL, "ctx->alloc and ctx->free must be both set or both NULL");
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = validate_problem(probs[i].items, probs[i].n_items, probs[i].capacity,
+                                  probs[i].n_pop);
+        if (rc) return set_error(rc, "problem %d: %s", i, qieo_last_error());
+        ArenaLayout L;
+        total += round256(arena_layout(probs[i].n_items, probs[i].n_pop, &L));
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    qieo_batch* b = new (std::nothrow) qieo_batch();
+    if (!b) return set_error(QIEO_ENOMEM, "host allocation failed");
+    hipError_t e;
+    if (ctx && ctx->stream) {
+        b->stream = (hipStream_t)ctx->stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
+            rc = hip_fail(e, "hipStreamCreate");
+            batch_release(b);
+            return rc;
+        }
+        b->own_stream = true;
+    }
+    if ((rc = b->pool.init(total, ctx))) {
+        batch_release(b);
+        return rc;
+    }
+    b->eng = new (std::nothrow) Engine(b->stream);
+    if (!b->eng) {
+        batch_release(b);
+        return set_error(QIEO_ENOMEM, "host allocation failed");
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if ((rc = b->eng->add(b->pool, probs[i].items, probs[i].n_items, probs[i].capacity,
+                              probs[i].n_pop, probs[i].seed, (uint64_t)i))) {
+            batch_release(b);
+            return rc;
+        }
+    }
+    *out = b;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_step_async(qieo_batch* b, const int32_t* n_gen_per_inst)
+{
+    clear_error();
+    if (!b || !n_gen_per_inst) return set_error(QIEO_EINVAL, "NULL argument");
+    return b->eng->run(n_gen_per_inst);
+}
+
+extern "C" int qieo_batch_sync(qieo_batch* b)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "NULL argument");
+    return b->eng->sync();
+}
+
+extern "C" int qieo_batch_step(qieo_batch* b, const int32_t* n_gen_per_inst)
+{
+    int rc = qieo_batch_step_async(b, n_gen_per_inst);
+    if (rc) return rc;
+    return qieo_batch_sync(b);
+}
+
+extern "C" int qieo_batch_size(const qieo_batch* b, int32_t* n)
+{
+    clear_error();
+    if (!b || !n) return set_error(QIEO_EINVAL, "NULL argument");
+    *n = (int32_t)b->eng->size();
+    return QIEO_OK;
+}
+
+static int batch_member(qieo_batch* b, int32_t i, Member** m)
+{
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    if (i < 0 || (size_t)i >= b->eng->size())
+        return set_error(QIEO_EINVAL, "instance %d outside [0, %zu)", i, b->eng->size());
+    *m = &b->eng->member((size_t)i);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_best(qieo_batch* b, int32_t i, qieo_result* out, uint32_t* bits,
+                               size_t n_words)
+{
+    clear_error();
+    Member* m;
+    int rc = batch_member(b, i, &m);
+    if (rc) return rc;
+    if (!out) return set_error(QIEO_EINVAL, "out is NULL");
+    return read_best(m->d, m->capacity, b->stream, out, bits, n_words);
+}
+
+extern "C" int qieo_batch_generations(qieo_batch* b, int32_t i, int64_t* out)
+{
+    clear_error();
+    Member* m;
+    int rc = batch_member(b, i, &m);
+    if (rc) return rc;
+    if (!out) return set_error(QIEO_EINVAL, "out is NULL");
+    *out = m->t;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_export_rows(qieo_batch* b, int32_t i, int32_t row0, int32_t n_rows,
+                                      float* alpha, float* beta, uint8_t* alleles,
+                                      int32_t* fitness, int32_t* profit, int32_t* weight,
+                                      int32_t* elite)
+{
+    clear_error();
+    Member* m;
+    int rc = batch_member(b, i, &m);
+    if (rc) return rc;
+    int e = b->eng->sync();
+    if (e) return e;
+    // the descriptor array is rebuilt lazily; make sure it describes member i
+    if ((e = b->eng->ensure_built())) return e;
+    return export_rows(m->d, b->eng->device_desc((size_t)i), m->t, b->stream, row0, n_rows,
+                       alpha, beta, alleles, fitness, profit, weight, elite);
+}
+
+extern "C" int qieo_batch_set_tile(qieo_batch* b, int32_t rows_per_block,
+                                   int32_t waves_per_block, int32_t flags)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    if (rows_per_block == 0) {
+        b->eng->force_shape(0, 0, 0);
+        return QIEO_OK;
+    }
+    if ((rows_per_block != 1 && rows_per_block != 2 && rows_per_block != 4) ||
+        waves_per_block < 1 || waves_per_block > 16 || flags < 0 || flags > 3)
+        return set_error(QIEO_EINVAL, "bad work shape (%d, %d, %d)", rows_per_block,
+                         waves_per_block, flags);
+    b->eng->force_shape(rows_per_block, waves_per_block, flags);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_set_graph(qieo_batch* b, int32_t enabled)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    b->eng->set_use_graph(enabled != 0);
+    return QIEO_OK;
+}
+
+extern "C" void qieo_batch_destroy(qieo_batch* b) { batch_release(b); }

@@ -1,0 +1,106 @@
+// Multi-instance engine: many resident populations advanced together, one
+// fused generation launch per shape class per generation, captured in a HIP
+// graph.  Used by the batch API and by the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <vector>
+
+#include "qieo_internal.hpp"
+
+namespace qieo {
+
+// First-fit offset allocator over one device allocation (the HBM budget of a
+// server, or the exact total of a batch).  Blocks are 256-byte aligned; freed
+// ranges are coalesced with their neighbours.
+class DevicePool {
+public:
+    DevicePool() = default;
+    ~DevicePool();
+    int init(size_t bytes, const qieo_dev_ctx* ctx);   // QIEO_OK / QIEO_ENOMEM
+    char* alloc(size_t bytes);                         // nullptr if no room
+    void release(char* p);
+    size_t capacity() const { return cap_; }
+    size_t used() const { return used_; }
+    size_t largest_free() const;
+
+private:
+    char* base_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+    qieo_dev_ctx ctx_{};
+    bool has_alloc_ = false;
+    std::map<size_t, size_t> free_;   // offset -> size
+    std::map<size_t, size_t> busy_;   // offset -> size
+};
+
+// One resident population inside an engine.
+struct Member {
+    InstDev d{};          // device pointers into its arena
+    ArenaLayout L{};
+    char* arena = nullptr;
+    int32_t ng = 0, np = 0, capacity = 0;
+    uint64_t seed = 0;
+    int64_t t = 0;        // generations completed (host mirror)
+    uint64_t id = 0;      // caller's identifier
+};
+
+// Work shape of one launch class.
+struct ShapeClass {
+    int R = 4, S = 8, flags = 0;
+    std::vector<Tile> tiles;
+    Tile* d_tiles = nullptr;   // device copy
+};
+
+class Engine {
+public:
+    explicit Engine(hipStream_t s) : stream_(s) {}
+    ~Engine();
+
+    // Membership.  add() uploads items and initialises the state on the
+    // engine's stream; the arena comes from `pool`.
+    int add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32_t capacity,
+            int32_t n_pop, uint64_t seed, uint64_t id);
+    void remove_at(size_t idx, DevicePool& pool);
+    size_t size() const { return members_.size(); }
+    Member& member(size_t i) { return members_[i]; }
+    const InstDev* device_desc(size_t i) const { return d_desc_ + i; }
+
+    // Runs gens[i] generations of member i (all members in the same launches)
+    // and the finishing step; enqueued on the stream, not waited for.
+    int run(const int32_t* gens);
+    int sync();
+
+    // Shape-class override for experiments and tuning: every class uses
+    // (R, S, flags) when R > 0.
+    void force_shape(int R, int S, int flags);
+    void set_use_graph(bool on) { use_graph_ = on; invalidate_graph(); }
+    // Uploads descriptors and tile tables if membership changed since the
+    // last launch (device_desc() is valid only after this).
+    int ensure_built() { return dirty_ ? rebuild() : QIEO_OK; }
+
+private:
+    int rebuild();               // descriptors and tile tables after membership change
+    int capture(int nmax);
+    int enqueue(int nmax);
+    void invalidate_graph();
+
+    hipStream_t stream_;
+    std::vector<Member> members_;
+    bool dirty_ = true;
+    InstDev* d_desc_ = nullptr;
+    size_t desc_cap_ = 0;
+    int32_t* d_gens_ = nullptr;
+    int32_t* h_gens_ = nullptr;    // pinned
+    size_t gens_cap_ = 0;
+    std::vector<ShapeClass> classes_;
+    int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
+    bool use_graph_ = true;
+    hipGraphExec_t graph_ = nullptr;
+    int graph_n_ = -1;
+    std::vector<int32_t> staging_;
+};
+
+}  // namespace qieo

@@ -404,17 +404,34 @@ extern "C" int qieo_generations(qieo_inst* h, int64_t* out)
     return QIEO_OK;
 }
 
-extern "C" int qieo_best(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t n_words)
+namespace qieo {
+
+// Temporary device buffer for reads of an instance's state.
+struct TempDev {
+    void* p = nullptr;
+    explicit TempDev(size_t n)
+    {
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+    }
+    ~TempDev()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
+              uint32_t* bits, size_t n_words)
 {
-    clear_error();
-    if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
-    const size_t need = ((size_t)h->ng + 31) / 32;
+    const size_t need = ((size_t)d.ng + 31) / 32;
     if (bits && n_words < need)
         return set_error(QIEO_EINVAL, "bits buffer has %zu words, needs %zu", n_words, need);
-    hipError_t e = hipStreamSynchronize(h->stream);
+    hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     int32_t rec[8];
-    if ((e = hipMemcpy(rec, h->d.best, sizeof rec, hipMemcpyDeviceToHost)) != hipSuccess)
+    if ((e = hipMemcpy(rec, d.best, sizeof rec, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "hipMemcpy(best)");
     if (!rec[0]) {
         *out = qieo_result{0, 0, 0, 0, -1, -1};
@@ -424,52 +441,42 @@ extern "C" int qieo_best(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t 
     out->fitness = rec[1];
     out->profit = rec[2];
     out->weight = rec[3];
-    out->feasible = rec[3] <= h->capacity ? 1 : 0;
+    out->feasible = rec[3] <= capacity ? 1 : 0;
     out->generation = (int64_t)(((uint64_t)(uint32_t)rec[5] << 32) | (uint32_t)rec[4]);
     out->chromosome = rec[6];
-    if (bits) {
-        uint32_t* tmp = (uint32_t*)dev_alloc(h, need * sizeof(uint32_t));
-        if (!tmp) return set_error(QIEO_ENOMEM, "device allocation failed");
-        int rc = QIEO_OK;
-        if ((e = launch_bits_unpack(h->d.best_bits, h->ng, tmp, h->stream)) != hipSuccess)
-            rc = hip_fail(e, "bits unpack kernel");
-        else if ((e = hipMemcpyAsync(bits, tmp, need * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                     h->stream)) != hipSuccess)
-            rc = hip_fail(e, "hipMemcpyAsync(bits)");
-        else if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
-            rc = hip_fail(e, "hipStreamSynchronize");
-        dev_free(h, tmp);
-        return rc;
-    }
+    if (!bits) return QIEO_OK;
+    TempDev tmp(need * sizeof(uint32_t));
+    if (!tmp.p) return set_error(QIEO_ENOMEM, "device allocation failed");
+    if ((e = launch_bits_unpack(d.best_bits, d.ng, (uint32_t*)tmp.p, s)) != hipSuccess)
+        return hip_fail(e, "bits unpack kernel");
+    if ((e = hipMemcpyAsync(bits, tmp.p, need * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(bits)");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return QIEO_OK;
 }
 
-extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, float* alpha,
-                                float* beta, uint8_t* alleles, int32_t* fitness,
-                                int32_t* profit, int32_t* weight, int32_t* elite)
+int export_rows(const InstDev& d, const InstDev* d_desc, int64_t t, hipStream_t s,
+                int32_t row0, int32_t n_rows, float* alpha, float* beta, uint8_t* alleles,
+                int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite)
 {
-    clear_error();
-    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
-    if (row0 < 0 || n_rows < 0 || (int64_t)row0 + n_rows > h->np)
-        return set_error(QIEO_EINVAL, "rows [%d, %d) outside [0, %d)", row0, row0 + n_rows,
-                         h->np);
-    hipError_t e = hipStreamSynchronize(h->stream);
+    if (row0 < 0 || n_rows < 0 || (int64_t)row0 + n_rows > d.np)
+        return set_error(QIEO_EINVAL, "rows [%d, %d) outside [0, %d)", row0, row0 + n_rows, d.np);
+    hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (elite) {
-        if (h->t == 0) {
+        if (t == 0) {
             *elite = -1;
         } else {
             unsigned long long key = 0;
-            if ((e = hipMemcpyAsync(&key, h->d.ekey + (h->t - 1) % 3, sizeof key,
-                                    hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
-                return hip_fail(e, "hipMemcpyAsync(elite)");
-            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
-                return hip_fail(e, "hipStreamSynchronize");
+            if ((e = hipMemcpy(&key, d.ekey + (t - 1) % 3, sizeof key, hipMemcpyDeviceToHost)) !=
+                hipSuccess)
+                return hip_fail(e, "hipMemcpy(elite)");
             *elite = (int32_t)(~(uint32_t)key);
         }
     }
     if (n_rows == 0) return QIEO_OK;
-    const size_t per = (size_t)n_rows * h->ng;
+    const size_t per = (size_t)n_rows * d.ng;
     // device staging only for the outputs asked for
     const size_t amp_bytes = per * sizeof(float);
     const size_t row_bytes = (size_t)n_rows * sizeof(int32_t);
@@ -487,37 +494,52 @@ extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, floa
     const size_t o_p = reserve(profit != nullptr, row_bytes);
     const size_t o_w = reserve(weight != nullptr, row_bytes);
     if (off == 0) return QIEO_OK;
-    char* tmp = (char*)dev_alloc(h, off);
-    if (!tmp) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", off);
-    auto at = [&](size_t o) { return o == (size_t)-1 ? nullptr : tmp + o; };
+    TempDev tmp(off);
+    if (!tmp.p) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", off);
+    char* base = (char*)tmp.p;
+    auto at = [&](size_t o) { return o == (size_t)-1 ? nullptr : base + o; };
     float* da = (float*)at(o_a);
     float* db = (float*)at(o_b);
     uint8_t* dx = (uint8_t*)at(o_x);
     int32_t* dfit = (int32_t*)at(o_f);
     int32_t* dprof = (int32_t*)at(o_p);
     int32_t* dwt = (int32_t*)at(o_w);
+    if ((e = launch_export(d_desc, row0, n_rows, d.ng, da, db, dx, dfit, dprof, dwt, s)) !=
+        hipSuccess)
+        return hip_fail(e, "export kernel");
+    struct { void* dst; const void* src; size_t n; } cp[] = {
+        {alpha, da, amp_bytes}, {beta, db, amp_bytes}, {alleles, dx, per},
+        {fitness, dfit, row_bytes}, {profit, dprof, row_bytes}, {weight, dwt, row_bytes}};
     int rc = QIEO_OK;
-    if ((e = launch_export(h->d_desc, row0, n_rows, h->ng, da, db, dx, dfit, dprof, dwt,
-                           h->stream)) != hipSuccess) {
-        rc = hip_fail(e, "export kernel");
-    } else {
-        struct { void* dst; const void* src; size_t n; } cp[] = {
-            {alpha, da, amp_bytes}, {beta, db, amp_bytes}, {alleles, dx, per},
-            {fitness, dfit, row_bytes}, {profit, dprof, row_bytes}, {weight, dwt, row_bytes}};
-        for (auto& c : cp) {
-            if (!c.dst) continue;
-            if ((e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToHost, h->stream)) !=
-                hipSuccess) {
-                rc = hip_fail(e, "hipMemcpyAsync(export)");
-                break;
-            }
+    for (auto& c : cp) {
+        if (!c.dst) continue;
+        if ((e = hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDeviceToHost, s)) != hipSuccess) {
+            rc = hip_fail(e, "hipMemcpyAsync(export)");
+            break;
         }
-        if (rc == QIEO_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess)
-            rc = hip_fail(e, "hipStreamSynchronize");
     }
-    (void)hipStreamSynchronize(h->stream);
-    dev_free(h, tmp);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == QIEO_OK)
+        rc = hip_fail(e, "hipStreamSynchronize");
     return rc;
+}
+
+}  // namespace qieo
+
+extern "C" int qieo_best(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t n_words)
+{
+    clear_error();
+    if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
+    return read_best(h->d, h->capacity, h->stream, out, bits, n_words);
+}
+
+extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, float* alpha,
+                                float* beta, uint8_t* alleles, int32_t* fitness,
+                                int32_t* profit, int32_t* weight, int32_t* elite)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    return export_rows(h->d, h->d_desc, h->t, h->stream, row0, n_rows, alpha, beta, alleles,
+                       fitness, profit, weight, elite);
 }
 
 extern "C" void qieo_destroy(qieo_inst* h) { inst_release(h); }

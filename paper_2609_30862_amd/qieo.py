@@ -41,6 +41,26 @@ class qieo_result(ctypes.Structure):
                 ("generation", ctypes.c_int64), ("chromosome", ctypes.c_int64)]
 
 
+class qieo_problem(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_void_p), ("n_items", ctypes.c_int32),
+                ("capacity", ctypes.c_int32), ("n_pop", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class qieo_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_resident", ctypes.c_int32),
+                ("gens_per_iter", ctypes.c_int32)]
+
+
+class qieo_server_stats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("resident", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("gene_updates", ctypes.c_double), ("pool_bytes", ctypes.c_size_t),
+                ("pool_used", ctypes.c_size_t), ("peak_resident", ctypes.c_int64),
+                ("peak_pool_used", ctypes.c_size_t), ("error", ctypes.c_int32)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -92,6 +112,45 @@ def _load():
     L.qieo_kernel_time.restype = ctypes.c_int
     L.qieo_kernel_time.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_int]
+    L.qieo_batch_create.restype = ctypes.c_int
+    L.qieo_batch_create.argtypes = [ctypes.POINTER(qieo_problem), i32,
+                                    ctypes.POINTER(qieo_dev_ctx), ctypes.POINTER(H)]
+    for n in ("qieo_batch_step", "qieo_batch_step_async"):
+        getattr(L, n).restype = ctypes.c_int
+        getattr(L, n).argtypes = [H, P]
+    L.qieo_batch_sync.restype = ctypes.c_int
+    L.qieo_batch_sync.argtypes = [H]
+    L.qieo_batch_size.restype = ctypes.c_int
+    L.qieo_batch_size.argtypes = [H, ctypes.POINTER(i32)]
+    L.qieo_batch_generations.restype = ctypes.c_int
+    L.qieo_batch_generations.argtypes = [H, i32, ctypes.POINTER(i64)]
+    L.qieo_batch_best.restype = ctypes.c_int
+    L.qieo_batch_best.argtypes = [H, i32, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
+    L.qieo_batch_export_rows.restype = ctypes.c_int
+    L.qieo_batch_export_rows.argtypes = [H, i32, i32, i32, P, P, P, P, P, P,
+                                         ctypes.POINTER(i32)]
+    L.qieo_batch_set_tile.restype = ctypes.c_int
+    L.qieo_batch_set_tile.argtypes = [H, i32, i32, i32]
+    L.qieo_batch_set_graph.restype = ctypes.c_int
+    L.qieo_batch_set_graph.argtypes = [H, i32]
+    L.qieo_batch_destroy.restype = None
+    L.qieo_batch_destroy.argtypes = [H]
+    L.qieo_server_create.restype = ctypes.c_int
+    L.qieo_server_create.argtypes = [ctypes.POINTER(qieo_server_cfg),
+                                     ctypes.POINTER(qieo_dev_ctx), ctypes.POINTER(H)]
+    L.qieo_server_submit.restype = ctypes.c_int
+    L.qieo_server_submit.argtypes = [H, ctypes.POINTER(qieo_problem), i32,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    for n in ("qieo_server_poll", "qieo_server_wait"):
+        getattr(L, n).restype = ctypes.c_int
+        getattr(L, n).argtypes = [H, ctypes.c_uint64, ctypes.POINTER(qieo_result), P,
+                                  ctypes.c_size_t, ctypes.POINTER(i64)]
+    L.qieo_server_release.restype = ctypes.c_int
+    L.qieo_server_release.argtypes = [H, ctypes.c_uint64]
+    L.qieo_server_get_stats.restype = ctypes.c_int
+    L.qieo_server_get_stats.argtypes = [H, ctypes.POINTER(qieo_server_stats)]
+    L.qieo_server_destroy.restype = None
+    L.qieo_server_destroy.argtypes = [H]
     return L
 
 
@@ -291,3 +350,164 @@ class Instance:
         _check(lib.qieo_kernel_time(self._h, ctypes.byref(n), ctypes.byref(ms), int(reset)),
                "qieo_kernel_time")
         return int(n.value), float(ms.value)
+
+
+def _export(fn, n_items, n_pop, row0, n_rows, amplitudes, alleles, where):
+    if n_rows is None:
+        n_rows = n_pop - row0
+    a = np.empty((n_rows, n_items), np.float32) if amplitudes else None
+    b = np.empty((n_rows, n_items), np.float32) if amplitudes else None
+    x = np.empty((n_rows, n_items), np.uint8) if alleles else None
+    f = np.empty(n_rows, np.int32)
+    p = np.empty(n_rows, np.int32)
+    w = np.empty(n_rows, np.int32)
+    e = ctypes.c_int32()
+    _check(fn(row0, n_rows, _ptr(a), _ptr(b), _ptr(x), _ptr(f), _ptr(p), _ptr(w),
+              ctypes.byref(e)), where)
+    return dict(alpha=a, beta=b, alleles=x, fitness=f, profit=p, weight=w, elite=int(e.value))
+
+
+class Batch:
+    """Many resident populations advanced together (qieo_batch_*)."""
+
+    def __init__(self, problems, stream: int | None = None):
+        """problems: iterable of (values, weights, capacity, n_pop, seed)."""
+        self._items = []
+        arr = (qieo_problem * len(problems))()
+        self.shapes = []
+        for k, (v, w, cap, n_pop, seed) in enumerate(problems):
+            it = items_array(v, w)
+            self._items.append(it)
+            arr[k] = qieo_problem(it.ctypes.data, it.shape[0], int(cap), int(n_pop),
+                                  int(seed) & (2**64 - 1))
+            self.shapes.append((int(n_pop), int(it.shape[0]), int(cap)))
+        h = ctypes.c_void_p()
+        ctx = None
+        if stream is not None:
+            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
+                                            ctypes.c_void_p(stream)))
+        _check(lib.qieo_batch_create(arr, len(problems), ctx, ctypes.byref(h)),
+               "qieo_batch_create")
+        self._h = h
+        self.n = len(problems)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and lib is not None:
+            try:
+                lib.qieo_batch_destroy(h)
+            except Exception:
+                pass
+
+    def __del__(self):
+        self.close()
+
+    def _counts(self, gens):
+        g = np.ascontiguousarray(np.broadcast_to(np.asarray(gens, dtype=np.int32), (self.n,)))
+        return g
+
+    def step(self, gens):
+        g = self._counts(gens)
+        _check(lib.qieo_batch_step(self._h, _ptr(g)), "qieo_batch_step")
+
+    def step_async(self, gens):
+        g = self._counts(gens)
+        _check(lib.qieo_batch_step_async(self._h, _ptr(g)), "qieo_batch_step_async")
+
+    def sync(self):
+        _check(lib.qieo_batch_sync(self._h), "qieo_batch_sync")
+
+    def generations(self, i: int) -> int:
+        t = ctypes.c_int64()
+        _check(lib.qieo_batch_generations(self._h, i, ctypes.byref(t)), "qieo_batch_generations")
+        return int(t.value)
+
+    def best(self, i: int) -> Result:
+        r = qieo_result()
+        ng = self.shapes[i][1]
+        bits = np.zeros((ng + 31) // 32, dtype=np.uint32)
+        _check(lib.qieo_batch_best(self._h, i, ctypes.byref(r), _ptr(bits), bits.size),
+               "qieo_batch_best")
+        return Result(r.fitness, r.profit, r.weight, bool(r.feasible), r.generation,
+                      r.chromosome, bits)
+
+    def export_rows(self, i: int, row0: int = 0, n_rows: int | None = None,
+                    amplitudes: bool = True, alleles: bool = True):
+        n_pop, ng, _ = self.shapes[i]
+        fn = lambda *a: lib.qieo_batch_export_rows(self._h, i, *a)
+        return _export(fn, ng, n_pop, row0, n_rows, amplitudes, alleles, "qieo_batch_export_rows")
+
+    def set_tile(self, rows_per_block: int = 0, waves_per_block: int = 0, flags: int = 0):
+        _check(lib.qieo_batch_set_tile(self._h, rows_per_block, waves_per_block, flags),
+               "qieo_batch_set_tile")
+
+    def set_graph(self, enabled: bool):
+        _check(lib.qieo_batch_set_graph(self._h, int(bool(enabled))), "qieo_batch_set_graph")
+
+
+class Server:
+    """Continuous-batching request server (qieo_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_resident: int = 0, gens_per_iter: int = 0,
+                 stream: int | None = None):
+        cfg = qieo_server_cfg(int(hbm_budget_bytes), int(max_resident), int(gens_per_iter))
+        h = ctypes.c_void_p()
+        ctx = None
+        if stream is not None:
+            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
+                                            ctypes.c_void_p(stream)))
+        _check(lib.qieo_server_create(ctypes.byref(cfg), ctx, ctypes.byref(h)),
+               "qieo_server_create")
+        self._h = h
+        self._n_items = {}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and lib is not None:
+            try:
+                lib.qieo_server_destroy(h)
+            except Exception:
+                pass
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, values, weights, capacity: int, n_pop: int, seed: int, n_gen: int) -> int:
+        it = items_array(values, weights)
+        prob = qieo_problem(it.ctypes.data, it.shape[0], int(capacity), int(n_pop),
+                            int(seed) & (2**64 - 1))
+        t = ctypes.c_uint64()
+        _check(lib.qieo_server_submit(self._h, ctypes.byref(prob), int(n_gen), ctypes.byref(t)),
+               "qieo_server_submit")
+        self._n_items[int(t.value)] = it.shape[0]
+        return int(t.value)
+
+    def _result(self, fn, ticket):
+        ng = self._n_items[ticket]
+        r = qieo_result()
+        bits = np.zeros((ng + 31) // 32, dtype=np.uint32)
+        lat = ctypes.c_int64()
+        rc = fn(self._h, ticket, ctypes.byref(r), _ptr(bits), bits.size, ctypes.byref(lat))
+        if rc == QIEO_EAGAIN:
+            return None
+        _check(rc, "qieo_server_result")
+        return Result(r.fitness, r.profit, r.weight, bool(r.feasible), r.generation,
+                      r.chromosome, bits), int(lat.value)
+
+    def poll(self, ticket: int):
+        """(Result, latency_ns) when finished, None while pending."""
+        return self._result(lib.qieo_server_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._result(lib.qieo_server_wait, ticket)
+
+    def release(self, ticket: int):
+        _check(lib.qieo_server_release(self._h, ticket), "qieo_server_release")
+        self._n_items.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = qieo_server_stats()
+        _check(lib.qieo_server_get_stats(self._h, ctypes.byref(st)), "qieo_server_get_stats")
+        return {name: getattr(st, name) for name, _ in qieo_server_stats._fields_}

@@ -1,0 +1,128 @@
+"""Batched execution: every instance of a batch follows, bit for bit, the
+trajectory the oracle computes for it alone, whatever the other instances,
+the per-instance generation counts, the work shapes or graph replay."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import assert_state_equal, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qieo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2609_30862_amd import qieo as q
+    return q
+
+
+class View:
+    """Instance-like view of member i of a batch (for assert_state_equal)."""
+
+    def __init__(self, b, i):
+        self.b, self.i = b, i
+        self.n_pop, self.n_items, _ = b.shapes[i]
+
+    def export_rows(self, row0=0, n_rows=None, amplitudes=True, alleles=True):
+        return self.b.export_rows(self.i, row0, n_rows, amplitudes, alleles)
+
+    def best(self):
+        return self.b.best(self.i)
+
+
+RAGGED = [(1, 1), (50, 32), (63, 3), (64, 7), (100, 16), (255, 2), (256, 33), (300, 5),
+          (700, 64), (1024, 9), (2100, 4), (5000, 17), (20000, 3), (130, 128)]
+
+
+def _ragged_instances():
+    return [workloads.random_instance(ng, n_pop, seed=1000 + k, wmax=10 + k)
+            for k, (ng, n_pop) in enumerate(RAGGED)]
+
+
+def _problems(insts):
+    return [(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
+
+
+def test_batch_matches_oracle_with_uneven_generation_counts(qieo, oracle_mod):
+    insts = _ragged_instances()
+    b = qieo.Batch(_problems(insts))
+    orcs = [oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
+    n = len(insts)
+    for call, gens in enumerate([[1] * n, [k % 4 for k in range(n)], [(3 * k) % 7 for k in range(n)],
+                                 [0] * n, [5] * n]):
+        say("batch call %d gens %s" % (call, gens))
+        b.step(gens)
+        for k, o in enumerate(orcs):
+            o.run(gens[k])
+            assert b.generations(k) == o.t
+            if o.t > 0:
+                assert_state_equal(View(b, k), o, label="batch call %d inst %d" % (call, k))
+
+
+@pytest.mark.parametrize("mode", ["no-graph", "R1S1", "R2S4f3", "R4S16f1"])
+def test_batch_modes_are_identical(qieo, mode):
+    insts = _ragged_instances()
+    ref = qieo.Batch(_problems(insts))
+    alt = qieo.Batch(_problems(insts))
+    if mode == "no-graph":
+        alt.set_graph(False)
+    else:
+        R, S = int(mode[1]), int(mode[3:].split("f")[0])
+        f = int(mode.split("f")[1]) if "f" in mode else 0
+        alt.set_tile(R, S, f)
+    say("batch mode %s" % mode)
+    for gens in ([3] * len(insts), [k % 3 for k in range(len(insts))]):
+        ref.step(gens)
+        alt.step(gens)
+    for k in range(len(insts)):
+        a, c = ref.export_rows(k), alt.export_rows(k)
+        for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+            assert np.array_equal(a[key], c[key]), (mode, k, key)
+        assert a["elite"] == c["elite"]
+        ra, rc = ref.best(k), alt.best(k)
+        assert (ra.fitness, ra.generation, ra.chromosome) == (rc.fitness, rc.generation,
+                                                               rc.chromosome)
+
+
+def test_batch_instance_equals_instance_alone(qieo):
+    insts = _ragged_instances()[5:10]
+    b = qieo.Batch(_problems(insts))
+    b.step(17)
+    for k, inst in enumerate(insts):
+        g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+        g.step(17)
+        a, c = g.export_rows(), b.export_rows(k)
+        for key in ("alpha", "beta", "alleles", "fitness"):
+            assert np.array_equal(a[key], c[key]), (k, key)
+        assert g.best().fitness == b.best(k).fitness
+
+
+def test_ragged_batch_of_512_full_size(qieo, oracle_mod):
+    """512 instances (Ng log-uniform in [50, 20000], Np in {32..256}, seeds
+    1000..1511), 500 generations in one call; sampled instances against the
+    oracle bit for bit, every instance's best against its LP bound."""
+    insts = workloads.batch_instances()
+    say("batch of %d instances, %.3g genes per generation"
+        % (len(insts), sum(i.genes for i in insts)))
+    b = qieo.Batch(_problems(insts))
+    b.step(500)
+    order = sorted(range(len(insts)), key=lambda k: insts[k].genes)
+    sample = order[:3] + order[250:252] + order[-2:]
+    threads = min(16, os.cpu_count() or 1)
+    for k in sample:
+        i = insts[k]
+        say("  oracle for instance %d (Np=%d Ng=%d)" % (k, i.n_pop, i.n_items))
+        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed, threads=threads)
+        o.run(500)
+        assert_state_equal(View(b, k), o, label="batch512 inst %d" % k)
+    for k, i in enumerate(insts):
+        r = b.best(k)
+        assert r.generation >= 0 and r.feasible
+        assert r.fitness <= oracle_mod.knap_lp_bound(i.values, i.weights, i.capacity)
+        bits = r.alleles(i.n_items).astype(np.int64)
+        assert int(bits @ i.values.astype(np.int64)) == r.profit

@@ -121,8 +121,18 @@ int qieo_sync(qieo_inst *h);
 int qieo_best(qieo_inst *h, qieo_result *out, uint32_t *bits_or_null,
               size_t n_words);
 
-/* Number of generations run so far. */
+/* Number of generations run so far (waits for queued work). */
 int qieo_generations(qieo_inst *h, int64_t *out);
+
+/* Termination by convergence (Sec. IV-A: the elite fitness is stable for a
+ * window of generations).  With window w in [1, 32], the run stops after the
+ * first generation t whose elite fitness equals that of generations
+ * t-w+1 .. t-1; later qieo_step calls run nothing.  0 (default) keeps fixed
+ * budgets.  Must be set before the first generation (QIEO_ESTATE). */
+int qieo_set_convergence(qieo_inst *h, int32_t window);
+/* converged = 1 once the window test has fired; generation = the generation
+ * after which it stopped (-1 if not converged). */
+int qieo_converged(qieo_inst *h, int32_t *converged, int64_t *generation);
 
 /* Copies rows [row0, row0 + n_rows) of the population state after the last
  * completed generation t-1, with that generation's CIP applied, to host
@@ -191,6 +201,9 @@ int qieo_batch_best(qieo_batch *b, int32_t i, qieo_result *out, uint32_t *bits,
 int qieo_batch_export_rows(qieo_batch *b, int32_t i, int32_t row0, int32_t n_rows,
                            float *alpha, float *beta, uint8_t *alleles, int32_t *fitness,
                            int32_t *profit, int32_t *weight, int32_t *elite);
+/* Convergence window for every instance of the batch (see qieo_set_convergence). */
+int qieo_batch_set_convergence(qieo_batch *b, int32_t window);
+int qieo_batch_converged(qieo_batch *b, int32_t i, int32_t *converged, int64_t *generation);
 /* Work shape for every launch of the batch (rows_per_block = 0 restores the
  * library's per-class choice); see qieo_set_tile and qieo_set_kernel_flags. */
 int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per_block,
@@ -211,6 +224,7 @@ typedef struct qieo_server_cfg {
     size_t hbm_budget_bytes;
     int32_t max_resident;
     int32_t gens_per_iter;
+    int32_t convergence_window;   /* as qieo_set_convergence, for every request (0 = off) */
 } qieo_server_cfg;
 
 typedef struct qieo_server_stats {

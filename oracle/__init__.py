@@ -58,6 +58,10 @@ def lib():
         for name in ("oracle_qip", "oracle_fe", "oracle_de", "oracle_cip", "oracle_generation"):
             getattr(L, name).argtypes = [P]
         L.oracle_run.argtypes = [P, i64]
+        L.oracle_converged.restype = ctypes.c_int
+        L.oracle_converged.argtypes = [P, ctypes.c_int]
+        L.oracle_run_until_converged.restype = i64
+        L.oracle_run_until_converged.argtypes = [P, i64, ctypes.c_int]
         L.oracle_philox4x32_10.argtypes = [P, P, P]
         L.oracle_uniform.restype = ctypes.c_float
         L.oracle_uniform.argtypes = [u64, i64, i64, i64]
@@ -165,6 +169,13 @@ class Oracle:
 
     def run(self, n: int):
         lib().oracle_run(self._h, int(n))
+
+    def converged(self, window: int) -> bool:
+        return bool(lib().oracle_converged(self._h, int(window)))
+
+    def run_until_converged(self, n: int, window: int) -> int:
+        """At most n generations, stopping once converged; returns how many ran."""
+        return int(lib().oracle_run_until_converged(self._h, int(n), int(window)))
 
     # state
     @property

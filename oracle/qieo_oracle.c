@@ -146,13 +146,15 @@ typedef struct oracle {
     int64_t best_f, best_P, best_W, best_gen, best_chrom;
     uint8_t *best_x;
     int threads;
+    int64_t *elite_f;   /* elite fitness of every completed generation */
+    int64_t elite_cap;
 } oracle;
 
 void oracle_free(oracle *s)
 {
     if (!s) return;
     free(s->v); free(s->w); free(s->alpha); free(s->beta); free(s->x);
-    free(s->P); free(s->W); free(s->fit); free(s->best_x);
+    free(s->P); free(s->W); free(s->fit); free(s->best_x); free(s->elite_f);
     free(s);
 }
 
@@ -240,6 +242,13 @@ void oracle_de(oracle *s)
     for (int64_t c = 1; c < s->np; ++c)
         if (s->fit[c] > s->fit[e]) e = c;
     s->elite = e;
+    if (s->t >= s->elite_cap) {
+        int64_t cap = s->elite_cap ? 2 * s->elite_cap : 1024;
+        while (cap <= s->t) cap *= 2;
+        int64_t *p = (int64_t *)realloc(s->elite_f, sizeof(int64_t) * (size_t)cap);
+        if (p) { s->elite_f = p; s->elite_cap = cap; }
+    }
+    if (s->t < s->elite_cap) s->elite_f[s->t] = s->fit[e];
     if (!s->has_best || s->fit[e] > s->best_f) {
         s->has_best = 1;
         s->best_f = s->fit[e];
@@ -282,6 +291,34 @@ void oracle_generation(oracle *s)
 void oracle_run(oracle *s, int64_t n)
 {
     for (int64_t g = 0; g < n; ++g) oracle_generation(s);
+}
+
+/* Termination test of Sec. IV-A, read for integer fitness: the run has
+ * converged after generation t when the elite fitness of the last `window`
+ * generations (t-window+1 .. t) is one value (a spread within 1e-6 of the
+ * mean means equality for integers). */
+int oracle_converged(const oracle *s, int window)
+{
+    if (window < 1 || s->t < window || s->t > s->elite_cap) return 0;
+    const int64_t last = s->elite_f[s->t - 1];
+    for (int64_t k = s->t - window; k < s->t - 1; ++k)
+        if (s->elite_f[k] != last) return 0;
+    return 1;
+}
+
+/* Runs at most n more generations, stopping after the first generation at
+ * which the run has converged (Fig. 1: terminate or next generation).
+ * Returns the number of generations run by this call. */
+int64_t oracle_run_until_converged(oracle *s, int64_t n, int window)
+{
+    int64_t g = 0;
+    if (oracle_converged(s, window)) return 0;
+    while (g < n) {
+        oracle_generation(s);
+        ++g;
+        if (oracle_converged(s, window)) break;
+    }
+    return g;
 }
 
 /* ------------------------------------------------------------------------ */

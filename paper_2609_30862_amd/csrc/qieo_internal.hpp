@@ -15,7 +15,7 @@ namespace qieo {
 // Byte offsets of every plane inside one instance's device arena.
 struct ArenaLayout {
     int32_t pitch, nchunk;
-    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase;
+    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv;
     size_t zero_from;
     size_t total;
 };
@@ -34,8 +34,11 @@ int check_device();
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
               uint32_t* bits, size_t n_words);
-int export_rows(const InstDev& d, const InstDev* d_desc, int64_t t, hipStream_t s,
+int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
                 int32_t row0, int32_t n_rows, float* alpha, float* beta, uint8_t* alleles,
                 int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite);
+int read_generations(const InstDev& d, hipStream_t s, int64_t* t);
+int read_convergence(const InstDev& d, hipStream_t s, int32_t* converged, int64_t* generation);
+int write_window(const InstDev& d, hipStream_t s, int32_t window);
 
 }  // namespace qieo

@@ -141,10 +141,35 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         fe_prev = key_fitness(key);
     }
 
-    if (row0 == 0 && wave == 0) {
-        if (lane == 0) I.ekey[(t + 1) % 3] = 0ull;
-        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+    // Termination test (convergence window): decided by every workgroup from
+    // values earlier launches wrote, so all of them agree.  Generation t-1
+    // completes convergence when its elite fitness equals that of the
+    // window-1 generations before it; then generation t is not run.
+    const int window = sload(I.conv + 3);
+    bool stop = false;
+    if (window > 0) {
+        if (sload(I.conv) != 0) return;            // converged in an earlier launch
+        if (pending && t >= window) {
+            stop = true;
+            for (int j = 1; j < window; ++j)
+                stop = stop && sload(I.conv + 8 + (int)((t - 1 - j) & (kConvRing - 1))) == fe_prev;
+        }
     }
+
+    if (row0 == 0 && wave == 0) {
+        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+        if (lane == 0) {
+            if (window > 0 && pending) I.conv[8 + (int)((t - 1) & (kConvRing - 1))] = fe_prev;
+            if (stop) {
+                I.conv[1] = (int32_t)(uint32_t)(uint64_t)(t - 1);
+                I.conv[2] = (int32_t)(uint32_t)((uint64_t)(t - 1) >> 32);
+                I.conv[0] = 1;
+            } else {
+                I.ekey[(t + 1) % 3] = 0ull;
+            }
+        }
+    }
+    if (stop) return;
 
     const int nrows = min(R, np - (int)row0);
     bool rot[R];
@@ -281,18 +306,45 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // advance of the generation counter.  One workgroup (one wave) per instance.
 // ---------------------------------------------------------------------------
 __global__ void finish_kernel(const InstDev* __restrict__ insts,
-                              const int32_t* __restrict__ gens_arr, int gens_all)
+                              const int32_t* __restrict__ gens_arr, int gens_all,
+                              int64_t* __restrict__ status)
 {
     const InstDev I = insts[blockIdx.x];
     const int gens = gens_arr ? gens_arr[blockIdx.x] : gens_all;
-    if (gens <= 0) return;
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x < 64) {
-        const int64_t tl = *I.tbase + gens - 1;
-        const unsigned long long key = I.ekey[tl % 3];
-        const uint32_t* xg = I.xbits + (size_t)(tl & 1) * I.np * I.nchunk * kWordsPerChunk;
-        best_update(I, tl, key_row(key), key_fitness(key), xg, lane);
-        if (lane == 0) *I.tbase = tl + 1;
+    if (threadIdx.x >= 64) return;
+    int64_t done = *I.tbase;
+    const int window = I.conv[3];
+    int converged = window > 0 ? I.conv[0] : 0;
+    if (gens > 0) {
+        if (converged) {
+            // a launch of this call (or of an earlier one) found convergence
+            done = (int64_t)(((uint64_t)(uint32_t)I.conv[2] << 32) | (uint32_t)I.conv[1]) + 1;
+        } else {
+            const int64_t tl = done + gens - 1;
+            const unsigned long long key = I.ekey[tl % 3];
+            const int32_t fe = key_fitness(key);
+            const uint32_t* xg = I.xbits + (size_t)(tl & 1) * I.np * I.nchunk * kWordsPerChunk;
+            best_update(I, tl, key_row(key), fe, xg, lane);
+            if (window > 0 && lane == 0) {
+                I.conv[8 + (int)(tl & (kConvRing - 1))] = fe;
+                bool stop = tl + 1 >= window;
+                for (int j = 1; j < window && stop; ++j)
+                    stop = I.conv[8 + (int)((tl - j) & (kConvRing - 1))] == fe;
+                if (stop) {
+                    I.conv[1] = (int32_t)(uint32_t)(uint64_t)tl;
+                    I.conv[2] = (int32_t)(uint32_t)((uint64_t)tl >> 32);
+                    I.conv[0] = 1;
+                    converged = 1;
+                }
+            }
+            done = tl + 1;
+        }
+        if (lane == 0) *I.tbase = done;
+    }
+    if (status && lane == 0) {
+        status[2 * blockIdx.x] = done;
+        status[2 * blockIdx.x + 1] = converged;
     }
 }
 
@@ -409,11 +461,11 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
 }
 
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
-                         hipStream_t s)
+                         int64_t* status, hipStream_t s)
 {
     if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(finish_kernel, dim3((unsigned)n_inst), dim3(64), 0, s, dI, gens_arr,
-                       gens_all);
+                       gens_all, status);
     return hipGetLastError();
 }
 

@@ -29,6 +29,9 @@ constexpr int kWordsPerChunk = 8;
 //                                          row, 0}
 //   best_bits   : uint32[nchunk*8]        alleles of the best, in xbits layout
 //   tbase       : int64[1]                number of generations completed
+//   conv        : int32[64]               convergence test: [0] converged flag,
+//                 [1..2] generation it converged at (lo, hi), [3] window
+//                 (0 = off), [8..40) elite fitness of generation g in slot g%32
 // Padding genes (ng <= i < pitch) hold alpha = 1, beta = 0, v = w = 0: they
 // are never observed as 1 and never rotate.  Each amplitude plane is followed
 // by kChunk floats of zeroed slack and v, w hold nchunk*kChunk entries, so a
@@ -46,6 +49,7 @@ struct InstDev {
     int32_t* best;
     uint32_t* best_bits;
     int64_t* tbase;
+    int32_t* conv;
     int32_t np, ng, pitch, nchunk;
     int32_t capacity;
     uint32_t seed_lo, seed_hi;
@@ -69,8 +73,10 @@ constexpr int kFlagNontemporal = 2;
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
+// status (may be NULL): per instance {generations completed, converged flag}.
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
-                         hipStream_t s);
+                         int64_t* status, hipStream_t s);
+constexpr int kConvRing = 32;      // longest convergence window
 hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng,
                          float* alpha, float* beta, uint8_t* alleles,
                          int32_t* fit, int32_t* prof, int32_t* wt, hipStream_t s);

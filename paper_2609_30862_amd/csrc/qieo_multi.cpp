@@ -110,6 +110,7 @@ Engine::~Engine()
         if (c.d_tiles) (void)hipFree(c.d_tiles);
     if (d_desc_) (void)hipFree(d_desc_);
     if (d_gens_) (void)hipFree(d_gens_);
+    if (d_status_) (void)hipFree(d_status_);
     if (h_gens_) (void)hipHostFree(h_gens_);
 }
 
@@ -121,7 +122,7 @@ void Engine::invalidate_graph()
 }
 
 int Engine::add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32_t capacity,
-                int32_t n_pop, uint64_t seed, uint64_t id)
+                int32_t n_pop, uint64_t seed, uint64_t id, int32_t window)
 {
     int rc = validate_problem(items, n_items, capacity, n_pop);
     if (rc) return rc;
@@ -147,6 +148,11 @@ int Engine::add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32
         pool.release(m.arena);
         return hip_fail(e, "hipStreamSynchronize");
     }
+    if (window > 0 && (rc = write_window(m.d, stream_, window))) {
+        pool.release(m.arena);
+        return rc;
+    }
+    m.window = window;
     members_.push_back(m);
     dirty_ = true;
     return QIEO_OK;
@@ -189,15 +195,19 @@ int Engine::rebuild()
     if (n > desc_cap_) {
         if (d_desc_) (void)hipFree(d_desc_);
         if (d_gens_) (void)hipFree(d_gens_);
+        if (d_status_) (void)hipFree(d_status_);
         if (h_gens_) (void)hipHostFree(h_gens_);
         d_desc_ = nullptr;
         d_gens_ = nullptr;
+        d_status_ = nullptr;
         h_gens_ = nullptr;
         const size_t cap = std::max<size_t>(n, 2 * desc_cap_);
         if ((e = hipMalloc(&d_desc_, cap * sizeof(InstDev))) != hipSuccess)
             return hip_fail(e, "hipMalloc(descriptors)");
         if ((e = hipMalloc(&d_gens_, cap * sizeof(int32_t))) != hipSuccess)
             return hip_fail(e, "hipMalloc(generation counts)");
+        if ((e = hipMalloc(&d_status_, 2 * cap * sizeof(int64_t))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(status)");
         if ((e = hipHostMalloc((void**)&h_gens_, cap * sizeof(int32_t), hipHostMallocDefault)) !=
             hipSuccess)
             return hip_fail(e, "hipHostMalloc");
@@ -273,7 +283,8 @@ int Engine::enqueue(int nmax)
                 return hip_fail(e, "generation kernel");
         }
     }
-    if ((e = launch_finish(d_desc_, (int)members_.size(), d_gens_, 0, stream_)) != hipSuccess)
+    if ((e = launch_finish(d_desc_, (int)members_.size(), d_gens_, 0, d_status_, stream_)) !=
+        hipSuccess)
         return hip_fail(e, "finish kernel");
     return QIEO_OK;
 }
@@ -336,6 +347,36 @@ int Engine::sync()
 {
     hipError_t e = hipStreamSynchronize(stream_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return QIEO_OK;
+}
+
+int Engine::refresh_status()
+{
+    const size_t n = members_.size();
+    if (n == 0 || !d_status_) return QIEO_OK;
+    std::vector<int64_t> st(2 * n);
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(st.data(), d_status_, st.size() * sizeof(int64_t), hipMemcpyDeviceToHost)) !=
+        hipSuccess)
+        return hip_fail(e, "hipMemcpy(status)");
+    for (size_t i = 0; i < n; ++i) {
+        members_[i].t = st[2 * i];
+        members_[i].converged = st[2 * i + 1] != 0;
+    }
+    return QIEO_OK;
+}
+
+int Engine::set_window_all(int32_t window)
+{
+    for (auto& m : members_) {
+        if (m.t != 0) return set_error(QIEO_ESTATE, "the convergence window is set before the first generation");
+    }
+    for (auto& m : members_) {
+        int rc = write_window(m.d, stream_, window);
+        if (rc) return rc;
+        m.window = window;
+    }
     return QIEO_OK;
 }
 
@@ -405,7 +446,7 @@ extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qie
     }
     for (int32_t i = 0; i < n; ++i) {
         if ((rc = b->eng->add(b->pool, probs[i].items, probs[i].n_items, probs[i].capacity,
-                              probs[i].n_pop, probs[i].seed, (uint64_t)i))) {
+                              probs[i].n_pop, probs[i].seed, (uint64_t)i, 0))) {
             batch_release(b);
             return rc;
         }
@@ -470,8 +511,26 @@ extern "C" int qieo_batch_generations(qieo_batch* b, int32_t i, int64_t* out)
     int rc = batch_member(b, i, &m);
     if (rc) return rc;
     if (!out) return set_error(QIEO_EINVAL, "out is NULL");
-    *out = m->t;
-    return QIEO_OK;
+    return read_generations(m->d, b->stream, out);
+}
+
+extern "C" int qieo_batch_set_convergence(qieo_batch* b, int32_t window)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    if (window < 0 || window > kConvRing)
+        return set_error(QIEO_EINVAL, "window must be in [0, %d] (got %d)", kConvRing, window);
+    return b->eng->set_window_all(window);
+}
+
+extern "C" int qieo_batch_converged(qieo_batch* b, int32_t i, int32_t* converged,
+                                    int64_t* generation)
+{
+    clear_error();
+    Member* m;
+    int rc = batch_member(b, i, &m);
+    if (rc) return rc;
+    return read_convergence(m->d, b->stream, converged, generation);
 }
 
 extern "C" int qieo_batch_export_rows(qieo_batch* b, int32_t i, int32_t row0, int32_t n_rows,
@@ -487,7 +546,7 @@ extern "C" int qieo_batch_export_rows(qieo_batch* b, int32_t i, int32_t row0, in
     if (e) return e;
     // the descriptor array is rebuilt lazily; make sure it describes member i
     if ((e = b->eng->ensure_built())) return e;
-    return export_rows(m->d, b->eng->device_desc((size_t)i), m->t, b->stream, row0, n_rows,
+    return export_rows(m->d, b->eng->device_desc((size_t)i), b->stream, row0, n_rows,
                        alpha, beta, alleles, fitness, profit, weight, elite);
 }
 

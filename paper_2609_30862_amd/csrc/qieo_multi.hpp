@@ -43,8 +43,10 @@ struct Member {
     char* arena = nullptr;
     int32_t ng = 0, np = 0, capacity = 0;
     uint64_t seed = 0;
-    int64_t t = 0;        // generations completed (host mirror)
+    int64_t t = 0;        // generations completed (host mirror; exact after refresh_status)
     uint64_t id = 0;      // caller's identifier
+    int32_t window = 0;   // convergence window (0 = fixed budget)
+    bool converged = false;
 };
 
 // Work shape of one launch class.
@@ -62,7 +64,7 @@ public:
     // Membership.  add() uploads items and initialises the state on the
     // engine's stream; the arena comes from `pool`.
     int add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32_t capacity,
-            int32_t n_pop, uint64_t seed, uint64_t id);
+            int32_t n_pop, uint64_t seed, uint64_t id, int32_t window);
     void remove_at(size_t idx, DevicePool& pool);
     size_t size() const { return members_.size(); }
     Member& member(size_t i) { return members_[i]; }
@@ -72,6 +74,10 @@ public:
     // and the finishing step; enqueued on the stream, not waited for.
     int run(const int32_t* gens);
     int sync();
+    // Reads every member's generation counter and converged flag as left by
+    // the last finished call (waits for the stream).
+    int refresh_status();
+    int set_window_all(int32_t window);
 
     // Shape-class override for experiments and tuning: every class uses
     // (R, S, flags) when R > 0.
@@ -93,6 +99,7 @@ private:
     InstDev* d_desc_ = nullptr;
     size_t desc_cap_ = 0;
     int32_t* d_gens_ = nullptr;
+    int64_t* d_status_ = nullptr;  // per member {generations completed, converged}
     int32_t* h_gens_ = nullptr;    // pinned
     size_t gens_cap_ = 0;
     std::vector<ShapeClass> classes_;

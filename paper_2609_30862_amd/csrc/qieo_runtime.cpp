@@ -75,6 +75,7 @@ size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L)
     L->best = take(8 * sizeof(int32_t));
     L->best_bits = take(wpr * sizeof(uint32_t));
     L->tbase = take(sizeof(int64_t));
+    L->conv = take(64 * sizeof(int32_t));
     L->total = off;
     // everything except the amplitude planes themselves is zero-initialised
     L->zero_from = 0;
@@ -97,6 +98,7 @@ InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int
     d.best = reinterpret_cast<int32_t*>(base + L.best);
     d.best_bits = reinterpret_cast<uint32_t*>(base + L.best_bits);
     d.tbase = reinterpret_cast<int64_t*>(base + L.tbase);
+    d.conv = reinterpret_cast<int32_t*>(base + L.conv);
     d.np = np;
     d.ng = ng;
     d.pitch = L.pitch;
@@ -373,7 +375,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
             return hip_fail(e, "generation kernel");
         if (h->timing) (void)hipEventRecord(b, h->stream);
     }
-    if ((e = launch_finish(h->d_desc, 1, nullptr, n, h->stream)) != hipSuccess)
+    if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
         return hip_fail(e, "finish kernel");
     h->t += n;
     return QIEO_OK;
@@ -400,8 +402,25 @@ extern "C" int qieo_generations(qieo_inst* h, int64_t* out)
 {
     clear_error();
     if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
-    *out = h->t;
-    return QIEO_OK;
+    return read_generations(h->d, h->stream, out);
+}
+
+extern "C" int qieo_set_convergence(qieo_inst* h, int32_t window)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (window < 0 || window > kConvRing)
+        return set_error(QIEO_EINVAL, "window must be in [0, %d] (got %d)", kConvRing, window);
+    if (h->t != 0)
+        return set_error(QIEO_ESTATE, "the convergence window is set before the first generation");
+    return write_window(h->d, h->stream, window);
+}
+
+extern "C" int qieo_converged(qieo_inst* h, int32_t* converged, int64_t* generation)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    return read_convergence(h->d, h->stream, converged, generation);
 }
 
 namespace qieo {
@@ -456,14 +475,48 @@ int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* ou
     return QIEO_OK;
 }
 
-int export_rows(const InstDev& d, const InstDev* d_desc, int64_t t, hipStream_t s,
+int read_generations(const InstDev& d, hipStream_t s, int64_t* t)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(t, d.tbase, sizeof(int64_t), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(generation counter)");
+    return QIEO_OK;
+}
+
+int read_convergence(const InstDev& d, hipStream_t s, int32_t* converged, int64_t* generation)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int32_t c[4];
+    if ((e = hipMemcpy(c, d.conv, sizeof c, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(convergence)");
+    if (converged) *converged = c[3] > 0 ? c[0] : 0;
+    if (generation)
+        *generation = (c[3] > 0 && c[0]) ? (int64_t)(((uint64_t)(uint32_t)c[2] << 32) | (uint32_t)c[1])
+                                        : -1;
+    return QIEO_OK;
+}
+
+int write_window(const InstDev& d, hipStream_t s, int32_t window)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(d.conv + 3, &window, sizeof window, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(window)");
+    return QIEO_OK;
+}
+
+int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
                 int32_t row0, int32_t n_rows, float* alpha, float* beta, uint8_t* alleles,
                 int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite)
 {
     if (row0 < 0 || n_rows < 0 || (int64_t)row0 + n_rows > d.np)
         return set_error(QIEO_EINVAL, "rows [%d, %d) outside [0, %d)", row0, row0 + n_rows, d.np);
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int64_t t = 0;
+    int rc0 = read_generations(d, s, &t);
+    if (rc0) return rc0;
+    hipError_t e;
     if (elite) {
         if (t == 0) {
             *elite = -1;
@@ -538,7 +591,7 @@ extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, floa
 {
     clear_error();
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
-    return export_rows(h->d, h->d_desc, h->t, h->stream, row0, n_rows, alpha, beta, alleles,
+    return export_rows(h->d, h->d_desc, h->stream, row0, n_rows, alpha, beta, alleles,
                        fitness, profit, weight, elite);
 }
 

@@ -106,7 +106,7 @@ static void server_loop(qieo_server* s)
                 continue;
             }
             int rc = s->eng->add(s->pool, r->items.data(), (int32_t)r->items.size(), r->capacity,
-                                 r->n_pop, r->seed, r->ticket);
+                                 r->n_pop, r->seed, r->ticket, s->cfg.convergence_window);
             if (rc == QIEO_ENOMEM) {
                 blocked = true;        // head of line waits for memory to free up
                 back.push_back(r);
@@ -158,6 +158,7 @@ static void server_loop(qieo_server* s)
         }
         int rc = s->eng->run(gens.data());
         if (rc == QIEO_OK) rc = s->eng->sync();
+        if (rc == QIEO_OK && s->cfg.convergence_window > 0) rc = s->eng->refresh_status();
         if (rc != QIEO_OK) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->worker_error = rc;
@@ -175,7 +176,8 @@ static void server_loop(qieo_server* s)
         std::vector<size_t> done;
         for (size_t i = 0; i < s->resident.size(); ++i) {
             s->resident[i]->remaining -= gens[i];
-            if (s->resident[i]->remaining == 0) done.push_back(i);
+            const bool conv = s->cfg.convergence_window > 0 && s->eng->member(i).converged;
+            if (s->resident[i]->remaining == 0 || conv) done.push_back(i);
         }
         for (size_t k = done.size(); k-- > 0;) {
             const size_t i = done[k];
@@ -226,6 +228,8 @@ extern "C" int qieo_server_create(const qieo_server_cfg* cfg, const qieo_dev_ctx
         return set_error(QIEO_EINVAL, "hbm_budget_bytes too small (%zu)", cfg->hbm_budget_bytes);
     if (cfg->max_resident < 0 || cfg->gens_per_iter < 0)
         return set_error(QIEO_EINVAL, "max_resident and gens_per_iter must be >= 0");
+    if (cfg->convergence_window < 0 || cfg->convergence_window > kConvRing)
+        return set_error(QIEO_EINVAL, "convergence_window must be in [0, %d]", kConvRing);
     if (ctx && ((ctx->alloc == nullptr) != (ctx->free == nullptr)))
         return set_error(QIEO_EINVAL, "ctx->alloc and ctx->free must be both set or both NULL");
     int rc = check_device();

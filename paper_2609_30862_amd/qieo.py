@@ -49,7 +49,7 @@ class qieo_problem(ctypes.Structure):
 
 class qieo_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_resident", ctypes.c_int32),
-                ("gens_per_iter", ctypes.c_int32)]
+                ("gens_per_iter", ctypes.c_int32), ("convergence_window", ctypes.c_int32)]
 
 
 class qieo_server_stats(ctypes.Structure):
@@ -91,6 +91,14 @@ def _load():
     L.qieo_best.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
     L.qieo_generations.restype = ctypes.c_int
     L.qieo_generations.argtypes = [H, ctypes.POINTER(i64)]
+    L.qieo_set_convergence.restype = ctypes.c_int
+    L.qieo_set_convergence.argtypes = [H, i32]
+    L.qieo_converged.restype = ctypes.c_int
+    L.qieo_converged.argtypes = [H, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.qieo_batch_set_convergence.restype = ctypes.c_int
+    L.qieo_batch_set_convergence.argtypes = [H, i32]
+    L.qieo_batch_converged.restype = ctypes.c_int
+    L.qieo_batch_converged.argtypes = [H, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.qieo_export_rows.restype = ctypes.c_int
     L.qieo_export_rows.argtypes = [H, i32, i32, P, P, P, P, P, P, ctypes.POINTER(i32)]
     L.qieo_destroy.restype = None
@@ -333,6 +341,15 @@ class Instance:
     def set_tile(self, rows_per_block: int = 0, waves_per_block: int = 0):
         _check(lib.qieo_set_tile(self._h, rows_per_block, waves_per_block), "qieo_set_tile")
 
+    def set_convergence(self, window: int):
+        _check(lib.qieo_set_convergence(self._h, int(window)), "qieo_set_convergence")
+
+    def converged(self):
+        """(converged, generation after which the run stopped or -1)."""
+        c, g = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.qieo_converged(self._h, ctypes.byref(c), ctypes.byref(g)), "qieo_converged")
+        return bool(c.value), int(g.value)
+
     def set_kernel_flags(self, flags: int):
         _check(lib.qieo_set_kernel_flags(self._h, int(flags)), "qieo_set_kernel_flags")
 
@@ -445,13 +462,23 @@ class Batch:
     def set_graph(self, enabled: bool):
         _check(lib.qieo_batch_set_graph(self._h, int(bool(enabled))), "qieo_batch_set_graph")
 
+    def set_convergence(self, window: int):
+        _check(lib.qieo_batch_set_convergence(self._h, int(window)), "qieo_batch_set_convergence")
+
+    def converged(self, i: int):
+        c, g = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.qieo_batch_converged(self._h, i, ctypes.byref(c), ctypes.byref(g)),
+               "qieo_batch_converged")
+        return bool(c.value), int(g.value)
+
 
 class Server:
     """Continuous-batching request server (qieo_server_*)."""
 
     def __init__(self, hbm_budget_bytes: int, max_resident: int = 0, gens_per_iter: int = 0,
-                 stream: int | None = None):
-        cfg = qieo_server_cfg(int(hbm_budget_bytes), int(max_resident), int(gens_per_iter))
+                 convergence_window: int = 0, stream: int | None = None):
+        cfg = qieo_server_cfg(int(hbm_budget_bytes), int(max_resident), int(gens_per_iter),
+                              int(convergence_window))
         h = ctypes.c_void_p()
         ctx = None
         if stream is not None:

@@ -164,3 +164,34 @@ def test_quality_report_small_instance(oracle_mod, capsys):
     gap = (opt - o.best().fitness) / opt
     print("small instance: best %d, DP optimum %d, gap %.4f" % (o.best().fitness, opt, gap))
     assert 0 <= gap < 0.2
+
+
+def test_convergence_window_stops_at_first_stable_window(oracle_mod):
+    """Sec. IV-A: stop once the elite fitness has been one value for `window`
+    generations.  The stopping point is recomputed here from the per-
+    generation elite fitness of an identical run."""
+    inst = workloads.small_instance()
+    for window in (2, 5, 20):
+        o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+        n = o.run_until_converged(5000, window)
+        ref = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+        hist = []
+        stop = None
+        for g in range(5000):
+            ref.generation()
+            hist.append(int(ref.fitness()[0].max()))
+            if len(hist) >= window and len(set(hist[-window:])) == 1:
+                stop = g + 1
+                break
+        assert stop is not None and n == stop, (window, n, stop)
+        assert o.converged(window)
+        assert o.run_until_converged(100, window) == 0      # nothing more once converged
+        assert o.t == stop
+
+
+def test_convergence_window_respects_the_cap(oracle_mod):
+    inst = workloads.random_instance(300, 64, seed=31)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    assert o.run_until_converged(40, 20) == 40
+    assert not o.converged(20)
+    assert not o.converged(0)

@@ -259,6 +259,32 @@ int qieo_server_get_stats(qieo_server *s, qieo_server_stats *out);
 /* Stops the worker after its current iteration and frees everything. */
 void qieo_server_destroy(qieo_server *s);
 
+/* ---- pipeline variants (the paper's four-region structure) -------------- */
+
+/* QIEO_PIPELINE_FUSED (default): one launch per generation.
+ * QIEO_PIPELINE_UNFUSED: per generation CIP, QIP and Evaluation as three
+ *   launches and DetermineElite as a fourth (the four timed regions of eq. (2),
+ *   Sec. III-B).
+ * QIEO_PIPELINE_UNFUSED_FE_DE: DetermineElite fused into Evaluation's last
+ *   write (Sec. VI, P4, second option).
+ * QIEO_PIPELINE_UNFUSED_HOST_DE: DetermineElite on the host: fitness copied
+ *   out, argmax on the CPU, elite copied back, every generation (Sec. VI, P4,
+ *   first option).
+ * QIEO_PIPELINE_CHROMOSOME: the chromosome-parallel mapping of eq. (3): one
+ *   GPU lane per chromosome walks its genes serially (fused steps).
+ * All variants give bit-identical results; they exist to measure the cost of
+ * each step and of the mapping.  Only the default runs the convergence test. */
+#define QIEO_PIPELINE_FUSED 0
+#define QIEO_PIPELINE_UNFUSED 1
+#define QIEO_PIPELINE_UNFUSED_FE_DE 2
+#define QIEO_PIPELINE_UNFUSED_HOST_DE 3
+#define QIEO_PIPELINE_CHROMOSOME 4
+int qieo_set_pipeline(qieo_inst *h, int32_t pipeline);
+/* With timing enabled: per stage {fused generation, CIP, QIP, Evaluation,
+ * DetermineElite} the number of timed launches (host DetermineElite: timed
+ * sections) and their summed milliseconds (arrays of 5). */
+int qieo_stage_time(qieo_inst *h, int64_t *launches, double *total_ms, int reset);
+
 /* ---- errors and introspection ------------------------------------------- */
 const char *qieo_strerror(int code);
 /* Message of the last failing call on this thread ("" if none). */

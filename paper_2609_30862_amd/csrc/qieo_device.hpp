@@ -168,4 +168,31 @@ __device__ __forceinline__ void cip_gene(float& a, float& b, uint64_t rot, uint6
     b = sel(mv, b, b2);
 }
 
+// The same gate for one gene owned by one lane (chromosome-parallel mapping):
+// identical operations in identical order, selected per lane instead of by
+// wave masks, so both mappings produce the same bits.
+__device__ __forceinline__ void cip_gene_lane(float& a, float& b, bool tgt)
+{
+    const float p = a * b;
+    float sd = tgt ? kSin : -kSin;
+    if (p < 0.0f) sd = tgt ? -kSin : kSin;
+    else if (!(p > 0.0f)) sd = kSin;
+    const bool skip = (tgt ? a : b) == 0.0f;
+    const float ca = kCos * a;
+    const float sb = sd * b;
+    const float a1 = ca - sb;
+    const float sa = sd * a;
+    const float cb = kCos * b;
+    const float b1 = sa + cb;
+    const float aa = a1 * a1;
+    const float bb = b1 * b1;
+    const float n = aa + bb;
+    const float hn = 0.5f * n;
+    const float g = 1.5f - hn;
+    if (!skip) {
+        a = a1 * g;
+        b = b1 * g;
+    }
+}
+
 }  // namespace qieo

@@ -99,7 +99,10 @@ __global__ void init_kernel(InstDev I)
 // the generation index is t = *tbase + k, and an instance whose call asked
 // for fewer than k+1 generations skips the launch.
 // ---------------------------------------------------------------------------
-template <int R, bool PF, bool NT>
+// MODE selects the steps one launch performs (kStepAll = the fused
+// generation); the unfused pipeline runs kStepCip, kStepQip and kStepFe as
+// three launches, then DetermineElite by de_kernel or on the host.
+template <int R, bool PF, bool NT, int MODE>
 __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
                                                          const Tile* __restrict__ tiles, int k,
                                                          const int32_t* __restrict__ gens_arr,
@@ -145,7 +148,9 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
     // values earlier launches wrote, so all of them agree.  Generation t-1
     // completes convergence when its elite fitness equals that of the
     // window-1 generations before it; then generation t is not run.
-    const int window = sload(I.conv + 3);
+    constexpr bool kCip = (MODE & kStepCip) != 0, kQip = (MODE & kStepQip) != 0;
+    constexpr bool kFe = (MODE & kStepFe) != 0, kDe = (MODE & kStepDe) != 0;
+    const int window = MODE == kStepAll ? sload(I.conv + 3) : 0;
     bool stop = false;
     if (window > 0) {
         if (sload(I.conv) != 0) return;            // converged in an earlier launch
@@ -156,7 +161,8 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         }
     }
 
-    if (row0 == 0 && wave == 0) {
+    // the first launch of a generation closes the previous one's bookkeeping
+    if (kCip && row0 == 0 && wave == 0) {
         if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
         if (lane == 0) {
             if (window > 0 && pending) I.conv[8 + (int)((t - 1) & (kConvRing - 1))] = fe_prev;
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
     const f32x4* brow4[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        rot[r] = pending && r < nrows && sload(I.fit + (par ^ 1) * np + row0 + r) < fe_prev;
+        rot[r] = kCip && pending && r < nrows && sload(I.fit + (par ^ 1) * np + row0 + r) < fe_prev;
         const size_t base = (size_t)(row0 + (r < nrows ? r : 0)) * I.pitch;
         arow[r] = (const f32x4*)(I.alpha + base);
         brow4[r] = (const f32x4*)(I.beta + base);
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r < nrows) {
-                nb[r] = gload(brow4[r], qx);
+                if (kQip || rot[r]) nb[r] = gload(brow4[r], qx);
                 if (rot[r]) na[r] = gload(arow[r], qx);
             }
         }
@@ -220,10 +226,13 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 #pragma unroll
             for (int r = 0; r < R; ++r) { cb[r] = nb[r]; ca[r] = na[r]; }
         }
-        const i32x4 v4 = gload((const i32x4*)I.v, q);
-        const i32x4 w4 = gload((const i32x4*)I.w, q);
+        i32x4 v4 = {0, 0, 0, 0}, w4 = {0, 0, 0, 0};
+        if (kFe) {
+            v4 = gload((const i32x4*)I.v, q);
+            w4 = gload((const i32x4*)I.w, q);
+        }
         uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0;
-        if (pending) {
+        if (kCip && pending) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(brow + ch * kWordsPerChunk);
             bm0 = load_mask(bw); bm1 = load_mask(bw + 1);
             bm2 = load_mask(bw + 2); bm3 = load_mask(bw + 3);
@@ -248,22 +257,37 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
                 a4 = f32x4{a0, a1, a2, a3};
                 b4 = f32x4{b0, b1, b2, b3};
             }
-            const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
-            const bool x0 = act && observe(d.r0, b4.x);
-            const bool x1 = act && observe(d.r1, b4.y);
-            const bool x2 = act && observe(d.r2, b4.z);
-            const bool x3 = act && observe(d.r3, b4.w);
-            const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
-            if (lane < kWordsPerChunk) {
-                const int j = lane >> 1;
-                const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
-                const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
-                gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+            bool x0 = false, x1 = false, x2 = false, x3 = false;
+            if (kQip) {
+                const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo,
+                                              I.seed_hi);
+                x0 = act && observe(d.r0, b4.x);
+                x1 = act && observe(d.r1, b4.y);
+                x2 = act && observe(d.r2, b4.z);
+                x3 = act && observe(d.r3, b4.w);
+                const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
+                if (lane < kWordsPerChunk) {
+                    const int j = lane >> 1;
+                    const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
+                    const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
+                    gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+                }
+            } else if (kFe) {
+                // Evaluation alone: alleles of this generation from the words
+                // the QIP launch stored
+                const uint64_t* xw =
+                    reinterpret_cast<const uint64_t*>(xcur + (size_t)c * wpr + ch * kWordsPerChunk);
+                x0 = (load_mask(xw) >> lane) & 1u;
+                x1 = (load_mask(xw + 1) >> lane) & 1u;
+                x2 = (load_mask(xw + 2) >> lane) & 1u;
+                x3 = (load_mask(xw + 3) >> lane) & 1u;
             }
-            accP[r] += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
-                       (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
-            accW[r] += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
-                       (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+            if (kFe) {
+                accP[r] += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
+                           (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
+                accW[r] += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
+                           (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+            }
             if (rot[r] && act) {
                 if (NT) {
                     gstore_nt((f32x4*)arow[r], q, a4);
@@ -276,6 +300,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         }
     }
 
+    if (!kFe) return;
     // Evaluation: close the gene-axis sums of eq. (1) inside the workgroup.
     __shared__ uint32_t red[16][R][2];
 #pragma unroll
@@ -297,8 +322,127 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         I.prof[slot] = Pi;
         I.wt[slot] = Wi;
         // DetermineElite: the largest key is the largest fitness, lowest row.
-        atomicMax(&I.ekey[t % 3], make_key(f, c));
+        if (kDe) atomicMax(&I.ekey[t % 3], make_key(f, c));
     }
+}
+
+// DetermineElite as a launch of its own (unfused pipeline): one workgroup
+// reduces the population's keys and stores the elite key of generation t.
+__global__ __launch_bounds__(1024) void de_kernel(const InstDev* __restrict__ insts, int k)
+{
+    const InstDev I = insts[0];
+    const int64_t t = *I.tbase + k;
+    const int par = (int)(t & 1);
+    unsigned long long best = 0ull;
+    for (int c = threadIdx.x; c < I.np; c += blockDim.x) {
+        const unsigned long long key = make_key(I.fit[par * I.np + c], c);
+        best = key > best ? key : best;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off, 64);
+        best = o > best ? o : best;
+    }
+    __shared__ unsigned long long red[16];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = red[w] > best ? red[w] : best;
+        I.ekey[t % 3] = best;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chromosome-parallel mapping (eq. (3) of the paper): one lane per
+// chromosome walks that chromosome's genes serially, doing CIP(t-1), QIP,
+// Evaluation and the elite atomicMax of generation t.  Neighbouring lanes
+// touch addresses a whole row apart, so loads do not coalesce: this kernel
+// exists to measure that mapping, not to be fast.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void chromosome_kernel(const InstDev* __restrict__ insts, int k,
+                                                        int gens)
+{
+    const InstDev I = insts[0];
+    if (k >= gens) return;
+    const int64_t t = sload(I.tbase) + k;
+    const int par = (int)(t & 1);
+    const int np = I.np;
+    const int wpr = I.nchunk * kWordsPerChunk;
+    const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
+    uint32_t* __restrict__ xcur = I.xbits + (size_t)par * np * wpr;
+    const int lane = threadIdx.x;
+    const bool pending = t > 0;
+    int32_t e_prev = 0, fe_prev = 0;
+    if (pending) {
+        const unsigned long long key = sload(I.ekey + (t - 1) % 3);
+        e_prev = key_row(key);
+        fe_prev = key_fitness(key);
+    }
+    if (blockIdx.x == 0) {
+        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+        if (lane == 0) I.ekey[(t + 1) % 3] = 0ull;
+    }
+    const int c = blockIdx.x * 64 + lane;
+    if (c >= np) return;
+    const bool rot = pending && I.fit[(par ^ 1) * np + c] < fe_prev;
+    float* arow = I.alpha + (size_t)c * I.pitch;
+    float* brow = I.beta + (size_t)c * I.pitch;
+    const uint32_t* own = xprev + (size_t)c * wpr;
+    const uint32_t* eli = xprev + (size_t)e_prev * wpr;
+    uint32_t P = 0u, W = 0u;
+    for (int ch = 0; ch < I.nchunk; ++ch) {
+        uint32_t words[kWordsPerChunk];
+        for (int w = 0; w < kWordsPerChunk; ++w) words[w] = 0u;
+        for (int L = 0; L < 64; ++L) {
+            const int g0 = ch * kChunk + 4 * L;
+            if (g0 >= I.pitch) break;
+            float a[4], b[4];
+            for (int j = 0; j < 4; ++j) {
+                a[j] = arow[g0 + j];
+                b[j] = brow[g0 + j];
+            }
+            const int wsel = L >> 5, bit = L & 31;
+            if (rot) {
+                for (int j = 0; j < 4; ++j) {
+                    const int wi = ch * kWordsPerChunk + 2 * j + wsel;
+                    const bool xo = (own[wi] >> bit) & 1u;
+                    const bool be = (eli[wi] >> bit) & 1u;
+                    if (xo != be) cip_gene_lane(a[j], b[j], be);
+                }
+            }
+            const Draw4 d = philox4x32_10((uint32_t)(g0 >> 2), (uint32_t)c, (uint32_t)t, 0u,
+                                          I.seed_lo, I.seed_hi);
+            const uint32_t r4[4] = {d.r0, d.r1, d.r2, d.r3};
+            for (int j = 0; j < 4; ++j) {
+                const bool x = g0 + j < I.ng && observe(r4[j], b[j]);
+                if (x) {
+                    words[2 * j + wsel] |= 1u << bit;
+                    P += (uint32_t)I.v[g0 + j];
+                    W += (uint32_t)I.w[g0 + j];
+                }
+                if (rot) {
+                    arow[g0 + j] = a[j];
+                    brow[g0 + j] = b[j];
+                }
+            }
+        }
+        for (int w = 0; w < kWordsPerChunk; ++w)
+            xcur[(size_t)c * wpr + ch * kWordsPerChunk + w] = words[w];
+    }
+    const int32_t Pi = (int32_t)P, Wi = (int32_t)W;
+    const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
+    const int slot = par * np + c;
+    I.fit[slot] = f;
+    I.prof[slot] = Pi;
+    I.wt[slot] = Wi;
+    atomicMax(&I.ekey[t % 3], make_key(f, c));
+}
+
+hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s)
+{
+    hipLaunchKernelGGL(chromosome_kernel, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, dI, k,
+                       gens);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -440,8 +584,8 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
 #define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
-    hipLaunchKernelGGL((generation_kernel<RR, PFF, NTT>), grid, block, 0, s, dI, tiles, k,      \
-                       gens_arr, gens_all)
+    hipLaunchKernelGGL((generation_kernel<RR, PFF, NTT, kStepAll>), grid, block, 0, s, dI,     \
+                       tiles, k, gens_arr, gens_all)
 #define QIEO_LAUNCH_R(RR)                                                                      \
     switch (flags & 3) {                                                                       \
     case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
@@ -457,6 +601,38 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
     }
 #undef QIEO_LAUNCH_R
 #undef QIEO_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int waves_per_block,
+                        int stage, int k, int gens, hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
+    if (stage == kStepDe) {
+        hipLaunchKernelGGL(de_kernel, dim3(1), dim3(1024), 0, s, dI, k);
+        return hipGetLastError();
+    }
+#define QIEO_STAGE(RR, MM)                                                                     \
+    hipLaunchKernelGGL((generation_kernel<RR, false, true, MM>), grid, block, 0, s, dI,        \
+                       (const Tile*)nullptr, k, (const int32_t*)nullptr, gens)
+#define QIEO_STAGE_R(RR)                                                                       \
+    switch (stage) {                                                                           \
+    case kStepCip: QIEO_STAGE(RR, kStepCip); break;                                            \
+    case kStepQip: QIEO_STAGE(RR, kStepQip); break;                                            \
+    case kStepFe: QIEO_STAGE(RR, kStepFe); break;                                              \
+    case kStepFe | kStepDe: QIEO_STAGE(RR, kStepFe | kStepDe); break;                          \
+    default: return hipErrorInvalidValue;                                                      \
+    }
+    switch (rows_per_block) {
+    case 1: QIEO_STAGE_R(1); break;
+    case 2: QIEO_STAGE_R(2); break;
+    case 4: QIEO_STAGE_R(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef QIEO_STAGE_R
+#undef QIEO_STAGE
     return hipGetLastError();
 }
 

@@ -69,11 +69,23 @@ hipError_t launch_init(const InstDev& I, hipStream_t s);
 // flags: bit 0 = prefetch the next chunk's amplitudes while computing the
 // current one; bit 1 = non-temporal amplitude stores.
 constexpr int kFlagPrefetch = 1;
+// Steps of one generation a launch may perform.
+constexpr int kStepCip = 1, kStepQip = 2, kStepFe = 4, kStepDe = 8;
+constexpr int kStepAll = kStepCip | kStepQip | kStepFe | kStepDe;
+// timing slots: fused generation, CIP, QIP, Evaluation, DetermineElite
+constexpr int kStages = 5;
 constexpr int kFlagNontemporal = 2;
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
 // status (may be NULL): per instance {generations completed, converged flag}.
+// One stage of the unfused pipeline for a single instance: kStepCip (CIP of
+// generation t-1 plus the previous generation's bookkeeping), kStepQip,
+// kStepFe, kStepFe | kStepDe, or kStepDe (the standalone elite reduction).
+hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int waves_per_block,
+                        int stage, int k, int gens, hipStream_t s);
+// Chromosome-parallel generation (one lane per chromosome), single instance.
+hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s);
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
                          int64_t* status, hipStream_t s);
 constexpr int kConvRing = 32;      // longest convergence window

@@ -209,11 +209,16 @@ struct qieo_inst {
     uint64_t seed = 0;
     int64_t t = 0;               // generations enqueued so far
     int R = 1, S = 1, flags = 0;
+    int pipeline = QIEO_PIPELINE_FUSED;
+    int32_t window = 0;
+    int32_t* h_fit = nullptr;                // pinned, host DetermineElite
+    unsigned long long* h_key = nullptr;     // pinned, host DetermineElite
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) per timed launch
+    std::vector<int> ev_stage;   // stage of each pair
     size_t ev_used = 0;
-    int64_t launches = 0;
-    double total_ms = 0.0;
+    int64_t launches[kStages] = {0, 0, 0, 0, 0};
+    double total_ms[kStages] = {0, 0, 0, 0, 0};
 };
 
 static void* dev_alloc(qieo_inst* h, size_t bytes)
@@ -239,6 +244,8 @@ static void inst_release(qieo_inst* h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->h_fit) (void)hipHostFree(h->h_fit);
+    if (h->h_key) (void)hipHostFree(h->h_key);
     dev_free(h, h->arena);
     dev_free(h, h->d_desc);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
@@ -323,7 +330,7 @@ extern "C" int qieo_create(const qieo_item* items, int32_t n_items, int32_t capa
     return qieo_create_ex(items, n_items, capacity, n_pop, seed, nullptr, out);
 }
 
-static int timed_event_pair(qieo_inst* h, hipEvent_t* a, hipEvent_t* b)
+static int timed_event_pair(qieo_inst* h, int stage, hipEvent_t* a, hipEvent_t* b)
 {
     while (h->ev.size() < 2 * (h->ev_used + 1)) {
         hipEvent_t e;
@@ -331,6 +338,8 @@ static int timed_event_pair(qieo_inst* h, hipEvent_t* a, hipEvent_t* b)
         if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
         h->ev.push_back(e);
     }
+    if (h->ev_stage.size() < h->ev_used + 1) h->ev_stage.resize(h->ev_used + 1);
+    h->ev_stage[h->ev_used] = stage;
     *a = h->ev[2 * h->ev_used];
     *b = h->ev[2 * h->ev_used + 1];
     h->ev_used++;
@@ -346,10 +355,32 @@ static int collect_timing(qieo_inst* h)
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-        h->total_ms += ms;
-        h->launches++;
+        h->total_ms[h->ev_stage[k]] += ms;
+        h->launches[h->ev_stage[k]]++;
     }
     h->ev_used = 0;
+    return QIEO_OK;
+}
+
+// Host DetermineElite of the unfused pipeline: fitness to the host, argmax
+// (lowest row on ties), elite key back to the device.
+static int host_elite(qieo_inst* h, int64_t t)
+{
+    hipError_t e;
+    const int par = (int)(t & 1);
+    if ((e = hipMemcpyAsync(h->h_fit, h->d.fit + (size_t)par * h->np, h->np * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(fitness)");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+        return hip_fail(e, "hipStreamSynchronize");
+    int32_t best = 0;
+    for (int32_t c = 1; c < h->np; ++c)
+        if (h->h_fit[c] > h->h_fit[best]) best = c;
+    *h->h_key = ((unsigned long long)((uint32_t)h->h_fit[best] ^ 0x80000000u) << 32) |
+                (unsigned long long)(~(uint32_t)best);
+    if ((e = hipMemcpyAsync(h->d.ekey + t % 3, h->h_key, sizeof(unsigned long long),
+                            hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(elite)");
     return QIEO_OK;
 }
 
@@ -363,17 +394,46 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         return set_error(QIEO_EINVAL, "generation index would exceed 2^31-1");
     hipError_t e;
     const int blocks = (h->np + h->R - 1) / h->R;
+    // stage list of one generation
+    int stages[4], nst = 0;
+    if (h->pipeline == QIEO_PIPELINE_FUSED) {
+        stages[nst++] = kStepAll;
+    } else if (h->pipeline == QIEO_PIPELINE_CHROMOSOME) {
+        stages[nst++] = -2;
+    } else {
+        stages[nst++] = kStepCip;
+        stages[nst++] = kStepQip;
+        stages[nst++] = h->pipeline == QIEO_PIPELINE_UNFUSED_FE_DE ? (kStepFe | kStepDe) : kStepFe;
+        if (h->pipeline == QIEO_PIPELINE_UNFUSED) stages[nst++] = kStepDe;
+        if (h->pipeline == QIEO_PIPELINE_UNFUSED_HOST_DE) stages[nst++] = -1;   // host
+    }
     for (int32_t k = 0; k < n; ++k) {
-        hipEvent_t a = nullptr, b = nullptr;
-        if (h->timing) {
-            int rc = timed_event_pair(h, &a, &b);
-            if (rc) return rc;
-            (void)hipEventRecord(a, h->stream);
+        for (int si = 0; si < nst; ++si) {
+            const int st = stages[si];
+            const int slot = (st == kStepAll || st == -2) ? 0 : st == kStepCip ? 1
+                           : st == kStepQip ? 2 : (st > 0 && (st & kStepFe)) ? 3 : 4;
+            hipEvent_t a = nullptr, b = nullptr;
+            if (h->timing) {
+                int rc = timed_event_pair(h, slot, &a, &b);
+                if (rc) return rc;
+                (void)hipEventRecord(a, h->stream);
+            }
+            if (st == kStepAll) {
+                if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k,
+                                           nullptr, n, h->stream)) != hipSuccess)
+                    return hip_fail(e, "generation kernel");
+            } else if (st == -1) {
+                int rc = host_elite(h, h->t + k);
+                if (rc) return rc;
+            } else if (st == -2) {
+                if ((e = launch_chromosome(h->d_desc, h->np, k, n, h->stream)) != hipSuccess)
+                    return hip_fail(e, "chromosome-parallel kernel");
+            } else if ((e = launch_stage(h->d_desc, blocks, h->R, h->S, st, k, n, h->stream)) !=
+                       hipSuccess) {
+                return hip_fail(e, "pipeline stage kernel");
+            }
+            if (h->timing) (void)hipEventRecord(b, h->stream);
         }
-        if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
-                                   h->stream)) != hipSuccess)
-            return hip_fail(e, "generation kernel");
-        if (h->timing) (void)hipEventRecord(b, h->stream);
     }
     if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
         return hip_fail(e, "finish kernel");
@@ -413,7 +473,11 @@ extern "C" int qieo_set_convergence(qieo_inst* h, int32_t window)
         return set_error(QIEO_EINVAL, "window must be in [0, %d] (got %d)", kConvRing, window);
     if (h->t != 0)
         return set_error(QIEO_ESTATE, "the convergence window is set before the first generation");
-    return write_window(h->d, h->stream, window);
+    if (window > 0 && h->pipeline != QIEO_PIPELINE_FUSED)
+        return set_error(QIEO_ESTATE, "the unfused pipelines do not run the convergence test");
+    int rc = write_window(h->d, h->stream, window);
+    if (rc == QIEO_OK) h->window = window;
+    return rc;
 }
 
 extern "C" int qieo_converged(qieo_inst* h, int32_t* converged, int64_t* generation)
@@ -646,12 +710,50 @@ extern "C" int qieo_kernel_time(qieo_inst* h, int64_t* launches, double* total_m
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
     int rc = collect_timing(h);
     if (rc) return rc;
-    if (launches) *launches = h->launches;
-    if (total_ms) *total_ms = h->total_ms;
+    if (launches) *launches = h->launches[0];
+    if (total_ms) *total_ms = h->total_ms[0];
     if (reset) {
-        h->launches = 0;
-        h->total_ms = 0.0;
+        h->launches[0] = 0;
+        h->total_ms[0] = 0.0;
     }
+    return QIEO_OK;
+}
+
+extern "C" int qieo_stage_time(qieo_inst* h, int64_t* launches, double* total_ms, int reset)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    int rc = collect_timing(h);
+    if (rc) return rc;
+    for (int i = 0; i < kStages; ++i) {
+        if (launches) launches[i] = h->launches[i];
+        if (total_ms) total_ms[i] = h->total_ms[i];
+        if (reset) {
+            h->launches[i] = 0;
+            h->total_ms[i] = 0.0;
+        }
+    }
+    return QIEO_OK;
+}
+
+extern "C" int qieo_set_pipeline(qieo_inst* h, int32_t pipeline)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (pipeline < QIEO_PIPELINE_FUSED || pipeline > QIEO_PIPELINE_CHROMOSOME)
+        return set_error(QIEO_EINVAL, "unknown pipeline %d", pipeline);
+    if (pipeline != QIEO_PIPELINE_FUSED && h->window > 0)
+        return set_error(QIEO_ESTATE, "the unfused pipelines do not run the convergence test");
+    if (pipeline == QIEO_PIPELINE_UNFUSED_HOST_DE && !h->h_fit) {
+        hipError_t e;
+        if ((e = hipHostMalloc((void**)&h->h_fit, (size_t)h->np * sizeof(int32_t),
+                               hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc");
+        if ((e = hipHostMalloc((void**)&h->h_key, sizeof(unsigned long long),
+                               hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc");
+    }
+    h->pipeline = pipeline;
     return QIEO_OK;
 }
 

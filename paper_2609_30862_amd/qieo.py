@@ -24,6 +24,13 @@ QIEO_EDEVICE = -4
 QIEO_EAGAIN = -5
 QIEO_ESTATE = -6
 
+PIPELINE_FUSED = 0
+PIPELINE_UNFUSED = 1
+PIPELINE_UNFUSED_FE_DE = 2
+PIPELINE_UNFUSED_HOST_DE = 3
+PIPELINE_CHROMOSOME = 4
+STAGES = ("fused", "cip", "qip", "fe", "de")
+
 
 class QieoError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
@@ -91,6 +98,10 @@ def _load():
     L.qieo_best.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
     L.qieo_generations.restype = ctypes.c_int
     L.qieo_generations.argtypes = [H, ctypes.POINTER(i64)]
+    L.qieo_set_pipeline.restype = ctypes.c_int
+    L.qieo_set_pipeline.argtypes = [H, i32]
+    L.qieo_stage_time.restype = ctypes.c_int
+    L.qieo_stage_time.argtypes = [H, P, P, ctypes.c_int]
     L.qieo_set_convergence.restype = ctypes.c_int
     L.qieo_set_convergence.argtypes = [H, i32]
     L.qieo_converged.restype = ctypes.c_int
@@ -343,6 +354,16 @@ class Instance:
 
     def set_convergence(self, window: int):
         _check(lib.qieo_set_convergence(self._h, int(window)), "qieo_set_convergence")
+
+    def set_pipeline(self, pipeline: int):
+        _check(lib.qieo_set_pipeline(self._h, int(pipeline)), "qieo_set_pipeline")
+
+    def stage_time(self, reset: bool = False) -> dict:
+        """{stage: (timed launches, total ms)} for fused, cip, qip, fe, de."""
+        n = np.zeros(5, np.int64)
+        ms = np.zeros(5, np.float64)
+        _check(lib.qieo_stage_time(self._h, _ptr(n), _ptr(ms), int(reset)), "qieo_stage_time")
+        return {k: (int(n[i]), float(ms[i])) for i, k in enumerate(STAGES)}
 
     def converged(self):
         """(converged, generation after which the run stopped or -1)."""

@@ -129,3 +129,40 @@ def test_medium_instance_checkpoints(qieo, oracle_mod):
         done = ck
         say("  compare at generation %d" % ck)
         assert_state_equal(g, o, label="medium gen %d" % ck)
+
+
+@pytest.mark.parametrize("pipeline", [1, 2, 3, 4])
+@pytest.mark.parametrize("ng,n_pop", [(100, 16), (1000, 9), (4097, 5), (300, 130)])
+def test_unfused_pipelines_same_trajectory(qieo, oracle_mod, pipeline, ng, n_pop):
+    """The four-launch pipelines (device, fused-into-Evaluation or host
+    DetermineElite) follow the oracle bit for bit, also when the pipeline
+    changes between calls."""
+    inst = workloads.random_instance(ng, n_pop, seed=ng + pipeline)
+    say("pipeline %d Ng=%d Np=%d" % (pipeline, ng, n_pop))
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_pipeline(pipeline)
+    for step in (1, 1, 5):
+        g.step(step)
+        o.run(step)
+        assert_state_equal(g, o, label="pipeline %d t=%d" % (pipeline, o.t))
+    g.set_pipeline(0)
+    g.step(3)
+    g.set_pipeline(pipeline)
+    g.step(4)
+    o.run(7)
+    assert_state_equal(g, o, label="pipeline %d mixed t=%d" % (pipeline, o.t))
+
+
+def test_stage_timing(qieo):
+    inst = workloads.random_instance(5000, 64, seed=3)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_timing(True)
+    g.set_pipeline(1)
+    g.step(4)
+    st = g.stage_time(reset=True)
+    assert st["cip"][0] == st["qip"][0] == st["fe"][0] == st["de"][0] == 4
+    assert all(st[k][1] > 0 for k in ("cip", "qip", "fe", "de"))
+    g.set_pipeline(3)
+    g.step(2)
+    st = g.stage_time()
+    assert st["de"][0] == 2 and st["de"][1] > 0

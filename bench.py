@@ -202,6 +202,44 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_fractions(args):
+    """Per-step time of the generation over an (Np, Ng) grid, for the fused
+    launch, the paper's four-launch pipeline with DetermineElite on the device
+    or on the host, and the chromosome-parallel mapping (eq. (3)).  Prints
+    one JSON line per cell."""
+    import torch
+    import workloads
+    from paper_2609_30862_amd import qieo
+
+    grid = [(np_, ng) for np_ in (256, 1024, 4096) for ng in (500, 2500, 10_000, 40_000, 200_000)]
+    for (np_, ng) in grid:
+        inst = workloads.random_instance(ng, np_, seed=ng + np_, wmax=100, offset=10)
+        g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+        g.set_timing(True)
+        cell = {"n_pop": np_, "n_items": ng}
+        for name, pipe, gens in (("fused", 0, 20), ("unfused_device_de", 1, 20),
+                                 ("unfused_host_de", 3, 20), ("chromosome", 4, 3)):
+            g.set_pipeline(pipe)
+            g.step(2)
+            g.stage_time(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(gens)
+            wall = (time.perf_counter() - t0) / gens * 1e3
+            st = g.stage_time(reset=True)
+            per = {k: v[1] / gens for k, v in st.items() if v[0]}
+            cell[name] = {"t_gen_ms": wall, "stage_ms": per}
+        f = cell["unfused_host_de"]["stage_ms"]
+        tot = sum(f.values())
+        cell["fractions_host_de"] = {k: v / tot for k, v in f.items()}
+        cell["rho"] = cell["chromosome"]["t_gen_ms"] / cell["fused"]["t_gen_ms"]
+        g.close()
+        log("Np=%5d Ng=%6d fused %.3f ms, unfused %.3f ms, host-DE %.3f ms, chromosome %.2f ms"
+            % (np_, ng, cell["fused"]["t_gen_ms"], cell["unfused_device_de"]["t_gen_ms"],
+               cell["unfused_host_de"]["t_gen_ms"], cell["chromosome"]["t_gen_ms"]))
+        print(json.dumps(cell), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +252,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["large", "batch", "serve"], default="large",
+    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions"],
+                    default="large",
                     help="large: the single 4096 x 200,000 instance (default); batch: 512 "
                          "ragged instances x 500 generations vs a per-instance launch loop; "
                          "serve: Poisson request stream through the continuous-batching server")
@@ -256,6 +295,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "fractions":
+        return bench_fractions(args)
     inst = workloads.large_instance(args.n_pop, args.n_items)
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
     g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)

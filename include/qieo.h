@@ -211,6 +211,11 @@ int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per
 /* 1 (default): each call's launches are captured once into a HIP graph and
  * replayed; 0: launched one by one. */
 int qieo_batch_set_graph(qieo_batch *b, int32_t enabled);
+/* 1 (default): members small enough for the persistent path (see
+ * qieo_set_persistent) run as one workgroup each for the whole call,
+ * concurrently with the per-generation launches of the others; 0: all
+ * members use per-generation launches.  Results are identical. */
+int qieo_batch_set_persistent(qieo_batch *b, int32_t enabled);
 void qieo_batch_destroy(qieo_batch *b);
 
 /* ---- server: continuous batching of solve requests ----------------------- */
@@ -258,6 +263,38 @@ int qieo_server_release(qieo_server *s, uint64_t ticket);
 int qieo_server_get_stats(qieo_server *s, qieo_server_stats *out);
 /* Stops the worker after its current iteration and frees everything. */
 void qieo_server_destroy(qieo_server *s);
+
+/* Persistent path for small populations: one single-workgroup launch runs all
+ * generations of a qieo_step call, block barriers replacing launch
+ * boundaries.  mode 0: never; 1 (default): when n_pop * (n_items rounded up
+ * to 64) <= 65536 and n_pop <= 2048; 2: whenever n_pop <= 2048.  Results are
+ * identical either way. */
+int qieo_set_persistent(qieo_inst *h, int32_t mode);
+
+/* ---- work-shape autotuner ------------------------------------------------ */
+
+typedef struct qieo_tune_result {
+    int32_t rows_per_block, waves_per_block, flags;
+    int32_t candidates;                 /* shapes timed */
+    double ms_per_generation;           /* of the chosen shape */
+    double worst_ms_per_generation;     /* of the slowest candidate */
+} qieo_tune_result;
+
+/* Times every work shape (rows per workgroup 1/2/4 x waves 2/4/8/16 x the four
+ * kernel variants) for trial_generations generations each on a scratch
+ * population of n_pop x n_items (its own device memory, freed before return;
+ * items NULL = unit-weight items, whose timing is the same), records the
+ * fastest in the tuning database under the shape's bucket (log2 of n_pop,
+ * log2 of 256-gene chunks per row) and returns it.  Later qieo_create calls
+ * whose shape falls in a tuned bucket use that shape.  QIEO_ENOMEM if the
+ * scratch population does not fit in device memory. */
+int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item *items, int32_t capacity,
+                  int32_t trial_generations, qieo_tune_result *out);
+/* Tuning database as JSON (one entry per line); load returns the number of
+ * entries read (>= 0) or a negative status. */
+int qieo_tune_db_save(const char *path);
+int qieo_tune_db_load(const char *path);
+void qieo_tune_db_clear(void);
 
 /* ---- pipeline variants (the paper's four-region structure) -------------- */
 

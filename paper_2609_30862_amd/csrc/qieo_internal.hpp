@@ -32,6 +32,8 @@ int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
                     const ArenaLayout& L, char* base, std::vector<int32_t>& staging);
 int check_device();
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
+// Shape from the autotuner's database, if the bucket was tuned.
+bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
               uint32_t* bits, size_t n_words);
 int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,

@@ -353,6 +353,185 @@ __global__ __launch_bounds__(1024) void de_kernel(const InstDev* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// Persistent single-workgroup path for small populations: one workgroup runs
+// generations k = 0..gens-1 of one instance (t = *tbase + k; *tbase is left
+// to finish_kernel, as for per-generation launches), with block barriers in
+// place of launch boundaries.  Work items are (row, chunk) pairs spread over
+// the S wavefronts; per-gene arithmetic is the fused kernel's.  Everything
+// this launch itself wrote earlier (alleles, fitness, elite key, convergence
+// ring) is re-read with vector loads after a barrier, never through the
+// scalar cache, which does not see the launch's own stores.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t vload_mask(const uint64_t* p)
+{
+    return uniform_mask(*(const volatile uint64_t*)p);
+}
+
+__device__ __forceinline__ int32_t vload_i32(const int32_t* p)
+{
+    return __builtin_amdgcn_readfirstlane(*(const volatile int32_t*)p);
+}
+
+__global__ __launch_bounds__(1024) void persistent_kernel(const InstDev* __restrict__ insts,
+                                                         const uint32_t* __restrict__ ids,
+                                                         const int32_t* __restrict__ gens_arr,
+                                                         int gens_all)
+{
+    const uint32_t inst = ids ? ids[blockIdx.x] : 0u;
+    const InstDev I = insts[inst];
+    const int gens = gens_arr ? gens_arr[inst] : gens_all;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int S = blockDim.x >> 6;
+    const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
+    const int64_t t0 = *(const volatile int64_t*)I.tbase;
+    const int window = I.conv[3];
+    __shared__ uint32_t sP[kPersistentMaxRows], sW[kPersistentMaxRows];
+    __shared__ unsigned long long skey[16];
+    __shared__ int sstop;
+
+    for (int k = 0; k < gens; ++k) {
+        const int64_t t = t0 + k;
+        const int par = (int)(t & 1);
+        const uint32_t* xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
+        uint32_t* xcur = I.xbits + (size_t)par * np * wpr;
+        const bool pending = t > 0;
+        int32_t e_prev = 0, fe_prev = 0;
+        if (pending) {
+            const unsigned long long key = *(const volatile unsigned long long*)(I.ekey + (t - 1) % 3);
+            e_prev = __builtin_amdgcn_readfirstlane(key_row(key));
+            fe_prev = __builtin_amdgcn_readfirstlane(key_fitness(key));
+        }
+        if (threadIdx.x == 0) {
+            int stop = 0;
+            if (window > 0) {
+                if (I.conv[0] != 0) {
+                    stop = 1;
+                } else if (pending && t >= window) {
+                    stop = 1;
+                    for (int j = 1; j < window && stop; ++j)
+                        stop = ((const volatile int32_t*)I.conv)[8 + (int)((t - 1 - j) & (kConvRing - 1))] == fe_prev;
+                }
+            }
+            sstop = stop;
+        }
+        for (int c = threadIdx.x; c < np; c += blockDim.x) { sP[c] = 0u; sW[c] = 0u; }
+        __syncthreads();
+        const bool stop = sstop != 0;
+        if (wave == 0) {
+            if (pending && !(window > 0 && I.conv[0] != 0))
+                best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+            // leave slot t+1 clear, as a per-generation launch of t would
+            if (lane == 0 && !stop) I.ekey[(t + 1) % 3] = 0ull;
+            if (lane == 0 && window > 0 && pending && I.conv[0] == 0) {
+                I.conv[8 + (int)((t - 1) & (kConvRing - 1))] = fe_prev;
+                if (stop) {
+                    I.conv[1] = (int32_t)(uint32_t)(uint64_t)(t - 1);
+                    I.conv[2] = (int32_t)(uint32_t)((uint64_t)(t - 1) >> 32);
+                    I.conv[0] = 1;
+                }
+            }
+        }
+        if (stop) break;
+
+        const uint32_t* brow = xprev + (size_t)e_prev * wpr;
+        for (int item = wave; item < np * nchunk; item += S) {
+            const int c = item / nchunk, ch = item - c * nchunk;
+            const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
+            const bool act = g0 < (uint32_t)I.pitch;
+            const uint32_t q = g0 >> 2;
+            const bool rot = pending && vload_i32(I.fit + (par ^ 1) * np + c) < fe_prev;
+            const f32x4* arow = (const f32x4*)(I.alpha + (size_t)c * I.pitch);
+            const f32x4* brow4 = (const f32x4*)(I.beta + (size_t)c * I.pitch);
+            f32x4 b4 = gload(brow4, q);
+            f32x4 a4 = b4;
+            if (rot) {
+                a4 = gload(arow, q);
+                const uint64_t* bw = reinterpret_cast<const uint64_t*>(brow + ch * kWordsPerChunk);
+                const uint64_t* xw =
+                    reinterpret_cast<const uint64_t*>(xprev + (size_t)c * wpr + ch * kWordsPerChunk);
+                const uint64_t bm0 = vload_mask(bw), bm1 = vload_mask(bw + 1);
+                const uint64_t bm2 = vload_mask(bw + 2), bm3 = vload_mask(bw + 3);
+                const uint64_t xm0 = vload_mask(xw), xm1 = vload_mask(xw + 1);
+                const uint64_t xm2 = vload_mask(xw + 2), xm3 = vload_mask(xw + 3);
+                float a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
+                float b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
+                cip_gene(a0, b0, xm0 ^ bm0, bm0);
+                cip_gene(a1, b1, xm1 ^ bm1, bm1);
+                cip_gene(a2, b2, xm2 ^ bm2, bm2);
+                cip_gene(a3, b3, xm3 ^ bm3, bm3);
+                a4 = f32x4{a0, a1, a2, a3};
+                b4 = f32x4{b0, b1, b2, b3};
+            }
+            const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+            const bool x0 = act && observe(d.r0, b4.x);
+            const bool x1 = act && observe(d.r1, b4.y);
+            const bool x2 = act && observe(d.r2, b4.z);
+            const bool x3 = act && observe(d.r3, b4.w);
+            const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
+            if (lane < kWordsPerChunk) {
+                const int j = lane >> 1;
+                const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
+                const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
+                gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+            }
+            const i32x4 v4 = gload((const i32x4*)I.v, q);
+            const i32x4 w4 = gload((const i32x4*)I.w, q);
+            uint32_t p = (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
+                         (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
+            uint32_t w = (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
+                         (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+            p = wave_sum(p);
+            w = wave_sum(w);
+            if (lane == 0) {
+                atomicAdd(&sP[c], p);
+                atomicAdd(&sW[c], w);
+            }
+            if (rot && act) {
+                gstore((f32x4*)arow, q, a4);
+                gstore((f32x4*)brow4, q, b4);
+            }
+        }
+        __syncthreads();
+        // Evaluation closes in LDS; DetermineElite is a block max of the keys
+        unsigned long long best = 0ull;
+        for (int c = threadIdx.x; c < np; c += blockDim.x) {
+            const int32_t Pi = (int32_t)sP[c], Wi = (int32_t)sW[c];
+            const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
+            const int slot = par * np + c;
+            I.fit[slot] = f;
+            I.prof[slot] = Pi;
+            I.wt[slot] = Wi;
+            const unsigned long long key = make_key(f, c);
+            best = key > best ? key : best;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(best, off, 64);
+            best = o > best ? o : best;
+        }
+        if (lane == 0) skey[wave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < S; ++w) best = skey[w] > best ? skey[w] : best;
+            I.ekey[t % 3] = best;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,
+                             int waves_per_block, const int32_t* gens_arr, int gens_all,
+                             hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(persistent_kernel, dim3((unsigned)n_blocks),
+                       dim3((unsigned)(64 * waves_per_block)), 0, s, dI, ids, gens_arr, gens_all);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Chromosome-parallel mapping (eq. (3) of the paper): one lane per
 // chromosome walks that chromosome's genes serially, doing CIP(t-1), QIP,
 // Evaluation and the elite atomicMax of generation t.  Neighbouring lanes

@@ -84,6 +84,14 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
 // kStepFe, kStepFe | kStepDe, or kStepDe (the standalone elite reduction).
 hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int waves_per_block,
                         int stage, int k, int gens, hipStream_t s);
+// Persistent single-workgroup path: workgroup b runs all of this call's
+// generations of instance ids[b] (ids NULL: instance 0); bookkeeping of the
+// call's last generation is left to launch_finish.
+constexpr int kPersistentMaxRows = 2048;          // LDS per-row sums
+constexpr int64_t kPersistentMaxGenes = 1 << 16;  // Np * pitch at or below which it pays
+hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,
+                             int waves_per_block, const int32_t* gens_arr, int gens_all,
+                             hipStream_t s);
 // Chromosome-parallel generation (one lane per chromosome), single instance.
 hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s);
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,

@@ -105,7 +105,12 @@ size_t DevicePool::largest_free() const
 Engine::~Engine()
 {
     if (stream_) (void)hipStreamSynchronize(stream_);
+    if (side_) (void)hipStreamSynchronize(side_);
     invalidate_graph();
+    if (d_pids_) (void)hipFree(d_pids_);
+    if (fork_) (void)hipEventDestroy(fork_);
+    if (join_) (void)hipEventDestroy(join_);
+    if (side_) (void)hipStreamDestroy(side_);
     for (auto& c : classes_)
         if (c.d_tiles) (void)hipFree(c.d_tiles);
     if (d_desc_) (void)hipFree(d_desc_);
@@ -223,10 +228,40 @@ int Engine::rebuild()
                             stream_)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(descriptors)");
 
-    // group members by shape class; within a class, longest rows first so the
-    // longest-running workgroups start first
+    // small members run persistently (one workgroup for the whole call);
+    // the rest are grouped by shape class; within a class, longest rows first
+    // so the longest-running workgroups start first
+    pids_.clear();
     std::vector<std::vector<size_t>> groups(4);
-    for (size_t i = 0; i < n; ++i) groups[class_of(members_[i].L.nchunk)].push_back(i);
+    for (size_t i = 0; i < n; ++i) {
+        const Member& m = members_[i];
+        if (use_persistent_ && m.np <= kPersistentMaxRows &&
+            (int64_t)m.np * m.L.pitch <= kPersistentMaxGenes)
+            pids_.push_back((uint32_t)i);
+        else
+            groups[class_of(m.L.nchunk)].push_back(i);
+    }
+    if (d_pids_) (void)hipFree(d_pids_);
+    d_pids_ = nullptr;
+    if (!pids_.empty()) {
+        // largest first: the longest workgroups start first
+        std::sort(pids_.begin(), pids_.end(), [&](uint32_t a, uint32_t b) {
+            return (int64_t)members_[a].np * members_[a].L.pitch >
+                   (int64_t)members_[b].np * members_[b].L.pitch;
+        });
+        if ((e = hipMalloc(&d_pids_, pids_.size() * sizeof(uint32_t))) != hipSuccess)
+            return hip_fail(e, "hipMalloc(persistent ids)");
+        if ((e = hipMemcpyAsync(d_pids_, pids_.data(), pids_.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, stream_)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(persistent ids)");
+        if (!side_) {
+            if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+            if ((e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&join_, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreate");
+        }
+    }
     static const int kS[4] = {1, 2, 4, 8};
     for (int c = 0; c < 4; ++c) {
         auto& g = groups[c];
@@ -276,6 +311,17 @@ int Engine::rebuild()
 int Engine::enqueue(int nmax)
 {
     hipError_t e;
+    if (!pids_.empty()) {
+        // fork: the persistent members advance on the side stream while the
+        // per-generation launches below advance the others
+        if ((e = hipEventRecord(fork_, stream_)) != hipSuccess ||
+            (e = hipStreamWaitEvent(side_, fork_, 0)) != hipSuccess)
+            return hip_fail(e, "fork");
+        if ((e = launch_persistent(d_desc_, d_pids_, (int)pids_.size(), 8, d_gens_, 0, side_)) !=
+            hipSuccess)
+            return hip_fail(e, "persistent kernel");
+        if ((e = hipEventRecord(join_, side_)) != hipSuccess) return hip_fail(e, "join");
+    }
     for (int k = 0; k < nmax; ++k) {
         for (auto& c : classes_) {
             if ((e = launch_generation(d_desc_, c.d_tiles, (int)c.tiles.size(), c.R, c.S, c.flags,
@@ -283,6 +329,8 @@ int Engine::enqueue(int nmax)
                 return hip_fail(e, "generation kernel");
         }
     }
+    if (!pids_.empty() && (e = hipStreamWaitEvent(stream_, join_, 0)) != hipSuccess)
+        return hip_fail(e, "join");
     if ((e = launch_finish(d_desc_, (int)members_.size(), d_gens_, 0, d_status_, stream_)) !=
         hipSuccess)
         return hip_fail(e, "finish kernel");
@@ -564,6 +612,14 @@ extern "C" int qieo_batch_set_tile(qieo_batch* b, int32_t rows_per_block,
         return set_error(QIEO_EINVAL, "bad work shape (%d, %d, %d)", rows_per_block,
                          waves_per_block, flags);
     b->eng->force_shape(rows_per_block, waves_per_block, flags);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_set_persistent(qieo_batch* b, int32_t enabled)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    b->eng->set_use_persistent(enabled != 0);
     return QIEO_OK;
 }
 

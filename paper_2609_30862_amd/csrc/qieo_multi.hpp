@@ -83,6 +83,7 @@ public:
     // (R, S, flags) when R > 0.
     void force_shape(int R, int S, int flags);
     void set_use_graph(bool on) { use_graph_ = on; invalidate_graph(); }
+    void set_use_persistent(bool on) { use_persistent_ = on; dirty_ = true; }
     // Uploads descriptors and tile tables if membership changed since the
     // last launch (device_desc() is valid only after this).
     int ensure_built() { return dirty_ ? rebuild() : QIEO_OK; }
@@ -103,6 +104,13 @@ private:
     int32_t* h_gens_ = nullptr;    // pinned
     size_t gens_cap_ = 0;
     std::vector<ShapeClass> classes_;
+    // small members: one persistent workgroup each, on a side stream forked
+    // from and joined back into the main one
+    std::vector<uint32_t> pids_;
+    uint32_t* d_pids_ = nullptr;
+    hipStream_t side_ = nullptr;
+    hipEvent_t fork_ = nullptr, join_ = nullptr;
+    bool use_persistent_ = true;
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;
     hipGraphExec_t graph_ = nullptr;

@@ -210,6 +210,7 @@ struct qieo_inst {
     int64_t t = 0;               // generations enqueued so far
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
+    int persistent = 1;          // 0 never, 1 when small enough, 2 whenever rows fit
     int32_t window = 0;
     int32_t* h_fit = nullptr;                // pinned, host DetermineElite
     unsigned long long* h_key = nullptr;     // pinned, host DetermineElite
@@ -314,7 +315,8 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
         inst_release(h);
         return rc;
     }
-    pick_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags);
+    if (!tuned_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags))
+        pick_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags);
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         rc = hip_fail(e, "hipStreamSynchronize");
         inst_release(h);
@@ -394,6 +396,26 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         return set_error(QIEO_EINVAL, "generation index would exceed 2^31-1");
     hipError_t e;
     const int blocks = (h->np + h->R - 1) / h->R;
+    // small populations: the whole call in one single-workgroup launch
+    const bool small = (int64_t)h->np * h->L.pitch <= kPersistentMaxGenes;
+    if (h->pipeline == QIEO_PIPELINE_FUSED && h->np <= kPersistentMaxRows &&
+        (h->persistent == 2 || (h->persistent == 1 && small))) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (h->timing) {
+            int rc = timed_event_pair(h, 0, &a, &b);
+            if (rc) return rc;
+            (void)hipEventRecord(a, h->stream);
+        }
+        const int waves = (int)std::min<int64_t>(16, (int64_t)h->np * h->L.nchunk);
+        if ((e = launch_persistent(h->d_desc, nullptr, 1, waves, nullptr, n, h->stream)) !=
+            hipSuccess)
+            return hip_fail(e, "persistent kernel");
+        if (h->timing) (void)hipEventRecord(b, h->stream);
+        if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
+            return hip_fail(e, "finish kernel");
+        h->t += n;
+        return QIEO_OK;
+    }
     // stage list of one generation
     int stages[4], nst = 0;
     if (h->pipeline == QIEO_PIPELINE_FUSED) {
@@ -672,7 +694,7 @@ extern "C" int qieo_set_tile(qieo_inst* h, int32_t rows_per_block, int32_t waves
         return set_error(QIEO_EINVAL, "waves_per_block must be in [1, 16] (got %d)",
                          waves_per_block);
     int R, S, F;
-    pick_tile(h->np, h->L.nchunk, &R, &S, &F);
+    if (!tuned_tile(h->np, h->L.nchunk, &R, &S, &F)) pick_tile(h->np, h->L.nchunk, &R, &S, &F);
     h->R = rows_per_block ? rows_per_block : R;
     h->S = waves_per_block ? waves_per_block : S;
     return QIEO_OK;
@@ -733,6 +755,15 @@ extern "C" int qieo_stage_time(qieo_inst* h, int64_t* launches, double* total_ms
             h->total_ms[i] = 0.0;
         }
     }
+    return QIEO_OK;
+}
+
+extern "C" int qieo_set_persistent(qieo_inst* h, int32_t mode)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (mode < 0 || mode > 2) return set_error(QIEO_EINVAL, "mode must be 0, 1 or 2 (got %d)", mode);
+    h->persistent = mode;
     return QIEO_OK;
 }
 

@@ -68,6 +68,13 @@ class qieo_server_stats(ctypes.Structure):
                 ("peak_pool_used", ctypes.c_size_t), ("error", ctypes.c_int32)]
 
 
+class qieo_tune_result(ctypes.Structure):
+    _fields_ = [("rows_per_block", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("ms_per_generation", ctypes.c_double),
+                ("worst_ms_per_generation", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -98,6 +105,16 @@ def _load():
     L.qieo_best.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
     L.qieo_generations.restype = ctypes.c_int
     L.qieo_generations.argtypes = [H, ctypes.POINTER(i64)]
+    L.qieo_autotune.restype = ctypes.c_int
+    L.qieo_autotune.argtypes = [i32, i32, P, i32, i32, ctypes.POINTER(qieo_tune_result)]
+    L.qieo_tune_db_save.restype = ctypes.c_int
+    L.qieo_tune_db_save.argtypes = [ctypes.c_char_p]
+    L.qieo_tune_db_load.restype = ctypes.c_int
+    L.qieo_tune_db_load.argtypes = [ctypes.c_char_p]
+    L.qieo_tune_db_clear.restype = None
+    L.qieo_tune_db_clear.argtypes = []
+    L.qieo_set_persistent.restype = ctypes.c_int
+    L.qieo_set_persistent.argtypes = [H, i32]
     L.qieo_set_pipeline.restype = ctypes.c_int
     L.qieo_set_pipeline.argtypes = [H, i32]
     L.qieo_stage_time.restype = ctypes.c_int
@@ -150,6 +167,8 @@ def _load():
                                          ctypes.POINTER(i32)]
     L.qieo_batch_set_tile.restype = ctypes.c_int
     L.qieo_batch_set_tile.argtypes = [H, i32, i32, i32]
+    L.qieo_batch_set_persistent.restype = ctypes.c_int
+    L.qieo_batch_set_persistent.argtypes = [H, i32]
     L.qieo_batch_set_graph.restype = ctypes.c_int
     L.qieo_batch_set_graph.argtypes = [H, i32]
     L.qieo_batch_destroy.restype = None
@@ -212,6 +231,30 @@ def items_array(values, weights):
 
 
 # --- C-named entry points ---------------------------------------------------
+
+def qieo_autotune(n_items: int, n_pop: int, trial_generations: int = 3, values=None,
+                  weights=None, capacity: int = 0) -> dict:
+    """Times every work shape on a scratch population and records the best."""
+    it = None if values is None else items_array(values, weights)
+    r = qieo_tune_result()
+    _check(lib.qieo_autotune(int(n_items), int(n_pop), _ptr(it), int(capacity),
+                             int(trial_generations), ctypes.byref(r)), "qieo_autotune")
+    return {name: getattr(r, name) for name, _ in qieo_tune_result._fields_}
+
+
+def qieo_tune_db_save(path: str):
+    _check(lib.qieo_tune_db_save(path.encode()), "qieo_tune_db_save")
+
+
+def qieo_tune_db_load(path: str) -> int:
+    n = lib.qieo_tune_db_load(path.encode())
+    _check(min(n, 0), "qieo_tune_db_load")
+    return n
+
+
+def qieo_tune_db_clear():
+    lib.qieo_tune_db_clear()
+
 
 def qieo_create(items: np.ndarray, n_items: int, capacity: int, n_pop: int, seed: int,
                 stream: int | None = None):
@@ -355,6 +398,9 @@ class Instance:
     def set_convergence(self, window: int):
         _check(lib.qieo_set_convergence(self._h, int(window)), "qieo_set_convergence")
 
+    def set_persistent(self, mode: int):
+        _check(lib.qieo_set_persistent(self._h, int(mode)), "qieo_set_persistent")
+
     def set_pipeline(self, pipeline: int):
         _check(lib.qieo_set_pipeline(self._h, int(pipeline)), "qieo_set_pipeline")
 
@@ -485,6 +531,10 @@ class Batch:
 
     def set_convergence(self, window: int):
         _check(lib.qieo_batch_set_convergence(self._h, int(window)), "qieo_batch_set_convergence")
+
+    def set_persistent(self, enabled: bool):
+        _check(lib.qieo_batch_set_persistent(self._h, int(bool(enabled))),
+               "qieo_batch_set_persistent")
 
     def converged(self, i: int):
         c, g = ctypes.c_int32(), ctypes.c_int64()

@@ -64,13 +64,17 @@ def test_batch_matches_oracle_with_uneven_generation_counts(qieo, oracle_mod):
                 assert_state_equal(View(b, k), o, label="batch call %d inst %d" % (call, k))
 
 
-@pytest.mark.parametrize("mode", ["no-graph", "R1S1", "R2S4f3", "R4S16f1"])
+@pytest.mark.parametrize("mode", ["no-graph", "no-persistent", "no-graph-no-persistent", "R1S1",
+                                  "R2S4f3", "R4S16f1"])
 def test_batch_modes_are_identical(qieo, mode):
     insts = _ragged_instances()
     ref = qieo.Batch(_problems(insts))
     alt = qieo.Batch(_problems(insts))
-    if mode == "no-graph":
-        alt.set_graph(False)
+    if mode.startswith("no-"):
+        if "graph" in mode:
+            alt.set_graph(False)
+        if "persistent" in mode:
+            alt.set_persistent(False)
     else:
         R, S = int(mode[1]), int(mode[3:].split("f")[0])
         f = int(mode.split("f")[1]) if "f" in mode else 0

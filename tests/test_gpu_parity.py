@@ -166,3 +166,42 @@ def test_stage_timing(qieo):
     g.step(2)
     st = g.stage_time()
     assert st["de"][0] == 2 and st["de"][1] > 0
+
+
+def test_autotuner_picks_a_shape_used_by_create(qieo, oracle_mod, tmp_path):
+    qieo.qieo_tune_db_clear()
+    r = qieo.qieo_autotune(3000, 48, trial_generations=2)
+    say("autotune 48 x 3000: %s" % r)
+    assert r["candidates"] > 10
+    assert r["ms_per_generation"] <= r["worst_ms_per_generation"]
+    inst = workloads.random_instance(3000, 48, seed=77)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    assert g.tile() == (r["rows_per_block"], r["waves_per_block"])
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.step(6)
+    o.run(6)
+    assert_state_equal(g, o, label="tuned shape")
+    path = str(tmp_path / "tune.json")
+    qieo.qieo_tune_db_save(path)
+    qieo.qieo_tune_db_clear()
+    assert qieo.qieo_tune_db_load(path) == 1
+    qieo.qieo_tune_db_clear()
+
+
+@pytest.mark.parametrize("ng,n_pop", [(100, 16), (700, 37), (3000, 20), (64, 1024), (257, 3)])
+@pytest.mark.parametrize("mode", [0, 2])
+def test_persistent_path_same_trajectory(qieo, oracle_mod, ng, n_pop, mode):
+    """Single-workgroup launches running many generations (mode 2) and
+    per-generation launches (mode 0) both follow the oracle."""
+    inst = workloads.random_instance(ng, n_pop, seed=ng * 3 + n_pop)
+    say("persistent mode %d Ng=%d Np=%d" % (mode, ng, n_pop))
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_persistent(mode)
+    for step in (1, 7, 30):
+        g.step(step)
+        o.run(step)
+        assert_state_equal(g, o, label="persistent %d t=%d" % (mode, o.t))
+    g.set_persistent(2 - mode)          # switching paths between calls is seamless
+    g.step(5)
+    o.run(5)
+    assert_state_equal(g, o, label="persistent switched t=%d" % o.t)

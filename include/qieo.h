@@ -104,6 +104,15 @@ int qieo_create_ex(const qieo_item *items, int32_t n_items, int32_t capacity,
                    int32_t n_pop, uint64_t seed, const qieo_dev_ctx *ctx,
                    qieo_inst **out);
 
+/* As qieo_create_ex with binary64 amplitudes (the paper's precision, Sec. V):
+ * the same steps with binary64 roundings of the same constants (cos and sin
+ * of 0.01 pi, 1/sqrt 2); the uniform draws are unchanged.  Twice the
+ * amplitude memory and traffic.  Such an instance runs the fused pipeline with
+ * per-generation launches; its amplitudes are read with
+ * qieo_export_rows_f64. */
+int qieo_create_f64(const qieo_item *items, int32_t n_items, int32_t capacity,
+                    int32_t n_pop, uint64_t seed, const qieo_dev_ctx *ctx, qieo_inst **out);
+
 /* Runs n_generations full generations (QIP, Evaluation, DetermineElite, CIP;
  * Sec. III-B, Fig. 1) and waits for them.  n_generations >= 0. */
 int qieo_step(qieo_inst *h, int32_t n_generations);
@@ -146,6 +155,12 @@ int qieo_export_rows(qieo_inst *h, int32_t row0, int32_t n_rows,
                      float *alpha, float *beta, uint8_t *alleles,
                      int32_t *fitness, int32_t *profit, int32_t *weight,
                      int32_t *elite);
+
+/* qieo_export_rows for a binary64 instance (alpha, beta as doubles). */
+int qieo_export_rows_f64(qieo_inst *h, int32_t row0, int32_t n_rows,
+                         double *alpha, double *beta, uint8_t *alleles,
+                         int32_t *fitness, int32_t *profit, int32_t *weight,
+                         int32_t *elite);
 
 /* Releases the handle and all its device memory (NULL is ignored). */
 void qieo_destroy(qieo_inst *h);

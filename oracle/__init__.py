@@ -53,6 +53,12 @@ def lib():
         i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         L.oracle_new.restype = P
         L.oracle_new.argtypes = [i32, i32, P, P, i64, u64, i64]
+        L.oracle_new_f64.restype = P
+        L.oracle_new_f64.argtypes = [i32, i32, P, P, i64, u64, i64]
+        L.oracle_cip_gene_f64.restype = ctypes.c_int
+        L.oracle_cip_gene_f64.argtypes = [P, P, ctypes.c_int]
+        L.oracle_get_amplitudes_f64.argtypes = [P, P, P]
+        L.oracle_set_amplitudes_f64.argtypes = [P, P, P]
         L.oracle_free.argtypes = [P]
         L.oracle_set_threads.argtypes = [P, ctypes.c_int]
         for name in ("oracle_qip", "oracle_fe", "oracle_de", "oracle_cip", "oracle_generation"):
@@ -116,6 +122,14 @@ def cip_gene(alpha: float, beta: float, tgt: int):
     return np.float32(a[0]), np.float32(b[0]), bool(r)
 
 
+def cip_gene_f64(alpha: float, beta: float, tgt: int):
+    """CIP on one gene in binary64; returns (alpha', beta', rotated)."""
+    a = np.array([alpha], dtype=np.float64)
+    b = np.array([beta], dtype=np.float64)
+    r = lib().oracle_cip_gene_f64(_ptr(a), _ptr(b), int(tgt))
+    return float(a[0]), float(b[0]), bool(r)
+
+
 @dataclass
 class Best:
     has_best: bool
@@ -131,15 +145,17 @@ class Oracle:
     """One QIEO population on the CPU (see qieo_oracle.c for the readings)."""
 
     def __init__(self, v, w, capacity: int, n_pop: int, seed: int,
-                 lam: int = 1, threads: int = 1):
+                 lam: int = 1, threads: int = 1, precision: int = 32):
         self.v = np.ascontiguousarray(v, dtype=np.int32)
         self.w = np.ascontiguousarray(w, dtype=np.int32)
         self.ng = int(self.v.size)
         self.np_ = int(n_pop)
         self.capacity = int(capacity)
         self.seed = int(seed)
-        h = lib().oracle_new(self.ng, self.np_, _ptr(self.v), _ptr(self.w),
-                             self.capacity, self.seed & (2**64 - 1), int(lam))
+        self.precision = int(precision)
+        new = lib().oracle_new_f64 if self.precision == 64 else lib().oracle_new
+        h = new(self.ng, self.np_, _ptr(self.v), _ptr(self.w),
+                self.capacity, self.seed & (2**64 - 1), int(lam))
         if not h:
             raise ValueError("oracle_new rejected the instance")
         self._h = ctypes.c_void_p(h)
@@ -187,15 +203,19 @@ class Oracle:
         return int(lib().oracle_elite(self._h))
 
     def amplitudes(self):
-        a = np.empty((self.np_, self.ng), dtype=np.float32)
-        b = np.empty((self.np_, self.ng), dtype=np.float32)
-        lib().oracle_get_amplitudes(self._h, _ptr(a), _ptr(b))
+        dt = np.float64 if self.precision == 64 else np.float32
+        a = np.empty((self.np_, self.ng), dtype=dt)
+        b = np.empty((self.np_, self.ng), dtype=dt)
+        get = lib().oracle_get_amplitudes_f64 if self.precision == 64 else lib().oracle_get_amplitudes
+        get(self._h, _ptr(a), _ptr(b))
         return a, b
 
     def set_amplitudes(self, alpha, beta):
-        a = np.ascontiguousarray(alpha, dtype=np.float32).reshape(self.np_, self.ng)
-        b = np.ascontiguousarray(beta, dtype=np.float32).reshape(self.np_, self.ng)
-        lib().oracle_set_amplitudes(self._h, _ptr(a), _ptr(b))
+        dt = np.float64 if self.precision == 64 else np.float32
+        a = np.ascontiguousarray(alpha, dtype=dt).reshape(self.np_, self.ng)
+        b = np.ascontiguousarray(beta, dtype=dt).reshape(self.np_, self.ng)
+        put = lib().oracle_set_amplitudes_f64 if self.precision == 64 else lib().oracle_set_amplitudes
+        put(self._h, _ptr(a), _ptr(b))
 
     def alleles(self) -> np.ndarray:
         x = np.empty((self.np_, self.ng), dtype=np.uint8)

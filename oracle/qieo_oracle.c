@@ -27,8 +27,13 @@
  *       counter {i/4, c, t, 0} and key {seed_lo, seed_hi}; gene i uses word
  *       i mod 4 of its call.
  *
- * Every floating-point operation below is one IEEE-754 binary32 operation
- * rounded to nearest (build with -ffp-contract=off, no fast-math, SSE).
+ *   R8  (binary64 variant, the paper's precision, Sec. V) the same steps on
+ *       binary64 amplitudes with binary64 roundings of the same constants;
+ *       the uniform draw stays the 24-bit value of R1.
+ *
+ * Every floating-point operation below is one IEEE-754 operation of the
+ * amplitude precision, rounded to nearest (build with -ffp-contract=off, no
+ * fast-math, SSE).
  *
  * Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
  * load this code.  The GPU library shares nothing with it.
@@ -101,6 +106,11 @@ float oracle_uniform(uint64_t seed, int64_t t, int64_t c, int64_t i)
 #define ROT_S  0x1.015122p-5f
 #define AMP0   0x1.6a09e6p-1f
 
+/* binary64 roundings (correctly rounded) of the same three constants */
+#define ROT_C64 0x1.ffbf52e9d1086p-1
+#define ROT_S64 0x1.015122df75860p-5
+#define AMP0_64 0x1.6a09e667f3bcdp-1
+
 /* CIP on one gene (readings R3, R4).  tgt is the elite's allele b[i].
  * Returns 1 if the gene was rotated, 0 if the zero-product rule skipped it. */
 int oracle_cip_gene(float *alpha, float *beta, int tgt)
@@ -128,6 +138,30 @@ int oracle_cip_gene(float *alpha, float *beta, int tgt)
     return 1;
 }
 
+/* The same gate in binary64 (reading R8). */
+int oracle_cip_gene_f64(double *alpha, double *beta, int tgt)
+{
+    double a = *alpha, b = *beta;
+    double p = a * b;
+    double sd;
+    if (p > 0.0) {
+        sd = tgt ? ROT_S64 : -ROT_S64;
+    } else if (p < 0.0) {
+        sd = tgt ? -ROT_S64 : ROT_S64;
+    } else {
+        if ((tgt && a == 0.0) || (!tgt && b == 0.0))
+            return 0;
+        sd = ROT_S64;
+    }
+    double a1 = ROT_C64 * a - sd * b;
+    double b1 = sd * a + ROT_C64 * b;
+    double n = a1 * a1 + b1 * b1;
+    double g = 1.5 - 0.5 * n;
+    *alpha = a1 * g;
+    *beta = b1 * g;
+    return 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* State.                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -148,6 +182,8 @@ typedef struct oracle {
     int threads;
     int64_t *elite_f;   /* elite fitness of every completed generation */
     int64_t elite_cap;
+    int f64;            /* binary64 amplitudes (reading R8) */
+    double *alpha_d, *beta_d;
 } oracle;
 
 void oracle_free(oracle *s)
@@ -155,6 +191,7 @@ void oracle_free(oracle *s)
     if (!s) return;
     free(s->v); free(s->w); free(s->alpha); free(s->beta); free(s->x);
     free(s->P); free(s->W); free(s->fit); free(s->best_x); free(s->elite_f);
+    free(s->alpha_d); free(s->beta_d);
     free(s);
 }
 
@@ -192,6 +229,26 @@ oracle *oracle_new(int32_t ng, int32_t np, const int32_t *v, const int32_t *w,
     return s;
 }
 
+/* The binary64 variant: same problem, amplitudes fl64(1/sqrt 2). */
+oracle *oracle_new_f64(int32_t ng, int32_t np, const int32_t *v, const int32_t *w,
+                       int64_t cap, uint64_t seed, int64_t lambda)
+{
+    oracle *s = oracle_new(ng, np, v, w, cap, seed, lambda);
+    if (!s) return NULL;
+    size_t n = (size_t)ng * (size_t)np;
+    s->alpha_d = (double *)malloc(sizeof(double) * n);
+    s->beta_d = (double *)malloc(sizeof(double) * n);
+    if (!s->alpha_d || !s->beta_d) {
+        oracle_free(s);
+        return NULL;
+    }
+    free(s->alpha); free(s->beta);
+    s->alpha = NULL; s->beta = NULL;
+    for (size_t k = 0; k < n; ++k) { s->alpha_d[k] = AMP0_64; s->beta_d[k] = AMP0_64; }
+    s->f64 = 1;
+    return s;
+}
+
 void oracle_set_threads(oracle *s, int threads) { s->threads = threads < 1 ? 1 : threads; }
 
 /* QIP (Sec. III-B): observe every qubit of every chromosome (reading R1, R2). */
@@ -207,9 +264,16 @@ void oracle_qip(oracle *s)
             for (int j = 0; j < 4; ++j) {
                 int64_t i = 4 * k + j;
                 if (i >= ng) break;
-                float b = s->beta[c * ng + i];
-                float b2 = b * b;
-                s->x[c * ng + i] = (uniform24(r[j]) < b2) ? 1 : 0;
+                if (s->f64) {
+                    double b = s->beta_d[c * ng + i];
+                    double b2 = b * b;
+                    double u = (double)(r[j] >> 8) * 0x1p-24;
+                    s->x[c * ng + i] = (u < b2) ? 1 : 0;
+                } else {
+                    float b = s->beta[c * ng + i];
+                    float b2 = b * b;
+                    s->x[c * ng + i] = (uniform24(r[j]) < b2) ? 1 : 0;
+                }
             }
         }
     }
@@ -273,7 +337,10 @@ void oracle_cip(oracle *s)
         if (!(s->fit[c] < fe)) continue;
         for (int64_t i = 0; i < ng; ++i) {
             if (s->x[c * ng + i] == b[i]) continue;
-            oracle_cip_gene(&s->alpha[c * ng + i], &s->beta[c * ng + i], b[i]);
+            if (s->f64)
+                oracle_cip_gene_f64(&s->alpha_d[c * ng + i], &s->beta_d[c * ng + i], b[i]);
+            else
+                oracle_cip_gene(&s->alpha[c * ng + i], &s->beta[c * ng + i], b[i]);
         }
     }
 }
@@ -324,9 +391,26 @@ int64_t oracle_run_until_converged(oracle *s, int64_t n, int window)
 /* ------------------------------------------------------------------------ */
 /* Accessors (copies into caller-owned buffers; any pointer may be NULL).   */
 /* ------------------------------------------------------------------------ */
+void oracle_get_amplitudes_f64(const oracle *s, double *alpha, double *beta)
+{
+    size_t n = (size_t)s->ng * (size_t)s->np;
+    if (!s->f64) return;
+    if (alpha) memcpy(alpha, s->alpha_d, n * sizeof(double));
+    if (beta) memcpy(beta, s->beta_d, n * sizeof(double));
+}
+
+void oracle_set_amplitudes_f64(oracle *s, const double *alpha, const double *beta)
+{
+    size_t n = (size_t)s->ng * (size_t)s->np;
+    if (!s->f64) return;
+    if (alpha) memcpy(s->alpha_d, alpha, n * sizeof(double));
+    if (beta) memcpy(s->beta_d, beta, n * sizeof(double));
+}
+
 void oracle_get_amplitudes(const oracle *s, float *alpha, float *beta)
 {
     size_t n = (size_t)s->ng * (size_t)s->np;
+    if (s->f64) return;
     if (alpha) memcpy(alpha, s->alpha, n * sizeof(float));
     if (beta) memcpy(beta, s->beta, n * sizeof(float));
 }
@@ -334,6 +418,7 @@ void oracle_get_amplitudes(const oracle *s, float *alpha, float *beta)
 void oracle_set_amplitudes(oracle *s, const float *alpha, const float *beta)
 {
     size_t n = (size_t)s->ng * (size_t)s->np;
+    if (s->f64) return;
     if (alpha) memcpy(s->alpha, alpha, n * sizeof(float));
     if (beta) memcpy(s->beta, beta, n * sizeof(float));
 }

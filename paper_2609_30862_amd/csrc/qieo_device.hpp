@@ -19,6 +19,17 @@ constexpr float kCos = 0x1.ffbf52p-1f;
 constexpr float kSin = 0x1.015122p-5f;
 constexpr float kAmp0 = 0x1.6a09e6p-1f;
 
+// The same three constants for binary64 amplitudes: correctly rounded
+// binary64 values of cos(0.01 pi), sin(0.01 pi) and 1/sqrt(2).
+template <typename T> struct Gate;
+template <> struct Gate<float> {
+    static constexpr float c = 0x1.ffbf52p-1f, s = 0x1.015122p-5f, a0 = 0x1.6a09e6p-1f;
+};
+template <> struct Gate<double> {
+    static constexpr double c = 0x1.ffbf52e9d1086p-1, s = 0x1.015122df75860p-5,
+                            a0 = 0x1.6a09e667f3bcdp-1;
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform (it is the
 // instance seed) and so is every round's key; counter word 0 is the only
@@ -55,11 +66,13 @@ __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return Draw4{c0, c1, c2, c3};
 }
 
-// Observation of one qubit: 1 iff the 24-bit uniform of r lies below beta^2.
-__device__ __forceinline__ bool observe(uint32_t r, float beta)
+// Observation of one qubit: 1 iff the 24-bit uniform of r lies below beta^2
+// (the uniform is exact in either precision).
+template <typename T>
+__device__ __forceinline__ bool observe(uint32_t r, T beta)
 {
-    const float u = (float)(r >> 8) * 0x1p-24f;
-    const float b2 = beta * beta;
+    const T u = (T)(r >> 8) * (T)0x1p-24;
+    const T b2 = beta * beta;
     return u < b2;
 }
 
@@ -82,6 +95,17 @@ __device__ __forceinline__ float sel(uint64_t m, float if0, float if1)
     return r;
 }
 
+__device__ __forceinline__ double sel(uint64_t m, double if0, double if1)
+{
+    const uint64_t a = __builtin_bit_cast(uint64_t, if0), b = __builtin_bit_cast(uint64_t, if1);
+    uint32_t lo, hi;
+    const uint64_t mm = uniform_mask(m);
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(lo) : "v"((uint32_t)a), "v"((uint32_t)b), "s"(mm));
+    asm("v_cndmask_b32 %0, %1, %2, %3"
+        : "=v"(hi) : "v"((uint32_t)(a >> 32)), "v"((uint32_t)(b >> 32)), "s"(mm));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // Memory helpers.  Streams of the amplitude planes use global (address space
 // 1) vector loads/stores from a wave-uniform row base plus a 32-bit per-lane
@@ -93,7 +117,11 @@ __device__ __forceinline__ float sel(uint64_t m, float if0, float if1)
 #define QIEO_AS_CONST __attribute__((address_space(4)))
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef f32x4 type; };
+template <> struct Vec4<double> { typedef f64x4 type; };
 
 template <typename T>
 __device__ __forceinline__ T gload(const T* base, uint32_t idx)
@@ -140,30 +168,32 @@ __device__ __forceinline__ uint64_t load_mask(const uint64_t* p)
 // steps by +0.01 pi unless the gene already sits on the target pole.  The
 // Newton factor g = 1.5 - 0.5 n pulls the norm back to 1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void cip_gene(float& a, float& b, uint64_t rot, uint64_t tgt)
+template <typename T>
+__device__ __forceinline__ void cip_gene(T& a, T& b, uint64_t rot, uint64_t tgt)
 {
-    const float p = a * b;
-    const float sdp = sel(tgt, -kSin, kSin);          // step for p > 0
-    const float sdn = sel(tgt, kSin, -kSin);          // step for p < 0
-    float sd = (p > 0.0f) ? sdp : kSin;
-    sd = (p < 0.0f) ? sdn : sd;
+    constexpr T kC = Gate<T>::c, kS = Gate<T>::s;
+    const T p = a * b;
+    const T sdp = sel(tgt, -kS, kS);          // step for p > 0
+    const T sdn = sel(tgt, kS, -kS);          // step for p < 0
+    T sd = (p > (T)0) ? sdp : kS;
+    sd = (p < (T)0) ? sdn : sd;
     // already on the target pole: target 1 with alpha == 0, target 0 with beta == 0
-    const float pole = sel(tgt, b, a);
-    const uint64_t skip = ballot(pole == 0.0f);
+    const T pole = sel(tgt, b, a);
+    const uint64_t skip = ballot(pole == (T)0);
     const uint64_t mv = rot & ~skip;
-    const float ca = kCos * a;
-    const float sb = sd * b;
-    const float a1 = ca - sb;
-    const float sa = sd * a;
-    const float cb = kCos * b;
-    const float b1 = sa + cb;
-    const float aa = a1 * a1;
-    const float bb = b1 * b1;
-    const float n = aa + bb;
-    const float hn = 0.5f * n;
-    const float g = 1.5f - hn;
-    const float a2 = a1 * g;
-    const float b2 = b1 * g;
+    const T ca = kC * a;
+    const T sb = sd * b;
+    const T a1 = ca - sb;
+    const T sa = sd * a;
+    const T cb = kC * b;
+    const T b1 = sa + cb;
+    const T aa = a1 * a1;
+    const T bb = b1 * b1;
+    const T n = aa + bb;
+    const T hn = (T)0.5 * n;
+    const T g = (T)1.5 - hn;
+    const T a2 = a1 * g;
+    const T b2 = b1 * g;
     a = sel(mv, a, a2);
     b = sel(mv, b, b2);
 }

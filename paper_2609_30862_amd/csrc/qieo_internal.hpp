@@ -24,12 +24,14 @@ int set_error(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 void clear_error();
 
-size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L);
+// elem: bytes per amplitude (4 binary32, 8 binary64)
+size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem = 4);
 InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
                    uint64_t seed);
 int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop);
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
-                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging);
+                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging,
+                    bool f64 = false);
 int check_device();
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 // Shape from the autotuner's database, if the bucket was tuned.
@@ -37,8 +39,9 @@ bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
               uint32_t* bits, size_t n_words);
 int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
-                int32_t row0, int32_t n_rows, float* alpha, float* beta, uint8_t* alleles,
-                int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite);
+                int32_t row0, int32_t n_rows, void* alpha, void* beta, uint8_t* alleles,
+                int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite,
+                bool f64 = false);
 int read_generations(const InstDev& d, hipStream_t s, int64_t* t);
 int read_convergence(const InstDev& d, hipStream_t s, int32_t* converged, int64_t* generation);
 int write_window(const InstDev& d, hipStream_t s, int32_t window);

@@ -82,15 +82,18 @@ __device__ void best_update(const InstDev& I, int64_t tg, int32_t e, int32_t fe,
 // Initial state: every real gene (alpha, beta) = (1/sqrt2, 1/sqrt2); padding
 // genes (1, 0).
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ void init_kernel(InstDev I)
 {
     const size_t n = (size_t)I.np * I.pitch;
+    T* alpha = reinterpret_cast<T*>(I.alpha);
+    T* beta = reinterpret_cast<T*>(I.beta);
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (size_t)gridDim.x * blockDim.x) {
         const int g = (int)(k % (size_t)I.pitch);
         const bool real = g < I.ng;
-        I.alpha[k] = real ? kAmp0 : 1.0f;
-        I.beta[k] = real ? kAmp0 : 0.0f;
+        alpha[k] = real ? Gate<T>::a0 : (T)1;
+        beta[k] = real ? Gate<T>::a0 : (T)0;
     }
 }
 
@@ -102,7 +105,7 @@ __global__ void init_kernel(InstDev I)
 // MODE selects the steps one launch performs (kStepAll = the fused
 // generation); the unfused pipeline runs kStepCip, kStepQip and kStepFe as
 // three launches, then DetermineElite by de_kernel or on the host.
-template <int R, bool PF, bool NT, int MODE>
+template <typename T, int R, bool PF, bool NT, int MODE>
 __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
                                                          const Tile* __restrict__ tiles, int k,
                                                          const int32_t* __restrict__ gens_arr,
@@ -178,15 +181,16 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
     if (stop) return;
 
     const int nrows = min(R, np - (int)row0);
+    typedef typename Vec4<T>::type V4;
     bool rot[R];
-    const f32x4* arow[R];
-    const f32x4* brow4[R];
+    const V4* arow[R];
+    const V4* brow4[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         rot[r] = kCip && pending && r < nrows && sload(I.fit + (par ^ 1) * np + row0 + r) < fe_prev;
         const size_t base = (size_t)(row0 + (r < nrows ? r : 0)) * I.pitch;
-        arow[r] = (const f32x4*)(I.alpha + base);
-        brow4[r] = (const f32x4*)(I.beta + base);
+        arow[r] = (const V4*)(reinterpret_cast<const T*>(I.alpha) + base);
+        brow4[r] = (const V4*)(reinterpret_cast<const T*>(I.beta) + base);
     }
 
     uint32_t accP[R], accW[R];
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
     // alpha only for rows that rotate (CIP).  Lanes past the row end (only in
     // a row's last chunk) read the slack after the plane or the next row;
     // their alleles are masked to 0 and their stores skipped.
-    f32x4 nb[R], na[R];
+    V4 nb[R], na[R];
     auto load_chunk = [&](int chx) {
         const uint32_t qx = (uint32_t)chx * (kChunk / 4) + lane;
 #pragma unroll
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
         const bool act = g0 < (uint32_t)I.pitch;
         const uint32_t q = g0 >> 2;          // float4 / int4 index in a row
-        f32x4 cb[R], ca[R];
+        V4 cb[R], ca[R];
         if (PF) {
 #pragma unroll
             for (int r = 0; r < R; ++r) { cb[r] = nb[r]; ca[r] = na[r]; }
@@ -241,21 +245,21 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         for (int r = 0; r < R; ++r) {
             if (r >= nrows) break;
             const int c = (int)row0 + r;
-            f32x4 b4 = cb[r];
-            f32x4 a4 = ca[r];
+            V4 b4 = cb[r];
+            V4 a4 = ca[r];
             if (rot[r]) {
                 const uint64_t* xw =
                     reinterpret_cast<const uint64_t*>(xprev + (size_t)c * wpr + ch * kWordsPerChunk);
                 const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
                 const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
-                float a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
-                float b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
+                T a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
+                T b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
                 cip_gene(a0, b0, xm0 ^ bm0, bm0);
                 cip_gene(a1, b1, xm1 ^ bm1, bm1);
                 cip_gene(a2, b2, xm2 ^ bm2, bm2);
                 cip_gene(a3, b3, xm3 ^ bm3, bm3);
-                a4 = f32x4{a0, a1, a2, a3};
-                b4 = f32x4{b0, b1, b2, b3};
+                a4 = V4{a0, a1, a2, a3};
+                b4 = V4{b0, b1, b2, b3};
             }
             bool x0 = false, x1 = false, x2 = false, x3 = false;
             if (kQip) {
@@ -290,11 +294,11 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
             }
             if (rot[r] && act) {
                 if (NT) {
-                    gstore_nt((f32x4*)arow[r], q, a4);
-                    gstore_nt((f32x4*)brow4[r], q, b4);
+                    gstore_nt((V4*)arow[r], q, a4);
+                    gstore_nt((V4*)brow4[r], q, b4);
                 } else {
-                    gstore((f32x4*)arow[r], q, a4);
-                    gstore((f32x4*)brow4[r], q, b4);
+                    gstore((V4*)arow[r], q, a4);
+                    gstore((V4*)brow4[r], q, b4);
                 }
             }
         }
@@ -676,8 +680,9 @@ __global__ void finish_kernel(const InstDev* __restrict__ insts,
 // amplitudes with CIP(t-1) applied (state untouched), alleles and fitness of
 // t-1.  Block = 256 threads = 4 waves, one gene per thread.
 // ---------------------------------------------------------------------------
-__global__ void export_kernel(const InstDev* __restrict__ insts, int row0, float* alpha,
-                              float* beta, uint8_t* alleles)
+template <typename T>
+__global__ void export_kernel(const InstDev* __restrict__ insts, int row0, T* alpha, T* beta,
+                              uint8_t* alleles)
 {
     const InstDev I = insts[0];
     const int64_t t = *I.tbase;
@@ -686,8 +691,8 @@ __global__ void export_kernel(const InstDev* __restrict__ insts, int row0, float
     const bool act = g < I.ng;
     const int wpr = I.nchunk * kWordsPerChunk;
     const size_t src = (size_t)c * I.pitch + (act ? g : 0);
-    float a = act ? I.alpha[src] : 1.0f;
-    float b = act ? I.beta[src] : 0.0f;
+    T a = act ? reinterpret_cast<const T*>(I.alpha)[src] : (T)1;
+    T b = act ? reinterpret_cast<const T*>(I.beta)[src] : (T)0;
     bool x = false, bel = false, rot = false;
     if (t > 0 && act) {
         const int par = (int)((t - 1) & 1);
@@ -746,12 +751,15 @@ __global__ void bits_unpack_kernel(const uint32_t* __restrict__ src, int ng, uin
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_init(const InstDev& I, hipStream_t s)
+hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64)
 {
     const size_t n = (size_t)I.np * I.pitch;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(init_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I);
+    if (f64)
+        hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, I);
+    else
+        hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, I);
     return hipGetLastError();
 }
 
@@ -763,8 +771,36 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
 #define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
-    hipLaunchKernelGGL((generation_kernel<RR, PFF, NTT, kStepAll>), grid, block, 0, s, dI,     \
-                       tiles, k, gens_arr, gens_all)
+    hipLaunchKernelGGL((generation_kernel<float, RR, PFF, NTT, kStepAll>), grid, block, 0, s,  \
+                       dI, tiles, k, gens_arr, gens_all)
+#define QIEO_LAUNCH_R(RR)                                                                      \
+    switch (flags & 3) {                                                                       \
+    case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
+    case 1: QIEO_LAUNCH(RR, true, false); break;                                               \
+    case 2: QIEO_LAUNCH(RR, false, true); break;                                               \
+    default: QIEO_LAUNCH(RR, true, true); break;                                               \
+    }
+    switch (rows_per_block) {
+    case 1: QIEO_LAUNCH_R(1); break;
+    case 2: QIEO_LAUNCH_R(2); break;
+    case 4: QIEO_LAUNCH_R(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef QIEO_LAUNCH_R
+#undef QIEO_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_block,
+                                 int waves_per_block, int flags, int k, int gens_all,
+                                 hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
+#define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
+    hipLaunchKernelGGL((generation_kernel<double, RR, PFF, NTT, kStepAll>), grid, block, 0, s, \
+                       dI, (const Tile*)nullptr, k, (const int32_t*)nullptr, gens_all)
 #define QIEO_LAUNCH_R(RR)                                                                      \
     switch (flags & 3) {                                                                       \
     case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
@@ -794,7 +830,7 @@ hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int
         return hipGetLastError();
     }
 #define QIEO_STAGE(RR, MM)                                                                     \
-    hipLaunchKernelGGL((generation_kernel<RR, false, true, MM>), grid, block, 0, s, dI,        \
+    hipLaunchKernelGGL((generation_kernel<float, RR, false, true, MM>), grid, block, 0, s, dI, \
                        (const Tile*)nullptr, k, (const int32_t*)nullptr, gens)
 #define QIEO_STAGE_R(RR)                                                                       \
     switch (stage) {                                                                           \
@@ -824,14 +860,19 @@ hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr,
     return hipGetLastError();
 }
 
-hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng, float* alpha,
-                         float* beta, uint8_t* alleles, int32_t* fit, int32_t* prof,
-                         int32_t* wt, hipStream_t s)
+hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng, void* alpha,
+                         void* beta, uint8_t* alleles, int32_t* fit, int32_t* prof,
+                         int32_t* wt, bool f64, hipStream_t s)
 {
     if (n_rows <= 0) return hipSuccess;
     if (alpha || beta || alleles) {
         const dim3 grid((unsigned)((ng + 255) / 256), (unsigned)n_rows);
-        hipLaunchKernelGGL(export_kernel, grid, dim3(256), 0, s, dI, row0, alpha, beta, alleles);
+        if (f64)
+            hipLaunchKernelGGL(export_kernel<double>, grid, dim3(256), 0, s, dI, row0,
+                               (double*)alpha, (double*)beta, alleles);
+        else
+            hipLaunchKernelGGL(export_kernel<float>, grid, dim3(256), 0, s, dI, row0,
+                               (float*)alpha, (float*)beta, alleles);
     }
     if (fit || prof || wt)
         hipLaunchKernelGGL(export_rows_kernel, dim3((unsigned)((n_rows + 255) / 256)), dim3(256),

@@ -13,7 +13,8 @@ constexpr int kChunk = 256;
 // lanes), stored as eight 32-bit words.
 constexpr int kWordsPerChunk = 8;
 
-// Device-side description of one resident population.  All arrays live in
+// Device-side description of one resident population.  alpha and beta are
+// typed float*; a binary64 instance stores doubles there (element size 8).  All arrays live in
 // device memory; the struct itself is read by the kernels from a device copy.
 //
 // Layout (pitch = genes per row rounded up to 64, nchunk = ceil(pitch/256)):
@@ -62,7 +63,7 @@ struct Tile {
 };
 
 // Host-side launchers (qieo_kernels.hip).
-hipError_t launch_init(const InstDev& I, hipStream_t s);
+hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
 // gens_arr (device, one entry per instance) or, when NULL, gens_all gives the
 // number of generations each instance runs in the current call; launch k
 // (0-based) skips instances with gens <= k.
@@ -98,8 +99,12 @@ hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr,
                          int64_t* status, hipStream_t s);
 constexpr int kConvRing = 32;      // longest convergence window
 hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng,
-                         float* alpha, float* beta, uint8_t* alleles,
-                         int32_t* fit, int32_t* prof, int32_t* wt, hipStream_t s);
+                         void* alpha, void* beta, uint8_t* alleles,
+                         int32_t* fit, int32_t* prof, int32_t* wt, bool f64, hipStream_t s);
+// binary64 amplitudes (alpha, beta planes hold doubles): fused launch only.
+hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_block,
+                                 int waves_per_block, int flags, int k, int gens_all,
+                                 hipStream_t s);
 hipError_t launch_bits_unpack(const uint32_t* src_words, int ng, uint32_t* dst_words,
                               hipStream_t s);
 

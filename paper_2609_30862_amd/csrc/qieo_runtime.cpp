@@ -50,7 +50,7 @@ void clear_error() { g_last_error.clear(); }
 // ---------------------------------------------------------------------------
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L)
+size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem)
 {
     const int32_t pitch = (int32_t)align_up((size_t)ng, 64);
     const int32_t nchunk = (pitch + kChunk - 1) / kChunk;
@@ -63,8 +63,8 @@ size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L)
     };
     L->pitch = pitch;
     L->nchunk = nchunk;
-    L->alpha = take(((size_t)np * pitch + kChunk) * sizeof(float));
-    L->beta = take(((size_t)np * pitch + kChunk) * sizeof(float));
+    L->alpha = take(((size_t)np * pitch + kChunk) * (size_t)elem);
+    L->beta = take(((size_t)np * pitch + kChunk) * (size_t)elem);
     L->xbits = take(2 * (size_t)np * wpr * sizeof(uint32_t));
     L->v = take((size_t)nchunk * kChunk * sizeof(int32_t));
     L->w = take((size_t)nchunk * kChunk * sizeof(int32_t));
@@ -133,7 +133,7 @@ int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, 
 
 // Upload item tables (zero-padded to pitch) and initialise the state.
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
-                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging)
+                    const ArenaLayout& L, char* base, std::vector<int32_t>& staging, bool f64)
 {
     const size_t pitch = (size_t)d.nchunk * kChunk;   // v, w are zero-padded to whole chunks
     staging.assign(2 * pitch, 0);
@@ -150,7 +150,7 @@ int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
     if ((e = hipMemcpyAsync(base + L.w, staging.data() + pitch, pitch * sizeof(int32_t),
                             hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(w)");
-    if ((e = launch_init(d, s)) != hipSuccess) return hip_fail(e, "init kernel");
+    if ((e = launch_init(d, s, f64)) != hipSuccess) return hip_fail(e, "init kernel");
     return QIEO_OK;
 }
 
@@ -210,6 +210,7 @@ struct qieo_inst {
     int64_t t = 0;               // generations enqueued so far
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
+    bool f64 = false;            // binary64 amplitudes
     int persistent = 1;          // 0 never, 1 when small enough, 2 whenever rows fit
     int32_t window = 0;
     int32_t* h_fit = nullptr;                // pinned, host DetermineElite
@@ -254,9 +255,9 @@ static void inst_release(qieo_inst* h)
     delete h;
 }
 
-extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t capacity,
-                              int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx,
-                              qieo_inst** out)
+static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity,
+                       int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx, bool f64,
+                       qieo_inst** out)
 {
     clear_error();
     if (!out) return set_error(QIEO_EINVAL, "out is NULL");
@@ -289,7 +290,8 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
     h->np = n_pop;
     h->capacity = capacity;
     h->seed = seed;
-    arena_layout(n_items, n_pop, &h->L);
+    h->f64 = f64;
+    arena_layout(n_items, n_pop, &h->L, f64 ? 8 : 4);
     h->arena = (char*)dev_alloc(h, h->L.total);
     h->d_desc = (InstDev*)dev_alloc(h, sizeof(InstDev));
     if (!h->arena || !h->d_desc) {
@@ -304,7 +306,7 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
     }
     h->d = bind_arena(h->arena, h->L, n_items, n_pop, capacity, seed);
     std::vector<int32_t> staging;
-    if ((rc = upload_and_init(h->d, items, h->stream, h->L, h->arena, staging))) {
+    if ((rc = upload_and_init(h->d, items, h->stream, h->L, h->arena, staging, f64))) {
         inst_release(h);
         return rc;
     }
@@ -315,8 +317,13 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
         inst_release(h);
         return rc;
     }
-    if (!tuned_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags))
+    if (f64 || !tuned_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags))
         pick_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags);
+    if (f64) {
+        // twice the registers per gene: at most 2 rows per workgroup
+        h->R = std::min(h->R, 2);
+        h->persistent = 0;
+    }
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         rc = hip_fail(e, "hipStreamSynchronize");
         inst_release(h);
@@ -326,10 +333,24 @@ extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t c
     return QIEO_OK;
 }
 
+extern "C" int qieo_create_ex(const qieo_item* items, int32_t n_items, int32_t capacity,
+                              int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx,
+                              qieo_inst** out)
+{
+    return create_impl(items, n_items, capacity, n_pop, seed, ctx, false, out);
+}
+
+extern "C" int qieo_create_f64(const qieo_item* items, int32_t n_items, int32_t capacity,
+                               int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx,
+                               qieo_inst** out)
+{
+    return create_impl(items, n_items, capacity, n_pop, seed, ctx, true, out);
+}
+
 extern "C" int qieo_create(const qieo_item* items, int32_t n_items, int32_t capacity,
                            int32_t n_pop, uint64_t seed, qieo_inst** out)
 {
-    return qieo_create_ex(items, n_items, capacity, n_pop, seed, nullptr, out);
+    return create_impl(items, n_items, capacity, n_pop, seed, nullptr, false, out);
 }
 
 static int timed_event_pair(qieo_inst* h, int stage, hipEvent_t* a, hipEvent_t* b)
@@ -396,6 +417,24 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         return set_error(QIEO_EINVAL, "generation index would exceed 2^31-1");
     hipError_t e;
     const int blocks = (h->np + h->R - 1) / h->R;
+    if (h->f64) {
+        for (int32_t k = 0; k < n; ++k) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (h->timing) {
+                int rc = timed_event_pair(h, 0, &a, &b);
+                if (rc) return rc;
+                (void)hipEventRecord(a, h->stream);
+            }
+            if ((e = launch_generation_f64(h->d_desc, blocks, h->R, h->S, h->flags, k, n,
+                                           h->stream)) != hipSuccess)
+                return hip_fail(e, "generation kernel (binary64)");
+            if (h->timing) (void)hipEventRecord(b, h->stream);
+        }
+        if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
+            return hip_fail(e, "finish kernel");
+        h->t += n;
+        return QIEO_OK;
+    }
     // small populations: the whole call in one single-workgroup launch
     const bool small = (int64_t)h->np * h->L.pitch <= kPersistentMaxGenes;
     if (h->pipeline == QIEO_PIPELINE_FUSED && h->np <= kPersistentMaxRows &&
@@ -594,8 +633,8 @@ int write_window(const InstDev& d, hipStream_t s, int32_t window)
 }
 
 int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
-                int32_t row0, int32_t n_rows, float* alpha, float* beta, uint8_t* alleles,
-                int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite)
+                int32_t row0, int32_t n_rows, void* alpha, void* beta, uint8_t* alleles,
+                int32_t* fitness, int32_t* profit, int32_t* weight, int32_t* elite, bool f64)
 {
     if (row0 < 0 || n_rows < 0 || (int64_t)row0 + n_rows > d.np)
         return set_error(QIEO_EINVAL, "rows [%d, %d) outside [0, %d)", row0, row0 + n_rows, d.np);
@@ -617,7 +656,7 @@ int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
     if (n_rows == 0) return QIEO_OK;
     const size_t per = (size_t)n_rows * d.ng;
     // device staging only for the outputs asked for
-    const size_t amp_bytes = per * sizeof(float);
+    const size_t amp_bytes = per * (f64 ? sizeof(double) : sizeof(float));
     const size_t row_bytes = (size_t)n_rows * sizeof(int32_t);
     size_t off = 0;
     auto reserve = [&](bool want, size_t n) {
@@ -637,13 +676,13 @@ int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
     if (!tmp.p) return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", off);
     char* base = (char*)tmp.p;
     auto at = [&](size_t o) { return o == (size_t)-1 ? nullptr : base + o; };
-    float* da = (float*)at(o_a);
-    float* db = (float*)at(o_b);
+    void* da = at(o_a);
+    void* db = at(o_b);
     uint8_t* dx = (uint8_t*)at(o_x);
     int32_t* dfit = (int32_t*)at(o_f);
     int32_t* dprof = (int32_t*)at(o_p);
     int32_t* dwt = (int32_t*)at(o_w);
-    if ((e = launch_export(d_desc, row0, n_rows, d.ng, da, db, dx, dfit, dprof, dwt, s)) !=
+    if ((e = launch_export(d_desc, row0, n_rows, d.ng, da, db, dx, dfit, dprof, dwt, f64, s)) !=
         hipSuccess)
         return hip_fail(e, "export kernel");
     struct { void* dst; const void* src; size_t n; } cp[] = {
@@ -677,8 +716,22 @@ extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, floa
 {
     clear_error();
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (h->f64 && (alpha || beta))
+        return set_error(QIEO_EINVAL, "binary64 instance: use qieo_export_rows_f64");
     return export_rows(h->d, h->d_desc, h->stream, row0, n_rows, alpha, beta, alleles,
-                       fitness, profit, weight, elite);
+                       fitness, profit, weight, elite, false);
+}
+
+extern "C" int qieo_export_rows_f64(qieo_inst* h, int32_t row0, int32_t n_rows, double* alpha,
+                                    double* beta, uint8_t* alleles, int32_t* fitness,
+                                    int32_t* profit, int32_t* weight, int32_t* elite)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (!h->f64 && (alpha || beta))
+        return set_error(QIEO_EINVAL, "binary32 instance: use qieo_export_rows");
+    return export_rows(h->d, h->d_desc, h->stream, row0, n_rows, alpha, beta, alleles,
+                       fitness, profit, weight, elite, true);
 }
 
 extern "C" void qieo_destroy(qieo_inst* h) { inst_release(h); }
@@ -763,6 +816,8 @@ extern "C" int qieo_set_persistent(qieo_inst* h, int32_t mode)
     clear_error();
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
     if (mode < 0 || mode > 2) return set_error(QIEO_EINVAL, "mode must be 0, 1 or 2 (got %d)", mode);
+    if (h->f64 && mode != 0)
+        return set_error(QIEO_ESTATE, "binary64 instances use per-generation launches");
     h->persistent = mode;
     return QIEO_OK;
 }
@@ -775,6 +830,8 @@ extern "C" int qieo_set_pipeline(qieo_inst* h, int32_t pipeline)
         return set_error(QIEO_EINVAL, "unknown pipeline %d", pipeline);
     if (pipeline != QIEO_PIPELINE_FUSED && h->window > 0)
         return set_error(QIEO_ESTATE, "the unfused pipelines do not run the convergence test");
+    if (pipeline != QIEO_PIPELINE_FUSED && h->f64)
+        return set_error(QIEO_ESTATE, "binary64 instances run the fused pipeline only");
     if (pipeline == QIEO_PIPELINE_UNFUSED_HOST_DE && !h->h_fit) {
         hipError_t e;
         if ((e = hipHostMalloc((void**)&h->h_fit, (size_t)h->np * sizeof(int32_t),

@@ -93,6 +93,11 @@ def _load():
     H = ctypes.c_void_p
     L.qieo_create.restype = ctypes.c_int
     L.qieo_create.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(H)]
+    L.qieo_create_f64.restype = ctypes.c_int
+    L.qieo_create_f64.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(qieo_dev_ctx),
+                                  ctypes.POINTER(H)]
+    L.qieo_export_rows_f64.restype = ctypes.c_int
+    L.qieo_export_rows_f64.argtypes = [H, i32, i32, P, P, P, P, P, P, ctypes.POINTER(i32)]
     L.qieo_create_ex.restype = ctypes.c_int
     L.qieo_create_ex.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(qieo_dev_ctx),
                                  ctypes.POINTER(H)]
@@ -257,10 +262,17 @@ def qieo_tune_db_clear():
 
 
 def qieo_create(items: np.ndarray, n_items: int, capacity: int, n_pop: int, seed: int,
-                stream: int | None = None):
+                stream: int | None = None, precision: int = 32):
     """items: int32 array [n_items, 2] of (profit, weight).  Returns a handle."""
     h = ctypes.c_void_p()
-    if stream is None:
+    if precision == 64:
+        ctx = None
+        if stream is not None:
+            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
+                                            ctypes.c_void_p(stream)))
+        rc = lib.qieo_create_f64(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1), ctx,
+                                 ctypes.byref(h))
+    elif stream is None:
         rc = lib.qieo_create(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1),
                              ctypes.byref(h))
     else:
@@ -324,14 +336,15 @@ class Instance:
     """One resident QIEO population (owner of a libqieo handle)."""
 
     def __init__(self, values, weights, capacity: int, n_pop: int, seed: int,
-                 stream: int | None = None):
+                 stream: int | None = None, precision: int = 32):
         self.items = items_array(values, weights)
         self.n_items = int(self.items.shape[0])
         self.n_pop = int(n_pop)
         self.capacity = int(capacity)
         self.seed = int(seed)
+        self.precision = int(precision)
         self._h = qieo_create(self.items, self.n_items, self.capacity, self.n_pop, self.seed,
-                              stream)
+                              stream, self.precision)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -380,15 +393,17 @@ class Instance:
         if n_rows is None:
             n_rows = self.n_pop - row0
         ng = self.n_items
-        a = np.empty((n_rows, ng), np.float32) if amplitudes else None
-        b = np.empty((n_rows, ng), np.float32) if amplitudes else None
+        dt = np.float64 if self.precision == 64 else np.float32
+        a = np.empty((n_rows, ng), dt) if amplitudes else None
+        b = np.empty((n_rows, ng), dt) if amplitudes else None
         x = np.empty((n_rows, ng), np.uint8) if alleles else None
         f = np.empty(n_rows, np.int32)
         p = np.empty(n_rows, np.int32)
         w = np.empty(n_rows, np.int32)
         e = ctypes.c_int32()
-        _check(lib.qieo_export_rows(self._h, row0, n_rows, _ptr(a), _ptr(b), _ptr(x), _ptr(f),
-                                    _ptr(p), _ptr(w), ctypes.byref(e)), "qieo_export_rows")
+        fn = lib.qieo_export_rows_f64 if self.precision == 64 else lib.qieo_export_rows
+        _check(fn(self._h, row0, n_rows, _ptr(a), _ptr(b), _ptr(x), _ptr(f), _ptr(p), _ptr(w),
+                  ctypes.byref(e)), "qieo_export_rows")
         return dict(alpha=a, beta=b, alleles=x, fitness=f, profit=p, weight=w,
                     elite=int(e.value))
 

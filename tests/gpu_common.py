@@ -10,9 +10,13 @@ def say(msg: str):
     sys.stdout.flush()
 
 
+def _bits(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint64 if a.dtype == np.float64 else np.uint32)
+
+
 def bits_equal(a: np.ndarray, b: np.ndarray) -> bool:
-    return np.array_equal(np.ascontiguousarray(a).view(np.uint32),
-                          np.ascontiguousarray(b).view(np.uint32))
+    return a.dtype == b.dtype and np.array_equal(_bits(a), _bits(b))
 
 
 def assert_state_equal(inst, orc, rows=None, label=""):
@@ -40,8 +44,8 @@ def assert_state_equal(inst, orc, rows=None, label=""):
         elite = st["elite"]
         sl = slice(r0, r1)
         if not bits_equal(st["alpha"], a_o[sl]) or not bits_equal(st["beta"], b_o[sl]):
-            bad = np.argwhere((st["alpha"].view(np.uint32) != a_o[sl].view(np.uint32)) |
-                              (st["beta"].view(np.uint32) != b_o[sl].view(np.uint32)))
+            bad = np.argwhere((_bits(st["alpha"]) != _bits(a_o[sl])) |
+                              (_bits(st["beta"]) != _bits(b_o[sl])))
             r, i = bad[0]
             raise AssertionError(
                 "%s amplitudes differ at row %d gene %d: gpu (%r, %r) oracle (%r, %r); %d genes"

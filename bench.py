@@ -249,6 +249,10 @@ def main():
     ap.add_argument("--n-items", type=int, default=200_000)
     ap.add_argument("--tile", type=str, default="", help="R,S work shape override")
     ap.add_argument("--kernel-flags", type=int, default=-1, help="generation kernel variant")
+    ap.add_argument("--precision", type=int, choices=[32, 64], default=32,
+                    help="amplitude precision (64: the paper's binary64)")
+    ap.add_argument("--autotune", type=int, default=0, metavar="GENS",
+                    help="time every work shape for GENS generations first and use the best")
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -299,7 +303,11 @@ def main():
         return bench_fractions(args)
     inst = workloads.large_instance(args.n_pop, args.n_items)
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
-    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    if args.autotune:
+        r = qieo.qieo_autotune(inst.n_items, inst.n_pop, args.autotune)
+        log("autotune: %s" % r)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                      precision=args.precision)
     if args.tile:
         r, s = (int(x) for x in args.tile.split(","))
         g.set_tile(r, s)
@@ -322,7 +330,7 @@ def main():
     genes = inst.n_pop * inst.n_items
     value = genes * args.steps / wall
     avg_ms = kern_ms / max(launches, 1)
-    bytes_per_launch = BYTES_PER_GENE_UPDATE * genes
+    bytes_per_launch = BYTES_PER_GENE_UPDATE * genes * (2 if args.precision == 64 else 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     best = g.best()
     log("wall %.3f s, %.3f ms/generation, kernel avg %.3f ms over %d launches, "
@@ -342,16 +350,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic",
         "config": {"workload": "qieo-knapsack single instance Np=%d Ng=%d, %d generations"
                                % (inst.n_pop, inst.n_items, args.steps),
                    "n_pop": inst.n_pop, "n_items": inst.n_items, "seed": inst.seed,
                    "generations_per_step": 1},
-        "hbm_frac_algorithmic": value * BYTES_PER_GENE_UPDATE / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac_algorithmic": value * bytes_per_launch / genes / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(inst.n_pop, inst.n_items),
+                     "traffic": (measured_traffic(inst.n_pop, inst.n_items)
+                                 if args.precision == 32 else None),
                      "kernel": "generation_kernel", "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_per_launch},
     }

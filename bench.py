@@ -84,29 +84,50 @@ def bench_batch(args):
     genes = sum(i.genes for i in insts)
     probs = [(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
     log("batch: %d instances, %.4g genes per generation, %d generations" % (len(insts), genes, gens))
+    variants = {}
+    for name, pers in (("no_persistent", False), ("persistent_small", True)):
+        b = qieo.Batch(probs)
+        b.set_persistent(pers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(gens)
+        variants[name] = time.perf_counter() - t0
+        best_batch = [b.best(k) for k in range(len(insts))]
+        b.close()
+        log("batched (%s): %.3f s" % (name, variants[name]))
+    wall_batch = min(variants.values())
+
+    # replay of the same call on a batch whose graph is already captured
     b = qieo.Batch(probs)
+    b.step(gens)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(gens)
-    wall_batch = time.perf_counter() - t0
-    best_batch = [b.best(k) for k in range(len(insts))]
+    variants["replay_second_call"] = time.perf_counter() - t0
     b.close()
-    log("batched: %.3f s" % wall_batch)
+    log("batched, second call of a captured graph: %.3f s" % variants["replay_second_call"])
 
-    wall_loop = 0.0
+    loops = {}
     same = 0
-    for k, i in enumerate(insts):
-        g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.step(gens)
-        wall_loop += time.perf_counter() - t0
-        r = g.best()
-        same += int((r.fitness, r.profit, r.generation, r.chromosome) ==
-                    (best_batch[k].fitness, best_batch[k].profit, best_batch[k].generation,
-                     best_batch[k].chromosome))
-        g.close()
-    log("per-instance loop: %.3f s; identical best records %d/%d" % (wall_loop, same, len(insts)))
+    for mode in ("graph", "launches"):
+        wall_loop = 0.0
+        for k, i in enumerate(insts):
+            g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+            g.set_graph(mode == "graph")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(gens)
+            wall_loop += time.perf_counter() - t0
+            if mode == "graph":
+                r = g.best()
+                same += int((r.fitness, r.profit, r.generation, r.chromosome) ==
+                            (best_batch[k].fitness, best_batch[k].profit,
+                             best_batch[k].generation, best_batch[k].chromosome))
+            g.close()
+        loops[mode] = wall_loop
+        log("per-instance loop (%s): %.3f s" % (mode, wall_loop))
+    log("identical best records %d/%d" % (same, len(insts)))
+    wall_loop = min(loops.values())
     out = {
         "metric": "gene-updates/s", "value": genes * gens / wall_batch, "unit": "gene-updates/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall_batch * 1e3,
@@ -114,7 +135,9 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": "qieo-knapsack batch of %d ragged instances, %d generations"
                                % (len(insts), gens)},
-        "per_instance_loop": {"value": genes * gens / wall_loop, "seconds": wall_loop},
+        "per_instance_loop": {"value": genes * gens / wall_loop, "seconds": wall_loop,
+                              "variants_seconds": loops},
+        "batch_variants_seconds": variants,
         "speedup_vs_loop": wall_loop / wall_batch,
         "identical_best": "%d/%d" % (same, len(insts)),
     }
@@ -240,6 +263,34 @@ def bench_fractions(args):
         print(json.dumps(cell), flush=True)
 
 
+def bench_launch(args):
+    """Small and medium single instances, where launch overhead matters: time
+    per generation with one launch per generation, with graph replay of the
+    whole call, and with the persistent single-workgroup path."""
+    import torch
+    import workloads
+    from paper_2609_30862_amd import qieo
+
+    shapes = [(16, 100), (32, 500), (64, 1000), (128, 500), (256, 500), (64, 4000),
+              (256, 2000), (1024, 10_000)]
+    for (np_, ng) in shapes:
+        inst = workloads.random_instance(ng, np_, seed=ng + np_)
+        cell = {"n_pop": np_, "n_items": ng}
+        for name, graph, pers in (("launches", 0, 0), ("graph", 1, 0), ("persistent", 0, 2)):
+            g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+            g.set_graph(graph)
+            g.set_persistent(pers)
+            g.step(500)                      # warm-up (and graph capture for n = 500)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(500)
+            cell[name] = (time.perf_counter() - t0) / 500 * 1e6
+            g.close()
+        log("Np=%5d Ng=%6d  us/generation: launches %.2f  graph %.2f  persistent %.2f"
+            % (np_, ng, cell["launches"], cell["graph"], cell["persistent"]))
+        print(json.dumps(cell), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,7 +307,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions"],
+    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions", "launch"],
                     default="large",
                     help="large: the single 4096 x 200,000 instance (default); batch: 512 "
                          "ragged instances x 500 generations vs a per-instance launch loop; "
@@ -301,6 +352,8 @@ def main():
         return bench_serve(args)
     if args.workload == "fractions":
         return bench_fractions(args)
+    if args.workload == "launch":
+        return bench_launch(args)
     inst = workloads.large_instance(args.n_pop, args.n_items)
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
     if args.autotune:

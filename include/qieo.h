@@ -281,10 +281,18 @@ void qieo_server_destroy(qieo_server *s);
 
 /* Persistent path for small populations: one single-workgroup launch runs all
  * generations of a qieo_step call, block barriers replacing launch
- * boundaries.  mode 0: never; 1 (default): when n_pop * (n_items rounded up
+ * boundaries.  mode 0 (default): never; 1: when n_pop * (n_items rounded up
  * to 64) <= 65536 and n_pop <= 2048; 2: whenever n_pop <= 2048.  Results are
- * identical either way. */
+ * identical either way.  On MI355X a generation costs the workgroup about as
+ * long as a back-to-back launch (~5 us), so the default is off. */
 int qieo_set_persistent(qieo_inst *h, int32_t mode);
+
+/* 1 (default): a qieo_step call of n >= 2 generations on the fused
+ * per-generation path is captured once into a HIP graph (n launches plus the
+ * finishing one) and replayed by later calls with the same n and shape; 0:
+ * launched one by one.  Timing mode always launches one by one.  Results are
+ * identical. */
+int qieo_set_graph(qieo_inst *h, int32_t enabled);
 
 /* ---- work-shape autotuner ------------------------------------------------ */
 

@@ -211,7 +211,11 @@ struct qieo_inst {
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
     bool f64 = false;            // binary64 amplitudes
-    int persistent = 1;          // 0 never, 1 when small enough, 2 whenever rows fit
+    int persistent = 0;          // 0 never (default), 1 when small enough, 2 whenever rows fit
+    bool use_graph = true;       // replay a captured graph of a call's launches
+    hipGraphExec_t graph = nullptr;
+    int32_t graph_n = -1;        // generations the cached graph runs
+    int graph_key = -1;          // shape/variant it was captured with
     int32_t window = 0;
     int32_t* h_fit = nullptr;                // pinned, host DetermineElite
     unsigned long long* h_key = nullptr;     // pinned, host DetermineElite
@@ -245,6 +249,7 @@ static void inst_release(qieo_inst* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->h_fit) (void)hipHostFree(h->h_fit);
     if (h->h_key) (void)hipHostFree(h->h_key);
@@ -452,6 +457,42 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         if (h->timing) (void)hipEventRecord(b, h->stream);
         if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
             return hip_fail(e, "finish kernel");
+        h->t += n;
+        return QIEO_OK;
+    }
+    // fused per-generation launches: replay one captured graph per call
+    if (h->pipeline == QIEO_PIPELINE_FUSED && h->use_graph && !h->timing && n >= 2) {
+        const int key = (h->R * 32 + h->S) * 4 + h->flags;
+        if (h->graph_n != n || h->graph_key != key) {
+            if (h->graph) (void)hipGraphExecDestroy(h->graph);
+            h->graph = nullptr;
+            h->graph_n = -1;
+            hipGraph_t g = nullptr;
+            if ((e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal)) !=
+                hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = hipSuccess;
+            for (int32_t k = 0; k < n && le == hipSuccess; ++k)
+                le = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k,
+                                       nullptr, n, h->stream);
+            if (le == hipSuccess) le = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream);
+            e = hipStreamEndCapture(h->stream, &g);
+            if (le != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(le, "captured launch");
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->graph = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            h->graph_n = n;
+            h->graph_key = key;
+        }
+        if ((e = hipGraphLaunch(h->graph, h->stream)) != hipSuccess)
+            return hip_fail(e, "hipGraphLaunch");
         h->t += n;
         return QIEO_OK;
     }
@@ -808,6 +849,14 @@ extern "C" int qieo_stage_time(qieo_inst* h, int64_t* launches, double* total_ms
             h->total_ms[i] = 0.0;
         }
     }
+    return QIEO_OK;
+}
+
+extern "C" int qieo_set_graph(qieo_inst* h, int32_t enabled)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    h->use_graph = enabled != 0;
     return QIEO_OK;
 }
 

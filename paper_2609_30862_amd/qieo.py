@@ -118,6 +118,8 @@ def _load():
     L.qieo_tune_db_load.argtypes = [ctypes.c_char_p]
     L.qieo_tune_db_clear.restype = None
     L.qieo_tune_db_clear.argtypes = []
+    L.qieo_set_graph.restype = ctypes.c_int
+    L.qieo_set_graph.argtypes = [H, i32]
     L.qieo_set_persistent.restype = ctypes.c_int
     L.qieo_set_persistent.argtypes = [H, i32]
     L.qieo_set_pipeline.restype = ctypes.c_int
@@ -412,6 +414,9 @@ class Instance:
 
     def set_convergence(self, window: int):
         _check(lib.qieo_set_convergence(self._h, int(window)), "qieo_set_convergence")
+
+    def set_graph(self, enabled: bool):
+        _check(lib.qieo_set_graph(self._h, int(bool(enabled))), "qieo_set_graph")
 
     def set_persistent(self, mode: int):
         _check(lib.qieo_set_persistent(self._h, int(mode)), "qieo_set_persistent")

@@ -205,3 +205,19 @@ def test_persistent_path_same_trajectory(qieo, oracle_mod, ng, n_pop, mode):
     g.step(5)
     o.run(5)
     assert_state_equal(g, o, label="persistent switched t=%d" % o.t)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_graph_replay_same_trajectory(qieo, oracle_mod, graph):
+    """Captured-graph replay of whole calls (same n twice, then another n,
+    then a shape change) follows the oracle."""
+    inst = workloads.random_instance(6000, 40, seed=12)
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_persistent(0)
+    g.set_graph(graph)
+    for n, tile in ((5, None), (5, None), (3, None), (5, (2, 4)), (5, (2, 4))):
+        if tile:
+            g.set_tile(*tile)
+        g.step(n)
+        o.run(n)
+        assert_state_equal(g, o, label="graph %d t=%d" % (graph, o.t))

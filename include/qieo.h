@@ -173,9 +173,14 @@ void qieo_destroy(qieo_inst *h);
 int qieo_set_tile(qieo_inst *h, int32_t rows_per_block, int32_t waves_per_block);
 /* Current work shape. */
 int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_block);
-/* Code variant of the generation kernel: bit 0 prefetches the next chunk's
- * amplitudes while the current one is computed, bit 1 stores amplitudes with
- * non-temporal hints.  Variants change speed only, never results. */
+/* Code variant of the generation kernel, a set of bits in [0, 15]: bit 0
+ * prefetches the next chunk's amplitudes while the current one is computed,
+ * bit 1 stores amplitudes with non-temporal hints, bit 2 loads them with
+ * non-temporal hints, bit 3 re-derives the previous generation's alleles
+ * from the stored beta and their draws instead of reading the stored allele
+ * words back (binary32 amplitudes; binary64 handles use bits 0-2 only).
+ * Variants change speed only, never results.  Out-of-range values give
+ * QIEO_EINVAL. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 
 /* ---- batch: many instances advanced together (one device pool) ---------- */
@@ -223,8 +228,12 @@ int qieo_batch_converged(qieo_batch *b, int32_t i, int32_t *converged, int64_t *
  * library's per-class choice); see qieo_set_tile and qieo_set_kernel_flags. */
 int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per_block,
                         int32_t flags);
-/* 1 (default): each call's launches are captured once into a HIP graph and
- * replayed; 0: launched one by one. */
+/* 1 (default): a call that repeats the previous one (same longest
+ * generation count, no membership change in between) is captured into a HIP
+ * graph, which later such calls replay; a one-off call is launched directly.
+ * 0: always launched one by one.  A capture that another thread's
+ * device-wide call invalidates falls back to direct launches.  Results are
+ * identical. */
 int qieo_batch_set_graph(qieo_batch *b, int32_t enabled);
 /* 1 (default): members small enough for the persistent path (see
  * qieo_set_persistent) run as one workgroup each for the whole call,
@@ -288,10 +297,13 @@ void qieo_server_destroy(qieo_server *s);
 int qieo_set_persistent(qieo_inst *h, int32_t mode);
 
 /* 1 (default): a qieo_step call of n >= 2 generations on the fused
- * per-generation path is captured once into a HIP graph (n launches plus the
- * finishing one) and replayed by later calls with the same n and shape; 0:
- * launched one by one.  Timing mode always launches one by one.  Results are
- * identical. */
+ * per-generation path that repeats the previous call (same n, work shape and
+ * variant) is captured into a HIP graph (n launches plus the finishing one),
+ * which later calls with the same n and shape replay; a one-off call is
+ * launched directly.  0: always launched one by one.  Timing mode always
+ * launches one by one.  If another thread's device-wide call invalidates a
+ * capture in progress, that call's launches are enqueued directly.  Results
+ * are identical in every case. */
 int qieo_set_graph(qieo_inst *h, int32_t enabled);
 
 /* ---- work-shape autotuner ------------------------------------------------ */

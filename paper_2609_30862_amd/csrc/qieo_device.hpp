@@ -135,6 +135,13 @@ __device__ __forceinline__ void gstore(T* base, uint32_t idx, T v)
     ((QIEO_AS_GLOBAL T*)base)[idx] = v;
 }
 
+// Streaming load of data this launch reads once (no L2 retention).
+template <typename T>
+__device__ __forceinline__ T gload_nt(const T* base, uint32_t idx)
+{
+    return __builtin_nontemporal_load(&((const QIEO_AS_GLOBAL T*)base)[idx]);
+}
+
 // Streaming store that is not expected to be re-read soon (no L2 retention).
 template <typename T>
 __device__ __forceinline__ void gstore_nt(T* base, uint32_t idx, T v)

@@ -33,7 +33,11 @@ int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
                     const ArenaLayout& L, char* base, std::vector<int32_t>& staging,
                     bool f64 = false);
 int check_device();
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes = 4);
+// hipMemcpyAsync on s, then waits for s.
+hipError_t copy_on(void* dst, const void* src, size_t n, hipMemcpyKind kind, hipStream_t s);
+// kFlag* bits for a work shape given the amplitude bytes one generation streams.
+int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes);
 // Shape from the autotuner's database, if the bucket was tuned.
 bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,

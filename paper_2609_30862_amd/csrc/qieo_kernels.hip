@@ -104,13 +104,19 @@ __global__ void init_kernel(InstDev I)
 // ---------------------------------------------------------------------------
 // MODE selects the steps one launch performs (kStepAll = the fused
 // generation); the unfused pipeline runs kStepCip, kStepQip and kStepFe as
-// three launches, then DetermineElite by de_kernel or on the host.
-template <typename T, int R, bool PF, bool NT, int MODE>
+// three launches, then DetermineElite by de_kernel or on the host.  FL is a
+// set of kFlag* bits; none of them changes a result.
+template <typename T, int R, int FL, int MODE>
 __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
                                                          const Tile* __restrict__ tiles, int k,
                                                          const int32_t* __restrict__ gens_arr,
                                                          int gens_all)
 {
+    constexpr bool PF = (FL & kFlagPrefetch) != 0, NT = (FL & kFlagNontemporal) != 0;
+    constexpr bool NTL = (FL & kFlagNontemporalLoads) != 0;
+    // the fused generation may re-derive the previous alleles instead of
+    // reading them back (the unfused slices always read them)
+    constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0 && MODE == kStepAll;
     uint32_t inst = 0, row0;
     if (tiles != nullptr) {
         const Tile tt = tiles[blockIdx.x];
@@ -209,8 +215,13 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r < nrows) {
-                if (kQip || rot[r]) nb[r] = gload(brow4[r], qx);
-                if (rot[r]) na[r] = gload(arow[r], qx);
+                if (NTL) {
+                    if (kQip || rot[r]) nb[r] = gload_nt(brow4[r], qx);
+                    if (rot[r]) na[r] = gload_nt(arow[r], qx);
+                } else {
+                    if (kQip || rot[r]) nb[r] = gload(brow4[r], qx);
+                    if (rot[r]) na[r] = gload(arow[r], qx);
+                }
             }
         }
     };
@@ -248,10 +259,23 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
             V4 b4 = cb[r];
             V4 a4 = ca[r];
             if (rot[r]) {
-                const uint64_t* xw =
-                    reinterpret_cast<const uint64_t*>(xprev + (size_t)c * wpr + ch * kWordsPerChunk);
-                const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
-                const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
+                uint64_t xm0, xm1, xm2, xm3;
+                if (RC) {
+                    // The stored beta is the one generation t-1 observed (its
+                    // rotation is still pending), so the same draw against it
+                    // gives back the alleles of t-1 bit for bit.
+                    const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u,
+                                                  I.seed_lo, I.seed_hi);
+                    xm0 = ballot(act && observe(d.r0, b4.x));
+                    xm1 = ballot(act && observe(d.r1, b4.y));
+                    xm2 = ballot(act && observe(d.r2, b4.z));
+                    xm3 = ballot(act && observe(d.r3, b4.w));
+                } else {
+                    const uint64_t* xw = reinterpret_cast<const uint64_t*>(
+                        xprev + (size_t)c * wpr + ch * kWordsPerChunk);
+                    xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
+                    xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+                }
                 T a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
                 T b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
                 cip_gene(a0, b0, xm0 ^ bm0, bm0);
@@ -770,15 +794,27 @@ hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
     if (n_blocks <= 0) return hipSuccess;
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
-#define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
-    hipLaunchKernelGGL((generation_kernel<float, RR, PFF, NTT, kStepAll>), grid, block, 0, s,  \
-                       dI, tiles, k, gens_arr, gens_all)
+#define QIEO_LAUNCH(RR, FF)                                                                    \
+    hipLaunchKernelGGL((generation_kernel<float, RR, FF, kStepAll>), grid, block, 0, s, dI,    \
+                       tiles, k, gens_arr, gens_all)
 #define QIEO_LAUNCH_R(RR)                                                                      \
-    switch (flags & 3) {                                                                       \
-    case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
-    case 1: QIEO_LAUNCH(RR, true, false); break;                                               \
-    case 2: QIEO_LAUNCH(RR, false, true); break;                                               \
-    default: QIEO_LAUNCH(RR, true, true); break;                                               \
+    switch (flags & kFlagAll) {                                                                \
+    case 0: QIEO_LAUNCH(RR, 0); break;                                                         \
+    case 1: QIEO_LAUNCH(RR, 1); break;                                                         \
+    case 2: QIEO_LAUNCH(RR, 2); break;                                                         \
+    case 3: QIEO_LAUNCH(RR, 3); break;                                                         \
+    case 4: QIEO_LAUNCH(RR, 4); break;                                                         \
+    case 5: QIEO_LAUNCH(RR, 5); break;                                                         \
+    case 6: QIEO_LAUNCH(RR, 6); break;                                                         \
+    case 7: QIEO_LAUNCH(RR, 7); break;                                                         \
+    case 8: QIEO_LAUNCH(RR, 8); break;                                                         \
+    case 9: QIEO_LAUNCH(RR, 9); break;                                                         \
+    case 10: QIEO_LAUNCH(RR, 10); break;                                                       \
+    case 11: QIEO_LAUNCH(RR, 11); break;                                                       \
+    case 12: QIEO_LAUNCH(RR, 12); break;                                                       \
+    case 13: QIEO_LAUNCH(RR, 13); break;                                                       \
+    case 14: QIEO_LAUNCH(RR, 14); break;                                                       \
+    default: QIEO_LAUNCH(RR, 15); break;                                                       \
     }
     switch (rows_per_block) {
     case 1: QIEO_LAUNCH_R(1); break;
@@ -798,15 +834,19 @@ hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_b
     if (n_blocks <= 0) return hipSuccess;
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
-#define QIEO_LAUNCH(RR, PFF, NTT)                                                              \
-    hipLaunchKernelGGL((generation_kernel<double, RR, PFF, NTT, kStepAll>), grid, block, 0, s, \
-                       dI, (const Tile*)nullptr, k, (const int32_t*)nullptr, gens_all)
+#define QIEO_LAUNCH(RR, FF)                                                                    \
+    hipLaunchKernelGGL((generation_kernel<double, RR, FF, kStepAll>), grid, block, 0, s, dI,   \
+                       (const Tile*)nullptr, k, (const int32_t*)nullptr, gens_all)
 #define QIEO_LAUNCH_R(RR)                                                                      \
-    switch (flags & 3) {                                                                       \
-    case 0: QIEO_LAUNCH(RR, false, false); break;                                              \
-    case 1: QIEO_LAUNCH(RR, true, false); break;                                               \
-    case 2: QIEO_LAUNCH(RR, false, true); break;                                               \
-    default: QIEO_LAUNCH(RR, true, true); break;                                               \
+    switch (flags & 7) {                                                                       \
+    case 0: QIEO_LAUNCH(RR, 0); break;                                                         \
+    case 1: QIEO_LAUNCH(RR, 1); break;                                                         \
+    case 2: QIEO_LAUNCH(RR, 2); break;                                                         \
+    case 3: QIEO_LAUNCH(RR, 3); break;                                                         \
+    case 4: QIEO_LAUNCH(RR, 4); break;                                                         \
+    case 5: QIEO_LAUNCH(RR, 5); break;                                                         \
+    case 6: QIEO_LAUNCH(RR, 6); break;                                                         \
+    default: QIEO_LAUNCH(RR, 7); break;                                                        \
     }
     switch (rows_per_block) {
     case 1: QIEO_LAUNCH_R(1); break;
@@ -830,8 +870,8 @@ hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int
         return hipGetLastError();
     }
 #define QIEO_STAGE(RR, MM)                                                                     \
-    hipLaunchKernelGGL((generation_kernel<float, RR, false, true, MM>), grid, block, 0, s, dI, \
-                       (const Tile*)nullptr, k, (const int32_t*)nullptr, gens)
+    hipLaunchKernelGGL((generation_kernel<float, RR, kFlagNontemporal, MM>), grid, block, 0, s, \
+                       dI, (const Tile*)nullptr, k, (const int32_t*)nullptr, gens)
 #define QIEO_STAGE_R(RR)                                                                       \
     switch (stage) {                                                                           \
     case kStepCip: QIEO_STAGE(RR, kStepCip); break;                                            \

@@ -68,8 +68,14 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
 // number of generations each instance runs in the current call; launch k
 // (0-based) skips instances with gens <= k.
 // flags: bit 0 = prefetch the next chunk's amplitudes while computing the
-// current one; bit 1 = non-temporal amplitude stores.
+// current one; bit 1 = non-temporal amplitude stores; bit 2 = non-temporal
+// amplitude loads; bit 3 = re-derive the previous generation's alleles from
+// beta and their draws instead of reading the stored words back (binary32
+// launches only; binary64 launches take bits 0-2).
 constexpr int kFlagPrefetch = 1;
+constexpr int kFlagNontemporalLoads = 4;
+constexpr int kFlagRecomputeAlleles = 8;
+constexpr int kFlagAll = 15;
 // Steps of one generation a launch may perform.
 constexpr int kStepCip = 1, kStepQip = 2, kStepFe = 4, kStepDe = 8;
 constexpr int kStepAll = kStepCip | kStepQip | kStepFe | kStepDe;

@@ -192,6 +192,7 @@ static int class_of(int32_t nchunk)
 int Engine::rebuild()
 {
     invalidate_graph();
+    prev_n_ = -1;
     for (auto& c : classes_)
         if (c.d_tiles) (void)hipFree(c.d_tiles);
     classes_.clear();
@@ -262,6 +263,10 @@ int Engine::rebuild()
                 return hip_fail(e, "hipEventCreate");
         }
     }
+    // amplitude bytes one generation of the whole batch streams (all classes
+    // run back to back, so they share the caches)
+    int64_t plane_bytes = 0;
+    for (auto& m : members_) plane_bytes += (int64_t)m.np * m.L.pitch * 2 * (int64_t)sizeof(float);
     static const int kS[4] = {1, 2, 4, 8};
     for (int c = 0; c < 4; ++c) {
         auto& g = groups[c];
@@ -285,7 +290,7 @@ int Engine::rebuild()
             for (size_t i : g) blocks += (members_[i].np + cand - 1) / cand;
             if (blocks * sc.S >= 8192) { sc.R = cand; break; }
         }
-        sc.flags = kFlagNontemporal | (max_nchunk >= 2 * sc.S ? kFlagPrefetch : 0);
+        sc.flags = variant_flags(sc.R, sc.S, max_nchunk, plane_bytes);
         if (force_R_ > 0) {
             sc.R = force_R_;
             sc.S = force_S_;
@@ -337,27 +342,31 @@ int Engine::enqueue(int nmax)
     return QIEO_OK;
 }
 
-int Engine::capture(int nmax)
+// Relaxed mode: the captured sequence holds launches, event records and
+// waits only.  Returns false, with no graph and the error state clear, if the
+// capture does not complete (another thread's device-wide call can
+// invalidate a capture in progress); the caller then enqueues directly.
+bool Engine::capture(int nmax)
 {
     invalidate_graph();
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int rc = enqueue(nmax);
-    e = hipStreamEndCapture(stream_, &g);
-    if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
+    if (hipStreamBeginCapture(stream_, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        clear_error();
+        return false;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        graph_ = nullptr;
-        return hip_fail(e, "hipGraphInstantiate");
+    const int rc = enqueue(nmax);
+    const hipError_t e = hipStreamEndCapture(stream_, &g);
+    hipGraphExec_t x = nullptr;
+    if (rc == QIEO_OK && e == hipSuccess && g &&
+        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+        graph_ = x;
+        graph_n_ = nmax;
     }
-    graph_n_ = nmax;
-    return QIEO_OK;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    clear_error();
+    return graph_ != nullptr;
 }
 
 int Engine::run(const int32_t* gens)
@@ -381,11 +390,22 @@ int Engine::run(const int32_t* gens)
     if ((e = hipMemcpyAsync(d_gens_, h_gens_, n * sizeof(int32_t), hipMemcpyHostToDevice,
                             stream_)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(generation counts)");
-    if (use_graph_) {
-        if (graph_n_ != nmax && (rc = capture(nmax))) return rc;
+    // a call is captured once it repeats (same longest count, same members):
+    // capturing a one-off call costs more than launching it
+    const bool repeat = prev_n_ == nmax;
+    prev_n_ = nmax;
+    bool done = false;
+    if (use_graph_ && (graph_n_ == nmax || (repeat && capture(nmax)))) {
         if ((e = hipGraphLaunch(graph_, stream_)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    } else if ((rc = enqueue(nmax))) {
-        return rc;
+        done = true;
+    }
+    if (!done) {
+        // a side stream left in a lost capture cannot be used
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (side_ && hipStreamIsCapturing(side_, &cs) == hipSuccess &&
+            cs != hipStreamCaptureStatusNone)
+            return set_error(QIEO_EDEVICE, "side stream left capturing by a lost graph capture");
+        if ((rc = enqueue(nmax))) return rc;
     }
     for (size_t i = 0; i < n; ++i) members_[i].t += gens[i];
     return QIEO_OK;
@@ -405,9 +425,9 @@ int Engine::refresh_status()
     std::vector<int64_t> st(2 * n);
     hipError_t e = hipStreamSynchronize(stream_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if ((e = hipMemcpy(st.data(), d_status_, st.size() * sizeof(int64_t), hipMemcpyDeviceToHost)) !=
-        hipSuccess)
-        return hip_fail(e, "hipMemcpy(status)");
+    if ((e = copy_on(st.data(), d_status_, st.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                     stream_)) != hipSuccess)
+        return hip_fail(e, "copy(status)");
     for (size_t i = 0; i < n; ++i) {
         members_[i].t = st[2 * i];
         members_[i].converged = st[2 * i + 1] != 0;
@@ -608,7 +628,7 @@ extern "C" int qieo_batch_set_tile(qieo_batch* b, int32_t rows_per_block,
         return QIEO_OK;
     }
     if ((rows_per_block != 1 && rows_per_block != 2 && rows_per_block != 4) ||
-        waves_per_block < 1 || waves_per_block > 16 || flags < 0 || flags > 3)
+        waves_per_block < 1 || waves_per_block > 16 || flags < 0 || flags > kFlagAll)
         return set_error(QIEO_EINVAL, "bad work shape (%d, %d, %d)", rows_per_block,
                          waves_per_block, flags);
     b->eng->force_shape(rows_per_block, waves_per_block, flags);

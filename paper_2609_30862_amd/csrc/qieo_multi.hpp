@@ -90,7 +90,7 @@ public:
 
 private:
     int rebuild();               // descriptors and tile tables after membership change
-    int capture(int nmax);
+    bool capture(int nmax);
     int enqueue(int nmax);
     void invalidate_graph();
 
@@ -115,6 +115,7 @@ private:
     bool use_graph_ = true;
     hipGraphExec_t graph_ = nullptr;
     int graph_n_ = -1;
+    int prev_n_ = -1;            // longest count of the previous call since the last rebuild
     std::vector<int32_t> staging_;
 };
 

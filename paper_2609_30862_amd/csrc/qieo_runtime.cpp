@@ -168,15 +168,31 @@ int check_device()
     return QIEO_OK;
 }
 
+// Variant bits for a work shape.  Non-temporal stores always: an amplitude
+// written now is read again one generation later, after the whole population
+// has streamed through the caches.  Non-temporal loads once the amplitude
+// planes one generation streams exceed the 256 MB last-level cache (below
+// that, the next generation's reads may still hit it; above, cached
+// amplitudes only evict the item tables and allele words).  Prefetch when a
+// wave walks more than one chunk, except with 4 rows per workgroup over long
+// rows (>= 32 chunks per wave), where four rows' loads already keep enough in
+// flight and the prefetch buffers cost occupancy.
+int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
+{
+    int f = kFlagNontemporal;
+    if (plane_bytes > ((int64_t)256 << 20)) f |= kFlagNontemporalLoads;
+    if (nchunk > S && !(R == 4 && nchunk >= 32 * (int64_t)S)) f |= kFlagPrefetch;
+    return f;
+}
+
 // Work shape for a single instance: rows per workgroup R, waves per
 // workgroup S and kernel variant flags.  Whole rows stay in one workgroup
 // (Evaluation closes in LDS); S splits the gene axis.  R is the largest of
 // 4, 2, 1 that still leaves >= 32 wavefronts per CU (8192 on 256 CUs), since
-// more rows per workgroup amortise the item-table and elite-mask reads;
-// prefetching pays once a wave walks several chunks.  On the 4096 x 200,000
-// workload this is (4, 8, prefetch | non-temporal), the fastest shape of a
-// full sweep of R in {1,2,4}, S in {4,8,16} and all flags.
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
+// more rows per workgroup amortise the item-table and elite-mask reads.  On
+// the 4096 x 200,000 workload this is (4, 8, non-temporal loads and stores),
+// the fastest of a sweep of R in {1,2,4}, S in {4,8} and the variant bits.
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes)
 {
     int s = 8;
     if (nchunk < s) s = std::max(1, nchunk);
@@ -186,7 +202,7 @@ void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
     }
     *R = r;
     *S = s;
-    *flags = (nchunk >= 2 * s ? kFlagPrefetch : 0) | kFlagNontemporal;
+    *flags = variant_flags(r, s, nchunk, (int64_t)np * nchunk * kChunk * 2 * (int64_t)elem_bytes);
 }
 
 }  // namespace qieo
@@ -216,6 +232,8 @@ struct qieo_inst {
     hipGraphExec_t graph = nullptr;
     int32_t graph_n = -1;        // generations the cached graph runs
     int graph_key = -1;          // shape/variant it was captured with
+    int32_t prev_n = -1;         // generations and shape/variant of the previous
+    int prev_key = -1;           // fused call (capture starts on a repeat)
     int32_t window = 0;
     int32_t* h_fit = nullptr;                // pinned, host DetermineElite
     unsigned long long* h_key = nullptr;     // pinned, host DetermineElite
@@ -258,6 +276,22 @@ static void inst_release(qieo_inst* h)
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
+}
+
+// The handle's work shape when the caller sets none: the tuning database's
+// entry for its bucket, else the built-in rule.  Binary64 amplitudes take
+// twice the registers per gene: at most 2 rows and 4 waves per workgroup,
+// prefetch, non-temporal stores (its 32-byte non-temporal loads were slower
+// in every binary64 shape measured).
+static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
+{
+    if (h->f64 || !tuned_tile(h->np, h->L.nchunk, R, S, F))
+        pick_tile(h->np, h->L.nchunk, R, S, F, h->f64 ? 8 : 4);
+    if (h->f64) {
+        *R = std::min(*R, 2);
+        *S = std::min(*S, 4);
+        *F = (*F & ~kFlagNontemporalLoads & ~kFlagPrefetch) | (h->L.nchunk > *S ? kFlagPrefetch : 0);
+    }
 }
 
 static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity,
@@ -322,13 +356,8 @@ static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity
         inst_release(h);
         return rc;
     }
-    if (f64 || !tuned_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags))
-        pick_tile(n_pop, h->L.nchunk, &h->R, &h->S, &h->flags);
-    if (f64) {
-        // twice the registers per gene: at most 2 rows per workgroup
-        h->R = std::min(h->R, 2);
-        h->persistent = 0;
-    }
+    default_shape(h, &h->R, &h->S, &h->flags);
+    if (f64) h->persistent = 0;
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         rc = hip_fail(e, "hipStreamSynchronize");
         inst_release(h);
@@ -412,6 +441,38 @@ static int host_elite(qieo_inst* h, int64_t t)
     return QIEO_OK;
 }
 
+// Captures the n fused launches of one call (and the finishing launch) into
+// h->graph.  Relaxed mode: the sequence holds kernel launches only.  If the
+// capture does not complete (another thread's device-wide call can
+// invalidate a capture in progress), h->graph stays NULL and the caller
+// enqueues the same launches directly; the error state is left clear.
+static void capture_call(qieo_inst* h, int32_t n, int blocks)
+{
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_n = -1;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipError_t le = hipSuccess;
+    for (int32_t k = 0; k < n && le == hipSuccess; ++k)
+        le = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
+                               h->stream);
+    if (le == hipSuccess) le = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream);
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    hipGraphExec_t x = nullptr;
+    if (le == hipSuccess && e == hipSuccess && g &&
+        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+        h->graph = x;
+        h->graph_n = n;
+        h->graph_key = (h->R * 32 + h->S) * 32 + h->flags;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+}
+
 extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
 {
     clear_error();
@@ -460,41 +521,24 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         h->t += n;
         return QIEO_OK;
     }
-    // fused per-generation launches: replay one captured graph per call
+    // fused per-generation launches: replay one captured graph per call.  A
+    // call is captured once it repeats (same generation count, same shape and
+    // variant as the previous call): capturing a one-off call costs more than
+    // launching it.
     if (h->pipeline == QIEO_PIPELINE_FUSED && h->use_graph && !h->timing && n >= 2) {
-        const int key = (h->R * 32 + h->S) * 4 + h->flags;
-        if (h->graph_n != n || h->graph_key != key) {
-            if (h->graph) (void)hipGraphExecDestroy(h->graph);
-            h->graph = nullptr;
-            h->graph_n = -1;
-            hipGraph_t g = nullptr;
-            if ((e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal)) !=
-                hipSuccess)
-                return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = hipSuccess;
-            for (int32_t k = 0; k < n && le == hipSuccess; ++k)
-                le = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k,
-                                       nullptr, n, h->stream);
-            if (le == hipSuccess) le = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream);
-            e = hipStreamEndCapture(h->stream, &g);
-            if (le != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return hip_fail(le, "captured launch");
-            }
-            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-            e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                h->graph = nullptr;
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            h->graph_n = n;
-            h->graph_key = key;
+        const int key = (h->R * 32 + h->S) * 32 + h->flags;
+        const bool cached = h->graph && h->graph_n == n && h->graph_key == key;
+        const bool repeat = h->prev_n == n && h->prev_key == key;
+        h->prev_n = n;
+        h->prev_key = key;
+        if (!cached && repeat) capture_call(h, n, blocks);
+        if (h->graph && h->graph_n == n && h->graph_key == key) {
+            if ((e = hipGraphLaunch(h->graph, h->stream)) != hipSuccess)
+                return hip_fail(e, "hipGraphLaunch");
+            h->t += n;
+            return QIEO_OK;
         }
-        if ((e = hipGraphLaunch(h->graph, h->stream)) != hipSuccess)
-            return hip_fail(e, "hipGraphLaunch");
-        h->t += n;
-        return QIEO_OK;
+        // no graph (the capture was lost): the same launches, enqueued directly
     }
     // stage list of one generation
     int stages[4], nst = 0;
@@ -591,6 +635,16 @@ extern "C" int qieo_converged(qieo_inst* h, int32_t* converged, int64_t* generat
 
 namespace qieo {
 
+// A small copy ordered on the instance's stream and waited for.  Plain
+// hipMemcpy would go through the null stream, a device-wide operation that
+// can disturb another thread's graph capture.
+hipError_t copy_on(void* dst, const void* src, size_t n, hipMemcpyKind kind, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, n, kind, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
 // Temporary device buffer for reads of an instance's state.
 struct TempDev {
     void* p = nullptr;
@@ -616,8 +670,8 @@ int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* ou
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     int32_t rec[8];
-    if ((e = hipMemcpy(rec, d.best, sizeof rec, hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy(best)");
+    if ((e = copy_on(rec, d.best, sizeof rec, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy(best)");
     if (!rec[0]) {
         *out = qieo_result{0, 0, 0, 0, -1, -1};
         if (bits) std::memset(bits, 0, need * sizeof(uint32_t));
@@ -645,8 +699,8 @@ int read_generations(const InstDev& d, hipStream_t s, int64_t* t)
 {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if ((e = hipMemcpy(t, d.tbase, sizeof(int64_t), hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy(generation counter)");
+    if ((e = copy_on(t, d.tbase, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy(generation counter)");
     return QIEO_OK;
 }
 
@@ -655,8 +709,8 @@ int read_convergence(const InstDev& d, hipStream_t s, int32_t* converged, int64_
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     int32_t c[4];
-    if ((e = hipMemcpy(c, d.conv, sizeof c, hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy(convergence)");
+    if ((e = copy_on(c, d.conv, sizeof c, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy(convergence)");
     if (converged) *converged = c[3] > 0 ? c[0] : 0;
     if (generation)
         *generation = (c[3] > 0 && c[0]) ? (int64_t)(((uint64_t)(uint32_t)c[2] << 32) | (uint32_t)c[1])
@@ -668,8 +722,8 @@ int write_window(const InstDev& d, hipStream_t s, int32_t window)
 {
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if ((e = hipMemcpy(d.conv + 3, &window, sizeof window, hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy(window)");
+    if ((e = copy_on(d.conv + 3, &window, sizeof window, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "copy(window)");
     return QIEO_OK;
 }
 
@@ -688,9 +742,9 @@ int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
             *elite = -1;
         } else {
             unsigned long long key = 0;
-            if ((e = hipMemcpy(&key, d.ekey + (t - 1) % 3, sizeof key, hipMemcpyDeviceToHost)) !=
+            if ((e = copy_on(&key, d.ekey + (t - 1) % 3, sizeof key, hipMemcpyDeviceToHost, s)) !=
                 hipSuccess)
-                return hip_fail(e, "hipMemcpy(elite)");
+                return hip_fail(e, "copy(elite)");
             *elite = (int32_t)(~(uint32_t)key);
         }
     }
@@ -788,7 +842,7 @@ extern "C" int qieo_set_tile(qieo_inst* h, int32_t rows_per_block, int32_t waves
         return set_error(QIEO_EINVAL, "waves_per_block must be in [1, 16] (got %d)",
                          waves_per_block);
     int R, S, F;
-    if (!tuned_tile(h->np, h->L.nchunk, &R, &S, &F)) pick_tile(h->np, h->L.nchunk, &R, &S, &F);
+    default_shape(h, &R, &S, &F);
     h->R = rows_per_block ? rows_per_block : R;
     h->S = waves_per_block ? waves_per_block : S;
     return QIEO_OK;
@@ -798,7 +852,8 @@ extern "C" int qieo_set_kernel_flags(qieo_inst* h, int32_t flags)
 {
     clear_error();
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
-    if (flags < 0 || flags > 3) return set_error(QIEO_EINVAL, "flags must be in [0, 3] (got %d)", flags);
+    if (flags < 0 || flags > kFlagAll)
+        return set_error(QIEO_EINVAL, "flags must be in [0, %d] (got %d)", kFlagAll, flags);
     h->flags = flags;
     return QIEO_OK;
 }

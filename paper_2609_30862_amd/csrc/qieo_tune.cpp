@@ -124,7 +124,7 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
     for (int R : {1, 2, 4})
         for (int S : {2, 4, 8, 16}) {
             if (S > std::max(2, L.nchunk) && S != 2) continue;
-            for (int f = 0; f < 4; ++f) cand.push_back(Entry{R, S, f, 0.0});
+            for (int f = 0; f <= kFlagAll; ++f) cand.push_back(Entry{R, S, f, 0.0});
         }
     // one generation of warm-up (generation 0 reads beta only), then trials
     auto run = [&](const Entry& c, int gens, double* ms) -> int {
@@ -212,7 +212,7 @@ extern "C" int qieo_tune_db_load(const char* path)
         if (std::sscanf(p, "\"np_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, \"S\": %d, "
                            "\"flags\": %d, \"ms\": %lf", &a, &b, &R, &S, &fl, &ms) != 6)
             continue;
-        if ((R != 1 && R != 2 && R != 4) || S < 1 || S > 16 || fl < 0 || fl > 3) continue;
+        if ((R != 1 && R != 2 && R != 4) || S < 1 || S > 16 || fl < 0 || fl > kFlagAll) continue;
         loaded[{a, b}] = Entry{R, S, fl, ms};
         ++n;
     }

@@ -53,7 +53,9 @@ def test_batch_matches_oracle_with_uneven_generation_counts(qieo, oracle_mod):
     b = qieo.Batch(_problems(insts))
     orcs = [oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
     n = len(insts)
-    for call, gens in enumerate([[1] * n, [k % 4 for k in range(n)], [(3 * k) % 7 for k in range(n)],
+    # calls 2 and 3 repeat call 1's longest count: captured, then replayed
+    for call, gens in enumerate([[1] * n, [k % 4 for k in range(n)], [(k + 1) % 4 for k in range(n)],
+                                 [(k + 2) % 4 for k in range(n)], [(3 * k) % 7 for k in range(n)],
                                  [0] * n, [5] * n]):
         say("batch call %d gens %s" % (call, gens))
         b.step(gens)
@@ -80,7 +82,10 @@ def test_batch_modes_are_identical(qieo, mode):
         f = int(mode.split("f")[1]) if "f" in mode else 0
         alt.set_tile(R, S, f)
     say("batch mode %s" % mode)
-    for gens in ([3] * len(insts), [k % 3 for k in range(len(insts))]):
+    # the second call repeats the first's longest count (captured), the third
+    # replays that graph with other per-instance counts
+    for gens in ([3] * len(insts), [k % 4 for k in range(len(insts))],
+                 [(k + 1) % 4 for k in range(len(insts))]):
         ref.step(gens)
         alt.step(gens)
     for k in range(len(insts)):

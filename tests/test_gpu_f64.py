@@ -37,7 +37,8 @@ def test_f64_every_generation(qieo, oracle_mod, ng, n_pop):
     assert_state_equal(g, o, label="f64 gen 55")
 
 
-@pytest.mark.parametrize("tile,flags", [((1, 4), 0), ((2, 8), 3), ((4, 2), 1)])
+@pytest.mark.parametrize("tile,flags", [((1, 4), 0), ((2, 8), 3), ((4, 2), 1), ((4, 8), 6),
+                                        ((2, 4), 7)])
 def test_f64_work_shapes(qieo, oracle_mod, tile, flags):
     inst = workloads.random_instance(2000, 19, seed=6)
     g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,

@@ -73,7 +73,9 @@ def test_ragged_shapes_every_generation(qieo, oracle_mod, ng, n_pop):
 
 
 @pytest.mark.parametrize("tile,flags", [((1, 1), 0), ((1, 3), 1), ((2, 2), 2), ((2, 16), 3),
-                                        ((4, 1), 1), ((4, 5), 3), ((4, 16), 0), ((1, 8), 3)])
+                                        ((4, 1), 1), ((4, 5), 3), ((4, 16), 0), ((1, 8), 3),
+                                        ((1, 2), 4), ((2, 4), 8), ((4, 8), 15), ((4, 3), 12),
+                                        ((2, 8), 11), ((1, 16), 9)])
 def test_work_shapes_same_trajectory(qieo, oracle_mod, tile, flags):
     inst = workloads.random_instance(1500, 23, seed=99)
     say("tile %s flags %d" % (tile, flags))
@@ -209,15 +211,55 @@ def test_persistent_path_same_trajectory(qieo, oracle_mod, ng, n_pop, mode):
 
 @pytest.mark.parametrize("graph", [0, 1])
 def test_graph_replay_same_trajectory(qieo, oracle_mod, graph):
-    """Captured-graph replay of whole calls (same n twice, then another n,
-    then a shape change) follows the oracle."""
+    """Captured-graph replay of whole calls (a call is captured when it
+    repeats: same n three times, another n, a shape change) follows the
+    oracle."""
     inst = workloads.random_instance(6000, 40, seed=12)
     g, o = _pair(qieo, oracle_mod, inst)
     g.set_persistent(0)
     g.set_graph(graph)
-    for n, tile in ((5, None), (5, None), (3, None), (5, (2, 4)), (5, (2, 4))):
+    for n, tile in ((5, None), (5, None), (5, None), (3, None), (3, None), (5, (2, 4)),
+                    (5, (2, 4)), (5, (2, 4))):
         if tile:
             g.set_tile(*tile)
         g.step(n)
         o.run(n)
         assert_state_equal(g, o, label="graph %d t=%d" % (graph, o.t))
+
+
+def test_graph_capture_with_concurrent_device_calls(qieo, oracle_mod):
+    """A call whose graph capture overlaps another thread's allocations,
+    frees and copies (a server or a second instance) still runs every
+    generation once: the capture either completes or the same launches are
+    enqueued directly."""
+    import threading
+    inst = workloads.random_instance(3000, 24, seed=14)
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_persistent(0)
+    g.set_graph(1)
+    stop = threading.Event()
+    errors = []
+
+    def churn():
+        other = workloads.random_instance(500, 8, seed=15)
+        try:
+            while not stop.is_set():
+                h = qieo.Instance(other.values, other.weights, other.capacity, other.n_pop,
+                                  other.seed)
+                h.step(1)
+                h.best()
+                h.close()
+        except Exception as exc:            # reported by the main thread
+            errors.append(exc)
+
+    th = threading.Thread(target=churn)
+    th.start()
+    try:
+        for n in (2, 2, 3, 3, 4, 4, 7, 7, 9, 9, 9):    # a new capture on every repeat
+            g.step(n)
+            o.run(n)
+            assert_state_equal(g, o, label="concurrent capture t=%d" % o.t)
+    finally:
+        stop.set()
+        th.join()
+    assert not errors, errors

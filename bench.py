@@ -54,20 +54,30 @@ def measured_traffic(n_pop: int, n_items: int):
         return None
 
 
-def cpu_baseline(inst, rows: int, gens: int):
-    """The CPU oracle, untuned and single-threaded, on a bounded sample of the
-    same workload: the first `rows` chromosomes of the population over the
-    full item list, for `gens` generations."""
+def cpu_baseline(inst, rows: int, gens: int, threads: int = 1):
+    """The CPU oracle, untuned, on a bounded sample of the same workload: the
+    first `rows` chromosomes of the population over the full item list, for
+    `gens` generations, on `threads` host threads (rows split among them)."""
     import oracle
-    o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed, threads=1)
+    o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed,
+                      threads=threads)
     o.run(1)                    # generation 0 observes only; time full generations
     t0 = time.perf_counter()
     o.run(gens)
     dt = time.perf_counter() - t0
-    return {"value": rows * inst.n_items * gens / dt, "unit": "gene-updates/s", "cores": 1,
+    return {"value": rows * inst.n_items * gens / dt, "unit": "gene-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "first %d of %d chromosomes x %d items, %d generations after "
                       "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt)}
+
+
+def host_threads() -> int:
+    """Host threads the process may use (its CPU affinity, at most 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def bench_batch(args):
@@ -426,6 +436,11 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows x %d generations" % (args.cpu_rows, args.cpu_gens))
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows, args.cpu_gens)
+        nt = host_threads()
+        log("cpu baseline: oracle on %d threads, %d rows x %d generations"
+            % (nt, args.cpu_rows * nt, args.cpu_gens))
+        out["cpu_baseline_threads"] = cpu_baseline(inst, min(inst.n_pop, args.cpu_rows * nt),
+                                                   args.cpu_gens, threads=nt)
     print(json.dumps(out), flush=True)
 
 

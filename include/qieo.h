@@ -156,6 +156,24 @@ int qieo_export_rows(qieo_inst *h, int32_t row0, int32_t n_rows,
                      int32_t *fitness, int32_t *profit, int32_t *weight,
                      int32_t *elite);
 
+/* Checkpoint and resume of the whole state between two generations (the
+ * population Q of Fig. 1, the generation counter, the best-so-far record and
+ * the convergence history).  qieo_state_size gives the bytes of a snapshot;
+ * qieo_export_state writes one into a caller-owned host buffer of at least
+ * that size: a versioned header (problem shape, seed, a hash of the items,
+ * precision, generations done) followed by the device state, including the
+ * last generation's rotation still pending.  qieo_import_state loads a
+ * snapshot into a handle created with the same items, capacity, n_pop, seed
+ * and precision (its own earlier state is replaced); the handle then
+ * continues the trajectory bit for bit as if it had run the exported
+ * generations itself.  A snapshot of another problem, precision or version,
+ * or a short buffer, gives QIEO_EINVAL and leaves the handle unchanged; a
+ * snapshot with a convergence window needs the fused pipeline (QIEO_ESTATE).
+ * Both wait for the handle's stream. */
+int qieo_state_size(qieo_inst *h, size_t *bytes);
+int qieo_export_state(qieo_inst *h, void *buf, size_t bytes);
+int qieo_import_state(qieo_inst *h, const void *buf, size_t bytes);
+
 /* qieo_export_rows for a binary64 instance (alpha, beta as doubles). */
 int qieo_export_rows_f64(qieo_inst *h, int32_t row0, int32_t n_rows,
                          double *alpha, double *beta, uint8_t *alleles,

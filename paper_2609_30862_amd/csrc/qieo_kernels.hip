@@ -13,8 +13,8 @@
 // wavefronts split each row into 256-gene chunks (wave w takes chunks w, w+S,
 // ...), so Evaluation's gene-axis reduction (eq. (1)) closes inside the
 // workgroup: wave shuffles, then LDS across the S waves, then one 64-bit
-// atomicMax per row for DetermineElite.  No cross-workgroup partial sums, no
-// tickets, no memory fences.
+// atomicMax per row that can still win, for DetermineElite.  No
+// cross-workgroup partial sums, no tickets, no memory fences.
 //
 // Per lane and chunk: 4 consecutive genes = one float4 of beta (and alpha
 // when the row rotates) = one Philox4x32-10 call.  The observed alleles of a
@@ -50,6 +50,19 @@ __device__ __forceinline__ unsigned long long make_key(int32_t f, int32_t row)
 {
     return ((unsigned long long)((uint32_t)f ^ 0x80000000u) << 32) |
            (unsigned long long)(~(uint32_t)row);
+}
+
+// Offers a row's key to the generation's elite slot.  Device-scope atomics
+// on one address serialise at the memory side (about 12 ns per wave
+// instruction on MI355X: 4096 rows cost 48 us), so the slot is read first
+// and the atomic issued only by a key that can still win; the slot only
+// grows during a generation, so a key not above a value once read is never
+// the maximum and skipping it leaves the result unchanged.
+__device__ __forceinline__ void offer_key(unsigned long long* slot, unsigned long long key)
+{
+    const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (key > cur) atomicMax(slot, key);
 }
 
 // Best-so-far update for generation tg whose elite is (e, fe).  Executed by
@@ -350,7 +363,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         I.prof[slot] = Pi;
         I.wt[slot] = Wi;
         // DetermineElite: the largest key is the largest fitness, lowest row.
-        if (kDe) atomicMax(&I.ekey[t % 3], make_key(f, c));
+        if (kDe) offer_key(&I.ekey[t % 3], make_key(f, c));
     }
 }
 
@@ -642,7 +655,7 @@ __global__ __launch_bounds__(64) void chromosome_kernel(const InstDev* __restric
     I.fit[slot] = f;
     I.prof[slot] = Pi;
     I.wt[slot] = Wi;
-    atomicMax(&I.ekey[t % 3], make_key(f, c));
+    offer_key(&I.ekey[t % 3], make_key(f, c));
 }
 
 hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s)

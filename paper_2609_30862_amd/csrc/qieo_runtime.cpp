@@ -223,6 +223,7 @@ struct qieo_inst {
     InstDev* h_desc = nullptr;   // pinned host staging of the descriptor
     int32_t ng = 0, np = 0, capacity = 0;
     uint64_t seed = 0;
+    uint64_t items_hash = 0;     // FNV-1a of the item array (checkpoint identity)
     int64_t t = 0;               // generations enqueued so far
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
@@ -294,6 +295,19 @@ static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
     }
 }
 
+// FNV-1a (64-bit) over the item array: identifies the problem a snapshot
+// belongs to.
+static uint64_t items_fnv1a(const qieo_item* items, int32_t n)
+{
+    uint64_t x = 0xcbf29ce484222325ull;
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(items);
+    for (size_t k = 0; k < (size_t)n * sizeof(qieo_item); ++k) {
+        x ^= p[k];
+        x *= 0x100000001b3ull;
+    }
+    return x;
+}
+
 static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity,
                        int32_t n_pop, uint64_t seed, const qieo_dev_ctx* ctx, bool f64,
                        qieo_inst** out)
@@ -329,6 +343,7 @@ static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity
     h->np = n_pop;
     h->capacity = capacity;
     h->seed = seed;
+    h->items_hash = items_fnv1a(items, n_items);
     h->f64 = f64;
     arena_layout(n_items, n_pop, &h->L, f64 ? 8 : 4);
     h->arena = (char*)dev_alloc(h, h->L.total);
@@ -966,3 +981,101 @@ extern "C" const char* qieo_strerror(int code)
 extern "C" const char* qieo_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char* qieo_version(void) { return "libqieo 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// Checkpoint and resume.  A snapshot is a fixed header followed by the whole
+// device arena: amplitude planes (the last generation's rotation still
+// pending), allele words, item tables, fitness slots, elite keys, best record
+// and bits, generation counter and convergence state.  Loading it into a
+// handle of the same problem restores every value the kernels read, so the
+// trajectory continues bit for bit.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct StateHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t elem_bytes;
+    int32_t n_items, n_pop, capacity, reserved;
+    uint64_t seed;
+    uint64_t items_hash;
+    int64_t generations;
+    uint64_t arena_bytes;
+};
+constexpr char kStateMagic[8] = {'Q', 'I', 'E', 'O', 'S', 'T', 'A', 'T'};
+constexpr uint32_t kStateVersion = 1;
+
+}  // namespace
+
+extern "C" int qieo_state_size(qieo_inst* h, size_t* bytes)
+{
+    clear_error();
+    if (!h || !bytes) return set_error(QIEO_EINVAL, "NULL argument");
+    *bytes = sizeof(StateHeader) + h->L.total;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_export_state(qieo_inst* h, void* buf, size_t bytes)
+{
+    clear_error();
+    if (!h || !buf) return set_error(QIEO_EINVAL, "NULL argument");
+    const size_t need = sizeof(StateHeader) + h->L.total;
+    if (bytes < need)
+        return set_error(QIEO_EINVAL, "state buffer has %zu bytes, needs %zu", bytes, need);
+    int64_t t = 0;
+    int rc = read_generations(h->d, h->stream, &t);
+    if (rc) return rc;
+    StateHeader hd{};
+    std::memcpy(hd.magic, kStateMagic, sizeof hd.magic);
+    hd.version = kStateVersion;
+    hd.elem_bytes = h->f64 ? 8u : 4u;
+    hd.n_items = h->ng;
+    hd.n_pop = h->np;
+    hd.capacity = h->capacity;
+    hd.seed = h->seed;
+    hd.items_hash = h->items_hash;
+    hd.generations = t;
+    hd.arena_bytes = h->L.total;
+    std::memcpy(buf, &hd, sizeof hd);
+    hipError_t e = copy_on((char*)buf + sizeof hd, h->arena, h->L.total, hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy(state)");
+    return QIEO_OK;
+}
+
+extern "C" int qieo_import_state(qieo_inst* h, const void* buf, size_t bytes)
+{
+    clear_error();
+    if (!h || !buf) return set_error(QIEO_EINVAL, "NULL argument");
+    if (bytes < sizeof(StateHeader)) return set_error(QIEO_EINVAL, "state buffer too short");
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, kStateMagic, sizeof hd.magic) != 0 || hd.version != kStateVersion)
+        return set_error(QIEO_EINVAL, "not a libqieo state snapshot (or another version)");
+    if (hd.elem_bytes != (h->f64 ? 8u : 4u))
+        return set_error(QIEO_EINVAL, "snapshot precision differs from the handle's");
+    if (hd.n_items != h->ng || hd.n_pop != h->np || hd.capacity != h->capacity ||
+        hd.seed != h->seed || hd.items_hash != h->items_hash)
+        return set_error(QIEO_EINVAL, "snapshot belongs to another problem (items, capacity, "
+                                      "population size or seed differ)");
+    if (hd.arena_bytes != h->L.total || bytes < sizeof hd + hd.arena_bytes)
+        return set_error(QIEO_EINVAL, "snapshot size does not match the handle's state");
+    const char* body = (const char*)buf + sizeof hd;
+    int64_t tb;
+    int32_t window;
+    std::memcpy(&tb, body + h->L.tbase, sizeof tb);
+    std::memcpy(&window, body + h->L.conv + 3 * sizeof(int32_t), sizeof window);
+    if (tb != hd.generations || tb < 0 || tb > (int64_t)INT32_MAX || window < 0 ||
+        window > kConvRing)
+        return set_error(QIEO_EINVAL, "snapshot is inconsistent");
+    if (window > 0 && h->pipeline != QIEO_PIPELINE_FUSED)
+        return set_error(QIEO_ESTATE, "snapshot has a convergence window: select the fused "
+                                      "pipeline first");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = copy_on(h->arena, body, h->L.total, hipMemcpyHostToDevice, h->stream)) != hipSuccess)
+        return hip_fail(e, "copy(state)");
+    h->t = tb;
+    h->window = window;
+    return QIEO_OK;
+}

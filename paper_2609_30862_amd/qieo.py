@@ -96,6 +96,12 @@ def _load():
     L.qieo_create_f64.restype = ctypes.c_int
     L.qieo_create_f64.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(qieo_dev_ctx),
                                   ctypes.POINTER(H)]
+    L.qieo_state_size.restype = ctypes.c_int
+    L.qieo_state_size.argtypes = [H, ctypes.POINTER(ctypes.c_size_t)]
+    L.qieo_export_state.restype = ctypes.c_int
+    L.qieo_export_state.argtypes = [H, P, ctypes.c_size_t]
+    L.qieo_import_state.restype = ctypes.c_int
+    L.qieo_import_state.argtypes = [H, P, ctypes.c_size_t]
     L.qieo_export_rows_f64.restype = ctypes.c_int
     L.qieo_export_rows_f64.argtypes = [H, i32, i32, P, P, P, P, P, P, ctypes.POINTER(i32)]
     L.qieo_create_ex.restype = ctypes.c_int
@@ -387,6 +393,19 @@ class Instance:
         r, bits = qieo_best(self._h, self.n_items)
         return Result(r.fitness, r.profit, r.weight, bool(r.feasible), r.generation,
                       r.chromosome, bits)
+
+    def export_state(self) -> np.ndarray:
+        """Snapshot of the whole state (uint8 array) for import_state."""
+        n = ctypes.c_size_t(0)
+        _check(lib.qieo_state_size(self._h, ctypes.byref(n)), "qieo_state_size")
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib.qieo_export_state(self._h, _ptr(buf), buf.nbytes), "qieo_export_state")
+        return buf
+
+    def import_state(self, buf):
+        """Continues from a snapshot taken by export_state on the same problem."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib.qieo_import_state(self._h, _ptr(buf), buf.nbytes), "qieo_import_state")
 
     def export_rows(self, row0: int = 0, n_rows: int | None = None, amplitudes: bool = True,
                     alleles: bool = True):

@@ -278,17 +278,20 @@ def bench_fractions(args):
 def bench_launch(args):
     """Small and medium single instances, where launch overhead matters: time
     per generation with one launch per generation, with graph replay of the
-    whole call, and with the persistent single-workgroup path."""
+    whole call, with the single-workgroup loop from LDS where the state fits
+    (persistent mode 1; per-generation launches otherwise), and with the
+    single-workgroup loop from global memory (mode 2, where LDS is too small)."""
     import torch
     import workloads
     from paper_2609_30862_amd import qieo
 
-    shapes = [(16, 100), (32, 500), (64, 1000), (128, 500), (256, 500), (64, 4000),
-              (256, 2000), (1024, 10_000)]
+    shapes = [(16, 100), (32, 500), (64, 100), (64, 1000), (128, 500), (24, 5000), (256, 500),
+              (64, 4000), (256, 2000), (1024, 10_000)]
     for (np_, ng) in shapes:
         inst = workloads.random_instance(ng, np_, seed=ng + np_)
         cell = {"n_pop": np_, "n_items": ng}
-        for name, graph, pers in (("launches", 0, 0), ("graph", 1, 0), ("persistent", 0, 2)):
+        for name, graph, pers in (("launches", 0, 0), ("graph", 1, 0), ("persistent", 0, 1),
+                                  ("persistent_any", 0, 2)):
             g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
             g.set_graph(graph)
             g.set_persistent(pers)
@@ -299,8 +302,9 @@ def bench_launch(args):
             g.step(500)
             cell[name] = (time.perf_counter() - t0) / 500 * 1e6
             g.close()
-        log("Np=%5d Ng=%6d  us/generation: launches %.2f  graph %.2f  persistent %.2f"
-            % (np_, ng, cell["launches"], cell["graph"], cell["persistent"]))
+        log("Np=%5d Ng=%6d  us/generation: launches %.2f  graph %.2f  persistent (LDS) %.2f  "
+            "persistent (any) %.2f" % (np_, ng, cell["launches"], cell["graph"], cell["persistent"],
+                                       cell["persistent_any"]))
         print(json.dumps(cell), flush=True)
 
 
@@ -337,9 +341,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(instances are independent; see the sharding design). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: libqieo runs each population on one GPU "
+              "and has no multi-GPU path (independent instances would be routed to GPUs "
+              "with no communication). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

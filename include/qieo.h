@@ -253,8 +253,8 @@ int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per
  * device-wide call invalidates falls back to direct launches.  Results are
  * identical. */
 int qieo_batch_set_graph(qieo_batch *b, int32_t enabled);
-/* 1 (default): members small enough for the persistent path (see
- * qieo_set_persistent) run as one workgroup each for the whole call,
+/* 1 (default): members whose whole state fits in one workgroup's LDS (see
+ * qieo_set_persistent, mode 1) run as one workgroup each for the whole call,
  * concurrently with the per-generation launches of the others; 0: all
  * members use per-generation launches.  Results are identical. */
 int qieo_batch_set_persistent(qieo_batch *b, int32_t enabled);
@@ -308,10 +308,12 @@ void qieo_server_destroy(qieo_server *s);
 
 /* Persistent path for small populations: one single-workgroup launch runs all
  * generations of a qieo_step call, block barriers replacing launch
- * boundaries.  mode 0 (default): never; 1: when n_pop * (n_items rounded up
- * to 64) <= 65536 and n_pop <= 2048; 2: whenever n_pop <= 2048.  Results are
- * identical either way.  On MI355X a generation costs the workgroup about as
- * long as a back-to-back launch (~5 us), so the default is off. */
+ * boundaries.  mode 0: never; 1 (default): for tiny populations, where it is
+ * faster than launches: the whole state (amplitudes, allele words, item
+ * tables, fitness) fits in one workgroup's LDS, which holds it for the call,
+ * and n_pop * ceil(n_items / 256) <= 16; 2: whenever the state fits in LDS,
+ * else from global memory when n_pop <= 2048.  Results are identical in every
+ * mode. */
 int qieo_set_persistent(qieo_inst *h, int32_t mode);
 
 /* 1 (default): a qieo_step call of n >= 2 generations on the fused

@@ -155,6 +155,52 @@ __device__ __forceinline__ T sload(const T* p)
     return *(const QIEO_AS_CONST T*)p;
 }
 
+// ---------------------------------------------------------------------------
+// Wave64 reductions through DPP lane moves (quad permutes, row mirrors, then
+// the row broadcasts of lane 15 and 31), which stay in registers; the
+// complete result ends in lane 63 and is read from there.  Integer sums and
+// maxima do not depend on the order of combination.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    // lanes outside ROWS, or whose source is out of range, receive 0
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_dpp(uint32_t v)
+{
+    v += dpp_u32<0xb1, 0xf>(v);       // quad_perm [1,0,3,2]: pairs
+    v += dpp_u32<0x4e, 0xf>(v);       // quad_perm [2,3,0,1]: quads
+    v += dpp_u32<0x141, 0xf>(v);      // row_half_mirror: 8 lanes
+    v += dpp_u32<0x140, 0xf>(v);      // row_mirror: 16-lane rows
+    v += dpp_u32<0x142, 0xa>(v);      // row_bcast:15 into rows 1, 3
+    v += dpp_u32<0x143, 0xc>(v);      // row_bcast:31 into rows 2, 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_max_u64(uint64_t v)
+{
+    const uint64_t lo = dpp_u32<CTRL, ROWS>((uint32_t)v);
+    const uint64_t hi = dpp_u32<CTRL, ROWS>((uint32_t)(v >> 32));
+    const uint64_t o = (hi << 32) | lo;
+    return o > v ? o : v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64_dpp(uint64_t v)
+{
+    v = dpp_max_u64<0xb1, 0xf>(v);
+    v = dpp_max_u64<0x4e, 0xf>(v);
+    v = dpp_max_u64<0x141, 0xf>(v);
+    v = dpp_max_u64<0x140, 0xf>(v);
+    v = dpp_max_u64<0x142, 0xa>(v);
+    v = dpp_max_u64<0x143, 0xc>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p)
 {
     return __ballot(p);

@@ -22,6 +22,9 @@
 // eight 32-bit words and re-read as wave-uniform lane masks, so CIP's
 // per-gene tests (own allele vs elite allele, target) are scalar mask logic
 // and v_cndmask selects.
+#include <algorithm>
+#include <mutex>
+
 #include "qieo_device.hpp"
 #include "qieo_kernels.hpp"
 
@@ -29,12 +32,9 @@ namespace qieo {
 
 namespace {
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+// Wave sums and maxima stay in registers (DPP lane moves); the result is
+// wave-uniform.  Integer sums do not depend on the order of combination.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_sum_dpp(v); }
 
 __device__ __forceinline__ int32_t key_fitness(unsigned long long key)
 {
@@ -379,11 +379,7 @@ __global__ __launch_bounds__(1024) void de_kernel(const InstDev* __restrict__ in
         const unsigned long long key = make_key(I.fit[par * I.np + c], c);
         best = key > best ? key : best;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off, 64);
-        best = o > best ? o : best;
-    }
+    best = wave_max_u64_dpp(best);
     __shared__ unsigned long long red[16];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
     __syncthreads();
@@ -546,11 +542,7 @@ __global__ __launch_bounds__(1024) void persistent_kernel(const InstDev* __restr
             const unsigned long long key = make_key(f, c);
             best = key > best ? key : best;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const unsigned long long o = __shfl_xor(best, off, 64);
-            best = o > best ? o : best;
-        }
+        best = wave_max_u64_dpp(best);
         if (lane == 0) skey[wave] = best;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -559,6 +551,316 @@ __global__ __launch_bounds__(1024) void persistent_kernel(const InstDev* __restr
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident variant of the persistent loop, for populations whose whole
+// state fits in one workgroup's LDS: amplitudes, both allele slots, item
+// tables, fitness slots, the best-so-far bits and the convergence ring are
+// staged into LDS once, every generation of the call runs on them behind two
+// workgroup barriers, and the state the per-generation launches would have
+// left in global memory (planes, allele words, fitness, elite keys, best
+// record, convergence ring and flags) is written once at the end.  No global
+// store is issued inside the loop, so the barriers never wait on memory.
+// Results are those of the per-generation launches, bit for bit.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void resident_kernel(const InstDev* __restrict__ insts,
+                                                       const uint32_t* __restrict__ ids,
+                                                       const int32_t* __restrict__ gens_arr,
+                                                       int gens_all)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ unsigned long long skey[16];
+    __shared__ int32_t sring[kConvRing];
+
+    const uint32_t inst = ids ? ids[blockIdx.x] : 0u;
+    const InstDev I = insts[inst];
+    const int gens = gens_arr ? gens_arr[inst] : gens_all;
+    if (gens <= 0) return;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int S = nthr >> 6;
+    const int np = I.np, pitch = I.pitch, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
+    const int plane = np * pitch;
+    const int items = np * nchunk;
+
+    float* sA = reinterpret_cast<float*>(lds);
+    float* sB = sA + plane;
+    uint32_t* sX = reinterpret_cast<uint32_t*>(sB + plane);         // [2][np][wpr] by parity
+    uint32_t* sBest = sX + 2 * np * wpr;                             // [wpr] best-so-far bits
+    int32_t* sV = reinterpret_cast<int32_t*>(sBest + wpr);           // [nchunk * 256]
+    int32_t* sWt = sV + nchunk * kChunk;
+    int32_t* sF = sWt + nchunk * kChunk;                             // [2][np] fitness
+    int32_t* sPr = sF + 2 * np;                                      // [2][np] profit
+    int32_t* sWw = sPr + 2 * np;                                     // [2][np] weight
+    uint32_t* sP = reinterpret_cast<uint32_t*>(sWw + 2 * np);        // [2][np] sums by parity
+    uint32_t* sW = sP + 2 * np;
+
+    // stage the state in
+    {
+        const f32x4* ga = reinterpret_cast<const f32x4*>(I.alpha);
+        const f32x4* gb = reinterpret_cast<const f32x4*>(I.beta);
+        f32x4* la = reinterpret_cast<f32x4*>(sA);
+        f32x4* lb = reinterpret_cast<f32x4*>(sB);
+        for (int i = tid; i < plane / 4; i += nthr) { la[i] = ga[i]; lb[i] = gb[i]; }
+        for (int i = tid; i < 2 * np * wpr; i += nthr) sX[i] = I.xbits[i];
+        for (int i = tid; i < nchunk * kChunk; i += nthr) { sV[i] = I.v[i]; sWt[i] = I.w[i]; }
+        for (int i = tid; i < 2 * np; i += nthr) {
+            sF[i] = I.fit[i];
+            sPr[i] = I.prof[i];
+            sWw[i] = I.wt[i];
+            sP[i] = 0u;
+            sW[i] = 0u;
+        }
+        if (tid < kConvRing) sring[tid] = I.conv[8 + tid];
+    }
+    const int64_t t0 = *(const volatile int64_t*)I.tbase;
+    const int window = I.conv[3];
+    const bool conv_flag = window > 0 && I.conv[0] != 0;
+    // best-so-far record, kept by every thread alike; written back if changed
+    int has = I.best[0];
+    int32_t bf = I.best[1], bp = 0, bw = 0, be = 0;
+    int64_t bt = 0;
+    bool best_changed = false;
+    // elite keys of the last two generations (every thread keeps them)
+    unsigned long long elite = t0 > 0 ? *(const volatile unsigned long long*)(I.ekey + (t0 - 1) % 3)
+                                      : 0ull;
+    unsigned long long elite_before = 0ull;
+    __syncthreads();
+
+    int64_t t = t0;
+    bool stopped = false;
+    for (int k = 0; k < gens; ++k, ++t) {
+        const int par = (int)(t & 1);
+        const uint32_t* xprev = sX + (par ^ 1) * np * wpr;
+        uint32_t* xcur = sX + par * np * wpr;
+        uint32_t* sPc = sP + par * np;
+        uint32_t* sWc = sW + par * np;
+        const bool pending = t > 0;
+        const int32_t e_prev =
+            pending ? min(max(__builtin_amdgcn_readfirstlane(key_row(elite)), 0), np - 1) : 0;
+        const int32_t fe_prev =
+            pending ? __builtin_amdgcn_readfirstlane(key_fitness(elite)) : 0;
+        // the draws of the wave's first item depend on no state: start them
+        // before the state-dependent work
+        Draw4 d_first{0u, 0u, 0u, 0u};
+        if (wave < items) {
+            const int c = wave / nchunk, ch = wave - c * nchunk;
+            const uint32_t q = ((uint32_t)(ch * kChunk) + 4u * lane) >> 2;
+            d_first = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+        }
+        // termination test on the elite fitness history (every thread alike)
+        bool stop = false;
+        if (window > 0) {
+            if (conv_flag) {
+                stop = true;
+            } else if (pending && t >= window) {
+                stop = true;
+                for (int j = 1; j < window && stop; ++j)
+                    stop = sring[(int)((t - 1 - j) & (kConvRing - 1))] == fe_prev;
+            }
+        }
+        // bookkeeping of generation t-1, as the first launch of t does it
+        if (pending && !conv_flag && (!has || fe_prev > bf)) {
+            for (int i = tid; i < wpr; i += nthr) sBest[i] = xprev[e_prev * wpr + i];
+            const int slot = (par ^ 1) * np + e_prev;
+            has = 1;
+            bf = fe_prev;
+            bp = sPr[slot];
+            bw = sWw[slot];
+            bt = t - 1;
+            be = e_prev;
+            best_changed = true;
+        }
+        if (tid == 0 && window > 0 && pending && !conv_flag)
+            sring[(int)((t - 1) & (kConvRing - 1))] = fe_prev;
+        if (stop) {
+            stopped = true;
+            break;
+        }
+
+        for (int item = wave; item < items; item += S) {
+            const int c = item / nchunk, ch = item - c * nchunk;
+            const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
+            const bool act = g0 < (uint32_t)pitch;
+            const int gi = c * pitch + (act ? (int)g0 : 0);        // inside the row
+            const uint32_t q = g0 >> 2;
+            const bool rot =
+                pending && __builtin_amdgcn_readfirstlane(sF[(par ^ 1) * np + c]) < fe_prev;
+            f32x4 b4 = *reinterpret_cast<const f32x4*>(sB + gi);
+            f32x4 a4 = b4;
+            if (rot) {
+                a4 = *reinterpret_cast<const f32x4*>(sA + gi);
+                const uint64_t* bwd =
+                    reinterpret_cast<const uint64_t*>(xprev + e_prev * wpr + ch * kWordsPerChunk);
+                const uint64_t* xw =
+                    reinterpret_cast<const uint64_t*>(xprev + c * wpr + ch * kWordsPerChunk);
+                const uint64_t bm0 = uniform_mask(bwd[0]), bm1 = uniform_mask(bwd[1]);
+                const uint64_t bm2 = uniform_mask(bwd[2]), bm3 = uniform_mask(bwd[3]);
+                const uint64_t xm0 = uniform_mask(xw[0]), xm1 = uniform_mask(xw[1]);
+                const uint64_t xm2 = uniform_mask(xw[2]), xm3 = uniform_mask(xw[3]);
+                float a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
+                float b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
+                cip_gene(a0, b0, xm0 ^ bm0, bm0);
+                cip_gene(a1, b1, xm1 ^ bm1, bm1);
+                cip_gene(a2, b2, xm2 ^ bm2, bm2);
+                cip_gene(a3, b3, xm3 ^ bm3, bm3);
+                a4 = f32x4{a0, a1, a2, a3};
+                b4 = f32x4{b0, b1, b2, b3};
+            }
+            const Draw4 d = item == wave ? d_first
+                                         : philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u,
+                                                         I.seed_lo, I.seed_hi);
+            const bool x0 = act && observe(d.r0, b4.x);
+            const bool x1 = act && observe(d.r1, b4.y);
+            const bool x2 = act && observe(d.r2, b4.z);
+            const bool x3 = act && observe(d.r3, b4.w);
+            const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
+            if (lane < kWordsPerChunk) {
+                const int j = lane >> 1;
+                const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
+                xcur[c * wpr + ch * kWordsPerChunk + lane] =
+                    (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
+            }
+            const int vi = act ? (int)g0 : 0;
+            const i32x4 v4 = *reinterpret_cast<const i32x4*>(sV + vi);
+            const i32x4 w4 = *reinterpret_cast<const i32x4*>(sWt + vi);
+            const uint32_t p = (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
+                               (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
+            const uint32_t w = (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
+                               (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+            const uint32_t ps = wave_sum(p);
+            const uint32_t ws = wave_sum(w);
+            if (lane == 0) {
+                if (nchunk == 1) {              // the wave owns the row's only chunk
+                    sPc[c] = ps;
+                    sWc[c] = ws;
+                } else {
+                    atomicAdd(&sPc[c], ps);
+                    atomicAdd(&sWc[c], ws);
+                }
+            }
+            if (rot && act) {
+                *reinterpret_cast<f32x4*>(sA + gi) = a4;
+                *reinterpret_cast<f32x4*>(sB + gi) = b4;
+            }
+        }
+        __syncthreads();
+        // Evaluation closes in LDS (and clears this parity's sums for t+2);
+        // DetermineElite is a block max of the keys
+        unsigned long long best = 0ull;
+        for (int c = tid; c < np; c += nthr) {
+            const int32_t Pi = (int32_t)sPc[c], Wi = (int32_t)sWc[c];
+            sPc[c] = 0u;
+            sWc[c] = 0u;
+            const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
+            const int slot = par * np + c;
+            sF[slot] = f;
+            sPr[slot] = Pi;
+            sWw[slot] = Wi;
+            const unsigned long long key = make_key(f, c);
+            best = key > best ? key : best;
+        }
+        best = wave_max_u64_dpp(best);
+        if (lane == 0) skey[wave] = best;
+        __syncthreads();
+        elite_before = elite;
+        elite = skey[0];
+        for (int w = 1; w < S; ++w) elite = skey[w] > elite ? skey[w] : elite;
+    }
+    __syncthreads();
+
+    // write the state back: what the per-generation launches of generations
+    // t0 .. t_end-1 (and, after a stop, the stopping launch) leave behind
+    const int64_t t_end = t;                        // generations completed: t_end - t0
+    {
+        f32x4* ga = reinterpret_cast<f32x4*>(I.alpha);
+        f32x4* gb = reinterpret_cast<f32x4*>(I.beta);
+        const f32x4* la = reinterpret_cast<const f32x4*>(sA);
+        const f32x4* lb = reinterpret_cast<const f32x4*>(sB);
+        for (int i = tid; i < plane / 4; i += nthr) { ga[i] = la[i]; gb[i] = lb[i]; }
+        for (int i = tid; i < 2 * np * wpr; i += nthr) I.xbits[i] = sX[i];
+        for (int i = tid; i < 2 * np; i += nthr) {
+            I.fit[i] = sF[i];
+            I.prof[i] = sPr[i];
+            I.wt[i] = sWw[i];
+        }
+        if (best_changed) {
+            for (int i = tid; i < wpr; i += nthr) I.best_bits[i] = sBest[i];
+            if (tid == 0) {
+                I.best[1] = bf;
+                I.best[2] = bp;
+                I.best[3] = bw;
+                I.best[4] = (int32_t)(uint32_t)(uint64_t)bt;
+                I.best[5] = (int32_t)(uint32_t)((uint64_t)bt >> 32);
+                I.best[6] = be;
+                I.best[0] = 1;
+            }
+        }
+        if (window > 0 && tid < kConvRing) I.conv[8 + tid] = sring[tid];
+        if (tid == 0) {
+            if (stopped && !conv_flag) {
+                I.conv[1] = (int32_t)(uint32_t)(uint64_t)(t_end - 1);
+                I.conv[2] = (int32_t)(uint32_t)((uint64_t)(t_end - 1) >> 32);
+                I.conv[0] = 1;
+            }
+            if (t_end > t0) {
+                I.ekey[(t_end - 1) % 3] = elite;
+                I.ekey[t_end % 3] = 0ull;
+                if (t_end - 2 >= t0) I.ekey[(t_end - 2) % 3] = elite_before;
+            }
+        }
+    }
+}
+
+size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk)
+{
+    const size_t wpr = (size_t)nchunk * kWordsPerChunk;
+    const size_t words = 2 * (size_t)np * pitch + 2 * (size_t)np * wpr + wpr +
+                         2 * (size_t)nchunk * kChunk + 10 * (size_t)np;
+    return words * sizeof(uint32_t);
+}
+
+size_t resident_lds_limit()
+{
+    static std::once_flag once;
+    static size_t usable = 0;
+    std::call_once(once, [] {
+        constexpr size_t kStatic = 1024;          // the kernel's own __shared__ variables
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess ||
+            (size_t)v <= kStatic) {
+            (void)hipGetLastError();
+            return;
+        }
+        const size_t want = (size_t)v - kStatic;
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&resident_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) ==
+            hipSuccess) {
+            usable = want;
+        } else {
+            (void)hipGetLastError();
+            usable = std::min<size_t>(want, 65536 - kStatic);
+        }
+    });
+    return usable;
+}
+
+hipError_t launch_resident(const InstDev* dI, const uint32_t* ids, int n_blocks,
+                           int waves_per_block, size_t lds_bytes, const int32_t* gens_arr,
+                           int gens_all, hipStream_t s)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    if (waves_per_block < 1 || waves_per_block > 16 || lds_bytes == 0 ||
+        lds_bytes > resident_lds_limit())
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(resident_kernel, dim3((unsigned)n_blocks),
+                       dim3((unsigned)(64 * waves_per_block)), lds_bytes, s, dI, ids, gens_arr,
+                       gens_all);
+    return hipGetLastError();
 }
 
 hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,

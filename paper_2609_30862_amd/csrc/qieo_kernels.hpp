@@ -96,6 +96,15 @@ hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int
 // call's last generation is left to launch_finish.
 constexpr int kPersistentMaxRows = 2048;          // LDS per-row sums
 constexpr int64_t kPersistentMaxGenes = 1 << 16;  // Np * pitch at or below which it pays
+// LDS-resident persistent loop: the whole state of each instance in one
+// workgroup's LDS (resident_lds_bytes of it) for the call.
+size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk);
+// Largest dynamic LDS the resident kernel may use on the current device
+// (0 if none); the first call opens the kernel up to it.
+size_t resident_lds_limit();
+hipError_t launch_resident(const InstDev* dI, const uint32_t* ids, int n_blocks,
+                           int waves_per_block, size_t lds_bytes, const int32_t* gens_arr,
+                           int gens_all, hipStream_t s);
 hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,
                              int waves_per_block, const int32_t* gens_arr, int gens_all,
                              hipStream_t s);

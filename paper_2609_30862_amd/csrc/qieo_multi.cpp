@@ -229,18 +229,23 @@ int Engine::rebuild()
                             stream_)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(descriptors)");
 
-    // small members run persistently (one workgroup for the whole call);
-    // the rest are grouped by shape class; within a class, longest rows first
-    // so the longest-running workgroups start first
+    // members whose whole state fits in one workgroup's LDS run the call
+    // there (one workgroup each); the rest are grouped by shape class; within
+    // a class, longest rows first so the longest-running workgroups start
+    // first
     pids_.clear();
+    pids_lds_ = 0;
+    const size_t lds_limit = use_persistent_ ? resident_lds_limit() : 0;
     std::vector<std::vector<size_t>> groups(4);
     for (size_t i = 0; i < n; ++i) {
         const Member& m = members_[i];
-        if (use_persistent_ && m.np <= kPersistentMaxRows &&
-            (int64_t)m.np * m.L.pitch <= kPersistentMaxGenes)
+        const size_t lds = resident_lds_bytes(m.np, m.L.pitch, m.L.nchunk);
+        if (use_persistent_ && lds <= lds_limit) {
             pids_.push_back((uint32_t)i);
-        else
+            pids_lds_ = std::max(pids_lds_, lds);
+        } else {
             groups[class_of(m.L.nchunk)].push_back(i);
+        }
     }
     if (d_pids_) (void)hipFree(d_pids_);
     d_pids_ = nullptr;
@@ -322,9 +327,9 @@ int Engine::enqueue(int nmax)
         if ((e = hipEventRecord(fork_, stream_)) != hipSuccess ||
             (e = hipStreamWaitEvent(side_, fork_, 0)) != hipSuccess)
             return hip_fail(e, "fork");
-        if ((e = launch_persistent(d_desc_, d_pids_, (int)pids_.size(), 8, d_gens_, 0, side_)) !=
-            hipSuccess)
-            return hip_fail(e, "persistent kernel");
+        if ((e = launch_resident(d_desc_, d_pids_, (int)pids_.size(), 8, pids_lds_, d_gens_, 0,
+                                 side_)) != hipSuccess)
+            return hip_fail(e, "resident kernel");
         if ((e = hipEventRecord(join_, side_)) != hipSuccess) return hip_fail(e, "join");
     }
     for (int k = 0; k < nmax; ++k) {

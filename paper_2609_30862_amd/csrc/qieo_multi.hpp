@@ -106,7 +106,8 @@ private:
     std::vector<ShapeClass> classes_;
     // small members: one persistent workgroup each, on a side stream forked
     // from and joined back into the main one
-    std::vector<uint32_t> pids_;
+    std::vector<uint32_t> pids_;     // members run by the LDS-resident kernel
+    size_t pids_lds_ = 0;            // its dynamic LDS (the largest member's need)
     uint32_t* d_pids_ = nullptr;
     hipStream_t side_ = nullptr;
     hipEvent_t fork_ = nullptr, join_ = nullptr;

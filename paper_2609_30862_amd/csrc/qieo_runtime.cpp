@@ -228,7 +228,7 @@ struct qieo_inst {
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
     bool f64 = false;            // binary64 amplitudes
-    int persistent = 0;          // 0 never (default), 1 when small enough, 2 whenever rows fit
+    int persistent = 1;          // 0 never, 1 (default) when the state fits LDS, 2 whenever rows fit
     bool use_graph = true;       // replay a captured graph of a call's launches
     hipGraphExec_t graph = nullptr;
     int32_t graph_n = -1;        // generations the cached graph runs
@@ -516,10 +516,17 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         h->t += n;
         return QIEO_OK;
     }
-    // small populations: the whole call in one single-workgroup launch
-    const bool small = (int64_t)h->np * h->L.pitch <= kPersistentMaxGenes;
-    if (h->pipeline == QIEO_PIPELINE_FUSED && h->np <= kPersistentMaxRows &&
-        (h->persistent == 2 || (h->persistent == 1 && small))) {
+    // small populations: the whole call in one single-workgroup launch, from
+    // LDS when the whole state fits there.  Mode 1 takes it only where it
+    // measured faster than launches: at most one (row, chunk) item per wave,
+    // since a wave's items run one after another, each a long dependent chain
+    // (2.5 us), while launches spread them over the whole chip.
+    const size_t lds = resident_lds_bytes(h->np, h->L.pitch, h->L.nchunk);
+    const int64_t items = (int64_t)h->np * h->L.nchunk;
+    const bool fits_lds = (h->persistent == 2 || (h->persistent == 1 && items <= 16)) &&
+                          lds <= resident_lds_limit();
+    if (h->pipeline == QIEO_PIPELINE_FUSED &&
+        (fits_lds || (h->persistent == 2 && h->np <= kPersistentMaxRows))) {
         hipEvent_t a = nullptr, b = nullptr;
         if (h->timing) {
             int rc = timed_event_pair(h, 0, &a, &b);
@@ -527,9 +534,9 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
             (void)hipEventRecord(a, h->stream);
         }
         const int waves = (int)std::min<int64_t>(16, (int64_t)h->np * h->L.nchunk);
-        if ((e = launch_persistent(h->d_desc, nullptr, 1, waves, nullptr, n, h->stream)) !=
-            hipSuccess)
-            return hip_fail(e, "persistent kernel");
+        e = fits_lds ? launch_resident(h->d_desc, nullptr, 1, waves, lds, nullptr, n, h->stream)
+                     : launch_persistent(h->d_desc, nullptr, 1, waves, nullptr, n, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "persistent kernel");
         if (h->timing) (void)hipEventRecord(b, h->stream);
         if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
             return hip_fail(e, "finish kernel");

@@ -74,4 +74,11 @@ def test_null_handles_are_rejected():
     assert L.qieo_step(None, 1) == qieo.QIEO_EINVAL
     assert L.qieo_sync(None) == qieo.QIEO_EINVAL
     assert L.qieo_set_tile(None, 1, 1) == qieo.QIEO_EINVAL
+    n = ctypes.c_size_t(0)
+    assert L.qieo_state_size(None, ctypes.byref(n)) == qieo.QIEO_EINVAL
+    buf = np.zeros(64, np.uint8)
+    assert L.qieo_export_state(None, buf.ctypes.data_as(ctypes.c_void_p), 64) == qieo.QIEO_EINVAL
+    assert L.qieo_import_state(None, buf.ctypes.data_as(ctypes.c_void_p), 64) == qieo.QIEO_EINVAL
+    assert L.qieo_set_persistent(None, 1) == qieo.QIEO_EINVAL
+    assert L.qieo_set_kernel_flags(None, 0) == qieo.QIEO_EINVAL
     L.qieo_destroy(None)

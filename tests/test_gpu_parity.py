@@ -190,11 +190,14 @@ def test_autotuner_picks_a_shape_used_by_create(qieo, oracle_mod, tmp_path):
     qieo.qieo_tune_db_clear()
 
 
-@pytest.mark.parametrize("ng,n_pop", [(100, 16), (700, 37), (3000, 20), (64, 1024), (257, 3)])
-@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("ng,n_pop", [(100, 16), (700, 37), (3000, 20), (64, 1024), (257, 3),
+                                      (500, 24), (1, 1), (2000, 9)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_persistent_path_same_trajectory(qieo, oracle_mod, ng, n_pop, mode):
-    """Single-workgroup launches running many generations (mode 2) and
-    per-generation launches (mode 0) both follow the oracle."""
+    """Per-generation launches (mode 0), the LDS-resident single-workgroup
+    loop where the state fits LDS (mode 1, else per-generation launches) and
+    the global-memory single-workgroup loop where it does not (mode 2) all
+    follow the oracle, and switching between them between calls is seamless."""
     inst = workloads.random_instance(ng, n_pop, seed=ng * 3 + n_pop)
     say("persistent mode %d Ng=%d Np=%d" % (mode, ng, n_pop))
     g, o = _pair(qieo, oracle_mod, inst)
@@ -203,10 +206,11 @@ def test_persistent_path_same_trajectory(qieo, oracle_mod, ng, n_pop, mode):
         g.step(step)
         o.run(step)
         assert_state_equal(g, o, label="persistent %d t=%d" % (mode, o.t))
-    g.set_persistent(2 - mode)          # switching paths between calls is seamless
-    g.step(5)
-    o.run(5)
-    assert_state_equal(g, o, label="persistent switched t=%d" % o.t)
+    for other in (mode + 1) % 3, (mode + 2) % 3:
+        g.set_persistent(other)
+        g.step(5)
+        o.run(5)
+        assert_state_equal(g, o, label="persistent %d -> %d t=%d" % (mode, other, o.t))
 
 
 @pytest.mark.parametrize("graph", [0, 1])

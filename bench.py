@@ -33,9 +33,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(n_pop: int, n_items: int):
+def measured_traffic(n_pop: int, n_items: int, shape=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on this workload with the current kernel sources; else None."""
+    was taken on this workload with the current kernel sources and the same
+    work shape (rows, waves, variant bits) when one is given; else None."""
     import hashlib
     if (n_pop, n_items) != (4096, 200_000):
         return None
@@ -46,8 +47,11 @@ def measured_traffic(n_pop: int, n_items: int):
             with open(os.path.join(ROOT, f), "rb") as fh:
                 h.update(fh.read())
         fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
-                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:",
+                                               "work_shape:")))
         if fig.get("kernel_source_sha256") != h.hexdigest():
+            return None
+        if shape is not None and fig.get("work_shape") != "%d %d %d" % tuple(shape):
             return None
         return float(fig["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -383,7 +387,8 @@ def main():
         g.set_tile(r, s)
     if args.kernel_flags >= 0:
         g.set_kernel_flags(args.kernel_flags)
-    log("work shape rows/block, waves/block = %s" % (g.tile(),))
+    shape = tuple(g.tile()) + (g.kernel_flags(),)
+    log("work shape rows/block, waves/block, variant bits = %s" % (shape,))
     g.step(args.warmup)
 
     g.set_timing(True)
@@ -429,11 +434,9 @@ def main():
         "hbm_frac_algorithmic": value * bytes_per_launch / genes / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     # counters were taken with the library's own work shape
-                     "traffic": (measured_traffic(inst.n_pop, inst.n_items)
-                                 if args.precision == 32 and not (args.tile or args.autotune or
-                                                                  args.kernel_flags >= 0)
-                                 else None),
+                     # counters were taken with one work shape and variant
+                     "traffic": (measured_traffic(inst.n_pop, inst.n_items, shape)
+                                 if args.precision == 32 else None),
                      "kernel": "generation_kernel", "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_per_launch},
     }

@@ -200,6 +200,8 @@ int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_bloc
  * Variants change speed only, never results.  Out-of-range values give
  * QIEO_EINVAL. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
+/* Current variant bits (the library's choice until qieo_set_kernel_flags). */
+int qieo_get_kernel_flags(qieo_inst *h, int32_t *flags);
 
 /* ---- batch: many instances advanced together (one device pool) ---------- */
 

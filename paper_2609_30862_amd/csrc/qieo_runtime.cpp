@@ -168,20 +168,21 @@ int check_device()
     return QIEO_OK;
 }
 
-// Variant bits for a work shape.  Non-temporal stores always: an amplitude
-// written now is read again one generation later, after the whole population
-// has streamed through the caches.  Non-temporal loads once the amplitude
-// planes one generation streams exceed the 256 MB last-level cache (below
-// that, the next generation's reads may still hit it; above, cached
-// amplitudes only evict the item tables and allele words).  Prefetch when a
-// wave walks more than one chunk, except with 4 rows per workgroup over long
-// rows (>= 32 chunks per wave), where four rows' loads already keep enough in
-// flight and the prefetch buffers cost occupancy.
+// Variant bits for a work shape, from sweeps over fifteen (Np, Ng) shapes
+// between 82 MB and 13 GB of amplitudes.  Once the planes one generation
+// streams exceed the 256 MB last-level cache: non-temporal loads (cached
+// amplitudes would only evict the item tables and allele words) and
+// non-temporal stores (nothing written survives until the next generation
+// reads it).  Below that size both hints cost time (up to 27 %): the next
+// generation's reads may still hit the cache.  Prefetch when a wave walks
+// more than one chunk, except in multi-row workgroups over long rows (>= 32
+// chunks per wave), where several rows' loads already keep enough in flight
+// and the prefetch buffers cost occupancy.
 int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
 {
-    int f = kFlagNontemporal;
-    if (plane_bytes > ((int64_t)256 << 20)) f |= kFlagNontemporalLoads;
-    if (nchunk > S && !(R == 4 && nchunk >= 32 * (int64_t)S)) f |= kFlagPrefetch;
+    int f = 0;
+    if (plane_bytes > ((int64_t)256 << 20)) f |= kFlagNontemporal | kFlagNontemporalLoads;
+    if (nchunk > S && !(R >= 2 && nchunk >= 32 * (int64_t)S)) f |= kFlagPrefetch;
     return f;
 }
 
@@ -189,20 +190,27 @@ int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
 // workgroup S and kernel variant flags.  Whole rows stay in one workgroup
 // (Evaluation closes in LDS); S splits the gene axis.  R is the largest of
 // 4, 2, 1 that still leaves >= 32 wavefronts per CU (8192 on 256 CUs), since
-// more rows per workgroup amortise the item-table and elite-mask reads.  On
-// the 4096 x 200,000 workload this is (4, 8, non-temporal loads and stores),
-// the fastest of a sweep of R in {1,2,4}, S in {4,8} and the variant bits.
+// more rows per workgroup amortise the item-table and elite-mask reads.
+// Streaming populations (planes beyond the last-level cache) with long rows
+// (>= 32 chunks) and at least 1024 of them take 2 rows x 16 waves, the
+// fastest shape on every such workload measured (2.56 ms against 2.63 for
+// 4 x 8 on 4096 x 200,000).
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes)
 {
+    const int64_t plane_bytes = (int64_t)np * nchunk * kChunk * 2 * (int64_t)elem_bytes;
     int s = 8;
     if (nchunk < s) s = std::max(1, nchunk);
     int r = 1;
     for (int cand : {4, 2}) {
         if ((int64_t)((np + cand - 1) / cand) * s >= 8192) { r = cand; break; }
     }
+    if (plane_bytes > ((int64_t)256 << 20) && nchunk >= 32 && np >= 1024) {
+        r = 2;
+        s = 16;
+    }
     *R = r;
     *S = s;
-    *flags = variant_flags(r, s, nchunk, (int64_t)np * nchunk * kChunk * 2 * (int64_t)elem_bytes);
+    *flags = variant_flags(r, s, nchunk, plane_bytes);
 }
 
 }  // namespace qieo
@@ -877,6 +885,14 @@ extern "C" int qieo_set_kernel_flags(qieo_inst* h, int32_t flags)
     if (flags < 0 || flags > kFlagAll)
         return set_error(QIEO_EINVAL, "flags must be in [0, %d] (got %d)", kFlagAll, flags);
     h->flags = flags;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_get_kernel_flags(qieo_inst* h, int32_t* flags)
+{
+    clear_error();
+    if (!h || !flags) return set_error(QIEO_EINVAL, "NULL argument");
+    *flags = h->flags;
     return QIEO_OK;
 }
 

@@ -96,6 +96,8 @@ def _load():
     L.qieo_create_f64.restype = ctypes.c_int
     L.qieo_create_f64.argtypes = [P, i32, i32, i32, u64, ctypes.POINTER(qieo_dev_ctx),
                                   ctypes.POINTER(H)]
+    L.qieo_get_kernel_flags.restype = ctypes.c_int
+    L.qieo_get_kernel_flags.argtypes = [H, ctypes.POINTER(i32)]
     L.qieo_state_size.restype = ctypes.c_int
     L.qieo_state_size.argtypes = [H, ctypes.POINTER(ctypes.c_size_t)]
     L.qieo_export_state.restype = ctypes.c_int
@@ -458,6 +460,11 @@ class Instance:
 
     def set_kernel_flags(self, flags: int):
         _check(lib.qieo_set_kernel_flags(self._h, int(flags)), "qieo_set_kernel_flags")
+
+    def kernel_flags(self) -> int:
+        f = ctypes.c_int32()
+        _check(lib.qieo_get_kernel_flags(self._h, ctypes.byref(f)), "qieo_get_kernel_flags")
+        return int(f.value)
 
     def tile(self):
         r, s = ctypes.c_int32(), ctypes.c_int32()

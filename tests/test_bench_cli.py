@@ -16,7 +16,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_profile_figures_parse():
-    """The committed counter summary carries the two machine-readable lines
+    """The committed counter summary carries the machine-readable lines
     bench.py looks for (whether they still match the sources is bench.py's
     own check at run time)."""
     sys.path.insert(0, ROOT)
@@ -24,7 +24,9 @@ def test_profile_figures_parse():
     text = open(os.path.join(ROOT, bench.PROFILE)).read()
     keys = [line.strip().split(": ", 1)[0] for line in text.splitlines()
             if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:"))]
-    assert sorted(keys) == ["kernel_source_sha256", "traffic_bytes_per_launch"]
+    keys += [line.strip().split(": ", 1)[0] for line in text.splitlines()
+             if line.strip().startswith("work_shape:")]
+    assert sorted(keys) == ["kernel_source_sha256", "traffic_bytes_per_launch", "work_shape"]
     for f in bench.KERNEL_SOURCES:
         assert os.path.exists(os.path.join(ROOT, f)), f
     json.dumps({"traffic": bench.measured_traffic(4096, 200_000)})

@@ -106,11 +106,14 @@ Engine::~Engine()
 {
     if (stream_) (void)hipStreamSynchronize(stream_);
     if (side_) (void)hipStreamSynchronize(side_);
+    for (hipStream_t cs : cstreams_) (void)hipStreamSynchronize(cs);
     invalidate_graph();
     if (d_pids_) (void)hipFree(d_pids_);
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
     if (side_) (void)hipStreamDestroy(side_);
+    for (hipEvent_t ev : cjoin_) (void)hipEventDestroy(ev);
+    for (hipStream_t cs : cstreams_) (void)hipStreamDestroy(cs);
     for (auto& c : classes_)
         if (c.d_tiles) (void)hipFree(c.d_tiles);
     if (d_desc_) (void)hipFree(d_desc_);
@@ -181,12 +184,16 @@ void Engine::force_shape(int R, int S, int flags)
 
 // Shape classes by chunks per row: a workgroup of S waves needs >= S chunks
 // per row to keep its waves busy, so short rows go to narrow workgroups.
+// Shape classes by 256-gene chunks per row: 1, 2-3, 4-7, 8-31, >= 32; the
+// class's waves per workgroup are 1, 2, 4, 8, 16.
+constexpr int kClasses = 5;
 static int class_of(int32_t nchunk)
 {
     if (nchunk <= 1) return 0;
     if (nchunk <= 3) return 1;
     if (nchunk <= 7) return 2;
-    return 3;
+    if (nchunk <= 31) return 3;
+    return 4;
 }
 
 int Engine::rebuild()
@@ -236,7 +243,7 @@ int Engine::rebuild()
     pids_.clear();
     pids_lds_ = 0;
     const size_t lds_limit = use_persistent_ ? resident_lds_limit() : 0;
-    std::vector<std::vector<size_t>> groups(4);
+    std::vector<std::vector<size_t>> groups(kClasses);
     for (size_t i = 0; i < n; ++i) {
         const Member& m = members_[i];
         const size_t lds = resident_lds_bytes(m.np, m.L.pitch, m.L.nchunk);
@@ -263,17 +270,18 @@ int Engine::rebuild()
         if (!side_) {
             if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess)
                 return hip_fail(e, "hipStreamCreate");
-            if ((e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess ||
-                (e = hipEventCreateWithFlags(&join_, hipEventDisableTiming)) != hipSuccess)
+            if ((e = hipEventCreateWithFlags(&join_, hipEventDisableTiming)) != hipSuccess)
                 return hip_fail(e, "hipEventCreate");
         }
     }
-    // amplitude bytes one generation of the whole batch streams (all classes
-    // run back to back, so they share the caches)
+    if (!fork_ && (e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    // amplitude bytes one generation of the whole batch streams (the classes
+    // run side by side, so they share the caches)
     int64_t plane_bytes = 0;
     for (auto& m : members_) plane_bytes += (int64_t)m.np * m.L.pitch * 2 * (int64_t)sizeof(float);
-    static const int kS[4] = {1, 2, 4, 8};
-    for (int c = 0; c < 4; ++c) {
+    static const int kS[kClasses] = {1, 2, 4, 8, 16};
+    for (int c = 0; c < kClasses; ++c) {
         auto& g = groups[c];
         if (g.empty()) continue;
         std::sort(g.begin(), g.end(), [&](size_t a, size_t b) {
@@ -289,7 +297,10 @@ int Engine::rebuild()
         }
         sc.S = kS[c];
         sc.R = 1;
+        // long rows: at most 2 rows per 16-wave workgroup, as for single
+        // streaming populations
         for (int cand : {4, 2}) {
+            if (sc.S == 16 && cand > 2) continue;
             // blocks of the class at R rows each, times S waves: keep >= 8192 waves
             int64_t blocks = 0;
             for (size_t i : g) blocks += (members_[i].np + cand - 1) / cand;
@@ -311,6 +322,18 @@ int Engine::rebuild()
             return hip_fail(e, "hipMemcpyAsync(tiles)");
         classes_.push_back(std::move(sc));
     }
+    while (cstreams_.size() + 1 < classes_.size()) {
+        hipStream_t cs = nullptr;
+        hipEvent_t ev = nullptr;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            return hip_fail(e, "hipEventCreate");
+        }
+        cstreams_.push_back(cs);
+        cjoin_.push_back(ev);
+    }
     // host vectors above are pageable and local: wait for their copies
     if ((e = hipStreamSynchronize(stream_)) != hipSuccess)
         return hip_fail(e, "hipStreamSynchronize");
@@ -318,27 +341,40 @@ int Engine::rebuild()
     return QIEO_OK;
 }
 
+// Members of different shape classes (and the LDS-resident members) share
+// nothing, so each class advances through all of its generations on a stream
+// of its own, forked from the main stream and joined back before the
+// finishing launch: a small class's launches overlap the large classes'
+// instead of queueing behind them every generation.
 int Engine::enqueue(int nmax)
 {
     hipError_t e;
+    const size_t nc = classes_.size();
+    const bool forked = !pids_.empty() || nc > 1;
+    if (forked && (e = hipEventRecord(fork_, stream_)) != hipSuccess) return hip_fail(e, "fork");
     if (!pids_.empty()) {
-        // fork: the persistent members advance on the side stream while the
-        // per-generation launches below advance the others
-        if ((e = hipEventRecord(fork_, stream_)) != hipSuccess ||
-            (e = hipStreamWaitEvent(side_, fork_, 0)) != hipSuccess)
-            return hip_fail(e, "fork");
+        if ((e = hipStreamWaitEvent(side_, fork_, 0)) != hipSuccess) return hip_fail(e, "fork");
         if ((e = launch_resident(d_desc_, d_pids_, (int)pids_.size(), 8, pids_lds_, d_gens_, 0,
                                  side_)) != hipSuccess)
             return hip_fail(e, "resident kernel");
         if ((e = hipEventRecord(join_, side_)) != hipSuccess) return hip_fail(e, "join");
     }
-    for (int k = 0; k < nmax; ++k) {
-        for (auto& c : classes_) {
+    for (size_t ci = 0; ci < nc; ++ci) {
+        const ShapeClass& c = classes_[ci];
+        hipStream_t cs = ci == 0 ? stream_ : cstreams_[ci - 1];
+        if (ci > 0 && (e = hipStreamWaitEvent(cs, fork_, 0)) != hipSuccess)
+            return hip_fail(e, "fork");
+        for (int k = 0; k < nmax; ++k) {
             if ((e = launch_generation(d_desc_, c.d_tiles, (int)c.tiles.size(), c.R, c.S, c.flags,
-                                       k, d_gens_, 0, stream_)) != hipSuccess)
+                                       k, d_gens_, 0, cs)) != hipSuccess)
                 return hip_fail(e, "generation kernel");
         }
+        if (ci > 0 && (e = hipEventRecord(cjoin_[ci - 1], cs)) != hipSuccess)
+            return hip_fail(e, "join");
     }
+    for (size_t ci = 1; ci < nc; ++ci)
+        if ((e = hipStreamWaitEvent(stream_, cjoin_[ci - 1], 0)) != hipSuccess)
+            return hip_fail(e, "join");
     if (!pids_.empty() && (e = hipStreamWaitEvent(stream_, join_, 0)) != hipSuccess)
         return hip_fail(e, "join");
     if ((e = launch_finish(d_desc_, (int)members_.size(), d_gens_, 0, d_status_, stream_)) !=
@@ -406,10 +442,13 @@ int Engine::run(const int32_t* gens)
     }
     if (!done) {
         // a side stream left in a lost capture cannot be used
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (side_ && hipStreamIsCapturing(side_, &cs) == hipSuccess &&
-            cs != hipStreamCaptureStatusNone)
-            return set_error(QIEO_EDEVICE, "side stream left capturing by a lost graph capture");
+        std::vector<hipStream_t> forks(cstreams_);
+        if (side_) forks.push_back(side_);
+        for (hipStream_t fs : forks) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(fs, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return set_error(QIEO_EDEVICE, "side stream left capturing by a lost graph capture");
+        }
         if ((rc = enqueue(nmax))) return rc;
     }
     for (size_t i = 0; i < n; ++i) members_[i].t += gens[i];
@@ -523,6 +562,11 @@ extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qie
             batch_release(b);
             return rc;
         }
+    }
+    // descriptors, shape classes and tile tables of the initial membership
+    if ((rc = b->eng->ensure_built())) {
+        batch_release(b);
+        return rc;
     }
     *out = b;
     return QIEO_OK;

@@ -111,6 +111,9 @@ private:
     uint32_t* d_pids_ = nullptr;
     hipStream_t side_ = nullptr;
     hipEvent_t fork_ = nullptr, join_ = nullptr;
+    // shape classes after the first run on streams of their own
+    std::vector<hipStream_t> cstreams_;
+    std::vector<hipEvent_t> cjoin_;
     bool use_persistent_ = true;
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;

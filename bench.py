@@ -241,6 +241,38 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_stream(args):
+    """HBM reference rates on the large workload's two amplitude planes
+    (4096 x 200,064 binary32 each, 3.28 GB), with stock torch kernels: an
+    in-place read-modify-write of both planes (16 B per gene, as one
+    generation), a read of both (sums) and a write of both (fills)."""
+    import torch
+    rows, pitch = args.n_pop, (args.n_items + 63) // 64 * 64
+    a = torch.zeros(rows * pitch, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    genes = rows * pitch
+    ops = {
+        "read+write in place": (lambda: (a.mul_(1.5), b.mul_(1.5)), 16),
+        "read only": (lambda: (a.sum(), b.sum()), 8),
+        "write only": (lambda: (a.fill_(0.5), b.fill_(0.5)), 8),
+    }
+    out = {}
+    for name, (fn, per_gene) in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[name] = {"ms": ms, "GB/s": per_gene * genes / (ms * 1e-3) / 1e9}
+        log("%-20s %.4f ms  %.1f GB/s" % (name, ms, out[name]["GB/s"]))
+    print(json.dumps({"workload": "stream", "rows": rows, "pitch": pitch, "rates": out}),
+          flush=True)
+
+
 def bench_fractions(args):
     """Per-step time of the generation over an (Np, Ng) grid, for the fused
     launch, the paper's four-launch pipeline with DetermineElite on the device
@@ -328,11 +360,15 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions", "launch"],
+    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions", "launch",
+                                           "stream"],
                     default="large",
                     help="large: the single 4096 x 200,000 instance (default); batch: 512 "
                          "ragged instances x 500 generations vs a per-instance launch loop; "
-                         "serve: Poisson request stream through the continuous-batching server")
+                         "serve: Poisson request stream through the continuous-batching server; "
+                         "fractions: per-step costs of the fused and unfused pipelines; "
+                         "launch: launch-bound small instances; stream: HBM reference rates "
+                         "on the large workload's planes")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=500.0, help="serve: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=128.0, help="serve: HBM budget")
@@ -373,6 +409,8 @@ def main():
         return bench_serve(args)
     if args.workload == "fractions":
         return bench_fractions(args)
+    if args.workload == "stream":
+        return bench_stream(args)
     if args.workload == "launch":
         return bench_launch(args)
     inst = workloads.large_instance(args.n_pop, args.n_items)
@@ -437,7 +475,8 @@ def main():
                      # counters were taken with one work shape and variant
                      "traffic": (measured_traffic(inst.n_pop, inst.n_items, shape)
                                  if args.precision == 32 else None),
-                     "kernel": "generation_kernel", "kernel_avg_ms": avg_ms,
+                     "kernel": ("segment_kernel + segment_fe_kernel" if shape[2] & 16
+                                else "generation_kernel"), "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu_baseline:

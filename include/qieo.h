@@ -191,14 +191,16 @@ void qieo_destroy(qieo_inst *h);
 int qieo_set_tile(qieo_inst *h, int32_t rows_per_block, int32_t waves_per_block);
 /* Current work shape. */
 int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_block);
-/* Code variant of the generation kernel, a set of bits in [0, 15]: bit 0
+/* Code variant of the generation kernel, a set of bits in [0, 31]: bit 0
  * prefetches the next chunk's amplitudes while the current one is computed,
  * bit 1 stores amplitudes with non-temporal hints, bit 2 loads them with
  * non-temporal hints, bit 3 re-derives the previous generation's alleles
  * from the stored beta and their draws instead of reading the stored allele
- * words back (binary32 amplitudes; binary64 handles use bits 0-2 only).
- * Variants change speed only, never results.  Out-of-range values give
- * QIEO_EINVAL. */
+ * words back, bit 4 runs each generation in segment order (one workgroup per
+ * 2048-gene segment of a row, launched in address order, then a small launch
+ * closing the rows' sums; the work shape of qieo_set_tile does not apply;
+ * bits 0 and 3 are ignored).  Binary64 handles use bits 0-2 only.  Variants
+ * change speed only, never results.  Out-of-range values give QIEO_EINVAL. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 /* Current variant bits (the library's choice until qieo_set_kernel_flags). */
 int qieo_get_kernel_flags(qieo_inst *h, int32_t *flags);
@@ -245,7 +247,8 @@ int qieo_batch_export_rows(qieo_batch *b, int32_t i, int32_t row0, int32_t n_row
 int qieo_batch_set_convergence(qieo_batch *b, int32_t window);
 int qieo_batch_converged(qieo_batch *b, int32_t i, int32_t *converged, int64_t *generation);
 /* Work shape for every launch of the batch (rows_per_block = 0 restores the
- * library's per-class choice); see qieo_set_tile and qieo_set_kernel_flags. */
+ * library's per-class choice); see qieo_set_tile and qieo_set_kernel_flags
+ * (bit 4, segment order, is for single instances: QIEO_EINVAL here). */
 int qieo_batch_set_tile(qieo_batch *b, int32_t rows_per_block, int32_t waves_per_block,
                         int32_t flags);
 /* 1 (default): a call that repeats the previous one (same longest

@@ -15,7 +15,7 @@ namespace qieo {
 // Byte offsets of every plane inside one instance's device arena.
 struct ArenaLayout {
     int32_t pitch, nchunk;
-    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv;
+    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv, part;
     size_t zero_from;
     size_t total;
 };

@@ -89,6 +89,44 @@ __device__ void best_update(const InstDev& I, int64_t tg, int32_t e, int32_t fe,
     }
 }
 
+// Opens generation t of instance I for one workgroup.  Termination test
+// (convergence window): decided by every workgroup from values earlier
+// launches wrote, so all of them agree; generation t-1 completes convergence
+// when its elite fitness equals that of the window-1 generations before it,
+// and then generation t is not run.  The instance's first workgroup (first)
+// also closes the previous generation's bookkeeping: best-so-far record,
+// elite fitness history, convergence flags, and the cleared elite slot of
+// t+1.  Returns false when generation t is not to run.
+__device__ __forceinline__ bool open_generation(const InstDev& I, int64_t t, int window,
+                                                bool first, int wave, int lane, int32_t e_prev,
+                                                int32_t fe_prev, const uint32_t* xprev)
+{
+    const bool pending = t > 0;
+    bool stop = false;
+    if (window > 0) {
+        if (sload(I.conv) != 0) return false;       // converged in an earlier launch
+        if (pending && t >= window) {
+            stop = true;
+            for (int j = 1; j < window; ++j)
+                stop = stop && sload(I.conv + 8 + (int)((t - 1 - j) & (kConvRing - 1))) == fe_prev;
+        }
+    }
+    if (first && wave == 0) {
+        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
+        if (lane == 0) {
+            if (window > 0 && pending) I.conv[8 + (int)((t - 1) & (kConvRing - 1))] = fe_prev;
+            if (stop) {
+                I.conv[1] = (int32_t)(uint32_t)(uint64_t)(t - 1);
+                I.conv[2] = (int32_t)(uint32_t)((uint64_t)(t - 1) >> 32);
+                I.conv[0] = 1;
+            } else {
+                I.ekey[(t + 1) % 3] = 0ull;
+            }
+        }
+    }
+    return !stop;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -166,38 +204,11 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         fe_prev = key_fitness(key);
     }
 
-    // Termination test (convergence window): decided by every workgroup from
-    // values earlier launches wrote, so all of them agree.  Generation t-1
-    // completes convergence when its elite fitness equals that of the
-    // window-1 generations before it; then generation t is not run.
     constexpr bool kCip = (MODE & kStepCip) != 0, kQip = (MODE & kStepQip) != 0;
     constexpr bool kFe = (MODE & kStepFe) != 0, kDe = (MODE & kStepDe) != 0;
     const int window = MODE == kStepAll ? sload(I.conv + 3) : 0;
-    bool stop = false;
-    if (window > 0) {
-        if (sload(I.conv) != 0) return;            // converged in an earlier launch
-        if (pending && t >= window) {
-            stop = true;
-            for (int j = 1; j < window; ++j)
-                stop = stop && sload(I.conv + 8 + (int)((t - 1 - j) & (kConvRing - 1))) == fe_prev;
-        }
-    }
-
-    // the first launch of a generation closes the previous one's bookkeeping
-    if (kCip && row0 == 0 && wave == 0) {
-        if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
-        if (lane == 0) {
-            if (window > 0 && pending) I.conv[8 + (int)((t - 1) & (kConvRing - 1))] = fe_prev;
-            if (stop) {
-                I.conv[1] = (int32_t)(uint32_t)(uint64_t)(t - 1);
-                I.conv[2] = (int32_t)(uint32_t)((uint64_t)(t - 1) >> 32);
-                I.conv[0] = 1;
-            } else {
-                I.ekey[(t + 1) % 3] = 0ull;
-            }
-        }
-    }
-    if (stop) return;
+    if (!open_generation(I, t, window, kCip && row0 == 0, wave, lane, e_prev, fe_prev, xprev))
+        return;
 
     const int nrows = min(R, np - (int)row0);
     typedef typename Vec4<T>::type V4;
@@ -364,6 +375,179 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
         I.wt[slot] = Wi;
         // DetermineElite: the largest key is the largest fitness, lowest row.
         if (kDe) offer_key(&I.ekey[t % 3], make_key(f, c));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused generation in segment order (single binary32 instance).  Rows are
+// cut into segments of kSegChunks chunks; workgroup b takes segment
+// b mod nseg of row b / nseg, so consecutive workgroups touch consecutive
+// addresses and the whole chip sweeps the amplitude planes in address order
+// (workgroups that each walk their own rows keep thousands of distant DRAM
+// pages open at once).  Wave w takes chunk w of the segment (in general
+// chunks w, w + kSegWaves, ...) and issues all its loads before computing.  Per gene the work is
+// the fused kernel's: CIP(t-1), QIP(t), Evaluation's sums; the segment's
+// (profit, weight) sums go to part[row][seg] with plain stores, and
+// segment_fe_kernel closes them into fitness and the elite once every
+// segment is done (the launch boundary is the only synchronisation).
+// ---------------------------------------------------------------------------
+template <int FL>
+__global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* __restrict__ insts, int k,
+                                                      int gens_all)
+{
+    constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
+    constexpr int CPW = kSegChunks / kSegWaves;          // chunks per wave
+    if (k >= gens_all) return;
+    const InstDev I = insts[0];
+    const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
+    const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
+    const int c = (int)blockIdx.x / nseg, seg = (int)blockIdx.x - c * nseg;
+    const int64_t t = sload(I.tbase) + k;
+    const int par = (int)(t & 1);
+    const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
+    uint32_t* __restrict__ xcur = I.xbits + (size_t)par * np * wpr;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    const bool pending = t > 0;
+    int32_t e_prev = 0, fe_prev = 0;
+    if (pending) {
+        const unsigned long long key = sload(I.ekey + (t - 1) % 3);
+        e_prev = key_row(key);
+        fe_prev = key_fitness(key);
+    }
+    if (!open_generation(I, t, sload(I.conv + 3), blockIdx.x == 0, wave, lane, e_prev, fe_prev,
+                         xprev))
+        return;
+
+    const bool rot = pending && sload(I.fit + (par ^ 1) * np + c) < fe_prev;
+    const f32x4* arow = (const f32x4*)(I.alpha + (size_t)c * I.pitch);
+    const f32x4* brow4 = (const f32x4*)(I.beta + (size_t)c * I.pitch);
+    const uint32_t* __restrict__ erow = xprev + (size_t)e_prev * wpr;
+    const uint32_t* __restrict__ orow = xprev + (size_t)c * wpr;
+
+    // every load of the wave first
+    f32x4 a4[CPW], b4[CPW];
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+        const int ch = seg * kSegChunks + u * kSegWaves + wave;
+        if (ch < nchunk) {
+            const uint32_t q = (uint32_t)ch * (kChunk / 4) + lane;
+            b4[u] = NTL ? gload_nt(brow4, q) : gload(brow4, q);
+            if (rot) a4[u] = NTL ? gload_nt(arow, q) : gload(arow, q);
+        }
+    }
+    uint32_t accP = 0u, accW = 0u;
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+        const int ch = seg * kSegChunks + u * kSegWaves + wave;
+        if (ch >= nchunk) break;
+        const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
+        const bool act = g0 < (uint32_t)I.pitch;
+        const uint32_t q = g0 >> 2;
+        f32x4 bb = b4[u], aa = a4[u];
+        if (rot) {
+            const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
+            const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
+            const uint64_t bm0 = load_mask(bw), bm1 = load_mask(bw + 1);
+            const uint64_t bm2 = load_mask(bw + 2), bm3 = load_mask(bw + 3);
+            const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
+            const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
+            float a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
+            float b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
+            cip_gene(a0, b0, xm0 ^ bm0, bm0);
+            cip_gene(a1, b1, xm1 ^ bm1, bm1);
+            cip_gene(a2, b2, xm2 ^ bm2, bm2);
+            cip_gene(a3, b3, xm3 ^ bm3, bm3);
+            aa = f32x4{a0, a1, a2, a3};
+            bb = f32x4{b0, b1, b2, b3};
+        }
+        const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+        const bool x0 = act && observe(d.r0, bb.x);
+        const bool x1 = act && observe(d.r1, bb.y);
+        const bool x2 = act && observe(d.r2, bb.z);
+        const bool x3 = act && observe(d.r3, bb.w);
+        const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
+        if (lane < kWordsPerChunk) {
+            const int j = lane >> 1;
+            const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
+            const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
+            gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+        }
+        const i32x4 v4 = gload((const i32x4*)I.v, q);
+        const i32x4 w4 = gload((const i32x4*)I.w, q);
+        accP += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
+                (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
+        accW += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
+                (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+        if (rot && act) {
+            if (NT) {
+                gstore_nt((f32x4*)arow, q, aa);
+                gstore_nt((f32x4*)brow4, q, bb);
+            } else {
+                gstore((f32x4*)arow, q, aa);
+                gstore((f32x4*)brow4, q, bb);
+            }
+        }
+    }
+    // the segment's sums of eq. (1)
+    __shared__ uint32_t red[kSegWaves][2];
+    const uint32_t p = wave_sum(accP), w = wave_sum(accW);
+    if (lane == 0) { red[wave][0] = p; red[wave][1] = w; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t P = 0u, W = 0u;
+        for (int i = 0; i < kSegWaves; ++i) { P += red[i][0]; W += red[i][1]; }
+        const size_t slot = ((size_t)c * nseg + seg) * 2;
+        I.part[slot] = P;
+        I.part[slot + 1] = W;
+    }
+}
+
+// Closes generation t of the segment path: one wave per row sums the row's
+// segment partials into profit and weight, applies eq. (1) and stores the
+// row's fitness slot; DetermineElite offers the workgroup's best key.
+__global__ __launch_bounds__(256) void segment_fe_kernel(const InstDev* __restrict__ insts, int k,
+                                                         int gens_all)
+{
+    if (k >= gens_all) return;
+    const InstDev I = insts[0];
+    const int64_t t = sload(I.tbase) + k;
+    if (sload(I.conv + 3) > 0 && sload(I.conv) != 0) return;   // generation t did not run
+    const int np = I.np;
+    const int nseg = (I.nchunk + kSegChunks - 1) / kSegChunks;
+    const int par = (int)(t & 1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = (int)blockIdx.x * (blockDim.x >> 6) + wave;
+    uint32_t P = 0u, W = 0u;
+    if (c < np) {
+        const uint32_t* row = I.part + (size_t)c * nseg * 2;
+        for (int sg = lane; sg < nseg; sg += 64) {
+            P += row[2 * sg];
+            W += row[2 * sg + 1];
+        }
+    }
+    P = wave_sum(P);
+    W = wave_sum(W);
+    __shared__ unsigned long long red[4];
+    if (lane == 0) {
+        unsigned long long key = 0ull;
+        if (c < np) {
+            const int32_t Pi = (int32_t)P, Wi = (int32_t)W;
+            const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
+            const int slot = par * np + c;
+            I.fit[slot] = f;
+            I.prof[slot] = Pi;
+            I.wt[slot] = Wi;
+            key = make_key(f, c);
+        }
+        red[wave] = key;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long best = red[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) best = red[i] > best ? red[i] : best;
+        offer_key(&I.ekey[t % 3], best);
     }
 }
 
@@ -1102,18 +1286,45 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64)
     return hipGetLastError();
 }
 
+hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
+                           hipStream_t s)
+{
+    const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
+    const dim3 grid((unsigned)((int64_t)np * nseg)), block(64 * kSegWaves);
+    switch (flags & (kFlagNontemporal | kFlagNontemporalLoads)) {
+    case 0: hipLaunchKernelGGL((segment_kernel<0>), grid, block, 0, s, dI, k, gens_all); break;
+    case kFlagNontemporal:
+        hipLaunchKernelGGL((segment_kernel<kFlagNontemporal>), grid, block, 0, s, dI, k, gens_all);
+        break;
+    case kFlagNontemporalLoads:
+        hipLaunchKernelGGL((segment_kernel<kFlagNontemporalLoads>), grid, block, 0, s, dI, k,
+                           gens_all);
+        break;
+    default:
+        hipLaunchKernelGGL((segment_kernel<kFlagNontemporal | kFlagNontemporalLoads>), grid, block,
+                           0, s, dI, k, gens_all);
+        break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(segment_fe_kernel, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, dI, k,
+                       gens_all);
+    return hipGetLastError();
+}
+
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s)
 {
     if (n_blocks <= 0) return hipSuccess;
+    if (flags & kFlagSegments) return hipErrorInvalidValue;    // launch_segments
     if (waves_per_block < 1 || waves_per_block > 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n_blocks), block((unsigned)(64 * waves_per_block));
 #define QIEO_LAUNCH(RR, FF)                                                                    \
     hipLaunchKernelGGL((generation_kernel<float, RR, FF, kStepAll>), grid, block, 0, s, dI,    \
                        tiles, k, gens_arr, gens_all)
 #define QIEO_LAUNCH_R(RR)                                                                      \
-    switch (flags & kFlagAll) {                                                                \
+    switch (flags & 15) {                                                                      \
     case 0: QIEO_LAUNCH(RR, 0); break;                                                         \
     case 1: QIEO_LAUNCH(RR, 1); break;                                                         \
     case 2: QIEO_LAUNCH(RR, 2); break;                                                         \

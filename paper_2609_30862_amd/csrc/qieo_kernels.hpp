@@ -51,6 +51,7 @@ struct InstDev {
     uint32_t* best_bits;
     int64_t* tbase;
     int32_t* conv;
+    uint32_t* part;              // [np][nseg] (profit, weight) partial sums, segment path
     int32_t np, ng, pitch, nchunk;
     int32_t capacity;
     uint32_t seed_lo, seed_hi;
@@ -71,11 +72,18 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
 // current one; bit 1 = non-temporal amplitude stores; bit 2 = non-temporal
 // amplitude loads; bit 3 = re-derive the previous generation's alleles from
 // beta and their draws instead of reading the stored words back (binary32
-// launches only; binary64 launches take bits 0-2).
+// launches only; binary64 launches take bits 0-2); bit 4 = segment order
+// (single binary32 instances only): one 4-wave workgroup per (row, segment of
+// kSegChunks chunks), launched in address order, then a small launch that
+// closes each row's partial sums into its fitness and the elite; the work
+// shape (rows, waves) does not apply.
 constexpr int kFlagPrefetch = 1;
 constexpr int kFlagNontemporalLoads = 4;
 constexpr int kFlagRecomputeAlleles = 8;
-constexpr int kFlagAll = 15;
+constexpr int kFlagSegments = 16;
+constexpr int kFlagAll = 31;
+constexpr int kSegChunks = 8;      // 256-gene chunks per segment (2048 genes)
+constexpr int kSegWaves = 8;       // waves per segment workgroup (one chunk each)
 // Steps of one generation a launch may perform.
 constexpr int kStepCip = 1, kStepQip = 2, kStepFe = 4, kStepDe = 8;
 constexpr int kStepAll = kStepCip | kStepQip | kStepFe | kStepDe;
@@ -85,6 +93,10 @@ constexpr int kFlagNontemporal = 2;
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
+// The fused generation in segment order for a single binary32 instance
+// (kFlagSegments): the segment launch and the launch that closes the rows.
+hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
+                           hipStream_t s);
 // status (may be NULL): per instance {generations completed, converged flag}.
 // One stage of the unfused pipeline for a single instance: kStepCip (CIP of
 // generation t-1 plus the previous generation's bookkeeping), kStepQip,

@@ -677,7 +677,8 @@ extern "C" int qieo_batch_set_tile(qieo_batch* b, int32_t rows_per_block,
         return QIEO_OK;
     }
     if ((rows_per_block != 1 && rows_per_block != 2 && rows_per_block != 4) ||
-        waves_per_block < 1 || waves_per_block > 16 || flags < 0 || flags > kFlagAll)
+        waves_per_block < 1 || waves_per_block > 16 || flags < 0 || flags > kFlagAll ||
+        (flags & kFlagSegments))
         return set_error(QIEO_EINVAL, "bad work shape (%d, %d, %d)", rows_per_block,
                          waves_per_block, flags);
     b->eng->force_shape(rows_per_block, waves_per_block, flags);

@@ -76,6 +76,8 @@ size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem)
     L->best_bits = take(wpr * sizeof(uint32_t));
     L->tbase = take(sizeof(int64_t));
     L->conv = take(64 * sizeof(int32_t));
+    const size_t nseg = ((size_t)nchunk + kSegChunks - 1) / kSegChunks;
+    L->part = take(nseg * (size_t)np * 2 * sizeof(uint32_t));
     L->total = off;
     // everything except the amplitude planes themselves is zero-initialised
     L->zero_from = 0;
@@ -99,6 +101,7 @@ InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int
     d.best_bits = reinterpret_cast<uint32_t*>(base + L.best_bits);
     d.tbase = reinterpret_cast<int64_t*>(base + L.tbase);
     d.conv = reinterpret_cast<int32_t*>(base + L.conv);
+    d.part = reinterpret_cast<uint32_t*>(base + L.part);
     d.np = np;
     d.ng = ng;
     d.pitch = L.pitch;
@@ -193,8 +196,11 @@ int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
 // more rows per workgroup amortise the item-table and elite-mask reads.
 // Streaming populations (planes beyond the last-level cache) with long rows
 // (>= 32 chunks) and at least 1024 of them take 2 rows x 16 waves, the
-// fastest shape on every such workload measured (2.56 ms against 2.63 for
-// 4 x 8 on 4096 x 200,000).
+// fastest row shape on every such workload measured.  Streaming binary32
+// populations run in segment order instead: faster than the best row shape
+// on all ten streaming workloads measured (6-14 %; 2.29 ms against 2.58 on
+// 4096 x 200,000), slower on cache-resident ones (11-18 %), where the row
+// kernel stays.
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes)
 {
     const int64_t plane_bytes = (int64_t)np * nchunk * kChunk * 2 * (int64_t)elem_bytes;
@@ -211,6 +217,8 @@ void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_
     *R = r;
     *S = s;
     *flags = variant_flags(r, s, nchunk, plane_bytes);
+    if (elem_bytes == 4 && plane_bytes > ((int64_t)256 << 20))
+        *flags = kFlagSegments | kFlagNontemporal | kFlagNontemporalLoads;
 }
 
 }  // namespace qieo
@@ -299,7 +307,8 @@ static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
     if (h->f64) {
         *R = std::min(*R, 2);
         *S = std::min(*S, 4);
-        *F = (*F & ~kFlagNontemporalLoads & ~kFlagPrefetch) | (h->L.nchunk > *S ? kFlagPrefetch : 0);
+        *F = (*F & ~(kFlagNontemporalLoads | kFlagPrefetch | kFlagSegments)) |
+             (h->L.nchunk > *S ? kFlagPrefetch : 0);
     }
 }
 
@@ -464,6 +473,16 @@ static int host_elite(qieo_inst* h, int64_t t)
     return QIEO_OK;
 }
 
+// Generation k of a call of n on the fused path: the row kernel with the
+// handle's work shape, or the segment-order launches.
+static hipError_t launch_fused(qieo_inst* h, int blocks, int k, int n)
+{
+    if (h->flags & kFlagSegments)
+        return launch_segments(h->d_desc, h->np, h->L.nchunk, h->flags, k, n, h->stream);
+    return launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
+                             h->stream);
+}
+
 // Captures the n fused launches of one call (and the finishing launch) into
 // h->graph.  Relaxed mode: the sequence holds kernel launches only.  If the
 // capture does not complete (another thread's device-wide call can
@@ -481,8 +500,7 @@ static void capture_call(qieo_inst* h, int32_t n, int blocks)
     }
     hipError_t le = hipSuccess;
     for (int32_t k = 0; k < n && le == hipSuccess; ++k)
-        le = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
-                               h->stream);
+        le = launch_fused(h, blocks, k, n);
     if (le == hipSuccess) le = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream);
     const hipError_t e = hipStreamEndCapture(h->stream, &g);
     hipGraphExec_t x = nullptr;
@@ -595,8 +613,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
                 (void)hipEventRecord(a, h->stream);
             }
             if (st == kStepAll) {
-                if ((e = launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k,
-                                           nullptr, n, h->stream)) != hipSuccess)
+                if ((e = launch_fused(h, blocks, k, n)) != hipSuccess)
                     return hip_fail(e, "generation kernel");
             } else if (st == -1) {
                 int rc = host_elite(h, h->t + k);
@@ -1026,7 +1043,7 @@ struct StateHeader {
     uint64_t arena_bytes;
 };
 constexpr char kStateMagic[8] = {'Q', 'I', 'E', 'O', 'S', 'T', 'A', 'T'};
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 
 }  // namespace
 

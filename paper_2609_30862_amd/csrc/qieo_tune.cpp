@@ -124,14 +124,20 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
     for (int R : {1, 2, 4})
         for (int S : {2, 4, 8, 16}) {
             if (S > std::max(2, L.nchunk) && S != 2) continue;
-            for (int f = 0; f <= kFlagAll; ++f) cand.push_back(Entry{R, S, f, 0.0});
+            for (int f = 0; f < kFlagSegments; ++f) cand.push_back(Entry{R, S, f, 0.0});
         }
+    // segment order: the work shape does not apply, only the cache hints
+    for (int f : {0, kFlagNontemporal, kFlagNontemporalLoads, kFlagNontemporal | kFlagNontemporalLoads})
+        cand.push_back(Entry{1, kSegWaves, kFlagSegments | f, 0.0});
     // one generation of warm-up (generation 0 reads beta only), then trials
     auto run = [&](const Entry& c, int gens, double* ms) -> int {
         const int blocks = (n_pop + c.R - 1) / c.R;
         hipError_t ee = hipEventRecord(e0, s);
         for (int k = 0; k < gens && ee == hipSuccess; ++k)
-            ee = launch_generation(d_desc, nullptr, blocks, c.R, c.S, c.flags, k, nullptr, gens, s);
+            ee = (c.flags & kFlagSegments)
+                     ? launch_segments(d_desc, n_pop, L.nchunk, c.flags, k, gens, s)
+                     : launch_generation(d_desc, nullptr, blocks, c.R, c.S, c.flags, k, nullptr,
+                                         gens, s);
         if (ee == hipSuccess) ee = launch_finish(d_desc, 1, nullptr, gens, nullptr, s);
         if (ee == hipSuccess) ee = hipEventRecord(e1, s);
         if (ee == hipSuccess) ee = hipEventSynchronize(e1);

@@ -267,3 +267,38 @@ def test_graph_capture_with_concurrent_device_calls(qieo, oracle_mod):
         stop.set()
         th.join()
     assert not errors, errors
+
+
+@pytest.mark.parametrize("ng,n_pop", [(1, 3), (255, 7), (2048, 4), (4096, 5), (4097, 9),
+                                      (9000, 33), (20000, 12)])
+@pytest.mark.parametrize("flags", [16, 22, 31])
+def test_segment_order_same_trajectory(qieo, oracle_mod, ng, n_pop, flags):
+    """The segment-order generation (one workgroup per 2048-gene segment of a
+    row, then a launch closing the rows) follows the oracle on rows shorter
+    than one segment, exactly one or two, and several with a ragged last one;
+    direct launches and graph replay."""
+    inst = workloads.random_instance(ng, n_pop, seed=ng + 31 * n_pop)
+    say("segments flags %d Ng=%d Np=%d" % (flags, ng, n_pop))
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_persistent(0)
+    g.set_kernel_flags(flags)
+    assert g.kernel_flags() == flags
+    for n in (1, 2, 3, 3, 3, 9):
+        g.step(n)
+        o.run(n)
+        assert_state_equal(g, o, label="segments %d t=%d" % (flags, o.t))
+
+
+def test_segment_order_with_convergence_window(qieo, oracle_mod):
+    inst = workloads.small_instance()
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_persistent(0)
+    g.set_kernel_flags(22)
+    g.set_convergence(20)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    n = o.run_until_converged(5000, 20)
+    for p in (7, 100, 5000):
+        g.step(p)
+    conv, at = g.converged()
+    assert conv and at == n - 1 and g.generations == n
+    assert_state_equal(g, o, label="segments converged")

@@ -199,8 +199,8 @@ int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_bloc
  * words back, bit 4 runs each generation in segment order (one workgroup per
  * 2048-gene segment of a row, launched in address order, then a small launch
  * closing the rows' sums; the work shape of qieo_set_tile does not apply;
- * bits 0 and 3 are ignored).  Binary64 handles use bits 0-2 only.  Variants
- * change speed only, never results.  Out-of-range values give QIEO_EINVAL. */
+ * bits 0 and 3 are ignored).  Binary64 handles ignore bit 3.  Variants change
+ * speed only, never results.  Out-of-range values give QIEO_EINVAL. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 /* Current variant bits (the library's choice until qieo_set_kernel_flags). */
 int qieo_get_kernel_flags(qieo_inst *h, int32_t *flags);

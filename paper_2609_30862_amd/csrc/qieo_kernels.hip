@@ -379,7 +379,8 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 }
 
 // ---------------------------------------------------------------------------
-// The fused generation in segment order (single binary32 instance).  Rows are
+// The fused generation in segment order (single instance; T the amplitude
+// type).  Rows are
 // cut into segments of kSegChunks chunks; workgroup b takes segment
 // b mod nseg of row b / nseg, so consecutive workgroups touch consecutive
 // addresses and the whole chip sweeps the amplitude planes in address order
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // segment_fe_kernel closes them into fitness and the elite once every
 // segment is done (the launch boundary is the only synchronisation).
 // ---------------------------------------------------------------------------
-template <int FL>
+template <typename T, int FL>
 __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* __restrict__ insts, int k,
                                                       int gens_all)
 {
@@ -421,13 +422,14 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
         return;
 
     const bool rot = pending && sload(I.fit + (par ^ 1) * np + c) < fe_prev;
-    const f32x4* arow = (const f32x4*)(I.alpha + (size_t)c * I.pitch);
-    const f32x4* brow4 = (const f32x4*)(I.beta + (size_t)c * I.pitch);
+    typedef typename Vec4<T>::type V4;
+    const V4* arow = (const V4*)(reinterpret_cast<const T*>(I.alpha) + (size_t)c * I.pitch);
+    const V4* brow4 = (const V4*)(reinterpret_cast<const T*>(I.beta) + (size_t)c * I.pitch);
     const uint32_t* __restrict__ erow = xprev + (size_t)e_prev * wpr;
     const uint32_t* __restrict__ orow = xprev + (size_t)c * wpr;
 
     // every load of the wave first
-    f32x4 a4[CPW], b4[CPW];
+    V4 a4[CPW], b4[CPW];
 #pragma unroll
     for (int u = 0; u < CPW; ++u) {
         const int ch = seg * kSegChunks + u * kSegWaves + wave;
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
         const bool act = g0 < (uint32_t)I.pitch;
         const uint32_t q = g0 >> 2;
-        f32x4 bb = b4[u], aa = a4[u];
+        V4 bb = b4[u], aa = a4[u];
         if (rot) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
             const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
@@ -453,14 +455,14 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
             const uint64_t bm2 = load_mask(bw + 2), bm3 = load_mask(bw + 3);
             const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
             const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
-            float a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
-            float b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
+            T a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
+            T b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
             cip_gene(a0, b0, xm0 ^ bm0, bm0);
             cip_gene(a1, b1, xm1 ^ bm1, bm1);
             cip_gene(a2, b2, xm2 ^ bm2, bm2);
             cip_gene(a3, b3, xm3 ^ bm3, bm3);
-            aa = f32x4{a0, a1, a2, a3};
-            bb = f32x4{b0, b1, b2, b3};
+            aa = V4{a0, a1, a2, a3};
+            bb = V4{b0, b1, b2, b3};
         }
         const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
         const bool x0 = act && observe(d.r0, bb.x);
@@ -482,11 +484,11 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
                 (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
         if (rot && act) {
             if (NT) {
-                gstore_nt((f32x4*)arow, q, aa);
-                gstore_nt((f32x4*)brow4, q, bb);
+                gstore_nt((V4*)arow, q, aa);
+                gstore_nt((V4*)brow4, q, bb);
             } else {
-                gstore((f32x4*)arow, q, aa);
-                gstore((f32x4*)brow4, q, bb);
+                gstore((V4*)arow, q, aa);
+                gstore((V4*)brow4, q, bb);
             }
         }
     }
@@ -1287,24 +1289,28 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64)
 }
 
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
-                           hipStream_t s)
+                           bool f64, hipStream_t s)
 {
     const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
-    const dim3 grid((unsigned)((int64_t)np * nseg)), block(64 * kSegWaves);
-    switch (flags & (kFlagNontemporal | kFlagNontemporalLoads)) {
-    case 0: hipLaunchKernelGGL((segment_kernel<0>), grid, block, 0, s, dI, k, gens_all); break;
-    case kFlagNontemporal:
-        hipLaunchKernelGGL((segment_kernel<kFlagNontemporal>), grid, block, 0, s, dI, k, gens_all);
-        break;
-    case kFlagNontemporalLoads:
-        hipLaunchKernelGGL((segment_kernel<kFlagNontemporalLoads>), grid, block, 0, s, dI, k,
-                           gens_all);
-        break;
-    default:
-        hipLaunchKernelGGL((segment_kernel<kFlagNontemporal | kFlagNontemporalLoads>), grid, block,
-                           0, s, dI, k, gens_all);
-        break;
+    const int64_t blocks = (int64_t)np * nseg;
+    if (np <= 0 || blocks > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(64 * kSegWaves);
+#define QIEO_SEG(TT, FF)                                                                       \
+    hipLaunchKernelGGL((segment_kernel<TT, FF>), grid, block, 0, s, dI, k, gens_all)
+#define QIEO_SEG_T(TT)                                                                         \
+    switch (flags & (kFlagNontemporal | kFlagNontemporalLoads)) {                              \
+    case 0: QIEO_SEG(TT, 0); break;                                                            \
+    case kFlagNontemporal: QIEO_SEG(TT, kFlagNontemporal); break;                              \
+    case kFlagNontemporalLoads: QIEO_SEG(TT, kFlagNontemporalLoads); break;                    \
+    default: QIEO_SEG(TT, kFlagNontemporal | kFlagNontemporalLoads); break;                    \
     }
+    if (f64) {
+        QIEO_SEG_T(double)
+    } else {
+        QIEO_SEG_T(float)
+    }
+#undef QIEO_SEG_T
+#undef QIEO_SEG
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(segment_fe_kernel, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, dI, k,

@@ -72,11 +72,11 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
 // current one; bit 1 = non-temporal amplitude stores; bit 2 = non-temporal
 // amplitude loads; bit 3 = re-derive the previous generation's alleles from
 // beta and their draws instead of reading the stored words back (binary32
-// launches only; binary64 launches take bits 0-2); bit 4 = segment order
-// (single binary32 instances only): one 4-wave workgroup per (row, segment of
-// kSegChunks chunks), launched in address order, then a small launch that
-// closes each row's partial sums into its fitness and the elite; the work
-// shape (rows, waves) does not apply.
+// row-order launches only); bit 4 = segment order (single instances only):
+// one workgroup of kSegWaves waves per (row, segment of kSegChunks chunks),
+// launched in address order, then a small launch that closes each row's
+// partial sums into its fitness and the elite; the work shape (rows, waves)
+// does not apply.
 constexpr int kFlagPrefetch = 1;
 constexpr int kFlagNontemporalLoads = 4;
 constexpr int kFlagRecomputeAlleles = 8;
@@ -93,10 +93,10 @@ constexpr int kFlagNontemporal = 2;
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
-// The fused generation in segment order for a single binary32 instance
+// The fused generation in segment order for a single instance
 // (kFlagSegments): the segment launch and the launch that closes the rows.
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
-                           hipStream_t s);
+                           bool f64, hipStream_t s);
 // status (may be NULL): per instance {generations completed, converged flag}.
 // One stage of the unfused pipeline for a single instance: kStepCip (CIP of
 // generation t-1 plus the previous generation's bookkeeping), kStepQip,

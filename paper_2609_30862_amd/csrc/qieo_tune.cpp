@@ -135,7 +135,7 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
         hipError_t ee = hipEventRecord(e0, s);
         for (int k = 0; k < gens && ee == hipSuccess; ++k)
             ee = (c.flags & kFlagSegments)
-                     ? launch_segments(d_desc, n_pop, L.nchunk, c.flags, k, gens, s)
+                     ? launch_segments(d_desc, n_pop, L.nchunk, c.flags, k, gens, false, s)
                      : launch_generation(d_desc, nullptr, blocks, c.R, c.S, c.flags, k, nullptr,
                                          gens, s);
         if (ee == hipSuccess) ee = launch_finish(d_desc, 1, nullptr, gens, nullptr, s);

@@ -38,7 +38,7 @@ def test_f64_every_generation(qieo, oracle_mod, ng, n_pop):
 
 
 @pytest.mark.parametrize("tile,flags", [((1, 4), 0), ((2, 8), 3), ((4, 2), 1), ((4, 8), 6),
-                                        ((2, 4), 7)])
+                                        ((2, 4), 7), ((2, 4), 16), ((2, 4), 18), ((2, 4), 22)])
 def test_f64_work_shapes(qieo, oracle_mod, tile, flags):
     inst = workloads.random_instance(2000, 19, seed=6)
     g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
@@ -76,3 +76,19 @@ def test_f64_rejects_f32_only_features(qieo):
         g.set_pipeline(1)
     with pytest.raises(qieo.QieoError):
         g.set_persistent(2)
+
+
+@pytest.mark.parametrize("ng,n_pop,flags", [(9000, 7, 22), (4097, 11, 18), (100, 5, 16)])
+def test_f64_segment_order(qieo, oracle_mod, ng, n_pop, flags):
+    """Binary64 amplitudes in segment order: several segments per row with a
+    ragged last one, and rows shorter than one segment."""
+    inst = workloads.random_instance(ng, n_pop, seed=ng + n_pop)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                      precision=64)
+    g.set_kernel_flags(flags)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          precision=64)
+    for n in (1, 2, 5, 12):
+        g.step(n)
+        o.run(n)
+        assert_state_equal(g, o, label="f64 segments t=%d" % o.t)

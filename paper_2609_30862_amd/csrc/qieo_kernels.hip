@@ -9,12 +9,22 @@
 // grid-wide barrier a generation needs: the elite of t-1 is final when the
 // launch of t starts.
 //
-// Work decomposition.  A workgroup owns R whole chromosomes (rows); its S
-// wavefronts split each row into 256-gene chunks (wave w takes chunks w, w+S,
-// ...), so Evaluation's gene-axis reduction (eq. (1)) closes inside the
-// workgroup: wave shuffles, then LDS across the S waves, then one 64-bit
-// atomicMax per row that can still win, for DetermineElite.  No
-// cross-workgroup partial sums, no tickets, no memory fences.
+// Work decomposition, row order (generation_kernel).  A workgroup owns R
+// whole chromosomes (rows); its S wavefronts split each row into 256-gene
+// chunks (wave w takes chunks w, w+S, ...), so Evaluation's gene-axis
+// reduction (eq. (1)) closes inside the workgroup: DPP wave reductions, then
+// LDS across the S waves, then one 64-bit atomicMax per row that can still
+// win, for DetermineElite.  No cross-workgroup partial sums, no tickets, no
+// memory fences.
+//
+// Segment order (segment_kernel + segment_fe_kernel), for populations that
+// stream from HBM: one workgroup per 2048-gene segment of a row, launched in
+// address order; segment sums are stored plainly and a second launch closes
+// each row's fitness and the elite.
+//
+// Single-workgroup loops (resident_kernel, persistent_kernel) run all
+// generations of a call for tiny populations, block barriers in place of
+// launch boundaries.
 //
 // Per lane and chunk: 4 consecutive genes = one float4 of beta (and alpha
 // when the row rotates) = one Philox4x32-10 call.  The observed alleles of a

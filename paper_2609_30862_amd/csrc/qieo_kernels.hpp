@@ -63,53 +63,65 @@ struct Tile {
     uint32_t row0;
 };
 
-// Host-side launchers (qieo_kernels.hip).
-hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
-// gens_arr (device, one entry per instance) or, when NULL, gens_all gives the
-// number of generations each instance runs in the current call; launch k
-// (0-based) skips instances with gens <= k.
-// flags: bit 0 = prefetch the next chunk's amplitudes while computing the
-// current one; bit 1 = non-temporal amplitude stores; bit 2 = non-temporal
-// amplitude loads; bit 3 = re-derive the previous generation's alleles from
-// beta and their draws instead of reading the stored words back (binary32
-// row-order launches only); bit 4 = segment order (single instances only):
-// one workgroup of kSegWaves waves per (row, segment of kSegChunks chunks),
-// launched in address order, then a small launch that closes each row's
-// partial sums into its fitness and the elite; the work shape (rows, waves)
-// does not apply.
+// Kernel variant bits ("flags"): bit 0 = prefetch the next chunk's
+// amplitudes while computing the current one; bit 1 = non-temporal amplitude
+// stores; bit 2 = non-temporal amplitude loads; bit 3 = re-derive the
+// previous generation's alleles from beta and their draws instead of reading
+// the stored words back (binary32 row-order launches only); bit 4 = segment
+// order (single instances only): one workgroup of kSegWaves waves per (row,
+// segment of kSegChunks chunks), launched in address order, then a small
+// launch that closes each row's partial sums into its fitness and the elite;
+// the work shape (rows, waves) does not apply.  No bit changes a result.
 constexpr int kFlagPrefetch = 1;
+constexpr int kFlagNontemporal = 2;
 constexpr int kFlagNontemporalLoads = 4;
 constexpr int kFlagRecomputeAlleles = 8;
 constexpr int kFlagSegments = 16;
 constexpr int kFlagAll = 31;
 constexpr int kSegChunks = 8;      // 256-gene chunks per segment (2048 genes)
 constexpr int kSegWaves = 8;       // waves per segment workgroup (one chunk each)
+
 // Steps of one generation a launch may perform.
 constexpr int kStepCip = 1, kStepQip = 2, kStepFe = 4, kStepDe = 8;
 constexpr int kStepAll = kStepCip | kStepQip | kStepFe | kStepDe;
 // timing slots: fused generation, CIP, QIP, Evaluation, DetermineElite
 constexpr int kStages = 5;
-constexpr int kFlagNontemporal = 2;
+constexpr int kConvRing = 32;      // longest convergence window
+// Single-workgroup loop from global memory: rows it can hold sums for in LDS.
+constexpr int kPersistentMaxRows = 2048;
+
+// ---- host-side launchers (qieo_kernels.hip) ------------------------------
+// Common conventions: gens_arr (device, one entry per instance) or, when
+// NULL, gens_all gives the number of generations each instance runs in the
+// current call; launch k (0-based) skips instances with gens <= k.  dI is the
+// device array of instance descriptors.
+hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64 = false);
+// Fused generation in row order: n_blocks workgroups of waves_per_block
+// waves, each owning rows_per_block rows (tiles NULL: rows of instance 0 from
+// blockIdx * rows_per_block).
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,
                              int rows_per_block, int waves_per_block, int flags, int k,
                              const int32_t* gens_arr, int gens_all, hipStream_t s);
+// The same for binary64 amplitudes (instance 0 only).
+hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_block,
+                                 int waves_per_block, int flags, int k, int gens_all,
+                                 hipStream_t s);
 // The fused generation in segment order for a single instance
 // (kFlagSegments): the segment launch and the launch that closes the rows.
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
                            bool f64, hipStream_t s);
-// status (may be NULL): per instance {generations completed, converged flag}.
 // One stage of the unfused pipeline for a single instance: kStepCip (CIP of
 // generation t-1 plus the previous generation's bookkeeping), kStepQip,
 // kStepFe, kStepFe | kStepDe, or kStepDe (the standalone elite reduction).
 hipError_t launch_stage(const InstDev* dI, int n_blocks, int rows_per_block, int waves_per_block,
                         int stage, int k, int gens, hipStream_t s);
-// Persistent single-workgroup path: workgroup b runs all of this call's
-// generations of instance ids[b] (ids NULL: instance 0); bookkeeping of the
-// call's last generation is left to launch_finish.
-constexpr int kPersistentMaxRows = 2048;          // LDS per-row sums
-constexpr int64_t kPersistentMaxGenes = 1 << 16;  // Np * pitch at or below which it pays
-// LDS-resident persistent loop: the whole state of each instance in one
-// workgroup's LDS (resident_lds_bytes of it) for the call.
+// Chromosome-parallel generation (one lane per chromosome), single instance.
+hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s);
+// Single-workgroup loops: workgroup b runs all of this call's generations of
+// instance ids[b] (ids NULL: instance 0); the call's last generation's
+// bookkeeping is left to launch_finish.  launch_resident keeps the whole
+// state in LDS (lds_bytes = resident_lds_bytes of the largest instance, at
+// most resident_lds_limit); launch_persistent works from global memory.
 size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk);
 // Largest dynamic LDS the resident kernel may use on the current device
 // (0 if none); the first call opens the kernel up to it.
@@ -120,18 +132,17 @@ hipError_t launch_resident(const InstDev* dI, const uint32_t* ids, int n_blocks,
 hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,
                              int waves_per_block, const int32_t* gens_arr, int gens_all,
                              hipStream_t s);
-// Chromosome-parallel generation (one lane per chromosome), single instance.
-hipError_t launch_chromosome(const InstDev* dI, int np, int k, int gens, hipStream_t s);
+// End of a call for n_inst instances: the last generation's best-so-far
+// update, the generation counter, convergence; status (may be NULL): per
+// instance {generations completed, converged flag}.
 hipError_t launch_finish(const InstDev* dI, int n_inst, const int32_t* gens_arr, int gens_all,
                          int64_t* status, hipStream_t s);
-constexpr int kConvRing = 32;      // longest convergence window
+// Copies rows [row0, row0 + n_rows) of instance 0's state, with the pending
+// rotation applied, into device buffers (any may be NULL).
 hipError_t launch_export(const InstDev* dI, int row0, int n_rows, int ng,
                          void* alpha, void* beta, uint8_t* alleles,
                          int32_t* fit, int32_t* prof, int32_t* wt, bool f64, hipStream_t s);
-// binary64 amplitudes (alpha, beta planes hold doubles): fused launch only.
-hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_block,
-                                 int waves_per_block, int flags, int k, int gens_all,
-                                 hipStream_t s);
+// Best-bits words (chunk ballot layout) to plain packed bits.
 hipError_t launch_bits_unpack(const uint32_t* src_words, int ng, uint32_t* dst_words,
                               hipStream_t s);
 

@@ -390,28 +390,28 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 
 // ---------------------------------------------------------------------------
 // The fused generation in segment order (single instance; T the amplitude
-// type).  Rows are
-// cut into segments of kSegChunks chunks; workgroup b takes segment
+// type).  Rows are cut into segments of SC chunks; workgroup b takes segment
 // b mod nseg of row b / nseg, so consecutive workgroups touch consecutive
 // addresses and the whole chip sweeps the amplitude planes in address order
 // (workgroups that each walk their own rows keep thousands of distant DRAM
-// pages open at once).  Wave w takes chunk w of the segment (in general
-// chunks w, w + kSegWaves, ...) and issues all its loads before computing.  Per gene the work is
+// pages open at once).  The SW waves take chunks w, w + SW, ... of the
+// segment and issue all their loads before computing.  Per gene the work is
 // the fused kernel's: CIP(t-1), QIP(t), Evaluation's sums; the segment's
 // (profit, weight) sums go to part[row][seg] with plain stores, and
 // segment_fe_kernel closes them into fitness and the elite once every
 // segment is done (the launch boundary is the only synchronisation).
 // ---------------------------------------------------------------------------
-template <typename T, int FL>
-__global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* __restrict__ insts, int k,
-                                                      int gens_all)
+template <typename T, int FL, int SC, int SW>
+__global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts, int k,
+                                                          int gens_all)
 {
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
-    constexpr int CPW = kSegChunks / kSegWaves;          // chunks per wave
+    static_assert(SC % SW == 0, "whole chunks per wave");
+    constexpr int CPW = SC / SW;                          // chunks per wave
     if (k >= gens_all) return;
     const InstDev I = insts[0];
     const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
-    const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
+    const int nseg = (nchunk + SC - 1) / SC;
     const int c = (int)blockIdx.x / nseg, seg = (int)blockIdx.x - c * nseg;
     const int64_t t = sload(I.tbase) + k;
     const int par = (int)(t & 1);
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
     V4 a4[CPW], b4[CPW];
 #pragma unroll
     for (int u = 0; u < CPW; ++u) {
-        const int ch = seg * kSegChunks + u * kSegWaves + wave;
+        const int ch = seg * SC + u * SW + wave;
         if (ch < nchunk) {
             const uint32_t q = (uint32_t)ch * (kChunk / 4) + lane;
             b4[u] = NTL ? gload_nt(brow4, q) : gload(brow4, q);
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
     uint32_t accP = 0u, accW = 0u;
 #pragma unroll
     for (int u = 0; u < CPW; ++u) {
-        const int ch = seg * kSegChunks + u * kSegWaves + wave;
+        const int ch = seg * SC + u * SW + wave;
         if (ch >= nchunk) break;
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
         const bool act = g0 < (uint32_t)I.pitch;
@@ -503,13 +503,13 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
         }
     }
     // the segment's sums of eq. (1)
-    __shared__ uint32_t red[kSegWaves][2];
+    __shared__ uint32_t red[SW][2];
     const uint32_t p = wave_sum(accP), w = wave_sum(accW);
     if (lane == 0) { red[wave][0] = p; red[wave][1] = w; }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t P = 0u, W = 0u;
-        for (int i = 0; i < kSegWaves; ++i) { P += red[i][0]; W += red[i][1]; }
+        for (int i = 0; i < SW; ++i) { P += red[i][0]; W += red[i][1]; }
         const size_t slot = ((size_t)c * nseg + seg) * 2;
         I.part[slot] = P;
         I.part[slot + 1] = W;
@@ -520,14 +520,14 @@ __global__ __launch_bounds__(64 * kSegWaves) void segment_kernel(const InstDev* 
 // segment partials into profit and weight, applies eq. (1) and stores the
 // row's fitness slot; DetermineElite offers the workgroup's best key.
 __global__ __launch_bounds__(256) void segment_fe_kernel(const InstDev* __restrict__ insts, int k,
-                                                         int gens_all)
+                                                         int gens_all, int seg_chunks)
 {
     if (k >= gens_all) return;
     const InstDev I = insts[0];
     const int64_t t = sload(I.tbase) + k;
     if (sload(I.conv + 3) > 0 && sload(I.conv) != 0) return;   // generation t did not run
     const int np = I.np;
-    const int nseg = (I.nchunk + kSegChunks - 1) / kSegChunks;
+    const int nseg = (I.nchunk + seg_chunks - 1) / seg_chunks;
     const int par = (int)(t & 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = (int)blockIdx.x * (blockDim.x >> 6) + wave;
@@ -1301,30 +1301,32 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64)
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
                            bool f64, hipStream_t s)
 {
-    const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
+    const int sc = f64 ? kSegChunks64 : kSegChunks32;
+    const int sw = f64 ? kSegWaves64 : kSegWaves32;
+    const int nseg = (nchunk + sc - 1) / sc;
     const int64_t blocks = (int64_t)np * nseg;
     if (np <= 0 || blocks > INT32_MAX) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)blocks), block(64 * kSegWaves);
-#define QIEO_SEG(TT, FF)                                                                       \
-    hipLaunchKernelGGL((segment_kernel<TT, FF>), grid, block, 0, s, dI, k, gens_all)
-#define QIEO_SEG_T(TT)                                                                         \
+    const dim3 grid((unsigned)blocks), block((unsigned)(64 * sw));
+#define QIEO_SEG(TT, FF, SC, SW)                                                               \
+    hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW>), grid, block, 0, s, dI, k, gens_all)
+#define QIEO_SEG_T(TT, SC, SW)                                                                 \
     switch (flags & (kFlagNontemporal | kFlagNontemporalLoads)) {                              \
-    case 0: QIEO_SEG(TT, 0); break;                                                            \
-    case kFlagNontemporal: QIEO_SEG(TT, kFlagNontemporal); break;                              \
-    case kFlagNontemporalLoads: QIEO_SEG(TT, kFlagNontemporalLoads); break;                    \
-    default: QIEO_SEG(TT, kFlagNontemporal | kFlagNontemporalLoads); break;                    \
+    case 0: QIEO_SEG(TT, 0, SC, SW); break;                                                    \
+    case kFlagNontemporal: QIEO_SEG(TT, kFlagNontemporal, SC, SW); break;                      \
+    case kFlagNontemporalLoads: QIEO_SEG(TT, kFlagNontemporalLoads, SC, SW); break;            \
+    default: QIEO_SEG(TT, kFlagNontemporal | kFlagNontemporalLoads, SC, SW); break;            \
     }
     if (f64) {
-        QIEO_SEG_T(double)
+        QIEO_SEG_T(double, kSegChunks64, kSegWaves64)
     } else {
-        QIEO_SEG_T(float)
+        QIEO_SEG_T(float, kSegChunks32, kSegWaves32)
     }
 #undef QIEO_SEG_T
 #undef QIEO_SEG
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(segment_fe_kernel, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, dI, k,
-                       gens_all);
+                       gens_all, sc);
     return hipGetLastError();
 }
 

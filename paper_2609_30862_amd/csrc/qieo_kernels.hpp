@@ -68,18 +68,22 @@ struct Tile {
 // stores; bit 2 = non-temporal amplitude loads; bit 3 = re-derive the
 // previous generation's alleles from beta and their draws instead of reading
 // the stored words back (binary32 row-order launches only); bit 4 = segment
-// order (single instances only): one workgroup of kSegWaves waves per (row,
-// segment of kSegChunks chunks), launched in address order, then a small
-// launch that closes each row's partial sums into its fitness and the elite;
-// the work shape (rows, waves) does not apply.  No bit changes a result.
+// order (single instances only): one workgroup per (row, segment of whole
+// chunks), launched in address order, then a small launch that closes each
+// row's partial sums into its fitness and the elite; the work shape (rows,
+// waves) does not apply.  No bit changes a result.
 constexpr int kFlagPrefetch = 1;
 constexpr int kFlagNontemporal = 2;
 constexpr int kFlagNontemporalLoads = 4;
 constexpr int kFlagRecomputeAlleles = 8;
 constexpr int kFlagSegments = 16;
 constexpr int kFlagAll = 31;
-constexpr int kSegChunks = 8;      // 256-gene chunks per segment (2048 genes)
-constexpr int kSegWaves = 8;       // waves per segment workgroup (one chunk each)
+// Segment geometry per amplitude type: 256-gene chunks per segment and waves
+// per segment workgroup (each wave takes whole chunks).  The partial-sum
+// array is sized for the shortest segment.
+constexpr int kSegChunks32 = 8, kSegWaves32 = 8;     // binary32: 2048 genes, 8 KB a plane
+constexpr int kSegChunks64 = 16, kSegWaves64 = 16;   // binary64: 4096 genes, 32 KB a plane
+constexpr int kSegChunksMin = kSegChunks32 < kSegChunks64 ? kSegChunks32 : kSegChunks64;
 
 // Steps of one generation a launch may perform.
 constexpr int kStepCip = 1, kStepQip = 2, kStepFe = 4, kStepDe = 8;

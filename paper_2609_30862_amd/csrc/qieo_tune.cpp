@@ -128,7 +128,7 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
         }
     // segment order: the work shape does not apply, only the cache hints
     for (int f : {0, kFlagNontemporal, kFlagNontemporalLoads, kFlagNontemporal | kFlagNontemporalLoads})
-        cand.push_back(Entry{1, kSegWaves, kFlagSegments | f, 0.0});
+        cand.push_back(Entry{1, kSegWaves32, kFlagSegments | f, 0.0});
     // one generation of warm-up (generation 0 reads beta only), then trials
     auto run = [&](const Entry& c, int gens, double* ms) -> int {
         const int blocks = (n_pop + c.R - 1) / c.R;

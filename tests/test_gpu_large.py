@@ -2,7 +2,8 @@
 (Np = 4096, Ng = 200,000, seed 2) in the launch configuration the benchmark
 times: every chromosome's fitness, the elite and the best-so-far record bit
 for bit at early generations (row-threaded oracle over the whole population),
-amplitudes and alleles of sampled rows, then invariants at generation 200."""
+amplitudes and alleles of sampled rows, then invariants at generation 200;
+the same early checks with binary64 amplitudes."""
 import os
 
 import numpy as np
@@ -76,3 +77,28 @@ def test_large_instance_full_size(qieo, oracle_mod):
     lp = oracle_mod.knap_lp_bound(inst.values, inst.weights, inst.capacity)
     assert best.fitness <= lp
     say("  best %d (generation %d), LP bound %.0f" % (best.fitness, best.generation, lp))
+
+
+def test_large_instance_binary64(qieo, oracle_mod):
+    inst = workloads.large_instance()
+    threads = min(16, os.cpu_count() or 1)
+    say("large instance %s, binary64, oracle threads %d" % (inst.name, threads))
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                      precision=64)
+    say("  variant bits %d" % g.kernel_flags())
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          threads=threads, precision=64)
+    done = 0
+    for ck in (1, 2, 4):
+        g.step(ck - done)
+        o.run(ck - done)
+        done = ck
+        say("  compare at generation %d" % ck)
+        st = g.export_rows(0, inst.n_pop, amplitudes=False, alleles=False)
+        f_o, P_o, W_o = o.fitness()
+        assert np.array_equal(st["fitness"].astype(np.int64), f_o)
+        assert np.array_equal(st["profit"].astype(np.int64), P_o)
+        assert np.array_equal(st["weight"].astype(np.int64), W_o)
+        assert st["elite"] == o.elite
+        rows = sorted(set(SAMPLE_ROWS + [o.elite]))
+        assert_state_equal(g, o, rows=rows, label="large f64 gen %d" % ck)

@@ -118,6 +118,7 @@ __device__ __forceinline__ double sel(uint64_t m, double if0, double if1)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef f32x4 type; };

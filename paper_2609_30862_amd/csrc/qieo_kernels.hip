@@ -438,15 +438,36 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     const uint32_t* __restrict__ erow = xprev + (size_t)e_prev * wpr;
     const uint32_t* __restrict__ orow = xprev + (size_t)c * wpr;
 
+    // Binary64 amplitudes move between HBM and the lanes through a per-wave
+    // LDS tile, so that every load and store instruction covers 1 KB of
+    // consecutive addresses (a lane's own 32 bytes would take two half-dense
+    // instructions): lane l transfers genes 2l, 2l+1 and 128 + 2l, 129 + 2l
+    // of the chunk and computes genes 4l .. 4l + 3.
+    constexpr bool kStage = sizeof(T) == 8;
+    __shared__ T stage[kStage ? SW : 1][2][kStage ? kChunk : 1];
+
     // every load of the wave first
     V4 a4[CPW], b4[CPW];
+    f64x2 la[CPW][2], lb[CPW][2];
 #pragma unroll
     for (int u = 0; u < CPW; ++u) {
         const int ch = seg * SC + u * SW + wave;
         if (ch < nchunk) {
-            const uint32_t q = (uint32_t)ch * (kChunk / 4) + lane;
-            b4[u] = NTL ? gload_nt(brow4, q) : gload(brow4, q);
-            if (rot) a4[u] = NTL ? gload_nt(arow, q) : gload(arow, q);
+            if constexpr (kStage) {
+                const uint32_t h0 = (uint32_t)ch * (kChunk / 2) + lane, h1 = h0 + kChunk / 4;
+                const f64x2* ar = (const f64x2*)arow;
+                const f64x2* br = (const f64x2*)brow4;
+                lb[u][0] = NTL ? gload_nt(br, h0) : gload(br, h0);
+                lb[u][1] = NTL ? gload_nt(br, h1) : gload(br, h1);
+                if (rot) {
+                    la[u][0] = NTL ? gload_nt(ar, h0) : gload(ar, h0);
+                    la[u][1] = NTL ? gload_nt(ar, h1) : gload(ar, h1);
+                }
+            } else {
+                const uint32_t q = (uint32_t)ch * (kChunk / 4) + lane;
+                b4[u] = NTL ? gload_nt(brow4, q) : gload(brow4, q);
+                if (rot) a4[u] = NTL ? gload_nt(arow, q) : gload(arow, q);
+            }
         }
     }
     uint32_t accP = 0u, accW = 0u;
@@ -457,6 +478,20 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
         const bool act = g0 < (uint32_t)I.pitch;
         const uint32_t q = g0 >> 2;
+        if constexpr (kStage) {
+            T* sa = stage[wave][0];
+            T* sb = stage[wave][1];
+            *(f64x2*)(sb + 2 * lane) = lb[u][0];
+            *(f64x2*)(sb + kChunk / 2 + 2 * lane) = lb[u][1];
+            if (rot) {
+                *(f64x2*)(sa + 2 * lane) = la[u][0];
+                *(f64x2*)(sa + kChunk / 2 + 2 * lane) = la[u][1];
+            }
+            __builtin_amdgcn_wave_barrier();
+            b4[u] = *(const V4*)(sb + 4 * lane);
+            if (rot) a4[u] = *(const V4*)(sa + 4 * lane);
+            __builtin_amdgcn_wave_barrier();
+        }
         V4 bb = b4[u], aa = a4[u];
         if (rot) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
@@ -492,7 +527,32 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
                 (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
         accW += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
                 (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
-        if (rot && act) {
+        if constexpr (kStage) {
+            if (rot) {
+                T* sa = stage[wave][0];
+                T* sb = stage[wave][1];
+                *(V4*)(sa + 4 * lane) = aa;
+                *(V4*)(sb + 4 * lane) = bb;
+                __builtin_amdgcn_wave_barrier();
+                const f64x2 a0 = *(const f64x2*)(sa + 2 * lane);
+                const f64x2 a1 = *(const f64x2*)(sa + kChunk / 2 + 2 * lane);
+                const f64x2 b0 = *(const f64x2*)(sb + 2 * lane);
+                const f64x2 b1 = *(const f64x2*)(sb + kChunk / 2 + 2 * lane);
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t h0 = (uint32_t)ch * (kChunk / 2) + lane;   // f64x2 index
+                const uint32_t h1 = h0 + kChunk / 4;
+                f64x2* ar = (f64x2*)arow;
+                f64x2* br = (f64x2*)brow4;
+                if (2 * h0 < (uint32_t)I.pitch) {
+                    if (NT) { gstore_nt(ar, h0, a0); gstore_nt(br, h0, b0); }
+                    else { gstore(ar, h0, a0); gstore(br, h0, b0); }
+                }
+                if (2 * h1 < (uint32_t)I.pitch) {
+                    if (NT) { gstore_nt(ar, h1, a1); gstore_nt(br, h1, b1); }
+                    else { gstore(ar, h1, a1); gstore(br, h1, b1); }
+                }
+            }
+        } else if (rot && act) {
             if (NT) {
                 gstore_nt((V4*)arow, q, aa);
                 gstore_nt((V4*)brow4, q, bb);

@@ -82,7 +82,7 @@ constexpr int kFlagAll = 31;
 // per segment workgroup (each wave takes whole chunks).  The partial-sum
 // array is sized for the shortest segment.
 constexpr int kSegChunks32 = 8, kSegWaves32 = 8;     // binary32: 2048 genes, 8 KB a plane
-constexpr int kSegChunks64 = 16, kSegWaves64 = 16;   // binary64: 4096 genes, 32 KB a plane
+constexpr int kSegChunks64 = 4, kSegWaves64 = 4;     // binary64: 1024 genes, 8 KB a plane
 constexpr int kSegChunksMin = kSegChunks32 < kSegChunks64 ? kSegChunks32 : kSegChunks64;
 
 // Steps of one generation a launch may perform.

@@ -245,14 +245,18 @@ def bench_stream(args):
     """HBM reference rates on the large workload's two amplitude planes
     (4096 x 200,064 binary32 each, 3.28 GB), with stock torch kernels: an
     in-place read-modify-write of both planes (16 B per gene, as one
-    generation), a read of both (sums) and a write of both (fills)."""
+    generation), the same read and write into two other planes, a read of
+    both (sums) and a write of both (fills)."""
     import torch
     rows, pitch = args.n_pop, (args.n_items + 63) // 64 * 64
     a = torch.zeros(rows * pitch, dtype=torch.float32, device="cuda")
     b = torch.zeros_like(a)
+    a2 = torch.zeros_like(a)
+    b2 = torch.zeros_like(a)
     genes = rows * pitch
     ops = {
         "read+write in place": (lambda: (a.mul_(1.5), b.mul_(1.5)), 16),
+        "read+write elsewhere": (lambda: (torch.mul(a, 1.5, out=a2), torch.mul(b, 1.5, out=b2)), 16),
         "read only": (lambda: (a.sum(), b.sum()), 8),
         "write only": (lambda: (a.fill_(0.5), b.fill_(0.5)), 8),
     }

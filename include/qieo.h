@@ -200,8 +200,8 @@ int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_bloc
  * segment of a row, 2048 genes for binary32 and 1024 for binary64, launched
  * in address order, then a small launch
  * closing the rows' sums; the work shape of qieo_set_tile does not apply;
- * bits 0 and 3 are ignored).  Binary64 handles ignore bit 3.  Variants change
- * speed only, never results.  Out-of-range values give QIEO_EINVAL. */
+ * bit 0 is ignored).  Binary64 handles ignore bit 3 in row order.  Variants
+ * change speed only, never results.  Out-of-range values give QIEO_EINVAL. */
 int qieo_set_kernel_flags(qieo_inst *h, int32_t flags);
 /* Current variant bits (the library's choice until qieo_set_kernel_flags). */
 int qieo_get_kernel_flags(qieo_inst *h, int32_t *flags);

@@ -406,6 +406,7 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
                                                           int gens_all)
 {
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
+    constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0;
     static_assert(SC % SW == 0, "whole chunks per wave");
     constexpr int CPW = SC / SW;                          // chunks per wave
     if (k >= gens_all) return;
@@ -495,11 +496,23 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         V4 bb = b4[u], aa = a4[u];
         if (rot) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
-            const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
             const uint64_t bm0 = load_mask(bw), bm1 = load_mask(bw + 1);
             const uint64_t bm2 = load_mask(bw + 2), bm3 = load_mask(bw + 3);
-            const uint64_t xm0 = load_mask(xw), xm1 = load_mask(xw + 1);
-            const uint64_t xm2 = load_mask(xw + 2), xm3 = load_mask(xw + 3);
+            uint64_t xm0, xm1, xm2, xm3;
+            if (RC) {
+                // the stored beta is the one generation t-1 observed, so its
+                // draws give back that generation's alleles bit for bit
+                const Draw4 dp = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u, I.seed_lo,
+                                               I.seed_hi);
+                xm0 = ballot(act && observe(dp.r0, bb.x));
+                xm1 = ballot(act && observe(dp.r1, bb.y));
+                xm2 = ballot(act && observe(dp.r2, bb.z));
+                xm3 = ballot(act && observe(dp.r3, bb.w));
+            } else {
+                const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
+                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
+                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+            }
             T a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
             T b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
             cip_gene(a0, b0, xm0 ^ bm0, bm0);
@@ -1366,15 +1379,22 @@ hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int
     const int nseg = (nchunk + sc - 1) / sc;
     const int64_t blocks = (int64_t)np * nseg;
     if (np <= 0 || blocks > INT32_MAX) return hipErrorInvalidValue;
+    static_assert(kFlagNontemporal == 2 && kFlagNontemporalLoads == 4 &&
+                      kFlagRecomputeAlleles == 8,
+                  "segment variants below are spelled out by value");
     const dim3 grid((unsigned)blocks), block((unsigned)(64 * sw));
 #define QIEO_SEG(TT, FF, SC, SW)                                                               \
     hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW>), grid, block, 0, s, dI, k, gens_all)
 #define QIEO_SEG_T(TT, SC, SW)                                                                 \
-    switch (flags & (kFlagNontemporal | kFlagNontemporalLoads)) {                              \
+    switch (flags & (kFlagNontemporal | kFlagNontemporalLoads | kFlagRecomputeAlleles)) {      \
     case 0: QIEO_SEG(TT, 0, SC, SW); break;                                                    \
-    case kFlagNontemporal: QIEO_SEG(TT, kFlagNontemporal, SC, SW); break;                      \
-    case kFlagNontemporalLoads: QIEO_SEG(TT, kFlagNontemporalLoads, SC, SW); break;            \
-    default: QIEO_SEG(TT, kFlagNontemporal | kFlagNontemporalLoads, SC, SW); break;            \
+    case 2: QIEO_SEG(TT, 2, SC, SW); break;                                                    \
+    case 4: QIEO_SEG(TT, 4, SC, SW); break;                                                    \
+    case 6: QIEO_SEG(TT, 6, SC, SW); break;                                                    \
+    case 8: QIEO_SEG(TT, 8, SC, SW); break;                                                    \
+    case 10: QIEO_SEG(TT, 10, SC, SW); break;                                                  \
+    case 12: QIEO_SEG(TT, 12, SC, SW); break;                                                  \
+    default: QIEO_SEG(TT, 14, SC, SW); break;                                                  \
     }
     if (f64) {
         QIEO_SEG_T(double, kSegChunks64, kSegWaves64)

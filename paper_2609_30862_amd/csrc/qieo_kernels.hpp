@@ -67,7 +67,7 @@ struct Tile {
 // amplitudes while computing the current one; bit 1 = non-temporal amplitude
 // stores; bit 2 = non-temporal amplitude loads; bit 3 = re-derive the
 // previous generation's alleles from beta and their draws instead of reading
-// the stored words back (binary32 row-order launches only); bit 4 = segment
+// the stored words back (not in binary64 row order); bit 4 = segment
 // order (single instances only): one workgroup per (row, segment of whole
 // chunks), launched in address order, then a small launch that closes each
 // row's partial sums into its fitness and the elite; the work shape (rows,

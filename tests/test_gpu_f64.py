@@ -80,7 +80,7 @@ def test_f64_rejects_f32_only_features(qieo):
 
 @pytest.mark.parametrize("ng,n_pop,flags", [(9000, 7, 22), (4097, 11, 18), (4096, 3, 22),
                                               (1025, 4, 22), (20000, 6, 22), (100, 5, 16),
-                                              (3000, 5, 20)])
+                                              (3000, 5, 20), (9000, 7, 30), (1025, 3, 8)])
 def test_f64_segment_order(qieo, oracle_mod, ng, n_pop, flags):
     """Binary64 amplitudes in segment order: several segments per row with a
     ragged last one, and rows shorter than one segment."""

@@ -360,6 +360,43 @@ void oracle_run(oracle *s, int64_t n)
     for (int64_t g = 0; g < n; ++g) oracle_generation(s);
 }
 
+/* One chromosome's part of generation t (binary32, lambda = 1).  Of the four
+ * steps of Fig. 1 only DetermineElite looks across chromosomes; given the
+ * elite of generation t-1 (its alleles, and whether chromosome c scored below
+ * it), chromosome c's generation t is: CIP of t-1 toward the elite (readings
+ * R3, R4), then QIP of t (R1, R7) and Evaluation, eq. (1).  alpha and beta
+ * (ng each) hold c's amplitudes as generation t-1 observed them and receive
+ * the rotated ones; x_prev and elite_prev are c's and the elite's alleles of
+ * t-1 (not read when below_elite is 0, as at t = 0); x_out receives the
+ * alleles of t; out = {fitness, profit, weight}.  Chromosome-local, so it
+ * serves populations too large for the whole-population oracle. */
+void oracle_row_generation(uint64_t seed, int64_t t, int64_t c, int64_t ng,
+                           const int32_t *v, const int32_t *w, int64_t cap,
+                           float *alpha, float *beta, const uint8_t *x_prev,
+                           const uint8_t *elite_prev, int below_elite,
+                           uint8_t *x_out, int64_t out[3])
+{
+    if (below_elite)
+        for (int64_t i = 0; i < ng; ++i)
+            if (x_prev[i] != elite_prev[i])
+                oracle_cip_gene(&alpha[i], &beta[i], elite_prev[i]);
+    int64_t P = 0, W = 0;
+    for (int64_t k = 0; 4 * k < ng; ++k) {
+        uint32_t r[4];
+        draws4(seed, t, c, k, r);
+        for (int j = 0; j < 4 && 4 * k + j < ng; ++j) {
+            const int64_t i = 4 * k + j;
+            const float b2 = beta[i] * beta[i];
+            x_out[i] = (uniform24(r[j]) < b2) ? 1 : 0;
+            P += (int64_t)v[i] * x_out[i];
+            W += (int64_t)w[i] * x_out[i];
+        }
+    }
+    out[0] = (W <= cap) ? P : -(W - cap);
+    out[1] = P;
+    out[2] = W;
+}
+
 /* Termination test of Sec. IV-A, read for integer fitness: the run has
  * converged after generation t when the elite fitness of the last `window`
  * generations (t-window+1 .. t) is one value (a spread within 1e-6 of the

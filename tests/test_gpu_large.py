@@ -102,3 +102,64 @@ def test_large_instance_binary64(qieo, oracle_mod):
         assert st["elite"] == o.elite
         rows = sorted(set(SAMPLE_ROWS + [o.elite]))
         assert_state_equal(g, o, rows=rows, label="large f64 gen %d" % ck)
+
+
+def test_population_beyond_2_32_genes(qieo, oracle_mod):
+    """32,768 chromosomes x 131,136 genes = 4.297e9 genes, past 2^32 (34 GB of
+    binary32 amplitudes), in the streaming launch configuration.  Only
+    DetermineElite looks across chromosomes, so each sampled chromosome, each
+    generation's elite and the elites' own histories are recomputed one
+    chromosome at a time by the oracle, given the GPU's elite sequence; that
+    sequence is checked against the argmax (lowest index) of the GPU's
+    fitness array, whose sampled entries must equal the oracle's."""
+    n_pop, ng = 32768, 131136
+    pitch = (ng + 63) // 64 * 64
+    assert n_pop * pitch > 2 ** 32
+    inst = workloads.random_instance(ng, n_pop, seed=9)
+    say("population of %d x %d = %.4g genes" % (n_pop, ng, n_pop * ng))
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    say("  variant bits %d" % g.kernel_flags())
+    tiny = oracle_mod.Oracle(inst.values[:1], inst.weights[:1], 1, 1, inst.seed)
+    a0 = np.full(ng, tiny.amplitudes()[0][0, 0], dtype=np.float32)   # the initial amplitude
+    del tiny
+    seed, v, w, cap = inst.seed, inst.values, inst.weights, inst.capacity
+    hist = {}       # chromosome -> per generation (alpha, beta as observed, alleles, fitness)
+    elites = []     # per generation: (row, fitness) from the GPU
+
+    def state(c, k):
+        h = hist.setdefault(c, [])
+        while len(h) <= k:
+            t = len(h)
+            if t == 0:
+                a, b, x, f, _, _ = oracle_mod.row_generation(seed, 0, c, v, w, cap, a0, a0)
+            else:
+                e, fe = elites[t - 1]
+                ex = state(e, t - 1)[2]
+                pa, pb, px, pf = h[t - 1]
+                a, b, x, f, _, _ = oracle_mod.row_generation(seed, t, c, v, w, cap, pa, pb,
+                                                             px, ex, pf < fe)
+            h.append((a, b, x, f))
+        return h[k]
+
+    sample = [0, 1, 2, 4095, 16384, 30001, 32766, 32767]
+    for k in range(3):
+        g.step(1)
+        st = g.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        fit = st["fitness"].astype(np.int64)
+        e = int(st["elite"])
+        assert e == int(np.argmax(fit))
+        elites.append((e, int(fit[e])))
+        for c in sorted(set(sample + [e])):
+            a, b, x, f = state(c, k)
+            assert f == fit[c], "generation %d row %d" % (k, c)
+            ex = state(e, k)[2]
+            # amplitudes after CIP(k), as the export applies the pending rotation
+            ra, rb, _, _, _, _ = oracle_mod.row_generation(seed, k + 1, c, v, w, cap, a, b, x,
+                                                           ex, f < fit[e])
+            s = g.export_rows(c, 1)
+            assert np.array_equal(s["alleles"][0], x), "alleles, generation %d row %d" % (k, c)
+            assert bits_equal(s["alpha"][0], ra) and bits_equal(s["beta"][0], rb), \
+                "amplitudes, generation %d row %d" % (k, c)
+        say("  generation %d: elite %d, fitness %d, %d rows checked" % (k, e, fit[e],
+                                                                      len(set(sample + [e]))))
+    g.close()

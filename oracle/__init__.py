@@ -154,6 +154,19 @@ def row_generation(seed: int, t: int, c: int, v, w, capacity: int, alpha, beta,
     return a, b, x, int(out[0]), int(out[1]), int(out[2])
 
 
+def row_generation_inplace(seed: int, t: int, c: int, v, w, capacity: int, alpha, beta,
+                           x_prev, elite_prev, below_elite: bool, x_out):
+    """row_generation on caller-owned contiguous arrays (int32 v, w; float32
+    alpha, beta updated in place; uint8 x_prev, elite_prev, x_out), without
+    copies; returns (fitness, profit, weight).  Thread-safe."""
+    out = np.zeros(3, np.int64)
+    lib().oracle_row_generation(seed & (2**64 - 1), int(t), int(c), v.size, _ptr(v), _ptr(w),
+                                int(capacity), _ptr(alpha), _ptr(beta), _ptr(x_prev),
+                                _ptr(elite_prev), int(bool(below_elite)), _ptr(x_out),
+                                _ptr(out))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
 @dataclass
 class Best:
     has_best: bool

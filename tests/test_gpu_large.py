@@ -163,3 +163,74 @@ def test_population_beyond_2_32_genes(qieo, oracle_mod):
         say("  generation %d: elite %d, fitness %d, %d rows checked" % (k, e, fit[e],
                                                                       len(set(sample + [e]))))
     g.close()
+
+
+def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod):
+    """The benchmark's run (3 generations, then 200 in one call) against a
+    run stepped one generation at a time, bit for bit; along the stepped run,
+    every generation's elite and 12 sampled rows are recomputed chromosome by
+    chromosome (oracle, 16 threads) from the GPU's elite sequence: their
+    fitness at all 203 generations, and at the end their alleles and
+    amplitudes."""
+    from concurrent.futures import ThreadPoolExecutor
+    inst = workloads.large_instance()
+    n_pop, ng, G = inst.n_pop, inst.n_items, 3 + inst.generations
+    g1 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed)
+    elites, fits = [], []
+    for k in range(G):
+        g1.step(1)
+        st = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        fit = st["fitness"].astype(np.int64)
+        e = int(st["elite"])
+        assert e == int(np.argmax(fit)), "generation %d" % k
+        elites.append((e, int(fit[e])))
+        fits.append(fit[SAMPLE_ROWS].copy())
+    g2 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed)
+    g2.step(3)
+    g2.step(inst.generations)
+    s1 = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
+    s2 = g2.export_rows(0, n_pop, amplitudes=False, alleles=False)
+    assert np.array_equal(s1["fitness"], s2["fitness"]) and s1["elite"] == s2["elite"]
+    say("  %d generations, %d distinct elites" % (G, len({e for e, _ in elites})))
+
+    v = np.ascontiguousarray(inst.values, np.int32)
+    w = np.ascontiguousarray(inst.weights, np.int32)
+    tiny = oracle_mod.Oracle(inst.values[:1], inst.weights[:1], 1, 1, inst.seed)
+    amp0 = tiny.amplitudes()[0][0, 0]
+    del tiny
+    rows = sorted(set(SAMPLE_ROWS) | {e for e, _ in elites})
+    st = {c: {"a": np.full(ng, amp0, np.float32), "b": np.full(ng, amp0, np.float32),
+              "x": np.zeros(ng, np.uint8), "y": np.zeros(ng, np.uint8), "f": 0} for c in rows}
+    elite_x = np.zeros(ng, np.uint8)
+
+    def advance(c, t, ex, fe):
+        r = st[c]
+        below = t > 0 and r["f"] < fe
+        f, _, _ = oracle_mod.row_generation_inplace(inst.seed, t, c, v, w, inst.capacity,
+                                                    r["a"], r["b"], r["x"], ex, below, r["y"])
+        r["x"], r["y"] = r["y"], r["x"]
+        r["f"] = f
+
+    with ThreadPoolExecutor(max_workers=16) as pool:
+        for t in range(G):
+            fe = elites[t - 1][1] if t > 0 else 0
+            list(pool.map(lambda c: advance(c, t, elite_x, fe), rows))
+            e, fe_t = elites[t]
+            assert st[e]["f"] == fe_t, "elite fitness, generation %d" % t
+            for j, c in enumerate(SAMPLE_ROWS):
+                assert st[c]["f"] == fits[t][j], "generation %d row %d" % (t, c)
+            elite_x = st[e]["x"].copy()
+        # state after generation G-1 with its rotation applied, as exported
+        e, fe = elites[G - 1]
+        for c in SAMPLE_ROWS:
+            r = st[c]
+            a, b = r["a"].copy(), r["b"].copy()
+            y = np.zeros(ng, np.uint8)
+            oracle_mod.row_generation_inplace(inst.seed, G, c, v, w, inst.capacity, a, b,
+                                              r["x"], elite_x, r["f"] < fe, y)
+            s = g2.export_rows(c, 1)
+            assert np.array_equal(s["alleles"][0], r["x"]), "alleles row %d" % c
+            assert bits_equal(s["alpha"][0], a) and bits_equal(s["beta"][0], b), \
+                "amplitudes row %d" % c
+    g1.close()
+    g2.close()

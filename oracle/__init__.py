@@ -75,6 +75,7 @@ def lib():
         L.oracle_cip_gene.argtypes = [P, P, ctypes.c_int]
         L.oracle_row_generation.argtypes = [u64, i64, i64, i64, P, P, i64, P, P, P, P,
                                             ctypes.c_int, P, P]
+        L.oracle_row_generation_f64.argtypes = L.oracle_row_generation.argtypes
         L.oracle_get_amplitudes.argtypes = [P, P, P]
         L.oracle_set_amplitudes.argtypes = [P, P, P]
         L.oracle_get_alleles.argtypes = [P, P]
@@ -133,37 +134,41 @@ def cip_gene_f64(alpha: float, beta: float, tgt: int):
 
 
 def row_generation(seed: int, t: int, c: int, v, w, capacity: int, alpha, beta,
-                   x_prev=None, elite_prev=None, below_elite: bool = False):
-    """Chromosome c's part of generation t (binary32): CIP of t-1 toward the
-    elite's alleles when the chromosome scored below the elite, then QIP and
-    Evaluation of t.  alpha, beta: its amplitudes as t-1 observed them.
-    Returns (alpha', beta', alleles of t, fitness, profit, weight)."""
+                   x_prev=None, elite_prev=None, below_elite: bool = False,
+                   precision: int = 32):
+    """Chromosome c's part of generation t: CIP of t-1 toward the elite's
+    alleles when the chromosome scored below the elite, then QIP and
+    Evaluation of t.  alpha, beta: its amplitudes as t-1 observed them
+    (binary32, or binary64 with precision=64).  Returns (alpha', beta',
+    alleles of t, fitness, profit, weight)."""
     v = np.ascontiguousarray(v, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.int32)
     ng = v.size
-    a = np.array(alpha, dtype=np.float32, copy=True).reshape(ng)
-    b = np.array(beta, dtype=np.float32, copy=True).reshape(ng)
+    dt = np.float64 if precision == 64 else np.float32
+    a = np.array(alpha, dtype=dt, copy=True).reshape(ng)
+    b = np.array(beta, dtype=dt, copy=True).reshape(ng)
     xp = np.zeros(ng, np.uint8) if x_prev is None else np.ascontiguousarray(x_prev, np.uint8)
     ep = np.zeros(ng, np.uint8) if elite_prev is None else np.ascontiguousarray(elite_prev,
                                                                                  np.uint8)
     x = np.zeros(ng, np.uint8)
     out = np.zeros(3, np.int64)
-    lib().oracle_row_generation(seed & (2**64 - 1), int(t), int(c), ng, _ptr(v), _ptr(w),
-                                int(capacity), _ptr(a), _ptr(b), _ptr(xp), _ptr(ep),
-                                int(bool(below_elite)), _ptr(x), _ptr(out))
+    fn = lib().oracle_row_generation_f64 if precision == 64 else lib().oracle_row_generation
+    fn(seed & (2**64 - 1), int(t), int(c), ng, _ptr(v), _ptr(w), int(capacity), _ptr(a),
+       _ptr(b), _ptr(xp), _ptr(ep), int(bool(below_elite)), _ptr(x), _ptr(out))
     return a, b, x, int(out[0]), int(out[1]), int(out[2])
 
 
 def row_generation_inplace(seed: int, t: int, c: int, v, w, capacity: int, alpha, beta,
                            x_prev, elite_prev, below_elite: bool, x_out):
     """row_generation on caller-owned contiguous arrays (int32 v, w; float32
-    alpha, beta updated in place; uint8 x_prev, elite_prev, x_out), without
-    copies; returns (fitness, profit, weight).  Thread-safe."""
+    or float64 alpha, beta updated in place; uint8 x_prev, elite_prev, x_out),
+    without copies; returns (fitness, profit, weight).  Thread-safe."""
     out = np.zeros(3, np.int64)
-    lib().oracle_row_generation(seed & (2**64 - 1), int(t), int(c), v.size, _ptr(v), _ptr(w),
-                                int(capacity), _ptr(alpha), _ptr(beta), _ptr(x_prev),
-                                _ptr(elite_prev), int(bool(below_elite)), _ptr(x_out),
-                                _ptr(out))
+    fn = (lib().oracle_row_generation_f64 if alpha.dtype == np.float64
+          else lib().oracle_row_generation)
+    fn(seed & (2**64 - 1), int(t), int(c), v.size, _ptr(v), _ptr(w), int(capacity),
+       _ptr(alpha), _ptr(beta), _ptr(x_prev), _ptr(elite_prev), int(bool(below_elite)),
+       _ptr(x_out), _ptr(out))
     return int(out[0]), int(out[1]), int(out[2])
 
 

@@ -397,6 +397,35 @@ void oracle_row_generation(uint64_t seed, int64_t t, int64_t c, int64_t ng,
     out[2] = W;
 }
 
+/* The same chromosome-local step with binary64 amplitudes (reading R8). */
+void oracle_row_generation_f64(uint64_t seed, int64_t t, int64_t c, int64_t ng,
+                               const int32_t *v, const int32_t *w, int64_t cap,
+                               double *alpha, double *beta, const uint8_t *x_prev,
+                               const uint8_t *elite_prev, int below_elite,
+                               uint8_t *x_out, int64_t out[3])
+{
+    if (below_elite)
+        for (int64_t i = 0; i < ng; ++i)
+            if (x_prev[i] != elite_prev[i])
+                oracle_cip_gene_f64(&alpha[i], &beta[i], elite_prev[i]);
+    int64_t P = 0, W = 0;
+    for (int64_t k = 0; 4 * k < ng; ++k) {
+        uint32_t r[4];
+        draws4(seed, t, c, k, r);
+        for (int j = 0; j < 4 && 4 * k + j < ng; ++j) {
+            const int64_t i = 4 * k + j;
+            const double b2 = beta[i] * beta[i];
+            const double u = (double)(r[j] >> 8) * 0x1p-24;
+            x_out[i] = (u < b2) ? 1 : 0;
+            P += (int64_t)v[i] * x_out[i];
+            W += (int64_t)w[i] * x_out[i];
+        }
+    }
+    out[0] = (W <= cap) ? P : -(W - cap);
+    out[1] = P;
+    out[2] = W;
+}
+
 /* Termination test of Sec. IV-A, read for integer fitness: the run has
  * converged after generation t when the elite fitness of the last `window`
  * generations (t-window+1 .. t) is one value (a spread within 1e-6 of the

@@ -165,17 +165,20 @@ def test_population_beyond_2_32_genes(qieo, oracle_mod):
     g.close()
 
 
-def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod):
+@pytest.mark.parametrize("precision", [32, 64])
+def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod, precision):
     """The benchmark's run (3 generations, then 200 in one call) against a
     run stepped one generation at a time, bit for bit; along the stepped run,
     every generation's elite and 12 sampled rows are recomputed chromosome by
     chromosome (oracle, 16 threads) from the GPU's elite sequence: their
     fitness at all 203 generations, and at the end their alleles and
-    amplitudes."""
+    amplitudes.  Binary32 and binary64 amplitudes."""
     from concurrent.futures import ThreadPoolExecutor
     inst = workloads.large_instance()
     n_pop, ng, G = inst.n_pop, inst.n_items, 3 + inst.generations
-    g1 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed)
+    dt = np.float64 if precision == 64 else np.float32
+    g1 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
+                       precision=precision)
     elites, fits = [], []
     for k in range(G):
         g1.step(1)
@@ -185,7 +188,8 @@ def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod):
         assert e == int(np.argmax(fit)), "generation %d" % k
         elites.append((e, int(fit[e])))
         fits.append(fit[SAMPLE_ROWS].copy())
-    g2 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed)
+    g2 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
+                       precision=precision)
     g2.step(3)
     g2.step(inst.generations)
     s1 = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
@@ -195,11 +199,12 @@ def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod):
 
     v = np.ascontiguousarray(inst.values, np.int32)
     w = np.ascontiguousarray(inst.weights, np.int32)
-    tiny = oracle_mod.Oracle(inst.values[:1], inst.weights[:1], 1, 1, inst.seed)
+    tiny = oracle_mod.Oracle(inst.values[:1], inst.weights[:1], 1, 1, inst.seed,
+                             precision=precision)
     amp0 = tiny.amplitudes()[0][0, 0]
     del tiny
     rows = sorted(set(SAMPLE_ROWS) | {e for e, _ in elites})
-    st = {c: {"a": np.full(ng, amp0, np.float32), "b": np.full(ng, amp0, np.float32),
+    st = {c: {"a": np.full(ng, amp0, dt), "b": np.full(ng, amp0, dt),
               "x": np.zeros(ng, np.uint8), "y": np.zeros(ng, np.uint8), "f": 0} for c in rows}
     elite_x = np.zeros(ng, np.uint8)
 

@@ -197,13 +197,16 @@ def test_convergence_window_respects_the_cap(oracle_mod):
     assert not o.converged(0)
 
 
-def test_row_generation_composes_to_the_population_oracle(oracle_mod):
+@pytest.mark.parametrize("precision", [32, 64])
+def test_row_generation_composes_to_the_population_oracle(oracle_mod, precision):
     """Every chromosome driven through the chromosome-local step, with
     DetermineElite taken over the rows' fitness (largest, lowest index),
     gives the population oracle's alleles, fitness, elite and amplitudes at
     every generation (ragged Ng, rows below, at and above the elite)."""
     inst = workloads.random_instance(301, 9, seed=4)
-    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          precision=precision)
+    bits = np.uint64 if precision == 64 else np.uint32
     a0, b0 = o.amplitudes()
     rows = [{"a": a0[c].copy(), "b": b0[c].copy(), "x": None, "f": None}
             for c in range(inst.n_pop)]
@@ -217,9 +220,9 @@ def test_row_generation_composes_to_the_population_oracle(oracle_mod):
             below = t > 0 and r["f"] < fe
             a, b, x, f, P, W = oracle_mod.row_generation(
                 inst.seed, t, c, inst.values, inst.weights, inst.capacity, r["a"], r["b"],
-                r["x"], elite_x, below)
-            assert np.array_equal(a.view(np.uint32), prev_a[c].view(np.uint32)), (t, c)
-            assert np.array_equal(b.view(np.uint32), prev_b[c].view(np.uint32)), (t, c)
+                r["x"], elite_x, below, precision=precision)
+            assert np.array_equal(a.view(bits), prev_a[c].view(bits)), (t, c)
+            assert np.array_equal(b.view(bits), prev_b[c].view(bits)), (t, c)
             assert np.array_equal(x, x_o[c]), (t, c)
             assert (f, P, W) == (f_o[c], P_o[c], W_o[c]), (t, c)
             r.update(a=a, b=b, x=x, f=f)

@@ -197,8 +197,8 @@ int qieo_get_tile(qieo_inst *h, int32_t *rows_per_block, int32_t *waves_per_bloc
  * non-temporal hints, bit 3 re-derives the previous generation's alleles
  * from the stored beta and their draws instead of reading the stored allele
  * words back, bit 4 runs each generation in segment order (one workgroup per
- * segment of a row, 2048 genes for binary32 and 1024 for binary64, launched
- * in address order, then a small launch
+ * 1024-gene segment of a row, each of the device's XCDs sweeping one
+ * contiguous run of segments in address order, then a small launch
  * closing the rows' sums; the work shape of qieo_set_tile does not apply;
  * bit 0 is ignored).  Binary64 handles ignore bit 3 in row order.  Variants
  * change speed only, never results.  Out-of-range values give QIEO_EINVAL. */

@@ -18,9 +18,10 @@
 // memory fences.
 //
 // Segment order (segment_kernel + segment_fe_kernel), for populations that
-// stream from HBM: one workgroup per 2048-gene segment of a row, launched in
-// address order; segment sums are stored plainly and a second launch closes
-// each row's fitness and the elite.
+// stream from HBM: one workgroup per 1024-gene segment of a row, numbered so
+// that each XCD sweeps one contiguous run of segments in address order;
+// segment sums are stored plainly and a second launch closes each row's
+// fitness and the elite.
 //
 // Single-workgroup loops (resident_kernel, persistent_kernel) run all
 // generations of a call for tiny populations, block barriers in place of
@@ -33,6 +34,7 @@
 // per-gene tests (own allele vs elite allele, target) are scalar mask logic
 // and v_cndmask selects.
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "qieo_device.hpp"
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // ---------------------------------------------------------------------------
 template <typename T, int FL, int SC, int SW>
 __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts, int k,
-                                                          int gens_all)
+                                                          int gens_all, int xcds)
 {
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
     constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0;
@@ -413,7 +415,16 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     const InstDev I = insts[0];
     const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
     const int nseg = (nchunk + SC - 1) / SC;
-    const int c = (int)blockIdx.x / nseg, seg = (int)blockIdx.x - c * nseg;
+    // Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD
+    // b mod xcds); renumbering them gives each XCD one contiguous run of
+    // segments, which it sweeps in address order.
+    int bid = (int)blockIdx.x;
+    if (xcds > 1) {
+        const int n = (int)gridDim.x, q = n / xcds, r = n % xcds;
+        const int x = bid % xcds, j = bid / xcds;
+        bid = x * q + (x < r ? x : r) + j;
+    }
+    const int c = bid / nseg, seg = bid - c * nseg;
     const int64_t t = sload(I.tbase) + k;
     const int par = (int)(t & 1);
     const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
@@ -428,8 +439,7 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         e_prev = key_row(key);
         fe_prev = key_fitness(key);
     }
-    if (!open_generation(I, t, sload(I.conv + 3), blockIdx.x == 0, wave, lane, e_prev, fe_prev,
-                         xprev))
+    if (!open_generation(I, t, sload(I.conv + 3), bid == 0, wave, lane, e_prev, fe_prev, xprev))
         return;
 
     const bool rot = pending && sload(I.fit + (par ^ 1) * np + c) < fe_prev;
@@ -1371,6 +1381,28 @@ hipError_t launch_init(const InstDev& I, hipStream_t s, bool f64)
     return hipGetLastError();
 }
 
+// XCDs of the current device (1 if the runtime cannot tell), cached per
+// device.
+static int xcd_count()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess ||
+            n < 1) {
+            (void)hipGetLastError();
+            n = 1;
+        }
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
                            bool f64, hipStream_t s)
 {
@@ -1383,8 +1415,9 @@ hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int
                       kFlagRecomputeAlleles == 8,
                   "segment variants below are spelled out by value");
     const dim3 grid((unsigned)blocks), block((unsigned)(64 * sw));
+    const int xcds = xcd_count();
 #define QIEO_SEG(TT, FF, SC, SW)                                                               \
-    hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW>), grid, block, 0, s, dI, k, gens_all)
+    hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW>), grid, block, 0, s, dI, k, gens_all, xcds)
 #define QIEO_SEG_T(TT, SC, SW)                                                                 \
     switch (flags & (kFlagNontemporal | kFlagNontemporalLoads | kFlagRecomputeAlleles)) {      \
     case 0: QIEO_SEG(TT, 0, SC, SW); break;                                                    \

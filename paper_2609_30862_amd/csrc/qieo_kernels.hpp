@@ -81,7 +81,7 @@ constexpr int kFlagAll = 31;
 // Segment geometry per amplitude type: 256-gene chunks per segment and waves
 // per segment workgroup (each wave takes whole chunks).  The partial-sum
 // array is sized for the shortest segment.
-constexpr int kSegChunks32 = 8, kSegWaves32 = 8;     // binary32: 2048 genes, 8 KB a plane
+constexpr int kSegChunks32 = 4, kSegWaves32 = 4;     // binary32: 1024 genes, 4 KB a plane
 constexpr int kSegChunks64 = 4, kSegWaves64 = 4;     // binary64: 1024 genes, 8 KB a plane
 constexpr int kSegChunksMin = kSegChunks32 < kSegChunks64 ? kSegChunks32 : kSegChunks64;
 

@@ -269,11 +269,11 @@ def test_graph_capture_with_concurrent_device_calls(qieo, oracle_mod):
     assert not errors, errors
 
 
-@pytest.mark.parametrize("ng,n_pop", [(1, 3), (255, 7), (2048, 4), (4096, 5), (4097, 9),
-                                      (9000, 33), (20000, 12)])
+@pytest.mark.parametrize("ng,n_pop", [(1, 3), (255, 7), (1024, 3), (1025, 2), (2048, 4),
+                                      (4096, 5), (4097, 9), (9000, 33), (20000, 12)])
 @pytest.mark.parametrize("flags", [16, 22, 31])
 def test_segment_order_same_trajectory(qieo, oracle_mod, ng, n_pop, flags):
-    """The segment-order generation (one workgroup per 2048-gene segment of a
+    """The segment-order generation (one workgroup per 1024-gene segment of a
     row, then a launch closing the rows) follows the oracle on rows shorter
     than one segment, exactly one or two, and several with a ragged last one;
     direct launches and graph replay."""

@@ -33,23 +33,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_code_digest(read=None) -> str:
+    """sha256 of the kernel sources' code: each line with its // comment and
+    surrounding blanks removed, empty lines dropped (comments do not change
+    what the counters measured).  read(path) -> text, default: the tree."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        text = read(f) if read else open(os.path.join(ROOT, f)).read()
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()
+
+
 def measured_traffic(n_pop: int, n_items: int, shape=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on this workload with the current kernel sources and the same
+    was taken on this workload with the current kernel code and the same
     work shape (rows, waves, variant bits) when one is given; else None."""
-    import hashlib
     if (n_pop, n_items) != (4096, 200_000):
         return None
     try:
         text = open(os.path.join(ROOT, PROFILE)).read()
-        h = hashlib.sha256()
-        for f in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, f), "rb") as fh:
-                h.update(fh.read())
         fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
-                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:",
+                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:",
                                                "work_shape:")))
-        if fig.get("kernel_source_sha256") != h.hexdigest():
+        if fig.get("kernel_code_sha256") != kernel_code_digest():
             return None
         if shape is not None and fig.get("work_shape") != "%d %d %d" % tuple(shape):
             return None

@@ -392,11 +392,12 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 
 // ---------------------------------------------------------------------------
 // The fused generation in segment order (single instance; T the amplitude
-// type).  Rows are cut into segments of SC chunks; workgroup b takes segment
-// b mod nseg of row b / nseg, so consecutive workgroups touch consecutive
-// addresses and the whole chip sweeps the amplitude planes in address order
-// (workgroups that each walk their own rows keep thousands of distant DRAM
-// pages open at once).  The SW waves take chunks w, w + SW, ... of the
+// type).  Rows are cut into segments of SC chunks; segment number s (segment
+// s mod nseg of row s / nseg) counts through the amplitude planes in address
+// order, and each XCD takes one contiguous run of segment numbers, so the
+// chip sweeps the planes in address order, eight runs at a time (workgroups
+// that each walk their own rows keep thousands of distant DRAM pages open at
+// once).  The SW waves take chunks w, w + SW, ... of the
 // segment and issue all their loads before computing.  Per gene the work is
 // the fused kernel's: CIP(t-1), QIP(t), Evaluation's sums; the segment's
 // (profit, weight) sums go to part[row][seg] with plain stores, and

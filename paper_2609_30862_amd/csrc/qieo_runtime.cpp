@@ -198,7 +198,7 @@ int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
 // (>= 32 chunks) and at least 1024 of them take 2 rows x 16 waves, the
 // fastest row shape on every such workload measured.  Streaming binary32
 // populations run in segment order instead: faster than the best row shape
-// on all ten streaming workloads measured (6-14 %; 2.29 ms against 2.58 on
+// on all ten streaming workloads measured (6-14 %; 2.23 ms against 2.56 on
 // 4096 x 200,000), slower on cache-resident ones (11-18 %), where the row
 // kernel stays.
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes)
@@ -297,11 +297,11 @@ static void inst_release(qieo_inst* h)
 
 // The handle's work shape when the caller sets none: the tuning database's
 // entry for its bucket, else the built-in rule.  Binary64 amplitudes: in
-// segment order with non-temporal stores when streaming (non-temporal loads
-// were slower there too); otherwise row order with at most 2 rows and 4 waves
-// per workgroup (twice the registers per gene), prefetch and cached loads
-// (its 32-byte non-temporal loads were slower in every binary64 shape
-// measured).
+// segment order with non-temporal loads and stores when streaming (its
+// transfers go through LDS as whole 1 KB lines); otherwise row order with at
+// most 2 rows and 4 waves per workgroup (twice the registers per gene),
+// prefetch and cached loads (the row kernel's 32-byte-per-lane non-temporal
+// loads were slower in every binary64 shape measured).
 static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
 {
     if (h->f64 || !tuned_tile(h->np, h->L.nchunk, R, S, F))
@@ -311,7 +311,7 @@ static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
         *S = std::min(*S, 4);
         const int64_t planes = (int64_t)h->np * h->L.nchunk * kChunk * 2 * 8;
         if (planes > ((int64_t)256 << 20))
-            // 5.05-5.07 ms per generation at 4096 x 200,000 against 5.76 in row order
+            // 4.42 ms per generation at 4096 x 200,000 against 5.76 in row order
             *F = kFlagSegments | kFlagNontemporal | kFlagNontemporalLoads;
         else
             *F = (*F & ~(kFlagNontemporalLoads | kFlagPrefetch | kFlagSegments)) |

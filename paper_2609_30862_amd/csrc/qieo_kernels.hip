@@ -404,18 +404,16 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // segment_fe_kernel closes them into fitness and the elite once every
 // segment is done (the launch boundary is the only synchronisation).
 // ---------------------------------------------------------------------------
-template <typename T, int FL, int SC, int SW>
-__global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts, int k,
+template <typename T, int FL, int SC, int SW, bool TILED>
+__global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts,
+                                                          const Tile* __restrict__ tiles, int k,
+                                                          const int32_t* __restrict__ gens_arr,
                                                           int gens_all, int xcds)
 {
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
     constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0;
     static_assert(SC % SW == 0, "whole chunks per wave");
     constexpr int CPW = SC / SW;                          // chunks per wave
-    if (k >= gens_all) return;
-    const InstDev I = insts[0];
-    const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
-    const int nseg = (nchunk + SC - 1) / SC;
     // Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD
     // b mod xcds); renumbering them gives each XCD one contiguous run of
     // segments, which it sweeps in address order.
@@ -425,7 +423,21 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         const int x = bid % xcds, j = bid / xcds;
         bid = x * q + (x < r ? x : r) + j;
     }
-    const int c = bid / nseg, seg = bid - c * nseg;
+    // segment number within the instance: the workgroup number (instance 0),
+    // or the tile's, whose row0 field then holds a segment number
+    uint32_t inst = 0, sno = (uint32_t)bid;
+    int gens = gens_all;
+    if constexpr (TILED) {
+        const Tile tt = tiles[bid];
+        inst = tt.inst;
+        sno = tt.row0;
+        gens = sload(gens_arr + inst);
+    }
+    if (k >= gens) return;
+    const InstDev I = insts[inst];
+    const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
+    const int nseg = (nchunk + SC - 1) / SC;
+    const int c = (int)sno / nseg, seg = (int)sno - c * nseg;
     const int64_t t = sload(I.tbase) + k;
     const int par = (int)(t & 1);
     const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
@@ -440,7 +452,7 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         e_prev = key_row(key);
         fe_prev = key_fitness(key);
     }
-    if (!open_generation(I, t, sload(I.conv + 3), bid == 0, wave, lane, e_prev, fe_prev, xprev))
+    if (!open_generation(I, t, sload(I.conv + 3), sno == 0, wave, lane, e_prev, fe_prev, xprev))
         return;
 
     const bool rot = pending && sload(I.fit + (par ^ 1) * np + c) < fe_prev;
@@ -603,18 +615,28 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
 // Closes generation t of the segment path: one wave per row sums the row's
 // segment partials into profit and weight, applies eq. (1) and stores the
 // row's fitness slot; DetermineElite offers the workgroup's best key.
-__global__ __launch_bounds__(256) void segment_fe_kernel(const InstDev* __restrict__ insts, int k,
+__global__ __launch_bounds__(256) void segment_fe_kernel(const InstDev* __restrict__ insts,
+                                                         const Tile* __restrict__ tiles, int k,
+                                                         const int32_t* __restrict__ gens_arr,
                                                          int gens_all, int seg_chunks)
 {
-    if (k >= gens_all) return;
-    const InstDev I = insts[0];
+    // the workgroup's four rows: from its number (instance 0) or its tile
+    uint32_t inst = 0, row0 = blockIdx.x * (blockDim.x >> 6);
+    if (tiles != nullptr) {
+        const Tile tt = tiles[blockIdx.x];
+        inst = tt.inst;
+        row0 = tt.row0;
+    }
+    const int gens = gens_arr ? sload(gens_arr + inst) : gens_all;
+    if (k >= gens) return;
+    const InstDev I = insts[inst];
     const int64_t t = sload(I.tbase) + k;
     if (sload(I.conv + 3) > 0 && sload(I.conv) != 0) return;   // generation t did not run
     const int np = I.np;
     const int nseg = (I.nchunk + seg_chunks - 1) / seg_chunks;
     const int par = (int)(t & 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = (int)blockIdx.x * (blockDim.x >> 6) + wave;
+    const int c = (int)row0 + wave;
     uint32_t P = 0u, W = 0u;
     if (c < np) {
         const uint32_t* row = I.part + (size_t)c * nseg * 2;
@@ -1404,21 +1426,29 @@ static int xcd_count()
     return n;
 }
 
-hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
-                           bool f64, hipStream_t s)
+// Segment launch and the launch closing the rows, for n_seg segment
+// workgroups and n_fe row-closing workgroups (four rows each).
+static hipError_t segments_common(const InstDev* dI, const Tile* seg_tiles, int64_t n_seg,
+                                  const Tile* fe_tiles, int64_t n_fe, int flags, int k,
+                                  const int32_t* gens_arr, int gens_all, bool f64, hipStream_t s)
 {
-    const int sc = f64 ? kSegChunks64 : kSegChunks32;
-    const int sw = f64 ? kSegWaves64 : kSegWaves32;
-    const int nseg = (nchunk + sc - 1) / sc;
-    const int64_t blocks = (int64_t)np * nseg;
-    if (np <= 0 || blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (n_seg <= 0 || n_fe <= 0 || n_seg > INT32_MAX) return hipErrorInvalidValue;
     static_assert(kFlagNontemporal == 2 && kFlagNontemporalLoads == 4 &&
                       kFlagRecomputeAlleles == 8,
                   "segment variants below are spelled out by value");
-    const dim3 grid((unsigned)blocks), block((unsigned)(64 * sw));
+    const int sc = f64 ? kSegChunks64 : kSegChunks32;
+    const int sw = f64 ? kSegWaves64 : kSegWaves32;
+    const dim3 grid((unsigned)n_seg), block((unsigned)(64 * sw));
     const int xcds = xcd_count();
 #define QIEO_SEG(TT, FF, SC, SW)                                                               \
-    hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW>), grid, block, 0, s, dI, k, gens_all, xcds)
+    do {                                                                                       \
+        if (seg_tiles)                                                                         \
+            hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW, true>), grid, block, 0, s, dI,  \
+                               seg_tiles, k, gens_arr, gens_all, xcds);                        \
+        else                                                                                   \
+            hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW, false>), grid, block, 0, s, dI, \
+                               seg_tiles, k, gens_arr, gens_all, xcds);                        \
+    } while (0)
 #define QIEO_SEG_T(TT, SC, SW)                                                                 \
     switch (flags & (kFlagNontemporal | kFlagNontemporalLoads | kFlagRecomputeAlleles)) {      \
     case 0: QIEO_SEG(TT, 0, SC, SW); break;                                                    \
@@ -1430,6 +1460,7 @@ hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int
     case 12: QIEO_SEG(TT, 12, SC, SW); break;                                                  \
     default: QIEO_SEG(TT, 14, SC, SW); break;                                                  \
     }
+    if (f64 && seg_tiles) return hipErrorInvalidValue;     // tiled launches are binary32
     if (f64) {
         QIEO_SEG_T(double, kSegChunks64, kSegWaves64)
     } else {
@@ -1439,9 +1470,26 @@ hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int
 #undef QIEO_SEG
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(segment_fe_kernel, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, s, dI, k,
-                       gens_all, sc);
+    hipLaunchKernelGGL(segment_fe_kernel, dim3((unsigned)n_fe), dim3(256), 0, s, dI, fe_tiles, k,
+                       gens_arr, gens_all, sc);
     return hipGetLastError();
+}
+
+hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
+                           bool f64, hipStream_t s)
+{
+    if (np <= 0) return hipErrorInvalidValue;
+    const int sc = f64 ? kSegChunks64 : kSegChunks32;
+    const int64_t nseg = (nchunk + sc - 1) / sc;
+    return segments_common(dI, nullptr, (int64_t)np * nseg, nullptr, (np + 3) / 4, flags, k,
+                           nullptr, gens_all, f64, s);
+}
+
+hipError_t launch_segments_tiled(const InstDev* dI, const Tile* seg_tiles, int n_seg,
+                                 const Tile* fe_tiles, int n_fe, int flags, int k,
+                                 const int32_t* gens_arr, hipStream_t s)
+{
+    return segments_common(dI, seg_tiles, n_seg, fe_tiles, n_fe, flags, k, gens_arr, 0, false, s);
 }
 
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,

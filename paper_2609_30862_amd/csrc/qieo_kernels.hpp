@@ -114,6 +114,12 @@ hipError_t launch_generation_f64(const InstDev* dI, int n_blocks, int rows_per_b
 // (kFlagSegments): the segment launch and the launch that closes the rows.
 hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
                            bool f64, hipStream_t s);
+// The same over tile tables (binary32): seg_tiles[b] = {instance, segment
+// number within it}, in address order; fe_tiles[b] = {instance, first of
+// the (up to) four rows the closing workgroup b takes}.
+hipError_t launch_segments_tiled(const InstDev* dI, const Tile* seg_tiles, int n_seg,
+                                 const Tile* fe_tiles, int n_fe, int flags, int k,
+                                 const int32_t* gens_arr, hipStream_t s);
 // One stage of the unfused pipeline for a single instance: kStepCip (CIP of
 // generation t-1 plus the previous generation's bookkeeping), kStepQip,
 // kStepFe, kStepFe | kStepDe, or kStepDe (the standalone elite reduction).

@@ -114,8 +114,10 @@ Engine::~Engine()
     if (side_) (void)hipStreamDestroy(side_);
     for (hipEvent_t ev : cjoin_) (void)hipEventDestroy(ev);
     for (hipStream_t cs : cstreams_) (void)hipStreamDestroy(cs);
-    for (auto& c : classes_)
+    for (auto& c : classes_) {
         if (c.d_tiles) (void)hipFree(c.d_tiles);
+        if (c.d_fe_tiles) (void)hipFree(c.d_fe_tiles);
+    }
     if (d_desc_) (void)hipFree(d_desc_);
     if (d_gens_) (void)hipFree(d_gens_);
     if (d_status_) (void)hipFree(d_status_);
@@ -200,8 +202,10 @@ int Engine::rebuild()
 {
     invalidate_graph();
     prev_n_ = -1;
-    for (auto& c : classes_)
+    for (auto& c : classes_) {
         if (c.d_tiles) (void)hipFree(c.d_tiles);
+        if (c.d_fe_tiles) (void)hipFree(c.d_fe_tiles);
+    }
     classes_.clear();
     const size_t n = members_.size();
     hipError_t e;
@@ -312,14 +316,45 @@ int Engine::rebuild()
             sc.S = force_S_;
             sc.flags = force_flags_;
         }
-        for (size_t i : g)
-            for (int32_t r0 = 0; r0 < members_[i].np; r0 += sc.R)
-                sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
+        // The longest rows (>= 32 chunks) of a batch that streams from HBM
+        // run in segment order: one tile per 1024-gene segment, members in
+        // arena address order, so the class sweeps its planes in address
+        // order; a second tile table gives the closing launch four rows per
+        // workgroup.
+        const bool seg = c == kClasses - 1 && use_segments_ && force_R_ == 0 &&
+                         plane_bytes > ((int64_t)256 << 20);
+        if (seg) {
+            std::sort(g.begin(), g.end(),
+                      [&](size_t a, size_t b) { return members_[a].arena < members_[b].arena; });
+            sc.flags = kFlagSegments | kFlagNontemporal | kFlagNontemporalLoads;
+            for (size_t i : g) {
+                const Member& m = members_[i];
+                const int64_t nseg = (m.L.nchunk + kSegChunks32 - 1) / kSegChunks32;
+                for (int64_t q = 0; q < (int64_t)m.np * nseg; ++q)
+                    sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)q});
+                for (int32_t r0 = 0; r0 < m.np; r0 += 4)
+                    sc.fe_tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
+            }
+            if (sc.tiles.size() > (size_t)INT32_MAX)
+                return set_error(QIEO_EINVAL, "segment tile table too large");
+        } else {
+            for (size_t i : g)
+                for (int32_t r0 = 0; r0 < members_[i].np; r0 += sc.R)
+                    sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
+        }
         if ((e = hipMalloc(&sc.d_tiles, sc.tiles.size() * sizeof(Tile))) != hipSuccess)
             return hip_fail(e, "hipMalloc(tiles)");
         if ((e = hipMemcpyAsync(sc.d_tiles, sc.tiles.data(), sc.tiles.size() * sizeof(Tile),
                                 hipMemcpyHostToDevice, stream_)) != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(tiles)");
+        if (!sc.fe_tiles.empty()) {
+            if ((e = hipMalloc(&sc.d_fe_tiles, sc.fe_tiles.size() * sizeof(Tile))) != hipSuccess)
+                return hip_fail(e, "hipMalloc(tiles)");
+            if ((e = hipMemcpyAsync(sc.d_fe_tiles, sc.fe_tiles.data(),
+                                    sc.fe_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                    stream_)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(tiles)");
+        }
         classes_.push_back(std::move(sc));
     }
     while (cstreams_.size() + 1 < classes_.size()) {
@@ -365,9 +400,13 @@ int Engine::enqueue(int nmax)
         if (ci > 0 && (e = hipStreamWaitEvent(cs, fork_, 0)) != hipSuccess)
             return hip_fail(e, "fork");
         for (int k = 0; k < nmax; ++k) {
-            if ((e = launch_generation(d_desc_, c.d_tiles, (int)c.tiles.size(), c.R, c.S, c.flags,
-                                       k, d_gens_, 0, cs)) != hipSuccess)
-                return hip_fail(e, "generation kernel");
+            e = (c.flags & kFlagSegments)
+                    ? launch_segments_tiled(d_desc_, c.d_tiles, (int)c.tiles.size(),
+                                            c.d_fe_tiles, (int)c.fe_tiles.size(), c.flags, k,
+                                            d_gens_, cs)
+                    : launch_generation(d_desc_, c.d_tiles, (int)c.tiles.size(), c.R, c.S,
+                                        c.flags, k, d_gens_, 0, cs);
+            if (e != hipSuccess) return hip_fail(e, "generation kernel");
         }
         if (ci > 0 && (e = hipEventRecord(cjoin_[ci - 1], cs)) != hipSuccess)
             return hip_fail(e, "join");
@@ -690,6 +729,14 @@ extern "C" int qieo_batch_set_persistent(qieo_batch* b, int32_t enabled)
     clear_error();
     if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
     b->eng->set_use_persistent(enabled != 0);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_set_segment_order(qieo_batch* b, int32_t enabled)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    b->eng->set_use_segments(enabled != 0);
     return QIEO_OK;
 }
 

@@ -54,6 +54,10 @@ struct ShapeClass {
     int R = 4, S = 8, flags = 0;
     std::vector<Tile> tiles;
     Tile* d_tiles = nullptr;   // device copy
+    // segment order (flags has kFlagSegments): tiles are {member, segment
+    // number} in address order, fe_tiles {member, first of four rows}
+    std::vector<Tile> fe_tiles;
+    Tile* d_fe_tiles = nullptr;
 };
 
 class Engine {
@@ -84,6 +88,7 @@ public:
     void force_shape(int R, int S, int flags);
     void set_use_graph(bool on) { use_graph_ = on; invalidate_graph(); }
     void set_use_persistent(bool on) { use_persistent_ = on; dirty_ = true; }
+    void set_use_segments(bool on) { use_segments_ = on; dirty_ = true; }
     // Uploads descriptors and tile tables if membership changed since the
     // last launch (device_desc() is valid only after this).
     int ensure_built() { return dirty_ ? rebuild() : QIEO_OK; }
@@ -115,6 +120,7 @@ private:
     std::vector<hipStream_t> cstreams_;
     std::vector<hipEvent_t> cjoin_;
     bool use_persistent_ = true;
+    bool use_segments_ = true;   // long-row class in segment order when streaming
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;
     hipGraphExec_t graph_ = nullptr;

@@ -184,6 +184,8 @@ def _load():
     L.qieo_batch_set_tile.argtypes = [H, i32, i32, i32]
     L.qieo_batch_set_persistent.restype = ctypes.c_int
     L.qieo_batch_set_persistent.argtypes = [H, i32]
+    L.qieo_batch_set_segment_order.restype = ctypes.c_int
+    L.qieo_batch_set_segment_order.argtypes = [H, i32]
     L.qieo_batch_set_graph.restype = ctypes.c_int
     L.qieo_batch_set_graph.argtypes = [H, i32]
     L.qieo_batch_destroy.restype = None
@@ -581,6 +583,11 @@ class Batch:
     def set_persistent(self, enabled: bool):
         _check(lib.qieo_batch_set_persistent(self._h, int(bool(enabled))),
                "qieo_batch_set_persistent")
+
+    def set_segment_order(self, enabled: bool):
+        """Long-row members in segment order when the batch streams (default)."""
+        _check(lib.qieo_batch_set_segment_order(self._h, int(bool(enabled))),
+               "qieo_batch_set_segment_order")
 
     def converged(self, i: int):
         c, g = ctypes.c_int32(), ctypes.c_int64()

@@ -81,4 +81,5 @@ def test_null_handles_are_rejected():
     assert L.qieo_import_state(None, buf.ctypes.data_as(ctypes.c_void_p), 64) == qieo.QIEO_EINVAL
     assert L.qieo_set_persistent(None, 1) == qieo.QIEO_EINVAL
     assert L.qieo_set_kernel_flags(None, 0) == qieo.QIEO_EINVAL
+    assert L.qieo_batch_set_segment_order(None, 1) == qieo.QIEO_EINVAL
     L.qieo_destroy(None)

@@ -189,6 +189,7 @@ void Engine::force_shape(int R, int S, int flags)
 // Shape classes by 256-gene chunks per row: 1, 2-3, 4-7, 8-31, >= 32; the
 // class's waves per workgroup are 1, 2, 4, 8, 16.
 constexpr int kClasses = 5;
+constexpr int64_t kMaxSegTiles = (int64_t)1 << 22;   // 32 MB of segment tiles
 static int class_of(int32_t nchunk)
 {
     if (nchunk <= 1) return 0;
@@ -321,8 +322,16 @@ int Engine::rebuild()
         // arena address order, so the class sweeps its planes in address
         // order; a second tile table gives the closing launch four rows per
         // workgroup.
+        // The segment table costs 8 bytes per 1024 genes and is rebuilt on
+        // every membership change; a server holding thousands of residents
+        // changes membership every few generations, so a class of more than
+        // kMaxSegTiles segments keeps row order.
+        int64_t n_seg_tiles = 0;
+        for (size_t i : g)
+            n_seg_tiles += (int64_t)members_[i].np *
+                           ((members_[i].L.nchunk + kSegChunks32 - 1) / kSegChunks32);
         const bool seg = c == kClasses - 1 && use_segments_ && force_R_ == 0 &&
-                         plane_bytes > ((int64_t)256 << 20);
+                         plane_bytes > ((int64_t)256 << 20) && n_seg_tiles <= kMaxSegTiles;
         if (seg) {
             std::sort(g.begin(), g.end(),
                       [&](size_t a, size_t b) { return members_[a].arena < members_[b].arena; });

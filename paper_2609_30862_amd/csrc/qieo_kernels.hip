@@ -404,11 +404,23 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // segment_fe_kernel closes them into fitness and the elite once every
 // segment is done (the launch boundary is the only synchronisation).
 // ---------------------------------------------------------------------------
+// Launch-wide constants of the segment numbering, computed on the host so
+// that no workgroup divides: the grid's split over the XCDs and, for a
+// single instance, the reciprocal of its segments per row.
+struct SegMap {
+    int32_t xcds;        // XCDs (1: no renumbering)
+    int32_t xshift;      // log2(xcds) when xcds is a power of two, else -1
+    int32_t q, r;        // grid size = q * xcds + r
+    int32_t nseg;        // segments per row (untiled launches)
+    int32_t mshift;      // row of segment number s = (s * magic) >> mshift
+    uint64_t magic;
+};
+
 template <typename T, int FL, int SC, int SW, bool TILED>
 __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts,
                                                           const Tile* __restrict__ tiles, int k,
                                                           const int32_t* __restrict__ gens_arr,
-                                                          int gens_all, int xcds)
+                                                          int gens_all, SegMap map)
 {
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
     constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0;
@@ -418,10 +430,16 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     // b mod xcds); renumbering them gives each XCD one contiguous run of
     // segments, which it sweeps in address order.
     int bid = (int)blockIdx.x;
-    if (xcds > 1) {
-        const int n = (int)gridDim.x, q = n / xcds, r = n % xcds;
-        const int x = bid % xcds, j = bid / xcds;
-        bid = x * q + (x < r ? x : r) + j;
+    if (map.xcds > 1) {
+        int x, j;
+        if (map.xshift >= 0) {
+            x = bid & (map.xcds - 1);
+            j = bid >> map.xshift;
+        } else {
+            x = bid % map.xcds;
+            j = bid / map.xcds;
+        }
+        bid = x * map.q + (x < map.r ? x : map.r) + j;
     }
     // segment number within the instance: the workgroup number (instance 0),
     // or the tile's, whose row0 field then holds a segment number
@@ -436,8 +454,15 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     if (k >= gens) return;
     const InstDev I = insts[inst];
     const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
-    const int nseg = (nchunk + SC - 1) / SC;
-    const int c = (int)sno / nseg, seg = (int)sno - c * nseg;
+    int nseg, c;
+    if constexpr (TILED) {
+        nseg = (nchunk + SC - 1) / SC;
+        c = (int)sno / nseg;
+    } else {
+        nseg = map.nseg;
+        c = (int)(((uint64_t)sno * map.magic) >> map.mshift);
+    }
+    const int seg = (int)sno - c * nseg;
     const int64_t t = sload(I.tbase) + k;
     const int par = (int)(t & 1);
     const uint32_t* __restrict__ xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
@@ -1429,25 +1454,43 @@ static int xcd_count()
 // Segment launch and the launch closing the rows, for n_seg segment
 // workgroups and n_fe row-closing workgroups (four rows each).
 static hipError_t segments_common(const InstDev* dI, const Tile* seg_tiles, int64_t n_seg,
-                                  const Tile* fe_tiles, int64_t n_fe, int flags, int k,
-                                  const int32_t* gens_arr, int gens_all, bool f64, hipStream_t s)
+                                  int nseg_row, const Tile* fe_tiles, int64_t n_fe, int flags,
+                                  int k, const int32_t* gens_arr, int gens_all, bool f64,
+                                  hipStream_t s)
 {
     if (n_seg <= 0 || n_fe <= 0 || n_seg > INT32_MAX) return hipErrorInvalidValue;
+    if (!seg_tiles && nseg_row < 1) return hipErrorInvalidValue;
     static_assert(kFlagNontemporal == 2 && kFlagNontemporalLoads == 4 &&
                       kFlagRecomputeAlleles == 8,
                   "segment variants below are spelled out by value");
     const int sc = f64 ? kSegChunks64 : kSegChunks32;
     const int sw = f64 ? kSegWaves64 : kSegWaves32;
     const dim3 grid((unsigned)n_seg), block((unsigned)(64 * sw));
-    const int xcds = xcd_count();
+    SegMap map{};
+    map.xcds = xcd_count();
+    map.xshift = -1;
+    for (int b = 0; b < 31; ++b)
+        if (map.xcds == (1 << b)) map.xshift = b;
+    map.q = (int32_t)(n_seg / map.xcds);
+    map.r = (int32_t)(n_seg % map.xcds);
+    if (!seg_tiles) {
+        // q = (s * magic) >> mshift equals s / nseg for every s < 2^31:
+        // mshift = 31 + ceil(log2 nseg), magic = ceil(2^mshift / nseg)
+        int l = 0;
+        while ((1ll << l) < nseg_row) ++l;
+        map.nseg = nseg_row;
+        map.mshift = 31 + l;
+        map.magic = (uint64_t)((((unsigned __int128)1 << map.mshift) + (unsigned)nseg_row - 1) /
+                               (unsigned)nseg_row);
+    }
 #define QIEO_SEG(TT, FF, SC, SW)                                                               \
     do {                                                                                       \
         if (seg_tiles)                                                                         \
             hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW, true>), grid, block, 0, s, dI,  \
-                               seg_tiles, k, gens_arr, gens_all, xcds);                        \
+                               seg_tiles, k, gens_arr, gens_all, map);                         \
         else                                                                                   \
             hipLaunchKernelGGL((segment_kernel<TT, FF, SC, SW, false>), grid, block, 0, s, dI, \
-                               seg_tiles, k, gens_arr, gens_all, xcds);                        \
+                               seg_tiles, k, gens_arr, gens_all, map);                         \
     } while (0)
 #define QIEO_SEG_T(TT, SC, SW)                                                                 \
     switch (flags & (kFlagNontemporal | kFlagNontemporalLoads | kFlagRecomputeAlleles)) {      \
@@ -1481,15 +1524,16 @@ hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int
     if (np <= 0) return hipErrorInvalidValue;
     const int sc = f64 ? kSegChunks64 : kSegChunks32;
     const int64_t nseg = (nchunk + sc - 1) / sc;
-    return segments_common(dI, nullptr, (int64_t)np * nseg, nullptr, (np + 3) / 4, flags, k,
-                           nullptr, gens_all, f64, s);
+    return segments_common(dI, nullptr, (int64_t)np * nseg, (int)nseg, nullptr, (np + 3) / 4,
+                           flags, k, nullptr, gens_all, f64, s);
 }
 
 hipError_t launch_segments_tiled(const InstDev* dI, const Tile* seg_tiles, int n_seg,
                                  const Tile* fe_tiles, int n_fe, int flags, int k,
                                  const int32_t* gens_arr, hipStream_t s)
 {
-    return segments_common(dI, seg_tiles, n_seg, fe_tiles, n_fe, flags, k, gens_arr, 0, false, s);
+    return segments_common(dI, seg_tiles, n_seg, 0, fe_tiles, n_fe, flags, k, gens_arr, 0, false,
+                           s);
 }
 
 hipError_t launch_generation(const InstDev* dI, const Tile* tiles, int n_blocks,

@@ -93,8 +93,9 @@ typedef struct qieo_inst qieo_inst;
 /* Creates one population of n_pop chromosomes of n_items qubit genes for the
  * knapsack (items, capacity) (Sec. III-A) and initialises every amplitude pair
  * on the device.  Requires n_items >= 1, n_pop >= 1, capacity >= 0, every
- * profit and weight >= 0 (QIEO_EINVAL), and sum(profit), sum(weight) <=
- * INT32_MAX (QIEO_EOVERFLOW).  seed keys the Philox draws.  On success *out
+ * profit and weight >= 0, n_items <= 2^30 - 256 and n_pop times n_items
+ * rounded up to 64 at most 2^36 genes (QIEO_EINVAL), and sum(profit),
+ * sum(weight) <= INT32_MAX (QIEO_EOVERFLOW).  seed keys the Philox draws.  On success *out
  * receives the handle; on failure nothing is allocated. */
 int qieo_create(const qieo_item *items, int32_t n_items, int32_t capacity,
                 int32_t n_pop, uint64_t seed, qieo_inst **out);
@@ -349,14 +350,18 @@ typedef struct qieo_tune_result {
     double worst_ms_per_generation;     /* of the slowest candidate */
 } qieo_tune_result;
 
-/* Times every work shape (rows per workgroup 1/2/4 x waves 2/4/8/16 x the four
- * kernel variants) for trial_generations generations each on a scratch
- * population of n_pop x n_items (its own device memory, freed before return;
- * items NULL = unit-weight items, whose timing is the same), records the
- * fastest in the tuning database under the shape's bucket (log2 of n_pop,
- * log2 of 256-gene chunks per row) and returns it.  Later qieo_create calls
- * whose shape falls in a tuned bucket use that shape.  QIEO_ENOMEM if the
- * scratch population does not fit in device memory. */
+/* Times every work shape (rows per workgroup 1/2/4 x waves 2/4/8/16, waves
+ * not above the chunks per row, x the sixteen row-order sets of variant bits
+ * 0-3; plus segment order under each of its four cache-hint settings) for
+ * trial_generations generations each on a scratch population of n_pop x
+ * n_items (its own device memory, freed before return; items NULL =
+ * unit-weight items, whose timing is the same), records the fastest in the
+ * tuning database under the shape's bucket (log2 of n_pop, log2 of 256-gene
+ * chunks per row) and returns it.  Later qieo_create calls whose shape falls
+ * in a tuned bucket use that shape.  A shape qieo_create would reject, or
+ * trial_generations outside [1, 1000], gives QIEO_EINVAL before any
+ * allocation; QIEO_ENOMEM if the scratch population does not fit in device
+ * memory. */
 int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item *items, int32_t capacity,
                   int32_t trial_generations, qieo_tune_result *out);
 /* Tuning database as JSON (one entry per line); load returns the number of

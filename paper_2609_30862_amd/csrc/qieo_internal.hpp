@@ -28,6 +28,8 @@ void clear_error();
 size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem = 4);
 InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
                    uint64_t seed);
+// n_items in [1, 2^30 - 256], n_pop >= 1, at most 2^36 genes (rows padded to 64)
+int validate_shape(int32_t n_items, int32_t n_pop);
 int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop);
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
                     const ArenaLayout& L, char* base, std::vector<int32_t>& staging,

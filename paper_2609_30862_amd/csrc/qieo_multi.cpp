@@ -210,6 +210,13 @@ int Engine::rebuild()
     classes_.clear();
     const size_t n = members_.size();
     hipError_t e;
+    // copies from the local host vectors below may still be in flight when a
+    // later step fails: drain the stream before they go out of scope
+    auto rebuild_fail = [&](hipError_t err, const char* what) {
+        (void)hipStreamSynchronize(stream_);
+        (void)hipGetLastError();
+        return hip_fail(err, what);
+    };
     if (n > desc_cap_) {
         if (d_desc_) (void)hipFree(d_desc_);
         if (d_gens_) (void)hipFree(d_gens_);
@@ -268,19 +275,19 @@ int Engine::rebuild()
                    (int64_t)members_[b].np * members_[b].L.pitch;
         });
         if ((e = hipMalloc(&d_pids_, pids_.size() * sizeof(uint32_t))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(persistent ids)");
+            return rebuild_fail(e, "hipMalloc(persistent ids)");
         if ((e = hipMemcpyAsync(d_pids_, pids_.data(), pids_.size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, stream_)) != hipSuccess)
-            return hip_fail(e, "hipMemcpyAsync(persistent ids)");
+            return rebuild_fail(e, "hipMemcpyAsync(persistent ids)");
         if (!side_) {
             if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess)
-                return hip_fail(e, "hipStreamCreate");
+                return rebuild_fail(e, "hipStreamCreate");
             if ((e = hipEventCreateWithFlags(&join_, hipEventDisableTiming)) != hipSuccess)
-                return hip_fail(e, "hipEventCreate");
+                return rebuild_fail(e, "hipEventCreate");
         }
     }
     if (!fork_ && (e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess)
-        return hip_fail(e, "hipEventCreate");
+        return rebuild_fail(e, "hipEventCreate");
     // amplitude bytes one generation of the whole batch streams (the classes
     // run side by side, so they share the caches)
     int64_t plane_bytes = 0;
@@ -351,36 +358,39 @@ int Engine::rebuild()
                 for (int32_t r0 = 0; r0 < members_[i].np; r0 += sc.R)
                     sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
         }
-        if ((e = hipMalloc(&sc.d_tiles, sc.tiles.size() * sizeof(Tile))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(tiles)");
-        if ((e = hipMemcpyAsync(sc.d_tiles, sc.tiles.data(), sc.tiles.size() * sizeof(Tile),
-                                hipMemcpyHostToDevice, stream_)) != hipSuccess)
-            return hip_fail(e, "hipMemcpyAsync(tiles)");
-        if (!sc.fe_tiles.empty()) {
-            if ((e = hipMalloc(&sc.d_fe_tiles, sc.fe_tiles.size() * sizeof(Tile))) != hipSuccess)
-                return hip_fail(e, "hipMalloc(tiles)");
-            if ((e = hipMemcpyAsync(sc.d_fe_tiles, sc.fe_tiles.data(),
-                                    sc.fe_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
-                                    stream_)) != hipSuccess)
-                return hip_fail(e, "hipMemcpyAsync(tiles)");
-        }
+        // owned by classes_ from here on, so an early return frees the tables
+        // at the next rebuild or in the destructor
         classes_.push_back(std::move(sc));
+        ShapeClass& cc = classes_.back();
+        if ((e = hipMalloc(&cc.d_tiles, cc.tiles.size() * sizeof(Tile))) != hipSuccess)
+            return rebuild_fail(e, "hipMalloc(tiles)");
+        if ((e = hipMemcpyAsync(cc.d_tiles, cc.tiles.data(), cc.tiles.size() * sizeof(Tile),
+                                hipMemcpyHostToDevice, stream_)) != hipSuccess)
+            return rebuild_fail(e, "hipMemcpyAsync(tiles)");
+        if (!cc.fe_tiles.empty()) {
+            if ((e = hipMalloc(&cc.d_fe_tiles, cc.fe_tiles.size() * sizeof(Tile))) != hipSuccess)
+                return rebuild_fail(e, "hipMalloc(tiles)");
+            if ((e = hipMemcpyAsync(cc.d_fe_tiles, cc.fe_tiles.data(),
+                                    cc.fe_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                    stream_)) != hipSuccess)
+                return rebuild_fail(e, "hipMemcpyAsync(tiles)");
+        }
     }
     while (cstreams_.size() + 1 < classes_.size()) {
         hipStream_t cs = nullptr;
         hipEvent_t ev = nullptr;
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, "hipStreamCreate");
+            return rebuild_fail(e, "hipStreamCreate");
         if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
             (void)hipStreamDestroy(cs);
-            return hip_fail(e, "hipEventCreate");
+            return rebuild_fail(e, "hipEventCreate");
         }
         cstreams_.push_back(cs);
         cjoin_.push_back(ev);
     }
     // host vectors above are pageable and local: wait for their copies
     if ((e = hipStreamSynchronize(stream_)) != hipSuccess)
-        return hip_fail(e, "hipStreamSynchronize");
+        return rebuild_fail(e, "hipStreamSynchronize");
     dirty_ = false;
     return QIEO_OK;
 }
@@ -579,6 +589,9 @@ extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qie
         if (rc) return set_error(rc, "problem %d: %s", i, qieo_last_error());
         ArenaLayout L;
         total += round256(arena_layout(probs[i].n_items, probs[i].n_pop, &L));
+        // each arena is below 2^41 bytes, so the sum stops short of wrapping
+        if (total > ((size_t)1 << 50))
+            return set_error(QIEO_ENOMEM, "the batch needs more than 2^50 bytes of device memory");
     }
     int rc = check_device();
     if (rc) return rc;

@@ -112,14 +112,26 @@ InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int
     return d;
 }
 
+int validate_shape(int32_t n_items, int32_t n_pop)
+{
+    if (n_items < 1) return set_error(QIEO_EINVAL, "n_items must be >= 1 (got %d)", n_items);
+    if (n_pop < 1) return set_error(QIEO_EINVAL, "n_pop must be >= 1 (got %d)", n_pop);
+    if (n_items > (1 << 30) - 256)
+        return set_error(QIEO_EINVAL, "n_items too large (%d)", n_items);
+    // keeps every plane size in the arena layout far from size_t wrap-around
+    // (2^36 genes is 512 GB of binary32 amplitudes, beyond any one device)
+    if ((int64_t)n_pop * (int64_t)align_up((size_t)n_items, 64) > ((int64_t)1 << 36))
+        return set_error(QIEO_EINVAL, "population of %d x %d genes exceeds 2^36 genes", n_pop,
+                         n_items);
+    return QIEO_OK;
+}
+
 int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop)
 {
     if (!items) return set_error(QIEO_EINVAL, "items is NULL");
-    if (n_items < 1) return set_error(QIEO_EINVAL, "n_items must be >= 1 (got %d)", n_items);
-    if (n_pop < 1) return set_error(QIEO_EINVAL, "n_pop must be >= 1 (got %d)", n_pop);
+    int rc = validate_shape(n_items, n_pop);
+    if (rc) return rc;
     if (capacity < 0) return set_error(QIEO_EINVAL, "capacity must be >= 0 (got %d)", capacity);
-    if (n_items > (1 << 30) - 256)
-        return set_error(QIEO_EINVAL, "n_items too large (%d)", n_items);
     int64_t sv = 0, sw = 0;
     for (int32_t i = 0; i < n_items; ++i) {
         if (items[i].profit < 0 || items[i].weight < 0)

@@ -67,10 +67,13 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
                              qieo_tune_result* out)
 {
     clear_error();
-    if (n_items < 1 || n_pop < 1 || trial_generations < 1 || trial_generations > 1000)
-        return set_error(QIEO_EINVAL, "bad tuning shape (Ng %d, Np %d, trials %d)", n_items,
-                         n_pop, trial_generations);
-    int rc = check_device();
+    if (trial_generations < 1 || trial_generations > 1000)
+        return set_error(QIEO_EINVAL, "trial_generations must be in [1, 1000] (got %d)",
+                         trial_generations);
+    // before the synthetic item table below is sized by n_items
+    int rc = validate_shape(n_items, n_pop);
+    if (rc) return rc;
+    rc = check_device();
     if (rc) return rc;
     std::vector<qieo_item> synth;
     if (!items) {

@@ -83,3 +83,35 @@ def test_null_handles_are_rejected():
     assert L.qieo_set_kernel_flags(None, 0) == qieo.QIEO_EINVAL
     assert L.qieo_batch_set_segment_order(None, 1) == qieo.QIEO_EINVAL
     L.qieo_destroy(None)
+
+
+
+@pytest.mark.parametrize("n_items,n_pop", [
+    ((1 << 30) - 256, 65),     # just over 2^36 genes
+    (64, 2**31 - 1),           # short rows, the largest population
+    (1, (1 << 30) + 1),        # rows padded to 64 genes count as 64
+])
+def test_create_rejects_populations_beyond_2_36_genes(n_items, n_pop):
+    # the size check comes before the item table is read, so a short table
+    # stands in for a long one here
+    from paper_2609_30862_amd import qieo
+    items = np.zeros((4, 2), np.int32)
+    h = ctypes.c_void_p()
+    rc = qieo.lib.qieo_create(items.ctypes.data_as(ctypes.c_void_p), n_items, 1, n_pop, 0,
+                              ctypes.byref(h))
+    assert rc == qieo.QIEO_EINVAL and not h.value
+    assert b"2^36" in qieo.lib.qieo_last_error()
+
+
+@pytest.mark.parametrize("n_items,n_pop,trials", [
+    (2**31 - 1, 1, 2),         # beyond 2^30 - 256 items
+    ((1 << 30) - 256, 65, 2),  # beyond 2^36 genes
+    (100, 0, 2),               # empty population
+    (100, 4, 0),               # no trial generations
+    (100, 4, 1001),            # too many trial generations
+])
+def test_autotune_rejects_bad_shapes_before_allocating(n_items, n_pop, trials):
+    # items NULL would otherwise size a synthetic table of n_items entries
+    from paper_2609_30862_amd import qieo
+    rc = qieo.lib.qieo_autotune(n_items, n_pop, None, 0, trials, None)
+    assert rc == qieo.QIEO_EINVAL

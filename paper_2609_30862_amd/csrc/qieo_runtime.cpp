@@ -1130,6 +1130,15 @@ extern "C" int qieo_import_state(qieo_inst* h, const void* buf, size_t bytes)
     if (tb != hd.generations || tb < 0 || tb > (int64_t)INT32_MAX || window < 0 ||
         window > kConvRing)
         return set_error(QIEO_EINVAL, "snapshot is inconsistent");
+    if (tb > 0) {
+        // the next generation rotates toward the elite row its key names
+        // (row = ~low word): a row outside the population would be read out
+        // of bounds on the device
+        uint64_t key;
+        std::memcpy(&key, body + h->L.ekey + (size_t)((tb - 1) % 3) * sizeof key, sizeof key);
+        if ((uint32_t)~(uint32_t)key >= (uint32_t)h->np)
+            return set_error(QIEO_EINVAL, "snapshot is inconsistent (elite row out of range)");
+    }
     if (window > 0 && h->pipeline != QIEO_PIPELINE_FUSED)
         return set_error(QIEO_ESTATE, "snapshot has a convergence window: select the fused "
                                       "pipeline first");

@@ -121,6 +121,22 @@ def test_foreign_snapshots_are_refused(qieo):
     corrupt[0] ^= 1
     with pytest.raises(qieo.QieoError):
         b.import_state(corrupt)                                     # not a snapshot
+    # an elite key naming a row outside the population: the 64-bit key is
+    # (fitness ^ 2^31) << 32 | ~row; find it in the arena image (8-byte
+    # aligned after the 64-byte header) and point it at row n_pop
+    rows = a.export_rows()
+    e_row, f_e = rows["elite"], int(rows["fitness"][rows["elite"]])
+    key = (((f_e & 0xFFFFFFFF) ^ 0x80000000) << 32) | (~e_row & 0xFFFFFFFF)
+    words = snap[64:64 + (snap.size - 64) // 8 * 8].view("<u8")
+    hits = np.flatnonzero(words == np.uint64(key))
+    assert hits.size >= 1
+    bad_key = snap.copy()
+    bad_words = bad_key[64:64 + words.size * 8].view("<u8")
+    bad_words[hits] = (bad_words[hits] & np.uint64(0xFFFFFFFF00000000)) | \
+        np.uint64(~inst.n_pop & 0xFFFFFFFF)
+    with pytest.raises(qieo.QieoError) as ei:
+        b.import_state(bad_key)                                     # elite row out of range
+    assert ei.value.code == qieo.QIEO_EINVAL
     after = b.export_rows()
     for key in ("alpha", "beta", "alleles", "fitness"):
         assert np.array_equal(before[key], after[key]), key

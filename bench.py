@@ -109,8 +109,9 @@ def bench_batch(args):
     probs = [(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
     log("batch: %d instances, %.4g genes per generation, %d generations" % (len(insts), genes, gens))
     variants = {}
-    for name, pers, seg in (("no_persistent", False, True), ("persistent_small", True, True),
-                            ("row_order_long_rows", True, False)):
+    for name, pers, seg in (("no_persistent", False, 1), ("persistent_small", True, 1),
+                            ("segment_order_32_chunk_rows_only", True, 2),
+                            ("row_order_long_rows", True, 0)):
         b = qieo.Batch(probs)
         b.set_persistent(pers)
         b.set_segment_order(seg)

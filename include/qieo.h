@@ -266,13 +266,15 @@ int qieo_batch_set_graph(qieo_batch *b, int32_t enabled);
  * members use per-generation launches.  Results are identical. */
 int qieo_batch_set_persistent(qieo_batch *b, int32_t enabled);
 /* 1 (default): when the batch's amplitude planes exceed 256 MB, members with
- * rows of 32 or more 256-gene chunks run in segment order (see
+ * rows of 8 or more 256-gene chunks run in segment order (see
  * qieo_set_kernel_flags, bit 4), all of them in one launch over a table of
  * 1024-gene segments in address order, plus one launch closing their rows,
- * as long as that table stays within 4M segments (4.3e9 genes); 0: row
- * order for every member.  Ignored while qieo_batch_set_tile forces a
- * shape.  Results are identical. */
-int qieo_batch_set_segment_order(qieo_batch *b, int32_t enabled);
+ * as long as that table stays within 4M segments (4.3e9 genes); if it would
+ * not, the members with rows of 32 or more chunks alone, under the same
+ * limit.  2: the members with rows of 32 or more chunks only.  0: row order
+ * for every member.  Other values give QIEO_EINVAL.  Ignored while
+ * qieo_batch_set_tile forces a shape.  Results are identical. */
+int qieo_batch_set_segment_order(qieo_batch *b, int32_t mode);
 void qieo_batch_destroy(qieo_batch *b);
 
 /* ---- server: continuous batching of solve requests ----------------------- */

@@ -88,7 +88,14 @@ public:
     void force_shape(int R, int S, int flags);
     void set_use_graph(bool on) { use_graph_ = on; invalidate_graph(); }
     void set_use_persistent(bool on) { use_persistent_ = on; dirty_ = true; }
-    void set_use_segments(bool on) { use_segments_ = on; dirty_ = true; }
+    // mode 0: row order everywhere; 1: segment order for rows of >= 8 chunks
+    // of a streaming batch; 2: only for rows of >= 32 chunks
+    void set_use_segments(int mode)
+    {
+        use_segments_ = mode != 0;
+        merge_segments_ = mode == 1;
+        dirty_ = true;
+    }
     // Uploads descriptors and tile tables if membership changed since the
     // last launch (device_desc() is valid only after this).
     int ensure_built() { return dirty_ ? rebuild() : QIEO_OK; }
@@ -121,6 +128,7 @@ private:
     std::vector<hipEvent_t> cjoin_;
     bool use_persistent_ = true;
     bool use_segments_ = true;   // long-row class in segment order when streaming
+    bool merge_segments_ = true;
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;
     hipGraphExec_t graph_ = nullptr;

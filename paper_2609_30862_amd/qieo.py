@@ -584,9 +584,11 @@ class Batch:
         _check(lib.qieo_batch_set_persistent(self._h, int(bool(enabled))),
                "qieo_batch_set_persistent")
 
-    def set_segment_order(self, enabled: bool):
-        """Long-row members in segment order when the batch streams (default)."""
-        _check(lib.qieo_batch_set_segment_order(self._h, int(bool(enabled))),
+    def set_segment_order(self, mode):
+        """1 / True (default): members with rows of 8 or more chunks in
+        segment order when the batch streams; 2: rows of 32 or more chunks
+        only; 0 / False: row order for every member."""
+        _check(lib.qieo_batch_set_segment_order(self._h, int(mode)),
                "qieo_batch_set_segment_order")
 
     def converged(self, i: int):

@@ -138,13 +138,15 @@ def test_ragged_batch_of_512_full_size(qieo, oracle_mod):
 
 
 def test_long_rows_in_segment_order(qieo, oracle_mod):
-    """A batch whose planes exceed 256 MB: members with rows of 32 or more
+    """A batch whose planes exceed 256 MB: members with rows of 8 or more
     chunks run in segment order (one launch over all their 1024-gene
     segments in address order, one closing their rows); bit-identical to the
-    same batch in row order and to the oracle, through uneven per-instance
+    same batch with only the rows of 32 or more chunks in segment order, to
+    the batch in row order and to the oracle, through uneven per-instance
     counts and graph replay."""
     shapes = [(8192, 256), (8193, 200), (9000, 128), (12345, 256), (16384, 256),
-              (20000, 256), (20001, 97), (30000, 64), (100, 32), (3000, 64), (2100, 40)]
+              (20000, 256), (20001, 97), (30000, 64), (100, 32), (3000, 64), (2100, 40),
+              (2048, 48), (1792, 24), (7900, 33)]
     shapes += [(16000, 256)] * 6
     insts = [workloads.random_instance(ng, n_pop, seed=500 + k)
              for k, (ng, n_pop) in enumerate(shapes)]
@@ -152,28 +154,37 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     assert planes > 256 << 20
     say("batch of %d, %.0f MB of planes" % (len(insts), planes / 2 ** 20))
     seg = qieo.Batch(_problems(insts))
+    seg32 = qieo.Batch(_problems(insts))
+    seg32.set_segment_order(2)
     row = qieo.Batch(_problems(insts))
     row.set_segment_order(False)
+    with pytest.raises(qieo.QieoError) as ei:
+        row.set_segment_order(3)
+    assert ei.value.code == qieo.QIEO_EINVAL
     n = len(insts)
     done = [0] * n
     for gens in ([3] * n, [k % 5 for k in range(n)], [k % 5 for k in range(n)],
                  [(k + 2) % 5 for k in range(n)]):
-        seg.step(gens)
-        row.step(gens)
+        for b in (seg, seg32, row):
+            b.step(gens)
         done = [d + g for d, g in zip(done, gens)]
     for k in range(n):
-        a, c = seg.export_rows(k), row.export_rows(k)
-        for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
-            assert np.array_equal(a[key], c[key]), (k, key)
-        assert a["elite"] == c["elite"]
-        ra, rc = seg.best(k), row.best(k)
-        assert (ra.fitness, ra.generation, ra.chromosome) == (rc.fitness, rc.generation,
-                                                               rc.chromosome)
-    for k in (1, 6, 7):
+        c = row.export_rows(k)
+        rc = row.best(k)
+        for other, label in ((seg, "rows of 8+ chunks"), (seg32, "rows of 32+ chunks")):
+            a = other.export_rows(k)
+            for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+                assert np.array_equal(a[key], c[key]), (label, k, key)
+            assert a["elite"] == c["elite"], (label, k)
+            ra = other.best(k)
+            assert (ra.fitness, ra.generation, ra.chromosome) == \
+                (rc.fitness, rc.generation, rc.chromosome), (label, k)
+    for k in (1, 6, 7, 9, 11, 13):
         i = insts[k]
         o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed,
                               threads=min(16, os.cpu_count() or 1))
         o.run(done[k])
         assert_state_equal(View(seg, k), o, label="segment-order member %d" % k)
     seg.close()
+    seg32.close()
     row.close()

@@ -298,7 +298,8 @@ int Engine::rebuild()
     // does, if its own table fits.  On the 512-instance ragged batch: 0.330 s
     // per 500 generations merged, 0.333 s with the 8-31-chunk class in row
     // order beside it (as a segment-order class of its own on a second
-    // stream it measured 0.339 s).
+    // stream it measured 0.339 s; every class of the batch in the one
+    // table, 0.333 s).
     auto seg_tiles_of = [&](const std::vector<size_t>& g) {
         int64_t n_tiles = 0;
         for (size_t i : g)
@@ -430,18 +431,18 @@ int Engine::enqueue(int nmax)
             return hip_fail(e, "resident kernel");
         if ((e = hipEventRecord(join_, side_)) != hipSuccess) return hip_fail(e, "join");
     }
-    for (size_t ci = 1; ci < nc; ++ci)
-        if ((e = hipStreamWaitEvent(cstreams_[ci - 1], fork_, 0)) != hipSuccess)
+    // Class after class, smallest rows first: the small classes'
+    // launch-bound generations run while the host is still issuing the
+    // long-row class's.  Issued generation by generation across the class
+    // streams instead (long rows first in each round), the long-row stream
+    // starts at once but shares the chip with the small kernels all along:
+    // 0.333 s against 0.330 s per call on the 512-instance batch.
+    for (size_t ci = 0; ci < nc; ++ci) {
+        const ShapeClass& c = classes_[ci];
+        hipStream_t cs = ci == 0 ? stream_ : cstreams_[ci - 1];
+        if (ci > 0 && (e = hipStreamWaitEvent(cs, fork_, 0)) != hipSuccess)
             return hip_fail(e, "fork");
-    // Generation by generation across the class streams, longest rows
-    // (the last class, most of the bytes) first in each round: enqueued
-    // class after class, the long-row stream's first launch waited for the
-    // host to issue every generation of the small classes (44 ms of a
-    // 335 ms call on the 512-instance batch, in graph replays too).
-    for (int k = 0; k < nmax; ++k) {
-        for (size_t ci = nc; ci-- > 0;) {
-            const ShapeClass& c = classes_[ci];
-            hipStream_t cs = ci == 0 ? stream_ : cstreams_[ci - 1];
+        for (int k = 0; k < nmax; ++k) {
             e = (c.flags & kFlagSegments)
                     ? launch_segments_tiled(d_desc_, c.d_tiles, (int)c.tiles.size(),
                                             c.d_fe_tiles, (int)c.fe_tiles.size(), c.flags, k,
@@ -450,10 +451,9 @@ int Engine::enqueue(int nmax)
                                         c.flags, k, d_gens_, 0, cs);
             if (e != hipSuccess) return hip_fail(e, "generation kernel");
         }
-    }
-    for (size_t ci = 1; ci < nc; ++ci)
-        if ((e = hipEventRecord(cjoin_[ci - 1], cstreams_[ci - 1])) != hipSuccess)
+        if (ci > 0 && (e = hipEventRecord(cjoin_[ci - 1], cs)) != hipSuccess)
             return hip_fail(e, "join");
+    }
     for (size_t ci = 1; ci < nc; ++ci)
         if ((e = hipStreamWaitEvent(stream_, cjoin_[ci - 1], 0)) != hipSuccess)
             return hip_fail(e, "join");

@@ -379,6 +379,9 @@ def main():
                     help="amplitude precision (64: the paper's binary64)")
     ap.add_argument("--autotune", type=int, default=0, metavar="GENS",
                     help="time every work shape for GENS generations first and use the best")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="large: timed runs, each on a fresh instance of the same seed "
+                         "(identical work); value is the median run")
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -442,39 +445,47 @@ def main():
     if args.autotune:
         r = qieo.qieo_autotune(inst.n_items, inst.n_pop, args.autotune)
         log("autotune: %s" % r)
-    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
-                      precision=args.precision)
-    if args.tile:
-        r, s = (int(x) for x in args.tile.split(","))
-        g.set_tile(r, s)
-    if args.kernel_flags >= 0:
-        g.set_kernel_flags(args.kernel_flags)
-    shape = tuple(g.tile()) + (g.kernel_flags(),)
-    log("work shape rows/block, waves/block, variant bits = %s" % (shape,))
-    g.step(args.warmup)
-
-    g.set_timing(True)
-    g.kernel_time(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.step_async(args.steps)
-    g.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launches, kern_ms = g.kernel_time(reset=True)
-    g.set_timing(False)
-
     genes = inst.n_pop * inst.n_items
-    value = genes * args.steps / wall
-    avg_ms = kern_ms / max(launches, 1)
     bytes_per_launch = BYTES_PER_GENE_UPDATE * genes * (2 if args.precision == 64 else 1)
+    runs = []
+    for rep in range(max(1, args.repeats)):
+        # a fresh population of the same seed: every run does the same work
+        g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          precision=args.precision)
+        if args.tile:
+            r, s = (int(x) for x in args.tile.split(","))
+            g.set_tile(r, s)
+        if args.kernel_flags >= 0:
+            g.set_kernel_flags(args.kernel_flags)
+        shape = tuple(g.tile()) + (g.kernel_flags(),)
+        if rep == 0:
+            log("work shape rows/block, waves/block, variant bits = %s" % (shape,))
+        g.step(args.warmup)
+
+        g.set_timing(True)
+        g.kernel_time(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step_async(args.steps)
+        g.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launches, kern_ms = g.kernel_time(reset=True)
+        g.set_timing(False)
+        avg_ms = kern_ms / max(launches, 1)
+        best = g.best()
+        log("run %d: wall %.3f s, %.3f ms/generation, kernel avg %.3f ms over %d launches, "
+            "%.1f GB/s algorithmic, best fitness %d (gen %d)"
+            % (rep, wall, wall / args.steps * 1e3, avg_ms, launches,
+               bytes_per_launch / (avg_ms * 1e-3) / 1e9, best.fitness, best.generation))
+        g.close()
+        runs.append((wall, avg_ms))
+
+    # the median run by wall time, and the median kernel average
+    wall = sorted(w for w, _ in runs)[len(runs) // 2]
+    avg_ms = sorted(a for _, a in runs)[len(runs) // 2]
+    value = genes * args.steps / wall
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    best = g.best()
-    log("wall %.3f s, %.3f ms/generation, kernel avg %.3f ms over %d launches, "
-        "%.1f GB/s algorithmic, best fitness %d (gen %d)"
-        % (wall, wall / args.steps * 1e3, avg_ms, launches, achieved, best.fitness,
-           best.generation))
-    g.close()
 
     out = {
         "metric": "gene-updates/s",
@@ -493,6 +504,9 @@ def main():
                                % (inst.n_pop, inst.n_items, args.steps),
                    "n_pop": inst.n_pop, "n_items": inst.n_items, "seed": inst.seed,
                    "generations_per_step": 1},
+        "repeats": len(runs),
+        "ms_per_step_runs": [w / args.steps * 1e3 for w, _ in runs],
+        "kernel_avg_ms_runs": [a for _, a in runs],
         "hbm_frac_algorithmic": value * bytes_per_launch / genes / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

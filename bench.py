@@ -6,9 +6,11 @@ QIP, Evaluation, DetermineElite, fused in one launch) over the resident
 population of the largest single-instance workload: Np = 4096 chromosomes of
 Ng = 200,000 items (weights U[1,100], value = weight + 10, capacity =
 floor(sum/2), seed 2).  The default K = 200 steps is that workload's whole
-generation budget.  Prints one JSON line.
+generation budget.  Five timed runs (--repeats), each on a fresh population
+of the same seed; the reported figures are the median run's.  Prints one
+JSON line.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 3] [--repeats 5]
 """
 from __future__ import annotations
 

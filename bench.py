@@ -70,10 +70,12 @@ def measured_traffic(n_pop: int, n_items: int, shape=None):
         return None
 
 
-def cpu_baseline(inst, rows: int, gens: int, threads: int = 1):
+def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 200):
     """The CPU oracle, untuned, on a bounded sample of the same workload: the
     first `rows` chromosomes of the population over the full item list, for
-    `gens` generations, on `threads` host threads (rows split among them)."""
+    `gens` generations, on `threads` host threads (rows split among them).
+    The whole population's time per generation and per run of `run_gens`
+    generations is extrapolated from the sample's rate, and labelled so."""
     import oracle
     o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed,
                       threads=threads)
@@ -81,10 +83,32 @@ def cpu_baseline(inst, rows: int, gens: int, threads: int = 1):
     t0 = time.perf_counter()
     o.run(gens)
     dt = time.perf_counter() - t0
-    return {"value": rows * inst.n_items * gens / dt, "unit": "gene-updates/s", "cores": threads,
+    rate = rows * inst.n_items * gens / dt
+    per_gen = inst.n_pop * inst.n_items / rate
+    return {"value": rate, "unit": "gene-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "first %d of %d chromosomes x %d items, %d generations after "
-                      "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt)}
+                      "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt),
+            "extrapolated_s_per_generation": per_gen,
+            "extrapolated_s_per_run": run_gens * per_gen, "run_generations": run_gens,
+            "host": host_info()}
+
+
+def host_info():
+    """The host the CPU baseline ran on, read at run time."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu": model, "nproc": os.cpu_count(), "usable_cpus": affinity}
 
 
 def host_threads() -> int:
@@ -535,12 +559,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows x %d generations" % (args.cpu_rows, args.cpu_gens))
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows, args.cpu_gens)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows, args.cpu_gens,
+                                           run_gens=args.steps)
         nt = host_threads()
         log("cpu baseline: oracle on %d threads, %d rows x %d generations"
             % (nt, args.cpu_rows * nt, args.cpu_gens))
         out["cpu_baseline_threads"] = cpu_baseline(inst, min(inst.n_pop, args.cpu_rows * nt),
-                                                   args.cpu_gens, threads=nt)
+                                                   args.cpu_gens, threads=nt,
+                                                   run_gens=args.steps)
     print(json.dumps(out), flush=True)
 
 

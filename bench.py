@@ -409,7 +409,8 @@ def bench_launch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed generations (default: the workload's budget, 200 for large)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-pop", type=int, default=4096)
     ap.add_argument("--n-items", type=int, default=200_000)
@@ -425,10 +426,12 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-gens", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["large", "batch", "serve", "fractions", "launch",
-                                           "stream"],
+    ap.add_argument("--workload", choices=["large", "medium", "small", "batch", "serve",
+                                           "fractions", "launch", "stream"],
                     default="large",
-                    help="large: the single 4096 x 200,000 instance (default); batch: 512 "
+                    help="large: the single 4096 x 200,000 instance (default); medium: "
+                         "1024 x 10,000, 1000 generations (its planes fit the 256 MB "
+                         "last-level cache); small: 16 x 100, 500 generations; batch: 512 "
                          "ragged instances x 500 generations vs a per-instance launch loop; "
                          "serve: Poisson request stream through the continuous-batching server; "
                          "fractions: per-step costs of the fused and unfused pipelines; "
@@ -480,7 +483,14 @@ def main():
         return bench_stream(args)
     if args.workload == "launch":
         return bench_launch(args)
-    inst = workloads.large_instance(args.n_pop, args.n_items)
+    if args.workload == "medium":
+        inst = workloads.medium_instance()
+    elif args.workload == "small":
+        inst = workloads.small_instance()
+    else:
+        inst = workloads.large_instance(args.n_pop, args.n_items)
+    if args.steps is None:
+        args.steps = inst.generations
     log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
     if args.autotune:
         r = qieo.qieo_autotune(inst.n_items, inst.n_pop, args.autotune)
@@ -512,7 +522,9 @@ def main():
         wall = time.perf_counter() - t0
         launches, kern_ms = g.kernel_time(reset=True)
         g.set_timing(False)
-        avg_ms = kern_ms / max(launches, 1)
+        # per generation: the events enclose each generation's launches, or
+        # the whole call where one single-workgroup launch runs all of them
+        avg_ms = kern_ms / args.steps
         best = g.best()
         log("run %d: wall %.3f s, %.3f ms/generation, kernel avg %.3f ms over %d launches, "
             "%.1f GB/s algorithmic, best fitness %d (gen %d)"
@@ -543,7 +555,10 @@ def main():
         "config": {"workload": "qieo-knapsack single instance Np=%d Ng=%d, %d generations"
                                % (inst.n_pop, inst.n_items, args.steps),
                    "n_pop": inst.n_pop, "n_items": inst.n_items, "seed": inst.seed,
-                   "generations_per_step": 1},
+                   "generations_per_step": 1,
+                   # amplitude planes within the 256 MB last-level cache: the
+                   # rate is the cache's, not HBM's
+                   "cache_resident": genes * 2 * (8 if args.precision == 64 else 4) <= 256 << 20},
         "repeats": len(runs),
         "ms_per_step_runs": [w / args.steps * 1e3 for w, _ in runs],
         "kernel_avg_ms_runs": [a for _, a in runs],

@@ -532,6 +532,7 @@ def main():
                bytes_per_launch / (avg_ms * 1e-3) / 1e9, best.fitness, best.generation))
         g.close()
         runs.append((wall, avg_ms))
+        one_launch = launches == 1 and args.steps > 1     # the single-workgroup path
 
     # the median run by wall time, and the median kernel average
     wall = sorted(w for w, _ in runs)[len(runs) // 2]
@@ -569,6 +570,7 @@ def main():
                      "traffic": (measured_traffic(inst.n_pop, inst.n_items, shape)
                                  if args.precision == 32 else None),
                      "kernel": ("segment_kernel + segment_fe_kernel" if shape[2] & 16
+                                else "resident_kernel (one launch per call)" if one_launch
                                 else "generation_kernel"), "kernel_avg_ms": avg_ms,
                      "bytes_per_launch": bytes_per_launch},
     }

@@ -127,7 +127,7 @@ private:
     std::vector<hipStream_t> cstreams_;
     std::vector<hipEvent_t> cjoin_;
     bool use_persistent_ = true;
-    bool use_segments_ = true;   // long-row class in segment order when streaming
+    bool use_segments_ = true;   // long rows in segment order when the batch streams
     bool merge_segments_ = true;
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;

@@ -239,3 +239,63 @@ def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod, precision
                 "amplitudes row %d" % c
     g1.close()
     g2.close()
+
+
+def test_rows_of_the_maximum_length(qieo, oracle_mod):
+    """Two chromosomes of 2^30 - 256 genes, the longest row the library
+    accepts (17 GB of binary32 amplitudes, segment order): both rows'
+    alleles, fitness and rotated amplitudes over two generations equal the
+    oracle's chromosome-by-chromosome step, and the elite is the argmax.
+    Values and weights in {1, 2} keep both sums within int32."""
+    from concurrent.futures import ThreadPoolExecutor
+    ng, n_pop, seed = (1 << 30) - 256, 2, 11
+    v, w, cap = workloads.independent_items(ng, 1, 2, seed=seed)
+    assert int(v.sum(dtype=np.int64)) < 2 ** 31 and int(w.sum(dtype=np.int64)) < 2 ** 31
+    say("rows of %d genes x %d" % (ng, n_pop))
+    g = qieo.Instance(v, w, cap, n_pop, seed)
+    assert g.kernel_flags() & 16                       # streaming: segment order
+    tiny = oracle_mod.Oracle(v[:1], w[:1], 1, 1, seed)
+    a0 = tiny.amplitudes()[0][0, 0]
+    del tiny
+    alpha = [np.full(ng, a0, dtype=np.float32) for _ in range(n_pop)]
+    beta = [np.full(ng, a0, dtype=np.float32) for _ in range(n_pop)]
+    none = np.zeros(ng, np.uint8)
+    x = [[np.zeros(ng, np.uint8) for _ in range(n_pop)] for _ in range(2)]
+    fit = [[0] * n_pop for _ in range(2)]
+
+    def oracle_step(t, c, x_prev, elite_x, below):
+        return oracle_mod.row_generation_inplace(seed, t, c, v, w, cap, alpha[c], beta[c],
+                                                 x_prev, elite_x, below, x[t][c])[0]
+
+    with ThreadPoolExecutor(n_pop) as pool:
+        # generation 0: observation and Evaluation only
+        g.step(1)
+        st = g.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        fit[0] = list(pool.map(lambda c: oracle_step(0, c, none, none, False), range(n_pop)))
+        assert list(st["fitness"]) == fit[0]
+        e0 = int(np.argmax(fit[0]))
+        assert st["elite"] == e0
+        held = []
+        for c in range(n_pop):
+            s = g.export_rows(c, 1)                   # amplitudes after CIP(0)
+            assert np.array_equal(s["alleles"][0], x[0][c]), "alleles, generation 0 row %d" % c
+            held.append((s["alpha"][0], s["beta"][0]))
+            del s
+        say("  generation 0: fitness %s, elite %d" % (fit[0], e0))
+        # generation 1: CIP(0) toward the elite's alleles, then QIP and Evaluation
+        fit[1] = list(pool.map(lambda c: oracle_step(1, c, x[0][c], x[0][e0],
+                                                     fit[0][c] < fit[0][e0]), range(n_pop)))
+        for c in range(n_pop):
+            assert bits_equal(held[c][0], alpha[c]) and bits_equal(held[c][1], beta[c]), \
+                "amplitudes after CIP(0), row %d" % c
+        del held
+        g.step(1)
+        st = g.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        assert list(st["fitness"]) == fit[1]
+        assert st["elite"] == int(np.argmax(fit[1]))
+        for c in range(n_pop):
+            s = g.export_rows(c, 1, amplitudes=False)
+            assert np.array_equal(s["alleles"][0], x[1][c]), "alleles, generation 1 row %d" % c
+            del s
+        say("  generation 1: fitness %s" % fit[1])
+    g.close()

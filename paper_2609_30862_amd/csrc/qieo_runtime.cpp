@@ -846,9 +846,19 @@ int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,
     int32_t* dfit = (int32_t*)at(o_f);
     int32_t* dprof = (int32_t*)at(o_p);
     int32_t* dwt = (int32_t*)at(o_w);
-    if ((e = launch_export(d_desc, row0, n_rows, d.ng, da, db, dx, dfit, dprof, dwt, f64, s)) !=
-        hipSuccess)
-        return hip_fail(e, "export kernel");
+    // the export kernel puts rows on the grid's y dimension (at most 65535):
+    // blocks of 32768 rows
+    constexpr int32_t kExportRows = 32768;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    for (int32_t r = 0; r < n_rows; r += kExportRows) {
+        const int32_t nr = std::min(kExportRows, n_rows - r);
+        const size_t o = (size_t)r * d.ng;
+        if ((e = launch_export(d_desc, row0 + r, nr, d.ng, da ? (char*)da + o * esz : nullptr,
+                               db ? (char*)db + o * esz : nullptr, dx ? dx + o : nullptr,
+                               dfit ? dfit + r : nullptr, dprof ? dprof + r : nullptr,
+                               dwt ? dwt + r : nullptr, f64, s)) != hipSuccess)
+            return hip_fail(e, "export kernel");
+    }
     struct { void* dst; const void* src; size_t n; } cp[] = {
         {alpha, da, amp_bytes}, {beta, db, amp_bytes}, {alleles, dx, per},
         {fitness, dfit, row_bytes}, {profit, dprof, row_bytes}, {weight, dwt, row_bytes}};

@@ -299,3 +299,19 @@ def test_rows_of_the_maximum_length(qieo, oracle_mod):
             del s
         say("  generation 1: fitness %s" % fit[1])
     g.close()
+
+
+def test_export_of_more_rows_than_one_grid_dimension_holds(qieo, oracle_mod):
+    """70,001 chromosomes of 50 genes: one export call of every row with
+    amplitudes and alleles (more rows than a grid's y dimension takes, so
+    the library exports them in blocks) equals the oracle's state, after
+    1 and 4 generations."""
+    inst = workloads.random_instance(50, 70_001, seed=13)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          threads=min(16, os.cpu_count() or 1))
+    for gens in (1, 3):
+        g.step(gens)
+        o.run(gens)
+        assert_state_equal(g, o, label="70,001 rows after %d generations" % o.t)
+    g.close()

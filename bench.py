@@ -77,12 +77,26 @@ def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 2
     The whole population's time per generation and per run of `run_gens`
     generations is extrapolated from the sample's rate, and labelled so."""
     import oracle
-    o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed,
-                      threads=threads)
-    o.run(1)                    # generation 0 observes only; time full generations
-    t0 = time.perf_counter()
-    o.run(gens)
-    dt = time.perf_counter() - t0
+    # the single-threaded run is pinned to one core of the process's set (the
+    # calling thread only; the mask is restored afterwards)
+    pinned, mask = None, None
+    if threads == 1 and hasattr(os, "sched_setaffinity"):
+        try:
+            mask = os.sched_getaffinity(0)
+            pinned = min(mask)
+            os.sched_setaffinity(0, {pinned})
+        except OSError:
+            pinned = None
+    try:
+        o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed,
+                          threads=threads)
+        o.run(1)                # generation 0 observes only; time full generations
+        t0 = time.perf_counter()
+        o.run(gens)
+        dt = time.perf_counter() - t0
+    finally:
+        if pinned is not None:
+            os.sched_setaffinity(0, mask)
     rate = rows * inst.n_items * gens / dt
     per_gen = inst.n_pop * inst.n_items / rate
     return {"value": rate, "unit": "gene-updates/s", "cores": threads,
@@ -91,7 +105,7 @@ def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 2
                       "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt),
             "extrapolated_s_per_generation": per_gen,
             "extrapolated_s_per_run": run_gens * per_gen, "run_generations": run_gens,
-            "host": host_info()}
+            "pinned_cpu": pinned, "host": host_info()}
 
 
 def host_info():

@@ -1,0 +1,167 @@
+// Host-side planning of the library: arena layout, argument validation,
+// work-shape rules, the offset allocator of a device pool, the batch's shape
+// classes and tile tables, segment numbering constants and snapshot
+// headers.  Plain C++ with no HIP call, so every piece here builds with a
+// host compiler alone and is checked on the CPU (including under the
+// address and undefined-behaviour sanitizers); the runtime, the batch
+// engine and the server use these functions and add the device calls.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <map>
+#include <vector>
+
+#include "../../include/qieo.h"
+#include "qieo_layout.hpp"
+
+namespace qieo {
+
+// ---- errors --------------------------------------------------------------
+// Stores a thread-local message (read by qieo_last_error) and returns code.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+const char* last_error();
+
+// ---- arena ---------------------------------------------------------------
+// Byte offsets of every plane inside one instance's device arena.
+// part_nseg: segments per row the partial-sum array holds (segments of
+// kSegChunksMin chunks); a segment-order launch must use no more.
+struct ArenaLayout {
+    int32_t pitch, nchunk;
+    int32_t part_nseg;
+    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv, part;
+    size_t zero_from;
+    size_t total;
+};
+
+// elem: bytes per amplitude (4 binary32, 8 binary64); returns L->total.
+// The shape must have passed validate_shape.
+size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem = 4);
+// True when a segment-order launch with segments of sc chunks stays inside
+// the arena's partial-sum array.
+bool segments_fit(const ArenaLayout& L, int sc);
+
+// n_items in [1, 2^30 - 256], n_pop >= 1, at most 2^36 genes (rows padded to 64)
+int validate_shape(int32_t n_items, int32_t n_pop);
+int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop);
+// FNV-1a (64-bit) over the item array: identifies the problem a snapshot
+// belongs to.
+uint64_t items_fnv1a(const qieo_item* items, int32_t n);
+
+// ---- work shapes ---------------------------------------------------------
+// kFlag* bits for a work shape given the amplitude bytes one generation streams.
+int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes);
+void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes = 4);
+// LDS bytes of the single-workgroup resident loop for one population.
+size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk);
+
+// Segment numbering constants of one segment-order launch of n_seg
+// workgroups on a device of `xcds` XCDs; nseg_row > 0 for an untiled launch
+// (segments per row of its single instance), 0 for a tiled one.
+SegMap seg_map_for(int64_t n_seg, int xcds, int32_t nseg_row);
+
+// ---- device pool bookkeeping --------------------------------------------
+// First-fit offset allocator over [0, capacity): blocks are 256-byte
+// aligned; freed ranges coalesce with their neighbours.
+class OffsetAllocator {
+public:
+    static constexpr size_t npos = (size_t)-1;
+    void reset(size_t capacity);               // capacity rounded up to 256
+    size_t alloc(size_t bytes);                // offset, or npos if no room
+    bool release(size_t offset);               // false if not a live block
+    size_t capacity() const { return cap_; }
+    size_t used() const { return used_; }
+    size_t largest_free() const;
+    size_t live_blocks() const { return busy_.size(); }
+    // Consistency of the free and busy maps (tests): disjoint, sorted,
+    // coalesced, 256-aligned, covering [0, capacity) exactly.
+    bool check() const;
+
+private:
+    size_t cap_ = 0, used_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> size
+    std::map<size_t, size_t> busy_;   // offset -> size
+};
+
+// ---- batch shape classes -------------------------------------------------
+// Shape classes by 256-gene chunks per row: 1, 2-3, 4-7, 8-31, >= 32; the
+// class's waves per workgroup are 1, 2, 4, 8, 16.
+constexpr int kClasses = 5;
+constexpr int kClassWaves[kClasses] = {1, 2, 4, 8, 16};
+// Largest segment tile table a class keeps (32 MB of tiles).
+constexpr int64_t kMaxSegTiles = (int64_t)1 << 22;
+int class_of(int32_t nchunk);
+
+// What the planner needs to know of one member of a batch.
+struct MemberShape {
+    int32_t np = 0, pitch = 0, nchunk = 0;
+    int32_t part_nseg = 0;        // from the member's arena layout
+    uint64_t addr = 0;            // arena address (segment tiles go in address order)
+};
+
+struct PlanOptions {
+    bool use_persistent = true;   // LDS-resident members as single workgroups
+    size_t lds_limit = 0;         // dynamic LDS the resident kernel may take
+    bool use_segments = true;     // long rows in segment order when the batch streams
+    bool merge_segments = true;   // rows of 8+ chunks in one segment table
+    int force_R = 0, force_S = 0, force_flags = 0;   // every class, when force_R > 0
+    // Tuned shapes: the autotuner's entry for (class, rows of the class,
+    // longest row in chunks), or NULL.
+    bool (*tuned)(int cls, int64_t rows, int32_t max_nchunk, int* R, int* S, int* flags) = nullptr;
+};
+
+// One launch class of a batch.  Row order: tiles {member, first row}, R
+// rows each.  Segment order (flags has kFlagSegments): tiles {member,
+// segment number} in arena address order, fe_tiles {member, first of four
+// rows}.
+struct ClassPlan {
+    int cls = 0;                  // shape class (0 .. kClasses-1)
+    int R = 1, S = 1, flags = 0;
+    bool tuned = false;           // shape from the tuning database
+    int64_t rows = 0;
+    int32_t max_nchunk = 0;
+    std::vector<Tile> tiles, fe_tiles;
+};
+
+struct BatchPlan {
+    std::vector<uint32_t> resident;   // members run by the LDS-resident kernel, largest first
+    size_t resident_lds = 0;          // its dynamic LDS (the largest member's need)
+    std::vector<ClassPlan> classes;   // smallest rows first
+};
+
+// Groups members into the resident set and the shape classes and builds
+// every tile table.  QIEO_EINVAL if a table would not fit a launch or a
+// member's arena cannot hold its segment sums.
+int plan_batch(const std::vector<MemberShape>& members, const PlanOptions& opt, BatchPlan* out);
+
+// ---- snapshots -----------------------------------------------------------
+struct StateHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t elem_bytes;
+    int32_t n_items, n_pop, capacity, reserved;
+    uint64_t seed;
+    uint64_t items_hash;
+    int64_t generations;
+    uint64_t arena_bytes;
+};
+
+// Identity of the handle a snapshot is loaded into.
+struct SnapshotId {
+    uint32_t elem_bytes;
+    int32_t n_items, n_pop, capacity;
+    uint64_t seed, items_hash;
+};
+
+StateHeader make_state_header(const SnapshotId& id, int64_t generations, uint64_t arena_bytes);
+// Checks a snapshot buffer (header plus arena image) against the handle's
+// identity and layout before anything is copied to the device: magic and
+// version, precision, problem, size, and the image's own generation
+// counter, convergence window and latest elite row.  On success returns
+// QIEO_OK with the image's generation count and window; else QIEO_EINVAL.
+int check_snapshot(const void* buf, size_t bytes, const SnapshotId& id, const ArenaLayout& L,
+                   int64_t* generations, int32_t* window);
+
+}  // namespace qieo

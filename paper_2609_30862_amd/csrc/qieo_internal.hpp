@@ -8,40 +8,26 @@
 #include <vector>
 
 #include "../../include/qieo.h"
+#include "qieo_host.hpp"
 #include "qieo_kernels.hpp"
 
 namespace qieo {
 
-// Byte offsets of every plane inside one instance's device arena.
-struct ArenaLayout {
-    int32_t pitch, nchunk;
-    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv, part;
-    size_t zero_from;
-    size_t total;
-};
-
-int set_error(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
-void clear_error();
 
-// elem: bytes per amplitude (4 binary32, 8 binary64)
-size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem = 4);
 InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
                    uint64_t seed);
-// n_items in [1, 2^30 - 256], n_pop >= 1, at most 2^36 genes (rows padded to 64)
-int validate_shape(int32_t n_items, int32_t n_pop);
-int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop);
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
                     const ArenaLayout& L, char* base, std::vector<int32_t>& staging,
                     bool f64 = false);
 int check_device();
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes = 4);
 // hipMemcpyAsync on s, then waits for s.
 hipError_t copy_on(void* dst, const void* src, size_t n, hipMemcpyKind kind, hipStream_t s);
-// kFlag* bits for a work shape given the amplitude bytes one generation streams.
-int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes);
 // Shape from the autotuner's database, if the bucket was tuned.
 bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
+// Shape of a batch's launch class (class, rows of the class, longest row in
+// chunks) from the autotuner's database, if that bucket was tuned.
+bool tuned_class(int cls, int64_t rows, int32_t max_nchunk, int* R, int* S, int* flags);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
               uint32_t* bits, size_t n_words);
 int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,

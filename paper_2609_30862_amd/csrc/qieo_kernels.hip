@@ -38,6 +38,7 @@
 #include <mutex>
 
 #include "qieo_device.hpp"
+#include "qieo_host.hpp"
 #include "qieo_kernels.hpp"
 
 namespace qieo {
@@ -404,18 +405,6 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 // segment_fe_kernel closes them into fitness and the elite once every
 // segment is done (the launch boundary is the only synchronisation).
 // ---------------------------------------------------------------------------
-// Launch-wide constants of the segment numbering, computed on the host so
-// that no workgroup divides: the grid's split over the XCDs and, for a
-// single instance, the reciprocal of its segments per row.
-struct SegMap {
-    int32_t xcds;        // XCDs (1: no renumbering)
-    int32_t xshift;      // log2(xcds) when xcds is a power of two, else -1
-    int32_t q, r;        // grid size = q * xcds + r
-    int32_t nseg;        // segments per row (untiled launches)
-    int32_t mshift;      // row of segment number s = (s * magic) >> mshift
-    uint64_t magic;
-};
-
 template <typename T, int FL, int SC, int SW, bool TILED>
 __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restrict__ insts,
                                                           const Tile* __restrict__ tiles, int k,
@@ -425,22 +414,14 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     constexpr bool NT = (FL & kFlagNontemporal) != 0, NTL = (FL & kFlagNontemporalLoads) != 0;
     constexpr bool RC = (FL & kFlagRecomputeAlleles) != 0;
     static_assert(SC % SW == 0, "whole chunks per wave");
+    // the arena's partial-sum array holds seg_count(nchunk, kSegChunksMin)
+    // entries per row; shorter segments would write past its end
+    static_assert(SC >= kSegChunksMin, "segments shorter than the partial-sum sizing");
     constexpr int CPW = SC / SW;                          // chunks per wave
     // Workgroups are dispatched to the XCDs round-robin (workgroup b to XCD
     // b mod xcds); renumbering them gives each XCD one contiguous run of
     // segments, which it sweeps in address order.
-    int bid = (int)blockIdx.x;
-    if (map.xcds > 1) {
-        int x, j;
-        if (map.xshift >= 0) {
-            x = bid & (map.xcds - 1);
-            j = bid >> map.xshift;
-        } else {
-            x = bid % map.xcds;
-            j = bid / map.xcds;
-        }
-        bid = x * map.q + (x < map.r ? x : map.r) + j;
-    }
+    const int bid = seg_renumber(map, (int32_t)blockIdx.x);
     // segment number within the instance: the workgroup number (instance 0),
     // or the tile's, whose row0 field then holds a segment number
     uint32_t inst = 0, sno = (uint32_t)bid;
@@ -456,11 +437,11 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
     const int np = I.np, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
     int nseg, c;
     if constexpr (TILED) {
-        nseg = (nchunk + SC - 1) / SC;
+        nseg = (int)seg_count(nchunk, SC);
         c = (int)sno / nseg;
     } else {
         nseg = map.nseg;
-        c = (int)(((uint64_t)sno * map.magic) >> map.mshift);
+        c = seg_row(map, sno);
     }
     const int seg = (int)sno - c * nseg;
     const int64_t t = sload(I.tbase) + k;
@@ -1141,14 +1122,6 @@ __global__ __launch_bounds__(1024) void resident_kernel(const InstDev* __restric
     }
 }
 
-size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk)
-{
-    const size_t wpr = (size_t)nchunk * kWordsPerChunk;
-    const size_t words = 2 * (size_t)np * pitch + 2 * (size_t)np * wpr + wpr +
-                         2 * (size_t)nchunk * kChunk + 10 * (size_t)np;
-    return words * sizeof(uint32_t);
-}
-
 size_t resident_lds_limit()
 {
     static std::once_flag once;
@@ -1466,23 +1439,7 @@ static hipError_t segments_common(const InstDev* dI, const Tile* seg_tiles, int6
     const int sc = f64 ? kSegChunks64 : kSegChunks32;
     const int sw = f64 ? kSegWaves64 : kSegWaves32;
     const dim3 grid((unsigned)n_seg), block((unsigned)(64 * sw));
-    SegMap map{};
-    map.xcds = xcd_count();
-    map.xshift = -1;
-    for (int b = 0; b < 31; ++b)
-        if (map.xcds == (1 << b)) map.xshift = b;
-    map.q = (int32_t)(n_seg / map.xcds);
-    map.r = (int32_t)(n_seg % map.xcds);
-    if (!seg_tiles) {
-        // q = (s * magic) >> mshift equals s / nseg for every s < 2^31:
-        // mshift = 31 + ceil(log2 nseg), magic = ceil(2^mshift / nseg)
-        int l = 0;
-        while ((1ll << l) < nseg_row) ++l;
-        map.nseg = nseg_row;
-        map.mshift = 31 + l;
-        map.magic = (uint64_t)((((unsigned __int128)1 << map.mshift) + (unsigned)nseg_row - 1) /
-                               (unsigned)nseg_row);
-    }
+    const SegMap map = seg_map_for(n_seg, xcd_count(), seg_tiles ? 0 : nseg_row);
 #define QIEO_SEG(TT, FF, SC, SW)                                                               \
     do {                                                                                       \
         if (seg_tiles)                                                                         \
@@ -1518,12 +1475,15 @@ static hipError_t segments_common(const InstDev* dI, const Tile* seg_tiles, int6
     return hipGetLastError();
 }
 
-hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int flags, int k, int gens_all,
-                           bool f64, hipStream_t s)
+hipError_t launch_segments(const InstDev* dI, int np, int nchunk, int part_nseg, int flags, int k,
+                           int gens_all, bool f64, hipStream_t s)
 {
     if (np <= 0) return hipErrorInvalidValue;
     const int sc = f64 ? kSegChunks64 : kSegChunks32;
-    const int64_t nseg = (nchunk + sc - 1) / sc;
+    const int64_t nseg = seg_count(nchunk, sc);
+    // each segment stores its sums at part[row][segment]: never more
+    // segments per row than the arena's partial-sum array holds
+    if (nseg > part_nseg) return hipErrorInvalidValue;
     return segments_common(dI, nullptr, (int64_t)np * nseg, (int)nseg, nullptr, (np + 3) / 4,
                            flags, k, nullptr, gens_all, f64, s);
 }

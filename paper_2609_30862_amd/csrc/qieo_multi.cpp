@@ -44,59 +44,19 @@ int DevicePool::init(size_t bytes, const qieo_dev_ctx* ctx)
         base_ = (char*)p;
     }
     if (!base_) return set_error(QIEO_ENOMEM, "device pool of %zu bytes could not be allocated", bytes);
-    cap_ = bytes;
-    used_ = 0;
-    free_.clear();
-    busy_.clear();
-    free_[0] = bytes;
+    book_.reset(bytes);
     return QIEO_OK;
 }
 
 char* DevicePool::alloc(size_t bytes)
 {
-    bytes = round256(std::max<size_t>(bytes, 1));
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-        if (it->second < bytes) continue;
-        const size_t off = it->first, sz = it->second;
-        free_.erase(it);
-        if (sz > bytes) free_[off + bytes] = sz - bytes;
-        busy_[off] = bytes;
-        used_ += bytes;
-        return base_ + off;
-    }
-    return nullptr;
+    const size_t off = book_.alloc(bytes);
+    return off == OffsetAllocator::npos ? nullptr : base_ + off;
 }
 
 void DevicePool::release(char* p)
 {
-    if (!p) return;
-    const size_t off = (size_t)(p - base_);
-    auto b = busy_.find(off);
-    if (b == busy_.end()) return;
-    size_t start = off, sz = b->second;
-    busy_.erase(b);
-    used_ -= sz;
-    auto next = free_.lower_bound(start);
-    if (next != free_.end() && start + sz == next->first) {
-        sz += next->second;
-        next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-        auto prev = std::prev(next);
-        if (prev->first + prev->second == start) {
-            start = prev->first;
-            sz += prev->second;
-            free_.erase(prev);
-        }
-    }
-    free_[start] = sz;
-}
-
-size_t DevicePool::largest_free() const
-{
-    size_t m = 0;
-    for (auto& f : free_) m = std::max(m, f.second);
-    return m;
+    if (p) (void)book_.release((size_t)(p - base_));
 }
 
 // ---------------------------------------------------------------------------
@@ -184,21 +144,6 @@ void Engine::force_shape(int R, int S, int flags)
     dirty_ = true;
 }
 
-// Shape classes by chunks per row: a workgroup of S waves needs >= S chunks
-// per row to keep its waves busy, so short rows go to narrow workgroups.
-// Shape classes by 256-gene chunks per row: 1, 2-3, 4-7, 8-31, >= 32; the
-// class's waves per workgroup are 1, 2, 4, 8, 16.
-constexpr int kClasses = 5;
-constexpr int64_t kMaxSegTiles = (int64_t)1 << 22;   // 32 MB of segment tiles
-static int class_of(int32_t nchunk)
-{
-    if (nchunk <= 1) return 0;
-    if (nchunk <= 3) return 1;
-    if (nchunk <= 7) return 2;
-    if (nchunk <= 31) return 3;
-    return 4;
-}
-
 int Engine::rebuild()
 {
     invalidate_graph();
@@ -248,32 +193,36 @@ int Engine::rebuild()
                             stream_)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(descriptors)");
 
-    // members whose whole state fits in one workgroup's LDS run the call
-    // there (one workgroup each); the rest are grouped by shape class; within
-    // a class, longest rows first so the longest-running workgroups start
-    // first
-    pids_.clear();
-    pids_lds_ = 0;
-    const size_t lds_limit = use_persistent_ ? resident_lds_limit() : 0;
-    std::vector<std::vector<size_t>> groups(kClasses);
+    // resident set, shape classes and tile tables (host planning)
+    std::vector<MemberShape> shapes(n);
     for (size_t i = 0; i < n; ++i) {
         const Member& m = members_[i];
-        const size_t lds = resident_lds_bytes(m.np, m.L.pitch, m.L.nchunk);
-        if (use_persistent_ && lds <= lds_limit) {
-            pids_.push_back((uint32_t)i);
-            pids_lds_ = std::max(pids_lds_, lds);
-        } else {
-            groups[class_of(m.L.nchunk)].push_back(i);
-        }
+        shapes[i].np = m.np;
+        shapes[i].pitch = m.L.pitch;
+        shapes[i].nchunk = m.L.nchunk;
+        shapes[i].part_nseg = m.L.part_nseg;
+        shapes[i].addr = (uint64_t)(uintptr_t)m.arena;
     }
+    PlanOptions opt;
+    opt.use_persistent = use_persistent_;
+    opt.lds_limit = use_persistent_ ? resident_lds_limit() : 0;
+    opt.use_segments = use_segments_;
+    opt.merge_segments = merge_segments_;
+    opt.force_R = force_R_;
+    opt.force_S = force_S_;
+    opt.force_flags = force_flags_;
+    opt.tuned = use_tuned_ ? tuned_class : nullptr;
+    BatchPlan plan;
+    int rc = plan_batch(shapes, opt, &plan);
+    if (rc) {
+        (void)hipStreamSynchronize(stream_);
+        return rc;
+    }
+    pids_ = std::move(plan.resident);
+    pids_lds_ = plan.resident_lds;
     if (d_pids_) (void)hipFree(d_pids_);
     d_pids_ = nullptr;
     if (!pids_.empty()) {
-        // largest first: the longest workgroups start first
-        std::sort(pids_.begin(), pids_.end(), [&](uint32_t a, uint32_t b) {
-            return (int64_t)members_[a].np * members_[a].L.pitch >
-                   (int64_t)members_[b].np * members_[b].L.pitch;
-        });
         if ((e = hipMalloc(&d_pids_, pids_.size() * sizeof(uint32_t))) != hipSuccess)
             return rebuild_fail(e, "hipMalloc(persistent ids)");
         if ((e = hipMemcpyAsync(d_pids_, pids_.data(), pids_.size() * sizeof(uint32_t),
@@ -288,94 +237,15 @@ int Engine::rebuild()
     }
     if (!fork_ && (e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess)
         return rebuild_fail(e, "hipEventCreate");
-    // amplitude bytes one generation of the whole batch streams (the classes
-    // run side by side, so they share the caches)
-    int64_t plane_bytes = 0;
-    for (auto& m : members_) plane_bytes += (int64_t)m.np * m.L.pitch * 2 * (int64_t)sizeof(float);
-    // A batch that streams from HBM runs the rows of 8 or more chunks in
-    // segment order, all in one table (one launch pair per generation), when
-    // that table stays within kMaxSegTiles; else only the >= 32-chunk class
-    // does, if its own table fits.  On the 512-instance ragged batch: 0.330 s
-    // per 500 generations merged, 0.333 s with the 8-31-chunk class in row
-    // order beside it (as a segment-order class of its own on a second
-    // stream it measured 0.339 s; every class of the batch in the one
-    // table, 0.333 s).
-    auto seg_tiles_of = [&](const std::vector<size_t>& g) {
-        int64_t n_tiles = 0;
-        for (size_t i : g)
-            n_tiles += (int64_t)members_[i].np *
-                       ((members_[i].L.nchunk + kSegChunks32 - 1) / kSegChunks32);
-        return n_tiles;
-    };
-    const bool streaming = use_segments_ && force_R_ == 0 && plane_bytes > ((int64_t)256 << 20);
-    if (streaming && merge_segments_ && !groups[kClasses - 2].empty() &&
-        seg_tiles_of(groups[kClasses - 2]) + seg_tiles_of(groups[kClasses - 1]) <= kMaxSegTiles) {
-        auto& g4 = groups[kClasses - 1];
-        g4.insert(g4.end(), groups[kClasses - 2].begin(), groups[kClasses - 2].end());
-        groups[kClasses - 2].clear();
-    }
-    static const int kS[kClasses] = {1, 2, 4, 8, 16};
-    for (int c = 0; c < kClasses; ++c) {
-        auto& g = groups[c];
-        if (g.empty()) continue;
-        std::sort(g.begin(), g.end(), [&](size_t a, size_t b) {
-            if (members_[a].L.nchunk != members_[b].L.nchunk)
-                return members_[a].L.nchunk > members_[b].L.nchunk;
-            return a < b;
-        });
+    for (ClassPlan& cp : plan.classes) {
         ShapeClass sc;
-        int64_t rows = 0, max_nchunk = 0;
-        for (size_t i : g) {
-            rows += members_[i].np;
-            max_nchunk = std::max<int64_t>(max_nchunk, members_[i].L.nchunk);
-        }
-        sc.S = kS[c];
-        sc.R = 1;
-        // long rows: at most 2 rows per 16-wave workgroup, as for single
-        // streaming populations
-        for (int cand : {4, 2}) {
-            if (sc.S == 16 && cand > 2) continue;
-            // blocks of the class at R rows each, times S waves: keep >= 8192 waves
-            int64_t blocks = 0;
-            for (size_t i : g) blocks += (members_[i].np + cand - 1) / cand;
-            if (blocks * sc.S >= 8192) { sc.R = cand; break; }
-        }
-        sc.flags = variant_flags(sc.R, sc.S, max_nchunk, plane_bytes);
-        if (force_R_ > 0) {
-            sc.R = force_R_;
-            sc.S = force_S_;
-            sc.flags = force_flags_;
-        }
-        // The long-row class of a batch that streams from HBM (rows of 8 or
-        // more chunks when the classes were merged above, else of 32 or
-        // more) runs in segment order: one tile per 1024-gene segment,
-        // members in arena address order, so the class sweeps its planes in
-        // address order; a second tile table gives the closing launch four
-        // rows per workgroup.
-        // The segment table costs 8 bytes per 1024 genes and is rebuilt on
-        // every membership change; a server holding thousands of residents
-        // changes membership every few generations, so a class of more than
-        // kMaxSegTiles segments keeps row order.
-        const bool seg = c == kClasses - 1 && streaming && seg_tiles_of(g) <= kMaxSegTiles;
-        if (seg) {
-            std::sort(g.begin(), g.end(),
-                      [&](size_t a, size_t b) { return members_[a].arena < members_[b].arena; });
-            sc.flags = kFlagSegments | kFlagNontemporal | kFlagNontemporalLoads;
-            for (size_t i : g) {
-                const Member& m = members_[i];
-                const int64_t nseg = (m.L.nchunk + kSegChunks32 - 1) / kSegChunks32;
-                for (int64_t q = 0; q < (int64_t)m.np * nseg; ++q)
-                    sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)q});
-                for (int32_t r0 = 0; r0 < m.np; r0 += 4)
-                    sc.fe_tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
-            }
-            if (sc.tiles.size() > (size_t)INT32_MAX)
-                return set_error(QIEO_EINVAL, "segment tile table too large");
-        } else {
-            for (size_t i : g)
-                for (int32_t r0 = 0; r0 < members_[i].np; r0 += sc.R)
-                    sc.tiles.push_back(Tile{(uint32_t)i, (uint32_t)r0});
-        }
+        sc.cls = cp.cls;
+        sc.R = cp.R;
+        sc.S = cp.S;
+        sc.flags = cp.flags;
+        sc.tuned = cp.tuned;
+        sc.tiles = std::move(cp.tiles);
+        sc.fe_tiles = std::move(cp.fe_tiles);
         // owned by classes_ from here on, so an early return frees the tables
         // at the next rebuild or in the destructor
         classes_.push_back(std::move(sc));

@@ -23,17 +23,15 @@ public:
     int init(size_t bytes, const qieo_dev_ctx* ctx);   // QIEO_OK / QIEO_ENOMEM
     char* alloc(size_t bytes);                         // nullptr if no room
     void release(char* p);
-    size_t capacity() const { return cap_; }
-    size_t used() const { return used_; }
-    size_t largest_free() const;
+    size_t capacity() const { return book_.capacity(); }
+    size_t used() const { return book_.used(); }
+    size_t largest_free() const { return book_.largest_free(); }
 
 private:
     char* base_ = nullptr;
-    size_t cap_ = 0, used_ = 0;
     qieo_dev_ctx ctx_{};
     bool has_alloc_ = false;
-    std::map<size_t, size_t> free_;   // offset -> size
-    std::map<size_t, size_t> busy_;   // offset -> size
+    OffsetAllocator book_;            // which byte ranges of the pool are in use
 };
 
 // One resident population inside an engine.
@@ -51,7 +49,9 @@ struct Member {
 
 // Work shape of one launch class.
 struct ShapeClass {
+    int cls = 0;               // shape class by chunks per row (class_of)
     int R = 4, S = 8, flags = 0;
+    bool tuned = false;        // shape taken from the tuning database
     std::vector<Tile> tiles;
     Tile* d_tiles = nullptr;   // device copy
     // segment order (flags has kFlagSegments): tiles are {member, segment
@@ -131,6 +131,7 @@ private:
     bool merge_segments_ = true;
     int force_R_ = 0, force_S_ = 0, force_flags_ = 0;
     bool use_graph_ = true;
+    bool use_tuned_ = true;      // class shapes from the tuning database where tuned
     hipGraphExec_t graph_ = nullptr;
     int graph_n_ = -1;
     int prev_n_ = -1;            // longest count of the previous call since the last rebuild

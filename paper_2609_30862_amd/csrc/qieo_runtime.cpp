@@ -25,65 +25,14 @@ using namespace qieo;
 // ---------------------------------------------------------------------------
 namespace qieo {
 
-static thread_local std::string g_last_error;
-
-int set_error(int code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
 int hip_fail(hipError_t e, const char* what)
 {
     return set_error(QIEO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-void clear_error() { g_last_error.clear(); }
-
 // ---------------------------------------------------------------------------
 // Device arena
 // ---------------------------------------------------------------------------
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem)
-{
-    const int32_t pitch = (int32_t)align_up((size_t)ng, 64);
-    const int32_t nchunk = (pitch + kChunk - 1) / kChunk;
-    const size_t wpr = (size_t)nchunk * kWordsPerChunk;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        const size_t o = off;
-        off = align_up(off + bytes, 256);
-        return o;
-    };
-    L->pitch = pitch;
-    L->nchunk = nchunk;
-    L->alpha = take(((size_t)np * pitch + kChunk) * (size_t)elem);
-    L->beta = take(((size_t)np * pitch + kChunk) * (size_t)elem);
-    L->xbits = take(2 * (size_t)np * wpr * sizeof(uint32_t));
-    L->v = take((size_t)nchunk * kChunk * sizeof(int32_t));
-    L->w = take((size_t)nchunk * kChunk * sizeof(int32_t));
-    L->fit = take(2 * (size_t)np * sizeof(int32_t));
-    L->prof = take(2 * (size_t)np * sizeof(int32_t));
-    L->wt = take(2 * (size_t)np * sizeof(int32_t));
-    L->ekey = take(3 * sizeof(unsigned long long));
-    L->best = take(8 * sizeof(int32_t));
-    L->best_bits = take(wpr * sizeof(uint32_t));
-    L->tbase = take(sizeof(int64_t));
-    L->conv = take(64 * sizeof(int32_t));
-    const size_t nseg = ((size_t)nchunk + kSegChunksMin - 1) / kSegChunksMin;
-    L->part = take(nseg * (size_t)np * 2 * sizeof(uint32_t));
-    L->total = off;
-    // everything except the amplitude planes themselves is zero-initialised
-    L->zero_from = 0;
-    return off;
-}
-
 InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
                    uint64_t seed)
 {
@@ -110,40 +59,6 @@ InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int
     d.seed_lo = (uint32_t)seed;
     d.seed_hi = (uint32_t)(seed >> 32);
     return d;
-}
-
-int validate_shape(int32_t n_items, int32_t n_pop)
-{
-    if (n_items < 1) return set_error(QIEO_EINVAL, "n_items must be >= 1 (got %d)", n_items);
-    if (n_pop < 1) return set_error(QIEO_EINVAL, "n_pop must be >= 1 (got %d)", n_pop);
-    if (n_items > (1 << 30) - 256)
-        return set_error(QIEO_EINVAL, "n_items too large (%d)", n_items);
-    // keeps every plane size in the arena layout far from size_t wrap-around
-    // (2^36 genes is 512 GB of binary32 amplitudes, beyond any one device)
-    if ((int64_t)n_pop * (int64_t)align_up((size_t)n_items, 64) > ((int64_t)1 << 36))
-        return set_error(QIEO_EINVAL, "population of %d x %d genes exceeds 2^36 genes", n_pop,
-                         n_items);
-    return QIEO_OK;
-}
-
-int validate_problem(const qieo_item* items, int32_t n_items, int32_t capacity, int32_t n_pop)
-{
-    if (!items) return set_error(QIEO_EINVAL, "items is NULL");
-    int rc = validate_shape(n_items, n_pop);
-    if (rc) return rc;
-    if (capacity < 0) return set_error(QIEO_EINVAL, "capacity must be >= 0 (got %d)", capacity);
-    int64_t sv = 0, sw = 0;
-    for (int32_t i = 0; i < n_items; ++i) {
-        if (items[i].profit < 0 || items[i].weight < 0)
-            return set_error(QIEO_EINVAL, "item %d has a negative profit or weight", i);
-        sv += items[i].profit;
-        sw += items[i].weight;
-    }
-    if (sv > INT32_MAX || sw > INT32_MAX)
-        return set_error(QIEO_EOVERFLOW,
-                         "sum of profits (%lld) or weights (%lld) exceeds INT32_MAX",
-                         (long long)sv, (long long)sw);
-    return QIEO_OK;
 }
 
 // Upload item tables (zero-padded to pitch) and initialise the state.
@@ -181,56 +96,6 @@ int check_device()
         return set_error(QIEO_EDEVICE, "device %d is %s, libqieo is built for gfx950", dev,
                          p.gcnArchName);
     return QIEO_OK;
-}
-
-// Variant bits for a work shape, from sweeps over fifteen (Np, Ng) shapes
-// between 82 MB and 13 GB of amplitudes.  Once the planes one generation
-// streams exceed the 256 MB last-level cache: non-temporal loads (cached
-// amplitudes would only evict the item tables and allele words) and
-// non-temporal stores (nothing written survives until the next generation
-// reads it).  Below that size both hints cost time (up to 27 %): the next
-// generation's reads may still hit the cache.  Prefetch when a wave walks
-// more than one chunk, except in multi-row workgroups over long rows (>= 32
-// chunks per wave), where several rows' loads already keep enough in flight
-// and the prefetch buffers cost occupancy.
-int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes)
-{
-    int f = 0;
-    if (plane_bytes > ((int64_t)256 << 20)) f |= kFlagNontemporal | kFlagNontemporalLoads;
-    if (nchunk > S && !(R >= 2 && nchunk >= 32 * (int64_t)S)) f |= kFlagPrefetch;
-    return f;
-}
-
-// Work shape for a single instance: rows per workgroup R, waves per
-// workgroup S and kernel variant flags.  Whole rows stay in one workgroup
-// (Evaluation closes in LDS); S splits the gene axis.  R is the largest of
-// 4, 2, 1 that still leaves >= 32 wavefronts per CU (8192 on 256 CUs), since
-// more rows per workgroup amortise the item-table and elite-mask reads.
-// Streaming populations (planes beyond the last-level cache) with long rows
-// (>= 32 chunks) and at least 1024 of them take 2 rows x 16 waves, the
-// fastest row shape on every such workload measured.  Streaming binary32
-// populations run in segment order instead: faster than the best row shape
-// on all ten streaming workloads measured (6-14 %; 2.23 ms against 2.56 on
-// 4096 x 200,000), slower on cache-resident ones (11-18 %), where the row
-// kernel stays.
-void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes)
-{
-    const int64_t plane_bytes = (int64_t)np * nchunk * kChunk * 2 * (int64_t)elem_bytes;
-    int s = 8;
-    if (nchunk < s) s = std::max(1, nchunk);
-    int r = 1;
-    for (int cand : {4, 2}) {
-        if ((int64_t)((np + cand - 1) / cand) * s >= 8192) { r = cand; break; }
-    }
-    if (plane_bytes > ((int64_t)256 << 20) && nchunk >= 32 && np >= 1024) {
-        r = 2;
-        s = 16;
-    }
-    *R = r;
-    *S = s;
-    *flags = variant_flags(r, s, nchunk, plane_bytes);
-    if (elem_bytes == 4 && plane_bytes > ((int64_t)256 << 20))
-        *flags = kFlagSegments | kFlagNontemporal | kFlagNontemporalLoads;
 }
 
 }  // namespace qieo
@@ -329,19 +194,6 @@ static void default_shape(const qieo_inst* h, int* R, int* S, int* F)
             *F = (*F & ~(kFlagNontemporalLoads | kFlagPrefetch | kFlagSegments)) |
                  (h->L.nchunk > *S ? kFlagPrefetch : 0);
     }
-}
-
-// FNV-1a (64-bit) over the item array: identifies the problem a snapshot
-// belongs to.
-static uint64_t items_fnv1a(const qieo_item* items, int32_t n)
-{
-    uint64_t x = 0xcbf29ce484222325ull;
-    const unsigned char* p = reinterpret_cast<const unsigned char*>(items);
-    for (size_t k = 0; k < (size_t)n * sizeof(qieo_item); ++k) {
-        x ^= p[k];
-        x *= 0x100000001b3ull;
-    }
-    return x;
 }
 
 static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity,
@@ -497,7 +349,8 @@ static int host_elite(qieo_inst* h, int64_t t)
 static hipError_t launch_fused(qieo_inst* h, int blocks, int k, int n)
 {
     if (h->flags & kFlagSegments)
-        return launch_segments(h->d_desc, h->np, h->L.nchunk, h->flags, k, n, h->f64, h->stream);
+        return launch_segments(h->d_desc, h->np, h->L.nchunk, h->L.part_nseg, h->flags, k, n,
+                               h->f64, h->stream);
     return launch_generation(h->d_desc, nullptr, blocks, h->R, h->S, h->flags, k, nullptr, n,
                              h->stream);
 }
@@ -552,8 +405,8 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
                 (void)hipEventRecord(a, h->stream);
             }
             e = (h->flags & kFlagSegments)
-                    ? launch_segments(h->d_desc, h->np, h->L.nchunk, h->flags, k, n, true,
-                                      h->stream)
+                    ? launch_segments(h->d_desc, h->np, h->L.nchunk, h->L.part_nseg, h->flags,
+                                      k, n, true, h->stream)
                     : launch_generation_f64(h->d_desc, blocks, h->R, h->S, h->flags, k, n,
                                             h->stream);
             if (e != hipSuccess) return hip_fail(e, "generation kernel (binary64)");
@@ -1050,7 +903,7 @@ extern "C" const char* qieo_strerror(int code)
     }
 }
 
-extern "C" const char* qieo_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* qieo_last_error(void) { return last_error(); }
 
 extern "C" const char* qieo_version(void) { return "libqieo 0.1 (gfx950)"; }
 
@@ -1062,22 +915,10 @@ extern "C" const char* qieo_version(void) { return "libqieo 0.1 (gfx950)"; }
 // handle of the same problem restores every value the kernels read, so the
 // trajectory continues bit for bit.
 // ---------------------------------------------------------------------------
-namespace {
-
-struct StateHeader {
-    char magic[8];
-    uint32_t version;
-    uint32_t elem_bytes;
-    int32_t n_items, n_pop, capacity, reserved;
-    uint64_t seed;
-    uint64_t items_hash;
-    int64_t generations;
-    uint64_t arena_bytes;
-};
-constexpr char kStateMagic[8] = {'Q', 'I', 'E', 'O', 'S', 'T', 'A', 'T'};
-constexpr uint32_t kStateVersion = 2;
-
-}  // namespace
+static SnapshotId snapshot_id(const qieo_inst* h)
+{
+    return SnapshotId{h->f64 ? 8u : 4u, h->ng, h->np, h->capacity, h->seed, h->items_hash};
+}
 
 extern "C" int qieo_state_size(qieo_inst* h, size_t* bytes)
 {
@@ -1097,17 +938,7 @@ extern "C" int qieo_export_state(qieo_inst* h, void* buf, size_t bytes)
     int64_t t = 0;
     int rc = read_generations(h->d, h->stream, &t);
     if (rc) return rc;
-    StateHeader hd{};
-    std::memcpy(hd.magic, kStateMagic, sizeof hd.magic);
-    hd.version = kStateVersion;
-    hd.elem_bytes = h->f64 ? 8u : 4u;
-    hd.n_items = h->ng;
-    hd.n_pop = h->np;
-    hd.capacity = h->capacity;
-    hd.seed = h->seed;
-    hd.items_hash = h->items_hash;
-    hd.generations = t;
-    hd.arena_bytes = h->L.total;
+    const StateHeader hd = make_state_header(snapshot_id(h), t, h->L.total);
     std::memcpy(buf, &hd, sizeof hd);
     hipError_t e = copy_on((char*)buf + sizeof hd, h->arena, h->L.total, hipMemcpyDeviceToHost,
                            h->stream);
@@ -1119,36 +950,11 @@ extern "C" int qieo_import_state(qieo_inst* h, const void* buf, size_t bytes)
 {
     clear_error();
     if (!h || !buf) return set_error(QIEO_EINVAL, "NULL argument");
-    if (bytes < sizeof(StateHeader)) return set_error(QIEO_EINVAL, "state buffer too short");
-    StateHeader hd;
-    std::memcpy(&hd, buf, sizeof hd);
-    if (std::memcmp(hd.magic, kStateMagic, sizeof hd.magic) != 0 || hd.version != kStateVersion)
-        return set_error(QIEO_EINVAL, "not a libqieo state snapshot (or another version)");
-    if (hd.elem_bytes != (h->f64 ? 8u : 4u))
-        return set_error(QIEO_EINVAL, "snapshot precision differs from the handle's");
-    if (hd.n_items != h->ng || hd.n_pop != h->np || hd.capacity != h->capacity ||
-        hd.seed != h->seed || hd.items_hash != h->items_hash)
-        return set_error(QIEO_EINVAL, "snapshot belongs to another problem (items, capacity, "
-                                      "population size or seed differ)");
-    if (hd.arena_bytes != h->L.total || bytes < sizeof hd + hd.arena_bytes)
-        return set_error(QIEO_EINVAL, "snapshot size does not match the handle's state");
-    const char* body = (const char*)buf + sizeof hd;
-    int64_t tb;
-    int32_t window;
-    std::memcpy(&tb, body + h->L.tbase, sizeof tb);
-    std::memcpy(&window, body + h->L.conv + 3 * sizeof(int32_t), sizeof window);
-    if (tb != hd.generations || tb < 0 || tb > (int64_t)INT32_MAX || window < 0 ||
-        window > kConvRing)
-        return set_error(QIEO_EINVAL, "snapshot is inconsistent");
-    if (tb > 0) {
-        // the next generation rotates toward the elite row its key names
-        // (row = ~low word): a row outside the population would be read out
-        // of bounds on the device
-        uint64_t key;
-        std::memcpy(&key, body + h->L.ekey + (size_t)((tb - 1) % 3) * sizeof key, sizeof key);
-        if ((uint32_t)~(uint32_t)key >= (uint32_t)h->np)
-            return set_error(QIEO_EINVAL, "snapshot is inconsistent (elite row out of range)");
-    }
+    int64_t tb = 0;
+    int32_t window = 0;
+    int rc = check_snapshot(buf, bytes, snapshot_id(h), h->L, &tb, &window);
+    if (rc) return rc;
+    const char* body = (const char*)buf + sizeof(StateHeader);
     if (window > 0 && h->pipeline != QIEO_PIPELINE_FUSED)
         return set_error(QIEO_ESTATE, "snapshot has a convergence window: select the fused "
                                       "pipeline first");

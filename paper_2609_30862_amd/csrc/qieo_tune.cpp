@@ -58,6 +58,12 @@ bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
     return true;
 }
 
+bool tuned_class(int cls, int64_t rows, int32_t max_nchunk, int* R, int* S, int* flags)
+{
+    (void)cls; (void)rows; (void)max_nchunk; (void)R; (void)S; (void)flags;
+    return false;
+}
+
 }  // namespace qieo
 
 using namespace qieo;
@@ -138,7 +144,7 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
         hipError_t ee = hipEventRecord(e0, s);
         for (int k = 0; k < gens && ee == hipSuccess; ++k)
             ee = (c.flags & kFlagSegments)
-                     ? launch_segments(d_desc, n_pop, L.nchunk, c.flags, k, gens, false, s)
+                     ? launch_segments(d_desc, n_pop, L.nchunk, L.part_nseg, c.flags, k, gens, false, s)
                      : launch_generation(d_desc, nullptr, blocks, c.R, c.S, c.flags, k, nullptr,
                                          gens, s);
         if (ee == hipSuccess) ee = launch_finish(d_desc, 1, nullptr, gens, nullptr, s);

@@ -2,15 +2,15 @@
 """Throughput benchmark of the QIEO generation on one MI355X.
 
 A step is one generation of the whole loop (CIP of the previous generation,
-QIP, Evaluation, DetermineElite, fused in one launch) over the resident
-population of the largest single-instance workload: Np = 4096 chromosomes of
-Ng = 200,000 items (weights U[1,100], value = weight + 10, capacity =
-floor(sum/2), seed 2).  The default K = 200 steps is that workload's whole
-generation budget.  Five timed runs (--repeats), each on a fresh population
-of the same seed; the reported figures are the median run's.  Prints one
-JSON line.
+QIP, Evaluation, DetermineElite, fused) over the resident population of the
+largest single-instance workload: Np = 4096 chromosomes of Ng = 200,000
+items (weights U[1,100], value = weight + 10, capacity = floor(sum/2), seed
+2), with binary64 amplitudes, the paper's precision (--precision 32 for
+binary32).  The default K = 200 steps is that workload's whole generation
+budget.  Five timed runs (--repeats), each on a fresh population of the same
+seed; the reported figures are the median run's.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 3] [--repeats 5]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 3] [--repeats 5] [--precision 64]
 """
 from __future__ import annotations
 
@@ -24,10 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, 8.0 TB/s
-BYTES_PER_GENE_UPDATE = 16      # binary32 (alpha, beta) read + write
+# (alpha, beta) read and written once per gene-update: 4 amplitudes
+AMPLITUDES_PER_GENE_UPDATE = 4
 KERNEL_SOURCES = ["paper_2609_30862_amd/csrc/qieo_kernels.hip",
                   "paper_2609_30862_amd/csrc/qieo_device.hpp",
-                  "paper_2609_30862_amd/csrc/qieo_kernels.hpp"]
+                  "paper_2609_30862_amd/csrc/qieo_kernels.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_layout.hpp"]
 PROFILE = "profiles/generation_kernel_np4096_ng200000.md"
 
 
@@ -50,27 +52,54 @@ def kernel_code_digest(read=None) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(n_pop: int, n_items: int, shape=None):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on this workload with the current kernel code and the same
-    work shape (rows, waves, variant bits) when one is given; else None."""
+def measured_traffic(n_pop: int, n_items: int, shape=None, precision: int = 64):
+    """HBM bytes per generation from the committed rocprofv3 counter summary,
+    if it was taken on this workload and amplitude precision with the current
+    kernel code and the same work shape (rows, waves, variant bits) when one
+    is given; else None.  The summary's machine-readable lines carry a
+    precision suffix (_f32, _f64)."""
     if (n_pop, n_items) != (4096, 200_000):
         return None
+    sfx = "_f64" if precision == 64 else "_f32"
+    keys = ("traffic_bytes_per_launch" + sfx, "kernel_code_sha256", "work_shape" + sfx)
     try:
         text = open(os.path.join(ROOT, PROFILE)).read()
         fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
-                   if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:",
-                                               "work_shape:")))
+                   if line.strip().startswith(tuple(k + ":" for k in keys)))
         if fig.get("kernel_code_sha256") != kernel_code_digest():
             return None
-        if shape is not None and fig.get("work_shape") != "%d %d %d" % tuple(shape):
+        if shape is not None and fig.get("work_shape" + sfx) != "%d %d %d" % tuple(shape):
             return None
-        return float(fig["traffic_bytes_per_launch"])
+        return float(fig["traffic_bytes_per_launch" + sfx])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 200):
+def rotating_rows(inst, precision: int, first: int, count: int):
+    """Rows that rotate in generations first .. first+count-1 of the run (CIP
+    of generation t-1, applied in the launch of t, moves every row whose
+    fitness at t-1 is below that generation's elite; the elite and its ties
+    only read beta).  The trajectory is deterministic, so a fresh run of the
+    same seed stepped one generation at a time sees the timed runs' rows.
+    Returns the per-generation counts."""
+    from paper_2609_30862_amd import qieo
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                      precision=precision)
+    counts = []
+    prev = None
+    for t in range(first + count):
+        if t >= first:
+            counts.append(0 if prev is None else int((prev[0] < prev[1]).sum()))
+        g.step(1)
+        st = g.export_rows(0, inst.n_pop, amplitudes=False, alleles=False)
+        fit = st["fitness"].astype("int64")
+        prev = (fit, fit[int(st["elite"])])
+    g.close()
+    return counts
+
+
+def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 200,
+                 precision: int = 64):
     """The CPU oracle, untuned, on a bounded sample of the same workload: the
     first `rows` chromosomes of the population over the full item list, for
     `gens` generations, on `threads` host threads (rows split among them).
@@ -89,7 +118,7 @@ def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 2
             pinned = None
     try:
         o = oracle.Oracle(inst.values, inst.weights, inst.capacity, rows, inst.seed,
-                          threads=threads)
+                          threads=threads, precision=precision)
         o.run(1)                # generation 0 observes only; time full generations
         t0 = time.perf_counter()
         o.run(gens)
@@ -102,7 +131,8 @@ def cpu_baseline(inst, rows: int, gens: int, threads: int = 1, run_gens: int = 2
     return {"value": rate, "unit": "gene-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": "first %d of %d chromosomes x %d items, %d generations after "
-                      "generation 0, %.1f s" % (rows, inst.n_pop, inst.n_items, gens, dt),
+                      "generation 0, binary%d amplitudes, %.1f s"
+                      % (rows, inst.n_pop, inst.n_items, gens, precision, dt),
             "extrapolated_s_per_generation": per_gen,
             "extrapolated_s_per_run": run_gens * per_gen, "run_generations": run_gens,
             "pinned_cpu": pinned, "host": host_info()}
@@ -430,15 +460,17 @@ def main():
     ap.add_argument("--n-items", type=int, default=200_000)
     ap.add_argument("--tile", type=str, default="", help="R,S work shape override")
     ap.add_argument("--kernel-flags", type=int, default=-1, help="generation kernel variant")
-    ap.add_argument("--precision", type=int, choices=[32, 64], default=32,
-                    help="amplitude precision (64: the paper's binary64)")
+    ap.add_argument("--precision", type=int, choices=[32, 64], default=None,
+                    help="amplitude precision: 64 is the paper's binary64 (default for the "
+                         "large workload), 32 binary32 (default for small and medium, whose "
+                         "configurations name binary32)")
     ap.add_argument("--autotune", type=int, default=0, metavar="GENS",
                     help="time every work shape for GENS generations first and use the best")
     ap.add_argument("--repeats", type=int, default=5,
                     help="large: timed runs, each on a fresh instance of the same seed "
                          "(identical work); value is the median run")
     ap.add_argument("--cpu-rows", type=int, default=256)
-    ap.add_argument("--cpu-gens", type=int, default=8)
+    ap.add_argument("--cpu-gens", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["large", "medium", "small", "batch", "serve",
                                            "fractions", "launch", "stream"],
@@ -505,12 +537,18 @@ def main():
         inst = workloads.large_instance(args.n_pop, args.n_items)
     if args.steps is None:
         args.steps = inst.generations
-    log("workload %s, %d steps, %d warmup" % (inst.name, args.steps, args.warmup))
+    if args.precision is None:
+        args.precision = 64 if args.workload == "large" else 32
+    elem = 8 if args.precision == 64 else 4
+    log("workload %s, binary%d amplitudes, %d steps, %d warmup"
+        % (inst.name, args.precision, args.steps, args.warmup))
     if args.autotune:
         r = qieo.qieo_autotune(inst.n_items, inst.n_pop, args.autotune)
         log("autotune: %s" % r)
     genes = inst.n_pop * inst.n_items
-    bytes_per_launch = BYTES_PER_GENE_UPDATE * genes * (2 if args.precision == 64 else 1)
+    # algorithmic bytes of a generation in which every row rotates: alpha
+    # and beta read and written once
+    bytes_per_launch = AMPLITUDES_PER_GENE_UPDATE * elem * genes
     runs = []
 
     def fresh():
@@ -566,7 +604,15 @@ def main():
     wall = sorted(w for w, _ in runs)[len(runs) // 2]
     avg_ms = sorted(a for _, a in runs)[len(runs) // 2]
     value = genes * args.steps / wall
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    # the rows that rotated in the timed generations: a row that does not
+    # rotate (the elite and its ties, every row at generation 0) reads only
+    # beta, so a generation moves elem * Ng * (Np + 3 * rotating rows) bytes
+    rot = rotating_rows(inst, args.precision, args.warmup, args.steps)
+    rot_frac = sum(rot) / float(inst.n_pop * args.steps)
+    bytes_exact = elem * inst.n_items * (inst.n_pop * args.steps + 3 * sum(rot)) / args.steps
+    log("rotating rows in the timed generations: %d of %d (%.5f)"
+        % (sum(rot), inst.n_pop * args.steps, rot_frac))
+    achieved = bytes_exact / (avg_ms * 1e-3) / 1e9
 
     out = {
         "metric": "gene-updates/s",
@@ -581,37 +627,49 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "qieo-knapsack single instance Np=%d Ng=%d, %d generations"
-                               % (inst.n_pop, inst.n_items, args.steps),
+        "config": {"workload": "qieo-knapsack single instance Np=%d Ng=%d, binary%d "
+                               "amplitudes, %d generations"
+                               % (inst.n_pop, inst.n_items, args.precision, args.steps),
                    "n_pop": inst.n_pop, "n_items": inst.n_items, "seed": inst.seed,
+                   "precision": "binary%d" % args.precision,
                    "generations_per_step": 1,
+                   # generation indices the timed region runs (after the
+                   # warm-up, on a fresh population of the seed)
+                   "timed_generations": [args.warmup, args.warmup + args.steps - 1],
                    # amplitude planes within the 256 MB last-level cache: the
                    # rate is the cache's, not HBM's
-                   "cache_resident": genes * 2 * (8 if args.precision == 64 else 4) <= 256 << 20},
+                   "cache_resident": genes * 2 * elem <= 256 << 20},
         "repeats": len(runs),
         "ms_per_step_runs": [w / args.steps * 1e3 for w, _ in runs],
         "kernel_avg_ms_runs": [a for _, a in runs],
-        "hbm_frac_algorithmic": value * bytes_per_launch / genes / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac_algorithmic": value * bytes_exact / genes / (HBM_PEAK_GBS * 1e9),
+        "rotating_rows": {"fraction": rot_frac, "rows": sum(rot),
+                          "of": inst.n_pop * args.steps,
+                          "min_per_generation": min(rot), "max_per_generation": max(rot)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      # counters were taken with one work shape and variant
-                     "traffic": (measured_traffic(inst.n_pop, inst.n_items, shape)
-                                 if args.precision == 32 else None),
+                     "traffic": measured_traffic(inst.n_pop, inst.n_items, shape,
+                                                 args.precision),
                      "kernel": ("segment_kernel + segment_fe_kernel" if shape[2] & 16
                                 else "resident_kernel (one launch per call)" if one_launch
                                 else "generation_kernel"), "kernel_avg_ms": avg_ms,
-                     "bytes_per_launch": bytes_per_launch},
+                     # algorithmic bytes of the timed generations' average
+                     # launch (rotating rows 4 amplitudes per gene, others 1)
+                     "bytes_per_launch": bytes_exact,
+                     "bytes_per_launch_all_rows_rotating": bytes_per_launch},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows x %d generations" % (args.cpu_rows, args.cpu_gens))
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows, args.cpu_gens,
-                                           run_gens=args.steps)
+                                           run_gens=args.steps, precision=args.precision)
         nt = host_threads()
         log("cpu baseline: oracle on %d threads, %d rows x %d generations"
             % (nt, args.cpu_rows * nt, args.cpu_gens))
         out["cpu_baseline_threads"] = cpu_baseline(inst, min(inst.n_pop, args.cpu_rows * nt),
                                                    args.cpu_gens, threads=nt,
-                                                   run_gens=args.steps)
+                                                   run_gens=args.steps,
+                                                   precision=args.precision)
     print(json.dumps(out), flush=True)
 
 

@@ -79,6 +79,7 @@ def lib():
         L.oracle_get_amplitudes.argtypes = [P, P, P]
         L.oracle_set_amplitudes.argtypes = [P, P, P]
         L.oracle_get_alleles.argtypes = [P, P]
+        L.oracle_get_rows.argtypes = [P, i64, i64, P, P, P]
         L.oracle_set_alleles.argtypes = [P, P]
         L.oracle_get_fitness.argtypes = [P, P, P, P]
         L.oracle_set_fitness.argtypes = [P, P]
@@ -258,6 +259,17 @@ class Oracle:
         b = np.ascontiguousarray(beta, dtype=dt).reshape(self.np_, self.ng)
         put = lib().oracle_set_amplitudes_f64 if self.precision == 64 else lib().oracle_set_amplitudes
         put(self._h, _ptr(a), _ptr(b))
+
+    def rows(self, row0: int, n_rows: int):
+        """Amplitudes (alpha, beta) and alleles of rows [row0, row0 + n_rows)."""
+        if row0 < 0 or n_rows < 0 or row0 + n_rows > self.np_:
+            raise ValueError("rows outside the population")
+        dt = np.float64 if self.precision == 64 else np.float32
+        a = np.empty((n_rows, self.ng), dtype=dt)
+        b = np.empty((n_rows, self.ng), dtype=dt)
+        x = np.empty((n_rows, self.ng), dtype=np.uint8)
+        lib().oracle_get_rows(self._h, int(row0), int(n_rows), _ptr(a), _ptr(b), _ptr(x))
+        return a, b, x
 
     def alleles(self) -> np.ndarray:
         x = np.empty((self.np_, self.ng), dtype=np.uint8)

@@ -489,6 +489,22 @@ void oracle_set_amplitudes(oracle *s, const float *alpha, const float *beta)
     if (beta) memcpy(s->beta, beta, n * sizeof(float));
 }
 
+/* Rows [row0, row0 + n) of the amplitudes, in the oracle's precision
+ * (float or double arrays of n * ng), and of the alleles; any pointer may be
+ * NULL.  Rows outside the population are not copied. */
+void oracle_get_rows(const oracle *s, int64_t row0, int64_t n, void *alpha, void *beta,
+                     uint8_t *x)
+{
+    if (row0 < 0 || n < 0 || row0 + n > s->np) return;
+    const size_t off = (size_t)row0 * (size_t)s->ng, cnt = (size_t)n * (size_t)s->ng;
+    const size_t el = s->f64 ? sizeof(double) : sizeof(float);
+    const char *a = s->f64 ? (const char *)s->alpha_d : (const char *)s->alpha;
+    const char *b = s->f64 ? (const char *)s->beta_d : (const char *)s->beta;
+    if (alpha) memcpy(alpha, a + off * el, cnt * el);
+    if (beta) memcpy(beta, b + off * el, cnt * el);
+    if (x) memcpy(x, s->x + off, cnt);
+}
+
 void oracle_get_alleles(const oracle *s, uint8_t *x)
 {
     memcpy(x, s->x, (size_t)s->ng * (size_t)s->np);

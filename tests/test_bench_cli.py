@@ -23,10 +23,11 @@ def test_profile_figures_parse():
     import bench
     text = open(os.path.join(ROOT, bench.PROFILE)).read()
     keys = [line.strip().split(": ", 1)[0] for line in text.splitlines()
-            if line.strip().startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:"))]
-    keys += [line.strip().split(": ", 1)[0] for line in text.splitlines()
-             if line.strip().startswith("work_shape:")]
-    assert sorted(keys) == ["kernel_code_sha256", "traffic_bytes_per_launch", "work_shape"]
+            if line.strip().startswith(("traffic_bytes_per_launch_", "kernel_code_sha256:",
+                                        "work_shape_"))]
+    assert sorted(keys) == ["kernel_code_sha256", "traffic_bytes_per_launch_f32",
+                            "traffic_bytes_per_launch_f64", "work_shape_f32", "work_shape_f64"]
     for f in bench.KERNEL_SOURCES:
         assert os.path.exists(os.path.join(ROOT, f)), f
-    json.dumps({"traffic": bench.measured_traffic(4096, 200_000)})
+    json.dumps({"traffic": [bench.measured_traffic(4096, 200_000, precision=p)
+                            for p in (32, 64)]})

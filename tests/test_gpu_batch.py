@@ -111,32 +111,6 @@ def test_batch_instance_equals_instance_alone(qieo):
         assert g.best().fitness == b.best(k).fitness
 
 
-def test_ragged_batch_of_512_full_size(qieo, oracle_mod):
-    """512 instances (Ng log-uniform in [50, 20000], Np in {32..256}, seeds
-    1000..1511), 500 generations in one call; sampled instances against the
-    oracle bit for bit, every instance's best against its LP bound."""
-    insts = workloads.batch_instances()
-    say("batch of %d instances, %.3g genes per generation"
-        % (len(insts), sum(i.genes for i in insts)))
-    b = qieo.Batch(_problems(insts))
-    b.step(500)
-    order = sorted(range(len(insts)), key=lambda k: insts[k].genes)
-    sample = order[:3] + order[250:252] + order[-2:]
-    threads = min(16, os.cpu_count() or 1)
-    for k in sample:
-        i = insts[k]
-        say("  oracle for instance %d (Np=%d Ng=%d)" % (k, i.n_pop, i.n_items))
-        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed, threads=threads)
-        o.run(500)
-        assert_state_equal(View(b, k), o, label="batch512 inst %d" % k)
-    for k, i in enumerate(insts):
-        r = b.best(k)
-        assert r.generation >= 0 and r.feasible
-        assert r.fitness <= oracle_mod.knap_lp_bound(i.values, i.weights, i.capacity)
-        bits = r.alleles(i.n_items).astype(np.int64)
-        assert int(bits @ i.values.astype(np.int64)) == r.profit
-
-
 def test_long_rows_in_segment_order(qieo, oracle_mod):
     """A batch whose planes exceed 256 MB: members with rows of 8 or more
     chunks run in segment order (one launch over all their 1024-gene

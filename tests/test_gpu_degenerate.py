@@ -67,35 +67,3 @@ def test_degenerate_instances_follow_the_oracle(qieo, oracle_mod, name, persiste
         assert (f >= 0).all() and b.feasible
     if name == "all values zero":
         assert b.fitness == 0
-
-
-def test_serving_stream_through_the_server(qieo, oracle_mod):
-    reqs = workloads.serving_requests(48)
-    say("serving stream: %d requests, %.3g gene-updates"
-        % (len(reqs), sum(r.instance.genes * r.instance.generations for r in reqs)))
-    s = qieo.Server(8 << 30, gens_per_iter=25)
-    tickets = [s.submit(r.instance.values, r.instance.weights, r.instance.capacity,
-                        r.instance.n_pop, r.instance.seed, r.instance.generations)
-               for r in reqs]
-    results = [s.wait(t)[0] for t in tickets]
-    st = s.stats()
-    s.close()
-    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["peak_resident"] > 1
-    order = sorted(range(len(reqs)), key=lambda k: reqs[k].instance.genes * reqs[k].instance.generations)
-    for k in order[:5]:
-        i = reqs[k].instance
-        say("  oracle for request %d (Np=%d Ng=%d, %d generations)"
-            % (k, i.n_pop, i.n_items, i.generations))
-        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed, threads=8)
-        o.run(i.generations)
-        ob, res = o.best(), results[k]
-        assert (res.fitness, res.profit, res.weight, res.generation, res.chromosome) == \
-            (ob.fitness, ob.profit, ob.weight, ob.generation, ob.chromosome), k
-        assert np.array_equal(res.alleles(i.n_items), ob.bits), k
-    for k, r in enumerate(reqs):
-        i, res = r.instance, results[k]
-        bits = res.alleles(i.n_items).astype(np.int64)
-        assert res.feasible and 0 <= res.generation < i.generations
-        assert int(bits @ i.values.astype(np.int64)) == res.profit
-        assert int(bits @ i.weights.astype(np.int64)) == res.weight <= i.capacity
-        assert res.fitness <= oracle_mod.knap_lp_bound(i.values, i.weights, i.capacity)

@@ -1,0 +1,241 @@
+"""Parity over whole populations at the full sizes of the three large
+workloads, against the CPU oracle, bit for bit:
+
+* the HBM-bound single instance (Np 4096, Ng 200,000, seed 2), binary32 and
+  binary64 amplitudes: every chromosome's fitness, profit and weight and the
+  elite after every one of the 203 generations of the benchmark's run (3
+  warm-up + 200), the best-so-far record along the way, and at the end every
+  row's amplitudes and alleles, both for a run stepped one generation at a
+  time and for the benchmark's own calls (3, then 200 in one call);
+* the batch of 512 ragged instances after its 500 generations in one call:
+  every instance's whole state (amplitudes, alleles, fitness, elite) and
+  best record with its bits;
+* the serving stream: its first 256 requests through the continuous-batching
+  server under a budget that forces admission and retirement mid-stream,
+  with a sample stratified by work (Np x Ng x generations, every work octile,
+  the rows of 32 or more chunks that stream in segment order included)
+  against the oracle run alone, and every request against the invariants.
+
+The oracle runs row-threaded on up to 16 host threads (identical results to
+one thread, pinned by the oracle's own tests)."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import assert_state_equal, bits_equal, say
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                     else (os.cpu_count() or 1)))
+
+
+@pytest.fixture(scope="module")
+def qieo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2609_30862_amd import qieo as q
+    return q
+
+
+def _best_equal(res, ob, n_items, label):
+    assert (res.fitness, res.profit, res.weight, res.generation, res.chromosome) == \
+        (ob.fitness, ob.profit, ob.weight, ob.generation, ob.chromosome), \
+        "%s: best %r, oracle %r" % (label, res, ob)
+    assert np.array_equal(res.alleles(n_items), ob.bits), label + ": best bits"
+
+
+def _rows_equal(g, o, row0, n_rows, label):
+    s = g.export_rows(row0, n_rows)
+    a, b, x = o.rows(row0, n_rows)
+    if not (bits_equal(s["alpha"], a) and bits_equal(s["beta"], b)):
+        bad = np.argwhere((s["alpha"] != a) | (s["beta"] != b))
+        r, i = bad[0]
+        raise AssertionError("%s: amplitudes differ at row %d gene %d (%d genes)"
+                             % (label, row0 + r, i, len(bad)))
+    if not np.array_equal(s["alleles"], x):
+        bad = np.argwhere(s["alleles"] != x)
+        raise AssertionError("%s: alleles differ at row %d gene %d (%d genes)"
+                             % (label, row0 + bad[0][0], bad[0][1], len(bad)))
+
+
+@pytest.mark.timeout(1500)
+@pytest.mark.parametrize("precision", [32, 64])
+def test_large_workload_whole_population_every_generation(qieo, oracle_mod, precision):
+    inst = workloads.large_instance()
+    warm, timed = 3, inst.generations
+    G = warm + timed
+    n_pop, ng = inst.n_pop, inst.n_items
+    say("large workload, binary%d, %d generations, oracle on %d threads"
+        % (precision, G, THREADS))
+    g1 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
+                       precision=precision)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
+                          threads=THREADS, precision=precision)
+    rotating = 0
+    prev, prev_e = None, 0
+    for t in range(G):
+        g1.step(1)
+        o.run(1)
+        st = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        f_o, P_o, W_o = o.fitness()
+        assert np.array_equal(st["fitness"].astype(np.int64), f_o), "fitness, generation %d" % t
+        assert np.array_equal(st["profit"].astype(np.int64), P_o), "profit, generation %d" % t
+        assert np.array_equal(st["weight"].astype(np.int64), W_o), "weight, generation %d" % t
+        assert st["elite"] == o.elite, "elite, generation %d" % t
+        if prev is not None:
+            rotating += int((prev < prev[prev_e]).sum())
+        prev, prev_e = f_o, o.elite
+        if t % 25 == 0 or t == G - 1:
+            r, ob = g1.best(), o.best()
+            assert (r.fitness, r.profit, r.weight, r.generation, r.chromosome) == \
+                (ob.fitness, ob.profit, ob.weight, ob.generation, ob.chromosome), \
+                "best, generation %d" % t
+            say("  generation %d: elite %d fitness %d" % (t, o.elite, int(f_o[o.elite])))
+    say("  %d rotating rows over generations 1..%d" % (rotating, G - 1))
+    # the benchmark's calls: 3 generations, then 200 in one call
+    g2 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
+                       precision=precision)
+    g2.step(warm)
+    g2.step(timed)
+    assert g2.generations == G
+    block = 256
+    for label, g in (("stepped run", g1), ("benchmark's calls", g2)):
+        for r0 in range(0, n_pop, block):
+            _rows_equal(g, o, r0, min(block, n_pop - r0), "binary%d %s" % (precision, label))
+        s = g.export_rows(0, n_pop, amplitudes=False, alleles=False)
+        assert np.array_equal(s["fitness"].astype(np.int64), o.fitness()[0]) and \
+            s["elite"] == o.elite, label
+        _best_equal(g.best(), o.best(), ng, "binary%d %s" % (precision, label))
+        say("  %s: all %d rows equal the oracle" % (label, n_pop))
+    g1.close()
+    g2.close()
+
+
+class View:
+    """Instance-like view of member i of a batch (for assert_state_equal)."""
+
+    def __init__(self, b, i):
+        self.b, self.i = b, i
+        self.n_pop, self.n_items, _ = b.shapes[i]
+
+    def export_rows(self, row0=0, n_rows=None, amplitudes=True, alleles=True):
+        return self.b.export_rows(self.i, row0, n_rows, amplitudes, alleles)
+
+    def best(self):
+        return self.b.best(self.i)
+
+
+@pytest.mark.timeout(1500)
+def test_batch_of_512_every_instance(qieo, oracle_mod):
+    insts = workloads.batch_instances()
+    gens = insts[0].generations
+    say("batch of %d instances x %d generations, oracle on %d workers"
+        % (len(insts), gens, THREADS))
+    b = qieo.Batch([(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts])
+    b.step(gens)
+
+    def run(k):
+        i = insts[k]
+        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        o.run(gens)
+        return k, o
+
+    # largest first, so the pool drains evenly
+    order = sorted(range(len(insts)), key=lambda k: -insts[k].genes)
+    done = 0
+    with ThreadPoolExecutor(max_workers=THREADS) as pool:
+        for k, o in pool.map(run, order):
+            assert b.generations(k) == gens
+            assert_state_equal(View(b, k), o, label="batch instance %d" % k)
+            done += 1
+            if done % 128 == 0:
+                say("  %d of %d instances equal the oracle" % (done, len(insts)))
+    b.close()
+
+
+def _stratified_sample(reqs, budget, strata=8):
+    """Requests of every work octile: per octile its smallest, median and
+    largest request whose oracle run fits the budget, plus the largest
+    affordable requests with rows of 32 or more chunks; greedy in order of
+    work until the budget is spent."""
+    work = np.array([r.instance.genes * r.instance.generations for r in reqs], dtype=np.float64)
+    order = np.argsort(work, kind="stable")
+    pick = []
+    cap = budget / 6
+    for s in range(strata):
+        part = [k for k in order[len(order) * s // strata: len(order) * (s + 1) // strata]
+                if work[k] <= cap]
+        if part:
+            pick += [part[0], part[len(part) // 2], part[-1]]
+    long_rows = [k for k in order if reqs[k].instance.n_items > 32 * 256 and work[k] <= cap]
+    pick += long_rows[-4:] + long_rows[:2]
+    out, total = [], 0.0
+    for k in sorted(set(int(k) for k in pick), key=lambda k: work[k]):
+        if total + work[k] <= budget:
+            out.append(k)
+            total += work[k]
+    return out, total
+
+
+@pytest.mark.timeout(1500)
+def test_serving_stream_stratified_sample(qieo, oracle_mod):
+    reqs = workloads.serving_requests(256)
+    work = [r.instance.genes * r.instance.generations for r in reqs]
+    # a budget of about an eighth of the requests' total footprint: requests
+    # queue, are admitted as others retire, and run beside 10-60 others
+    footprint = sum(r.instance.n_pop * ((r.instance.n_items + 63) // 64 * 64) * 8.25
+                    for r in reqs)
+    budget = int(max(footprint / 8, 2 << 30))
+    say("serving stream: %d requests, %.3g gene-updates, budget %.2f GB"
+        % (len(reqs), sum(work), budget / 2 ** 30))
+    s = qieo.Server(budget, gens_per_iter=25)
+    tickets = [s.submit(r.instance.values, r.instance.weights, r.instance.capacity,
+                        r.instance.n_pop, r.instance.seed, r.instance.generations)
+               for r in reqs]
+    results = [s.wait(t)[0] for t in tickets]
+    st = s.stats()
+    s.close()
+    say("  served: peak %d resident, %.2f GB of the pool at most"
+        % (st["peak_resident"], st["peak_pool_used"] / 2 ** 30))
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["peak_resident"] >= 8
+    # the residents' planes exceeded the last-level cache, so the long-row
+    # residents streamed in segment order
+    assert st["peak_pool_used"] > 512 << 20
+    for k, r in enumerate(reqs):
+        i, res = r.instance, results[k]
+        bits = res.alleles(i.n_items).astype(np.int64)
+        assert res.feasible and 0 <= res.generation < i.generations, k
+        assert int(bits @ i.values.astype(np.int64)) == res.profit, k
+        assert int(bits @ i.weights.astype(np.int64)) == res.weight <= i.capacity, k
+        assert res.fitness <= oracle_mod.knap_lp_bound(i.values, i.weights, i.capacity), k
+    sample, total = _stratified_sample(reqs, budget=1.6e11)
+    long_rows = [k for k in sample if reqs[k].instance.n_items > 32 * 256]
+    say("  oracle on %d sampled requests (%d with rows of 32+ chunks), %.3g gene-updates"
+        % (len(sample), len(long_rows), total))
+    assert len(sample) >= 16 and len(long_rows) >= 4
+    assert max(work[k] for k in sample) >= 1e10           # large requests included
+    small = [k for k in sample if work[k] < 2e9]
+    large = [k for k in sample if work[k] >= 2e9]
+
+    def run(k, threads):
+        i = reqs[k].instance
+        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed, threads=threads)
+        o.run(i.generations)
+        return k, o.best()
+
+    for k in large:
+        _, ob = run(k, THREADS)
+        i = reqs[k].instance
+        _best_equal(results[k], ob, i.n_items,
+                    "request %d (Np %d, Ng %d, %d generations)" % (k, i.n_pop, i.n_items,
+                                                                  i.generations))
+    with ThreadPoolExecutor(max_workers=THREADS) as pool:
+        for k, ob in pool.map(lambda k: run(k, 1), small):
+            _best_equal(results[k], ob, reqs[k].instance.n_items, "request %d" % k)
+    say("  %d sampled requests equal the oracle" % len(sample))

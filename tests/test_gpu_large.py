@@ -1,9 +1,7 @@
-"""Parity at the full size of the largest single-instance workload
-(Np = 4096, Ng = 200,000, seed 2) in the launch configuration the benchmark
-times: every chromosome's fitness, the elite and the best-so-far record bit
-for bit at early generations (row-threaded oracle over the whole population),
-amplitudes and alleles of sampled rows, then invariants at generation 200;
-the same early checks with binary64 amplitudes."""
+"""Parity at sizes beyond the workloads: a population past 2^32 genes, rows
+of the maximum length the library accepts, and an export of more rows than
+one grid dimension holds.  (The whole-population checks of the largest
+workload are in test_gpu_full_population.py.)"""
 import os
 
 import numpy as np
@@ -14,9 +12,6 @@ from gpu_common import assert_state_equal, bits_equal, say
 
 pytestmark = pytest.mark.gpu
 
-SAMPLE_ROWS = [0, 1, 2, 3, 1000, 2047, 2048, 3333, 4092, 4093, 4094, 4095]
-
-
 @pytest.fixture(scope="module")
 def qieo():
     import torch
@@ -24,84 +19,6 @@ def qieo():
         pytest.fail("GPU test run without a visible GPU")
     from paper_2609_30862_amd import qieo as q
     return q
-
-
-def test_large_instance_full_size(qieo, oracle_mod):
-    inst = workloads.large_instance()
-    threads = min(16, os.cpu_count() or 1)
-    say("large instance %s, oracle threads %d" % (inst.name, threads))
-    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
-    say("  work shape %s" % (g.tile(),))
-    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
-                          threads=threads)
-    done = 0
-    for ck in (1, 2, 3, 5):
-        g.step(ck - done)
-        o.run(ck - done)
-        done = ck
-        say("  compare at generation %d" % ck)
-        # all rows: fitness, profit, weight (no amplitudes)
-        st = g.export_rows(0, inst.n_pop, amplitudes=False, alleles=False)
-        f_o, P_o, W_o = o.fitness()
-        assert np.array_equal(st["fitness"].astype(np.int64), f_o)
-        assert np.array_equal(st["profit"].astype(np.int64), P_o)
-        assert np.array_equal(st["weight"].astype(np.int64), W_o)
-        assert st["elite"] == o.elite
-        # sampled rows: amplitudes and alleles, plus the elite's row
-        rows = sorted(set(SAMPLE_ROWS + [o.elite]))
-        assert_state_equal(g, o, rows=rows, label="large gen %d" % ck)
-    del o
-
-    say("  run to generation %d" % inst.generations)
-    g.step(inst.generations - done)
-    assert g.generations == inst.generations
-    st = g.export_rows(0, inst.n_pop, amplitudes=False, alleles=False)
-    fit = st["fitness"].astype(np.int64)
-    assert st["elite"] == int(np.argmax(fit))            # lowest index among ties
-    v = inst.values.astype(np.int64)
-    w = inst.weights.astype(np.int64)
-    for r in SAMPLE_ROWS:
-        s = g.export_rows(r, 1)
-        x = s["alleles"][0].astype(np.int64)
-        P, W = int(x @ v), int(x @ w)
-        assert (s["profit"][0], s["weight"][0]) == (P, W)
-        assert s["fitness"][0] == (P if W <= inst.capacity else -(W - inst.capacity))
-        a = s["alpha"][0].astype(np.float64)
-        b = s["beta"][0].astype(np.float64)
-        assert np.abs(a * a + b * b - 1.0).max() <= 1e-5
-    best = g.best()
-    bits = best.alleles(inst.n_items).astype(np.int64)
-    assert int(bits @ v) == best.profit and int(bits @ w) == best.weight
-    assert best.feasible and best.fitness == best.profit
-    assert best.fitness >= int(fit.max())
-    lp = oracle_mod.knap_lp_bound(inst.values, inst.weights, inst.capacity)
-    assert best.fitness <= lp
-    say("  best %d (generation %d), LP bound %.0f" % (best.fitness, best.generation, lp))
-
-
-def test_large_instance_binary64(qieo, oracle_mod):
-    inst = workloads.large_instance()
-    threads = min(16, os.cpu_count() or 1)
-    say("large instance %s, binary64, oracle threads %d" % (inst.name, threads))
-    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
-                      precision=64)
-    say("  variant bits %d" % g.kernel_flags())
-    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
-                          threads=threads, precision=64)
-    done = 0
-    for ck in (1, 2, 4):
-        g.step(ck - done)
-        o.run(ck - done)
-        done = ck
-        say("  compare at generation %d" % ck)
-        st = g.export_rows(0, inst.n_pop, amplitudes=False, alleles=False)
-        f_o, P_o, W_o = o.fitness()
-        assert np.array_equal(st["fitness"].astype(np.int64), f_o)
-        assert np.array_equal(st["profit"].astype(np.int64), P_o)
-        assert np.array_equal(st["weight"].astype(np.int64), W_o)
-        assert st["elite"] == o.elite
-        rows = sorted(set(SAMPLE_ROWS + [o.elite]))
-        assert_state_equal(g, o, rows=rows, label="large f64 gen %d" % ck)
 
 
 def test_population_beyond_2_32_genes(qieo, oracle_mod):
@@ -163,82 +80,6 @@ def test_population_beyond_2_32_genes(qieo, oracle_mod):
         say("  generation %d: elite %d, fitness %d, %d rows checked" % (k, e, fit[e],
                                                                       len(set(sample + [e]))))
     g.close()
-
-
-@pytest.mark.parametrize("precision", [32, 64])
-def test_large_instance_sampled_rows_all_generations(qieo, oracle_mod, precision):
-    """The benchmark's run (3 generations, then 200 in one call) against a
-    run stepped one generation at a time, bit for bit; along the stepped run,
-    every generation's elite and 12 sampled rows are recomputed chromosome by
-    chromosome (oracle, 16 threads) from the GPU's elite sequence: their
-    fitness at all 203 generations, and at the end their alleles and
-    amplitudes.  Binary32 and binary64 amplitudes."""
-    from concurrent.futures import ThreadPoolExecutor
-    inst = workloads.large_instance()
-    n_pop, ng, G = inst.n_pop, inst.n_items, 3 + inst.generations
-    dt = np.float64 if precision == 64 else np.float32
-    g1 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
-                       precision=precision)
-    elites, fits = [], []
-    for k in range(G):
-        g1.step(1)
-        st = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
-        fit = st["fitness"].astype(np.int64)
-        e = int(st["elite"])
-        assert e == int(np.argmax(fit)), "generation %d" % k
-        elites.append((e, int(fit[e])))
-        fits.append(fit[SAMPLE_ROWS].copy())
-    g2 = qieo.Instance(inst.values, inst.weights, inst.capacity, n_pop, inst.seed,
-                       precision=precision)
-    g2.step(3)
-    g2.step(inst.generations)
-    s1 = g1.export_rows(0, n_pop, amplitudes=False, alleles=False)
-    s2 = g2.export_rows(0, n_pop, amplitudes=False, alleles=False)
-    assert np.array_equal(s1["fitness"], s2["fitness"]) and s1["elite"] == s2["elite"]
-    say("  %d generations, %d distinct elites" % (G, len({e for e, _ in elites})))
-
-    v = np.ascontiguousarray(inst.values, np.int32)
-    w = np.ascontiguousarray(inst.weights, np.int32)
-    tiny = oracle_mod.Oracle(inst.values[:1], inst.weights[:1], 1, 1, inst.seed,
-                             precision=precision)
-    amp0 = tiny.amplitudes()[0][0, 0]
-    del tiny
-    rows = sorted(set(SAMPLE_ROWS) | {e for e, _ in elites})
-    st = {c: {"a": np.full(ng, amp0, dt), "b": np.full(ng, amp0, dt),
-              "x": np.zeros(ng, np.uint8), "y": np.zeros(ng, np.uint8), "f": 0} for c in rows}
-    elite_x = np.zeros(ng, np.uint8)
-
-    def advance(c, t, ex, fe):
-        r = st[c]
-        below = t > 0 and r["f"] < fe
-        f, _, _ = oracle_mod.row_generation_inplace(inst.seed, t, c, v, w, inst.capacity,
-                                                    r["a"], r["b"], r["x"], ex, below, r["y"])
-        r["x"], r["y"] = r["y"], r["x"]
-        r["f"] = f
-
-    with ThreadPoolExecutor(max_workers=16) as pool:
-        for t in range(G):
-            fe = elites[t - 1][1] if t > 0 else 0
-            list(pool.map(lambda c: advance(c, t, elite_x, fe), rows))
-            e, fe_t = elites[t]
-            assert st[e]["f"] == fe_t, "elite fitness, generation %d" % t
-            for j, c in enumerate(SAMPLE_ROWS):
-                assert st[c]["f"] == fits[t][j], "generation %d row %d" % (t, c)
-            elite_x = st[e]["x"].copy()
-        # state after generation G-1 with its rotation applied, as exported
-        e, fe = elites[G - 1]
-        for c in SAMPLE_ROWS:
-            r = st[c]
-            a, b = r["a"].copy(), r["b"].copy()
-            y = np.zeros(ng, np.uint8)
-            oracle_mod.row_generation_inplace(inst.seed, G, c, v, w, inst.capacity, a, b,
-                                              r["x"], elite_x, r["f"] < fe, y)
-            s = g2.export_rows(c, 1)
-            assert np.array_equal(s["alleles"][0], r["x"]), "alleles row %d" % c
-            assert bits_equal(s["alpha"][0], a) and bits_equal(s["beta"][0], b), \
-                "amplitudes row %d" % c
-    g1.close()
-    g2.close()
 
 
 def test_rows_of_the_maximum_length(qieo, oracle_mod):

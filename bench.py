@@ -178,6 +178,22 @@ def bench_batch(args):
     genes = sum(i.genes for i in insts)
     probs = [(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
     log("batch: %d instances, %.4g genes per generation, %d generations" % (len(insts), genes, gens))
+    tuned = None
+    if args.autotune:
+        # class shapes tuned on the batch itself (its state is restored); the
+        # tuning database then gives them to every batch built below
+        b = qieo.Batch(probs)
+        t0 = time.perf_counter()
+        tuned = b.autotune(args.autotune)
+        b.close()
+        for c in tuned:
+            log("tuned class %d (%d rows, <= %d chunks): R %d S %d bits %d, %.4f ms/generation "
+                "(default R %d S %d bits %d: %.4f)"
+                % (c["shape_class"], c["rows"], c["max_chunks"], c["rows_per_block"],
+                   c["waves_per_block"], c["flags"], c["ms_per_generation"],
+                   c["default_rows_per_block"], c["default_waves_per_block"], c["default_flags"],
+                   c["default_ms_per_generation"]))
+        log("class tuning took %.1f s" % (time.perf_counter() - t0))
     variants = {}
     for name, pers, seg in (("no_persistent", False, 1), ("persistent_small", True, 1),
                             ("segment_order_32_chunk_rows_only", True, 2),
@@ -230,7 +246,8 @@ def bench_batch(args):
         log("per-instance loop (%s): %.3f s" % (mode, wall_loop))
     if args.skip_loop:
         out = {"workload": "batch", "batch_variants_seconds": variants,
-               "value": genes * gens / wall_batch, "unit": "gene-updates/s"}
+               "value": genes * gens / wall_batch, "unit": "gene-updates/s",
+               "tuned_classes": tuned}
         print(json.dumps(out), flush=True)
         return
     log("identical best records %d/%d" % (same, len(insts)))
@@ -258,6 +275,7 @@ def bench_batch(args):
         "speedup_vs_loop": wall_loop / wall_batch,
         "latency_s": latency,
         "identical_best": "%d/%d" % (same, len(insts)),
+        "tuned_classes": tuned,
     }
     print(json.dumps(out), flush=True)
 

@@ -356,18 +356,57 @@ typedef struct qieo_tune_result {
  * not above the chunks per row, x the sixteen row-order sets of variant bits
  * 0-3; plus segment order under each of its four cache-hint settings) for
  * trial_generations generations each on a scratch population of n_pop x
- * n_items (its own device memory, freed before return; items NULL =
- * unit-weight items, whose timing is the same), records the fastest in the
- * tuning database under the shape's bucket (log2 of n_pop, log2 of 256-gene
- * chunks per row) and returns it.  Later qieo_create calls whose shape falls
- * in a tuned bucket use that shape.  A shape qieo_create would reject, or
- * trial_generations outside [1, 1000], gives QIEO_EINVAL before any
- * allocation; QIEO_ENOMEM if the scratch population does not fit in device
- * memory. */
+ * n_items (its own device memory, twice the population's, freed before
+ * return; items NULL = items like the workloads': weights uniform in
+ * [1, 100], value = weight + 10, capacity half the weight sum).  Every
+ * candidate runs the same generations from the same state (a copy of the
+ * scratch population after two warm-up generations, restored before each
+ * candidate), twice, in opposite orders; the faster time counts.  Records
+ * the fastest in the tuning database under the shape's bucket (log2 of
+ * n_pop, log2 of 256-gene chunks per row) and returns it.  Later qieo_create
+ * calls whose shape falls in a tuned bucket use that shape.  A shape
+ * qieo_create would reject, or trial_generations outside [1, 1000], gives
+ * QIEO_EINVAL before any allocation; QIEO_ENOMEM if the scratch population
+ * does not fit in device memory. */
 int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item *items, int32_t capacity,
                   int32_t trial_generations, qieo_tune_result *out);
-/* Tuning database as JSON (one entry per line); load returns the number of
- * entries read (>= 0) or a negative status. */
+
+/* One launch class of a batch (members grouped by 256-gene chunks per row:
+ * class 0 = 1 chunk, 1 = 2-3, 2 = 4-7, 3 = 8-31, 4 = 32 or more; a batch
+ * whose planes exceed 256 MB runs its classes 3 and 4 together in segment
+ * order, as class 4) as timed by qieo_batch_autotune. */
+typedef struct qieo_class_tune {
+    int32_t shape_class;
+    int32_t rows;                       /* chromosomes in the class */
+    int32_t max_chunks;                 /* its longest row, in 256-gene chunks */
+    int32_t rows_per_block, waves_per_block, flags;   /* the chosen shape */
+    int32_t default_rows_per_block, default_waves_per_block, default_flags;
+    int32_t candidates;                 /* shapes timed */
+    double ms_per_generation;           /* the chosen shape's, the class alone */
+    double default_ms_per_generation;   /* the built-in rule's shape, the class alone */
+} qieo_class_tune;
+
+/* Tunes the work shape of every launch class of batch b on the batch itself:
+ * per class, row order with rows per workgroup 1/2/4 x waves per workgroup
+ * half, equal to and twice the class's default x variant bits 0-2, and for
+ * the long-row class of a batch whose planes exceed 256 MB segment order
+ * under its four cache-hint settings; each candidate runs trial_generations
+ * generations of that class alone, from the same state (the members' state
+ * is saved first and restored before every candidate and at the end: the
+ * batch's trajectory does not move), twice in opposite orders, the faster
+ * time counting.  Records each class's fastest shape in the tuning database
+ * (bucket: class, log2 of its rows, log2 of its longest row) and rebuilds
+ * the batch's classes with them; later batches and servers whose classes
+ * fall in a tuned bucket use them too.  out (may be NULL) receives up to
+ * max_out entries, *n_out (may be NULL) the number of classes.  Needs device
+ * memory for a copy of the members' state (QIEO_ENOMEM otherwise);
+ * trial_generations outside [1, 1000] gives QIEO_EINVAL.  Results of later
+ * calls are unchanged (work shapes never change results). */
+int qieo_batch_autotune(qieo_batch *b, int32_t trial_generations, qieo_class_tune *out,
+                        int32_t max_out, int32_t *n_out);
+/* Tuning database as JSON (one entry per line, single-instance buckets and
+ * batch classes); load returns the number of entries read (>= 0) or a
+ * negative status. */
 int qieo_tune_db_save(const char *path);
 int qieo_tune_db_load(const char *path);
 void qieo_tune_db_clear(void);

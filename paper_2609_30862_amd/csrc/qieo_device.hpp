@@ -95,6 +95,13 @@ __device__ __forceinline__ float sel(uint64_t m, float if0, float if1)
     return r;
 }
 
+__device__ __forceinline__ uint32_t sel(uint64_t m, uint32_t if0, uint32_t if1)
+{
+    uint32_t r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(if0), "v"(if1), "s"(uniform_mask(m)));
+    return r;
+}
+
 __device__ __forceinline__ double sel(uint64_t m, double if0, double if1)
 {
     const uint64_t a = __builtin_bit_cast(uint64_t, if0), b = __builtin_bit_cast(uint64_t, if1);
@@ -217,24 +224,33 @@ __device__ __forceinline__ uint64_t load_mask(const uint64_t* p)
 // ---------------------------------------------------------------------------
 // CIP on one gene, given as lane masks: rot = lanes whose gene must move
 // toward the elite, tgt = lanes whose elite allele is 1.  Direction: positive
-// angle raises beta^2 when alpha*beta > 0, so the sign of the step is
-// sign(alpha*beta) for target 1 and its opposite for target 0; a zero product
-// steps by +0.01 pi unless the gene already sits on the target pole.  The
-// Newton factor g = 1.5 - 0.5 n pulls the norm back to 1.
+// angle raises beta^2 when alpha*beta > 0, so the step is +0.01 pi toward 1
+// and -0.01 pi toward 0 when the product is positive, the opposite when it is
+// negative; a zero product steps by +0.01 pi unless the gene already sits on
+// the target pole (target 1 with alpha == 0, target 0 with beta == 0).  The
+// sign logic runs on the comparisons' lane masks in scalar registers; the
+// pole test is needed only when a moving lane has a zero product, which the
+// wave decides once.  The Newton factor g = 1.5 - 0.5 n pulls the norm back
+// to 1: 0.5 n is exact (a halving; a subnormal n leaves 1.5 - 0.5 n = 1.5
+// either way), so the fused g = fma(-0.5, n, 1.5) rounds once to the same
+// value as the two separately rounded operations.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ void cip_gene(T& a, T& b, uint64_t rot, uint64_t tgt)
 {
     constexpr T kC = Gate<T>::c, kS = Gate<T>::s;
     const T p = a * b;
-    const T sdp = sel(tgt, -kS, kS);          // step for p > 0
-    const T sdn = sel(tgt, kS, -kS);          // step for p < 0
-    T sd = (p > (T)0) ? sdp : kS;
-    sd = (p < (T)0) ? sdn : sd;
-    // already on the target pole: target 1 with alpha == 0, target 0 with beta == 0
-    const T pole = sel(tgt, b, a);
-    const uint64_t skip = ballot(pole == (T)0);
-    const uint64_t mv = rot & ~skip;
+    const uint64_t pos = ballot(p > (T)0), neg = ballot(p < (T)0);
+    const uint64_t minus = (pos & ~tgt) | (neg & tgt);
+    const T sd = sel(minus, kS, -kS);
+    uint64_t mv = rot;
+    if ((rot & ~(pos | neg)) != 0) {
+        const T pole = sel(tgt, b, a);
+        mv &= ~ballot(pole == (T)0);
+    }
     const T ca = kC * a;
     const T sb = sd * b;
     const T a1 = ca - sb;
@@ -244,12 +260,35 @@ __device__ __forceinline__ void cip_gene(T& a, T& b, uint64_t rot, uint64_t tgt)
     const T aa = a1 * a1;
     const T bb = b1 * b1;
     const T n = aa + bb;
-    const T hn = (T)0.5 * n;
-    const T g = (T)1.5 - hn;
+    const T g = fma_((T)-0.5, n, (T)1.5);
     const T a2 = a1 * g;
     const T b2 = b1 * g;
     a = sel(mv, a, a2);
     b = sel(mv, b, b2);
+}
+
+// The alleles of one 256-gene chunk, four 64-bit wave masks (slot j of every
+// lane), stored as eight words by lane 0 in two 16-byte stores.
+__device__ __forceinline__ void store_chunk_words(uint32_t* dst, uint64_t m0, uint64_t m1,
+                                                  uint64_t m2, uint64_t m3, int lane)
+{
+    if (lane == 0) {
+        const i32x4 lo = {(int)(uint32_t)m0, (int)(uint32_t)(m0 >> 32), (int)(uint32_t)m1,
+                          (int)(uint32_t)(m1 >> 32)};
+        const i32x4 hi = {(int)(uint32_t)m2, (int)(uint32_t)(m2 >> 32), (int)(uint32_t)m3,
+                          (int)(uint32_t)(m3 >> 32)};
+        gstore((i32x4*)dst, 0u, lo);
+        gstore((i32x4*)dst, 1u, hi);
+    }
+}
+
+// Evaluation's per-lane sum of eq. (1) over the lane's four genes: the items
+// of the genes whose allele bit is set in the masks.
+__device__ __forceinline__ uint32_t masked_sum4(uint64_t m0, uint64_t m1, uint64_t m2,
+                                                uint64_t m3, i32x4 v)
+{
+    return sel(m0, 0u, (uint32_t)v.x) + sel(m1, 0u, (uint32_t)v.y) + sel(m2, 0u, (uint32_t)v.z) +
+           sel(m3, 0u, (uint32_t)v.w);
 }
 
 // The same gate for one gene owned by one lane (chromosome-parallel mapping):

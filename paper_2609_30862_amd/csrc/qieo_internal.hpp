@@ -15,6 +15,22 @@ namespace qieo {
 
 int hip_fail(hipError_t e, const char* what);
 
+// Device memory through the caller's allocator when a qieo_dev_ctx gives
+// one, else hipMalloc / hipFree.
+struct DevMem {
+    qieo_dev_ctx ctx{};
+    bool custom = false;
+    void set(const qieo_dev_ctx* c)
+    {
+        if (c && c->alloc) {
+            ctx = *c;
+            custom = true;
+        }
+    }
+    void* alloc(size_t bytes) const;    // nullptr on failure (HIP error state cleared)
+    void release(void* p) const;        // nullptr is ignored
+};
+
 InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int32_t cap,
                    uint64_t seed);
 int upload_and_init(const InstDev& d, const qieo_item* items, hipStream_t s,
@@ -28,6 +44,8 @@ bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags);
 // Shape of a batch's launch class (class, rows of the class, longest row in
 // chunks) from the autotuner's database, if that bucket was tuned.
 bool tuned_class(int cls, int64_t rows, int32_t max_nchunk, int* R, int* S, int* flags);
+// Records the tuned shape of a batch's launch class in that database.
+void record_class(int cls, int64_t rows, int32_t max_nchunk, int R, int S, int flags, double ms);
 int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
               uint32_t* bits, size_t n_words);
 int export_rows(const InstDev& d, const InstDev* d_desc, hipStream_t s,

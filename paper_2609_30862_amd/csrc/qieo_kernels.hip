@@ -170,8 +170,17 @@ __global__ void init_kernel(InstDev I)
 // generation); the unfused pipeline runs kStepCip, kStepQip and kStepFe as
 // three launches, then DetermineElite by de_kernel or on the host.  FL is a
 // set of kFlag* bits; none of them changes a result.
+// Waves per SIMD the compiler must leave room for (register budget): with
+// one binary32 row per workgroup of 8 waves, 8 per SIMD put all 32 waves of
+// four workgroups on a CU at once, so 1024 rows run in one round on 256 CUs
+// (at 7, a quarter of the workgroups waited for a second round).  Wider
+// tiles keep the compiler's own budget (a tighter one spills registers).
+template <typename T, int R>
+constexpr int kRowWavesPerSimd = sizeof(T) == 4 && R == 1 ? 8 : 1;
+
 template <typename T, int R, int FL, int MODE>
-__global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restrict__ insts,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(kRowWavesPerSimd<T, R>))) void
+generation_kernel(const InstDev* __restrict__ insts,
                                                          const Tile* __restrict__ tiles, int k,
                                                          const int32_t* __restrict__ gens_arr,
                                                          int gens_all)
@@ -266,7 +275,8 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
 
     for (int ch = wave; ch < nchunk; ch += S) {
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
-        const bool act = g0 < (uint32_t)I.pitch;
+        // lanes inside the row (all but part of a row's last chunk)
+        const uint64_t actm = ballot(g0 < (uint32_t)I.pitch);
         const uint32_t q = g0 >> 2;          // float4 / int4 index in a row
         V4 cb[R], ca[R];
         if (PF) {
@@ -295,23 +305,29 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
             const int c = (int)row0 + r;
             V4 b4 = cb[r];
             V4 a4 = ca[r];
+            // the row's stored alleles of t-1 (scalar loads, in flight while
+            // the draws below are computed)
+            uint64_t xm0 = 0, xm1 = 0, xm2 = 0, xm3 = 0;
+            if (rot[r] && !RC) {
+                const uint64_t* xw = reinterpret_cast<const uint64_t*>(
+                    xprev + (size_t)c * wpr + ch * kWordsPerChunk);
+                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
+                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+            }
+            // the draws of generation t depend on no loaded value
+            Draw4 d{0u, 0u, 0u, 0u};
+            if (kQip) d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
             if (rot[r]) {
-                uint64_t xm0, xm1, xm2, xm3;
                 if (RC) {
                     // The stored beta is the one generation t-1 observed (its
                     // rotation is still pending), so the same draw against it
                     // gives back the alleles of t-1 bit for bit.
-                    const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u,
-                                                  I.seed_lo, I.seed_hi);
-                    xm0 = ballot(act && observe(d.r0, b4.x));
-                    xm1 = ballot(act && observe(d.r1, b4.y));
-                    xm2 = ballot(act && observe(d.r2, b4.z));
-                    xm3 = ballot(act && observe(d.r3, b4.w));
-                } else {
-                    const uint64_t* xw = reinterpret_cast<const uint64_t*>(
-                        xprev + (size_t)c * wpr + ch * kWordsPerChunk);
-                    xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
-                    xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+                    const Draw4 dp = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u,
+                                                   I.seed_lo, I.seed_hi);
+                    xm0 = ballot(observe(dp.r0, b4.x)) & actm;
+                    xm1 = ballot(observe(dp.r1, b4.y)) & actm;
+                    xm2 = ballot(observe(dp.r2, b4.z)) & actm;
+                    xm3 = ballot(observe(dp.r3, b4.w)) & actm;
                 }
                 T a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
                 T b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
@@ -322,38 +338,27 @@ __global__ __launch_bounds__(1024) void generation_kernel(const InstDev* __restr
                 a4 = V4{a0, a1, a2, a3};
                 b4 = V4{b0, b1, b2, b3};
             }
-            bool x0 = false, x1 = false, x2 = false, x3 = false;
+            uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
             if (kQip) {
-                const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo,
-                                              I.seed_hi);
-                x0 = act && observe(d.r0, b4.x);
-                x1 = act && observe(d.r1, b4.y);
-                x2 = act && observe(d.r2, b4.z);
-                x3 = act && observe(d.r3, b4.w);
-                const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
-                if (lane < kWordsPerChunk) {
-                    const int j = lane >> 1;
-                    const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
-                    const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
-                    gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
-                }
+                m0 = ballot(observe(d.r0, b4.x)) & actm;
+                m1 = ballot(observe(d.r1, b4.y)) & actm;
+                m2 = ballot(observe(d.r2, b4.z)) & actm;
+                m3 = ballot(observe(d.r3, b4.w)) & actm;
+                store_chunk_words(xcur + (size_t)c * wpr + ch * kWordsPerChunk, m0, m1, m2, m3,
+                                  lane);
             } else if (kFe) {
                 // Evaluation alone: alleles of this generation from the words
                 // the QIP launch stored
                 const uint64_t* xw =
                     reinterpret_cast<const uint64_t*>(xcur + (size_t)c * wpr + ch * kWordsPerChunk);
-                x0 = (load_mask(xw) >> lane) & 1u;
-                x1 = (load_mask(xw + 1) >> lane) & 1u;
-                x2 = (load_mask(xw + 2) >> lane) & 1u;
-                x3 = (load_mask(xw + 3) >> lane) & 1u;
+                m0 = load_mask(xw); m1 = load_mask(xw + 1);
+                m2 = load_mask(xw + 2); m3 = load_mask(xw + 3);
             }
             if (kFe) {
-                accP[r] += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
-                           (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
-                accW[r] += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
-                           (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+                accP[r] += masked_sum4(m0, m1, m2, m3, v4);
+                accW[r] += masked_sum4(m0, m1, m2, m3, w4);
             }
-            if (rot[r] && act) {
+            if (rot[r] && g0 < (uint32_t)I.pitch) {
                 if (NT) {
                     gstore_nt((V4*)arow[r], q, a4);
                     gstore_nt((V4*)brow4[r], q, b4);
@@ -506,8 +511,24 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         const int ch = seg * SC + u * SW + wave;
         if (ch >= nchunk) break;
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
-        const bool act = g0 < (uint32_t)I.pitch;
+        const uint64_t actm = ballot(g0 < (uint32_t)I.pitch);
         const uint32_t q = g0 >> 2;
+        // the elite's and the row's own alleles of t-1 (scalar loads, in
+        // flight while the draws are computed)
+        uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0, xm0 = 0, xm1 = 0, xm2 = 0, xm3 = 0;
+        if (rot) {
+            const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
+            bm0 = load_mask(bw); bm1 = load_mask(bw + 1);
+            bm2 = load_mask(bw + 2); bm3 = load_mask(bw + 3);
+            if (!RC) {
+                const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
+                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
+                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+            }
+        }
+        const i32x4 v4 = gload((const i32x4*)I.v, q);
+        const i32x4 w4 = gload((const i32x4*)I.w, q);
+        const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
         if constexpr (kStage) {
             T* sa = stage[wave][0];
             T* sb = stage[wave][1];
@@ -524,23 +545,15 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         }
         V4 bb = b4[u], aa = a4[u];
         if (rot) {
-            const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
-            const uint64_t bm0 = load_mask(bw), bm1 = load_mask(bw + 1);
-            const uint64_t bm2 = load_mask(bw + 2), bm3 = load_mask(bw + 3);
-            uint64_t xm0, xm1, xm2, xm3;
             if (RC) {
                 // the stored beta is the one generation t-1 observed, so its
                 // draws give back that generation's alleles bit for bit
                 const Draw4 dp = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u, I.seed_lo,
                                                I.seed_hi);
-                xm0 = ballot(act && observe(dp.r0, bb.x));
-                xm1 = ballot(act && observe(dp.r1, bb.y));
-                xm2 = ballot(act && observe(dp.r2, bb.z));
-                xm3 = ballot(act && observe(dp.r3, bb.w));
-            } else {
-                const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
-                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
-                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+                xm0 = ballot(observe(dp.r0, bb.x)) & actm;
+                xm1 = ballot(observe(dp.r1, bb.y)) & actm;
+                xm2 = ballot(observe(dp.r2, bb.z)) & actm;
+                xm3 = ballot(observe(dp.r3, bb.w)) & actm;
             }
             T a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
             T b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
@@ -551,24 +564,13 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
             aa = V4{a0, a1, a2, a3};
             bb = V4{b0, b1, b2, b3};
         }
-        const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
-        const bool x0 = act && observe(d.r0, bb.x);
-        const bool x1 = act && observe(d.r1, bb.y);
-        const bool x2 = act && observe(d.r2, bb.z);
-        const bool x3 = act && observe(d.r3, bb.w);
-        const uint64_t m0 = ballot(x0), m1 = ballot(x1), m2 = ballot(x2), m3 = ballot(x3);
-        if (lane < kWordsPerChunk) {
-            const int j = lane >> 1;
-            const uint64_t mm = j == 0 ? m0 : (j == 1 ? m1 : (j == 2 ? m2 : m3));
-            const uint32_t word = (lane & 1) ? (uint32_t)(mm >> 32) : (uint32_t)mm;
-            gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
-        }
-        const i32x4 v4 = gload((const i32x4*)I.v, q);
-        const i32x4 w4 = gload((const i32x4*)I.w, q);
-        accP += (x0 ? (uint32_t)v4.x : 0u) + (x1 ? (uint32_t)v4.y : 0u) +
-                (x2 ? (uint32_t)v4.z : 0u) + (x3 ? (uint32_t)v4.w : 0u);
-        accW += (x0 ? (uint32_t)w4.x : 0u) + (x1 ? (uint32_t)w4.y : 0u) +
-                (x2 ? (uint32_t)w4.z : 0u) + (x3 ? (uint32_t)w4.w : 0u);
+        const uint64_t m0 = ballot(observe(d.r0, bb.x)) & actm;
+        const uint64_t m1 = ballot(observe(d.r1, bb.y)) & actm;
+        const uint64_t m2 = ballot(observe(d.r2, bb.z)) & actm;
+        const uint64_t m3 = ballot(observe(d.r3, bb.w)) & actm;
+        store_chunk_words(xcur + (size_t)c * wpr + ch * kWordsPerChunk, m0, m1, m2, m3, lane);
+        accP += masked_sum4(m0, m1, m2, m3, v4);
+        accW += masked_sum4(m0, m1, m2, m3, w4);
         if constexpr (kStage) {
             if (rot) {
                 T* sa = stage[wave][0];
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
                     else { gstore(ar, h1, a1); gstore(br, h1, b1); }
                 }
             }
-        } else if (rot && act) {
+        } else if (rot && g0 < (uint32_t)I.pitch) {
             if (NT) {
                 gstore_nt((V4*)arow, q, aa);
                 gstore_nt((V4*)brow4, q, bb);

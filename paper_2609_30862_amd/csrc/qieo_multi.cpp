@@ -23,26 +23,14 @@ static size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
 DevicePool::~DevicePool()
 {
-    if (!base_) return;
-    if (has_alloc_) ctx_.free(base_, ctx_.user);
-    else (void)hipFree(base_);
+    mem_.release(base_);
 }
 
 int DevicePool::init(size_t bytes, const qieo_dev_ctx* ctx)
 {
     bytes = round256(std::max<size_t>(bytes, 256));
-    if (ctx && ctx->alloc) {
-        ctx_ = *ctx;
-        has_alloc_ = true;
-        base_ = (char*)ctx->alloc(bytes, ctx->user);
-    } else {
-        void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-        }
-        base_ = (char*)p;
-    }
+    mem_.set(ctx);
+    base_ = (char*)mem_.alloc(bytes);
     if (!base_) return set_error(QIEO_ENOMEM, "device pool of %zu bytes could not be allocated", bytes);
     book_.reset(bytes);
     return QIEO_OK;
@@ -68,19 +56,19 @@ Engine::~Engine()
     if (side_) (void)hipStreamSynchronize(side_);
     for (hipStream_t cs : cstreams_) (void)hipStreamSynchronize(cs);
     invalidate_graph();
-    if (d_pids_) (void)hipFree(d_pids_);
+    mem_.release(d_pids_);
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
     if (side_) (void)hipStreamDestroy(side_);
     for (hipEvent_t ev : cjoin_) (void)hipEventDestroy(ev);
     for (hipStream_t cs : cstreams_) (void)hipStreamDestroy(cs);
     for (auto& c : classes_) {
-        if (c.d_tiles) (void)hipFree(c.d_tiles);
-        if (c.d_fe_tiles) (void)hipFree(c.d_fe_tiles);
+        mem_.release(c.d_tiles);
+        mem_.release(c.d_fe_tiles);
     }
-    if (d_desc_) (void)hipFree(d_desc_);
-    if (d_gens_) (void)hipFree(d_gens_);
-    if (d_status_) (void)hipFree(d_status_);
+    mem_.release(d_desc_);
+    mem_.release(d_gens_);
+    mem_.release(d_status_);
     if (h_gens_) (void)hipHostFree(h_gens_);
 }
 
@@ -148,9 +136,15 @@ int Engine::rebuild()
 {
     invalidate_graph();
     prev_n_ = -1;
+    // the tables below are freed and replaced: no queued launch may still
+    // read them (a caller's allocator may hand their memory out again at once)
+    {
+        const hipError_t se = hipStreamSynchronize(stream_);
+        if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+    }
     for (auto& c : classes_) {
-        if (c.d_tiles) (void)hipFree(c.d_tiles);
-        if (c.d_fe_tiles) (void)hipFree(c.d_fe_tiles);
+        mem_.release(c.d_tiles);
+        mem_.release(c.d_fe_tiles);
     }
     classes_.clear();
     const size_t n = members_.size();
@@ -162,22 +156,29 @@ int Engine::rebuild()
         (void)hipGetLastError();
         return hip_fail(err, what);
     };
+    auto rebuild_nomem = [&](const char* what) {
+        (void)hipStreamSynchronize(stream_);
+        return set_error(QIEO_ENOMEM, "device allocation of the %s failed", what);
+    };
     if (n > desc_cap_) {
-        if (d_desc_) (void)hipFree(d_desc_);
-        if (d_gens_) (void)hipFree(d_gens_);
-        if (d_status_) (void)hipFree(d_status_);
+        // the tables grow to twice their size (or n); they are unusable until
+        // every allocation below has succeeded
+        const size_t cap = std::max<size_t>(n, 2 * desc_cap_);
+        mem_.release(d_desc_);
+        mem_.release(d_gens_);
+        mem_.release(d_status_);
         if (h_gens_) (void)hipHostFree(h_gens_);
         d_desc_ = nullptr;
         d_gens_ = nullptr;
         d_status_ = nullptr;
         h_gens_ = nullptr;
-        const size_t cap = std::max<size_t>(n, 2 * desc_cap_);
-        if ((e = hipMalloc(&d_desc_, cap * sizeof(InstDev))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(descriptors)");
-        if ((e = hipMalloc(&d_gens_, cap * sizeof(int32_t))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(generation counts)");
-        if ((e = hipMalloc(&d_status_, 2 * cap * sizeof(int64_t))) != hipSuccess)
-            return hip_fail(e, "hipMalloc(status)");
+        desc_cap_ = gens_cap_ = 0;
+        if (!(d_desc_ = (InstDev*)mem_.alloc(cap * sizeof(InstDev))))
+            return set_error(QIEO_ENOMEM, "device allocation of the descriptors failed");
+        if (!(d_gens_ = (int32_t*)mem_.alloc(cap * sizeof(int32_t))))
+            return set_error(QIEO_ENOMEM, "device allocation of the generation counts failed");
+        if (!(d_status_ = (int64_t*)mem_.alloc(2 * cap * sizeof(int64_t))))
+            return set_error(QIEO_ENOMEM, "device allocation of the status words failed");
         if ((e = hipHostMalloc((void**)&h_gens_, cap * sizeof(int32_t), hipHostMallocDefault)) !=
             hipSuccess)
             return hip_fail(e, "hipHostMalloc");
@@ -220,11 +221,11 @@ int Engine::rebuild()
     }
     pids_ = std::move(plan.resident);
     pids_lds_ = plan.resident_lds;
-    if (d_pids_) (void)hipFree(d_pids_);
+    mem_.release(d_pids_);
     d_pids_ = nullptr;
     if (!pids_.empty()) {
-        if ((e = hipMalloc(&d_pids_, pids_.size() * sizeof(uint32_t))) != hipSuccess)
-            return rebuild_fail(e, "hipMalloc(persistent ids)");
+        if (!(d_pids_ = (uint32_t*)mem_.alloc(pids_.size() * sizeof(uint32_t))))
+            return rebuild_nomem("persistent ids");
         if ((e = hipMemcpyAsync(d_pids_, pids_.data(), pids_.size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice, stream_)) != hipSuccess)
             return rebuild_fail(e, "hipMemcpyAsync(persistent ids)");
@@ -250,14 +251,14 @@ int Engine::rebuild()
         // at the next rebuild or in the destructor
         classes_.push_back(std::move(sc));
         ShapeClass& cc = classes_.back();
-        if ((e = hipMalloc(&cc.d_tiles, cc.tiles.size() * sizeof(Tile))) != hipSuccess)
-            return rebuild_fail(e, "hipMalloc(tiles)");
+        if (!(cc.d_tiles = (Tile*)mem_.alloc(cc.tiles.size() * sizeof(Tile))))
+            return rebuild_nomem("tiles");
         if ((e = hipMemcpyAsync(cc.d_tiles, cc.tiles.data(), cc.tiles.size() * sizeof(Tile),
                                 hipMemcpyHostToDevice, stream_)) != hipSuccess)
             return rebuild_fail(e, "hipMemcpyAsync(tiles)");
         if (!cc.fe_tiles.empty()) {
-            if ((e = hipMalloc(&cc.d_fe_tiles, cc.fe_tiles.size() * sizeof(Tile))) != hipSuccess)
-                return rebuild_fail(e, "hipMalloc(tiles)");
+            if (!(cc.d_fe_tiles = (Tile*)mem_.alloc(cc.fe_tiles.size() * sizeof(Tile))))
+                return rebuild_nomem("tiles");
             if ((e = hipMemcpyAsync(cc.d_fe_tiles, cc.fe_tiles.data(),
                                     cc.fe_tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
                                     stream_)) != hipSuccess)
@@ -431,6 +432,168 @@ int Engine::refresh_status()
     return QIEO_OK;
 }
 
+int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
+{
+    out->clear();
+    int rc = ensure_built();
+    if (rc) return rc;
+    const size_t n = members_.size();
+    if (n == 0 || classes_.empty()) return QIEO_OK;
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    // the built-in rule's classes (the shapes a tuned entry replaces)
+    std::vector<MemberShape> shapes(n);
+    for (size_t i = 0; i < n; ++i) {
+        const Member& m = members_[i];
+        shapes[i] = MemberShape{m.np, m.L.pitch, m.L.nchunk, m.L.part_nseg,
+                                (uint64_t)(uintptr_t)m.arena};
+    }
+    PlanOptions opt;
+    opt.use_persistent = use_persistent_;
+    opt.lds_limit = use_persistent_ ? resident_lds_limit() : 0;
+    opt.use_segments = use_segments_;
+    opt.merge_segments = merge_segments_;
+    BatchPlan plan;
+    if ((rc = plan_batch(shapes, opt, &plan))) return rc;
+    // every member's state, saved once, restored before each candidate and
+    // at the end
+    std::vector<size_t> off(n + 1, 0);
+    for (size_t i = 0; i < n; ++i) off[i + 1] = off[i] + (members_[i].L.total + 255) / 256 * 256;
+    char* backup = (char*)mem_.alloc(off[n]);
+    if (!backup) return set_error(QIEO_ENOMEM, "no device memory for a copy of the batch state");
+    std::vector<void*> temps;           // tile tables of the candidates
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(stream_);
+        for (void* p : temps) mem_.release(p);
+        mem_.release(backup);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        dirty_ = true;                  // the next call rebuilds with the tuned shapes
+        return code;
+    };
+    for (size_t i = 0; i < n && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(backup + off[i], members_[i].arena, members_[i].L.total,
+                           hipMemcpyDeviceToDevice, stream_);
+    for (size_t i = 0; i < n; ++i) h_gens_[i] = gens;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_gens_, h_gens_, n * sizeof(int32_t), hipMemcpyHostToDevice, stream_);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return done(hip_fail(e, "tuning set-up"));
+    auto restore = [&](const std::vector<uint32_t>& ids) {
+        hipError_t ee = hipSuccess;
+        for (uint32_t i : ids) {
+            if (ee != hipSuccess) break;
+            ee = hipMemcpyAsync(members_[i].arena, backup + off[i], members_[i].L.total,
+                                hipMemcpyDeviceToDevice, stream_);
+        }
+        return ee;
+    };
+    auto upload = [&](const std::vector<Tile>& t, Tile** d) {
+        *d = (Tile*)mem_.alloc(t.size() * sizeof(Tile));
+        if (!*d) return set_error(QIEO_ENOMEM, "device allocation of tuning tiles failed");
+        temps.push_back(*d);
+        const hipError_t ee = hipMemcpyAsync(*d, t.data(), t.size() * sizeof(Tile),
+                                             hipMemcpyHostToDevice, stream_);
+        return ee == hipSuccess ? QIEO_OK : hip_fail(ee, "hipMemcpyAsync(tiles)");
+    };
+    for (const ClassPlan& def : plan.classes) {
+        // the class's members, longest rows first (as the planner orders them)
+        std::vector<uint32_t> ids;
+        if (def.flags & kFlagSegments) {
+            for (const Tile& t : def.fe_tiles)
+                if (ids.empty() || ids.back() != t.inst) ids.push_back(t.inst);
+        } else {
+            for (const Tile& t : def.tiles)
+                if (ids.empty() || ids.back() != t.inst) ids.push_back(t.inst);
+        }
+        struct Cand {
+            int R, S, flags;
+            const Tile* tiles;
+            int n_tiles;
+            const Tile* fe;
+            int n_fe;
+            double ms;
+        };
+        std::vector<Cand> cand;
+        // row order at rows per workgroup 1, 2, 4
+        Tile* d_rows[3] = {nullptr, nullptr, nullptr};
+        int n_rows[3] = {0, 0, 0};
+        for (int ri = 0; ri < 3; ++ri) {
+            const int R = 1 << ri;
+            std::vector<Tile> t;
+            for (uint32_t i : ids)
+                for (int32_t r0 = 0; r0 < members_[i].np; r0 += R) t.push_back(Tile{i, (uint32_t)r0});
+            if ((rc = upload(t, &d_rows[ri]))) return done(rc);
+            n_rows[ri] = (int)t.size();
+        }
+        const int S0 = kClassWaves[def.cls];
+        std::vector<int> waves;
+        for (int S : {std::max(1, S0 / 2), S0, std::min(16, 2 * S0)})
+            if (std::find(waves.begin(), waves.end(), S) == waves.end()) waves.push_back(S);
+        for (int ri = 0; ri < 3; ++ri)
+            for (int S : waves)
+                for (int f = 0; f < 8; ++f)
+                    cand.push_back(Cand{1 << ri, S, f, d_rows[ri], n_rows[ri], nullptr, 0, 1e300});
+        if (def.flags & kFlagSegments) {
+            Tile *d_seg = nullptr, *d_fe = nullptr;
+            if ((rc = upload(def.tiles, &d_seg)) || (rc = upload(def.fe_tiles, &d_fe)))
+                return done(rc);
+            for (int f : {0, kFlagNontemporal, kFlagNontemporalLoads,
+                          kFlagNontemporal | kFlagNontemporalLoads})
+                cand.push_back(Cand{1, kSegWaves32, kFlagSegments | f, d_seg, (int)def.tiles.size(),
+                                    d_fe, (int)def.fe_tiles.size(), 1e300});
+        }
+        auto time_one = [&](Cand& c) {
+            hipError_t ee = restore(ids);
+            if (ee == hipSuccess) ee = hipEventRecord(e0, stream_);
+            for (int k = 0; k < gens && ee == hipSuccess; ++k)
+                ee = (c.flags & kFlagSegments)
+                         ? launch_segments_tiled(d_desc_, c.tiles, c.n_tiles, c.fe, c.n_fe,
+                                                 c.flags, k, d_gens_, stream_)
+                         : launch_generation(d_desc_, c.tiles, c.n_tiles, c.R, c.S, c.flags, k,
+                                             d_gens_, 0, stream_);
+            if (ee == hipSuccess) ee = hipEventRecord(e1, stream_);
+            if (ee == hipSuccess) ee = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (ee == hipSuccess) ee = hipEventElapsedTime(&ms, e0, e1);
+            if (ee != hipSuccess) return hip_fail(ee, "tuning launch");
+            c.ms = std::min(c.ms, (double)ms / gens);
+            return QIEO_OK;
+        };
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t j = 0; j < cand.size(); ++j)
+                if ((rc = time_one(cand[pass == 0 ? j : cand.size() - 1 - j]))) return done(rc);
+        const Cand* best = &cand[0];
+        const Cand* dflt = nullptr;
+        for (const Cand& c : cand) {
+            if (c.ms < best->ms) best = &c;
+            if (c.R == def.R && c.S == def.S && c.flags == def.flags) dflt = &c;
+        }
+        record_class(def.cls, def.rows, def.max_nchunk, best->R, best->S, best->flags, best->ms);
+        qieo_class_tune r{};
+        r.shape_class = def.cls;
+        r.rows = (int32_t)std::min<int64_t>(def.rows, INT32_MAX);
+        r.max_chunks = def.max_nchunk;
+        r.rows_per_block = best->R;
+        r.waves_per_block = best->S;
+        r.flags = best->flags;
+        r.default_rows_per_block = def.R;
+        r.default_waves_per_block = def.S;
+        r.default_flags = def.flags;
+        r.candidates = (int32_t)cand.size();
+        r.ms_per_generation = best->ms;
+        r.default_ms_per_generation = dflt ? dflt->ms : -1.0;
+        out->push_back(r);
+    }
+    // the batch's own state back, as it was before tuning
+    std::vector<uint32_t> all(n);
+    for (size_t i = 0; i < n; ++i) all[i] = (uint32_t)i;
+    if ((e = restore(all)) != hipSuccess) return done(hip_fail(e, "restore"));
+    return done(QIEO_OK);
+}
+
 int Engine::set_window_all(int32_t window)
 {
     for (auto& m : members_) {
@@ -506,7 +669,7 @@ extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qie
         batch_release(b);
         return rc;
     }
-    b->eng = new (std::nothrow) Engine(b->stream);
+    b->eng = new (std::nothrow) Engine(b->stream, ctx);
     if (!b->eng) {
         batch_release(b);
         return set_error(QIEO_ENOMEM, "host allocation failed");
@@ -655,6 +818,23 @@ extern "C" int qieo_batch_set_segment_order(qieo_batch* b, int32_t enabled)
     if (enabled < 0 || enabled > 2)
         return set_error(QIEO_EINVAL, "segment order mode must be 0, 1 or 2 (got %d)", enabled);
     b->eng->set_use_segments(enabled);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_autotune(qieo_batch* b, int32_t trial_generations,
+                                   qieo_class_tune* out, int32_t max_out, int32_t* n_out)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    if (trial_generations < 1 || trial_generations > 1000)
+        return set_error(QIEO_EINVAL, "trial_generations must be in [1, 1000] (got %d)",
+                         trial_generations);
+    if (max_out < 0 || (max_out > 0 && !out)) return set_error(QIEO_EINVAL, "bad output array");
+    std::vector<qieo_class_tune> res;
+    const int rc = b->eng->tune_classes(trial_generations, &res);
+    if (rc) return rc;
+    for (size_t i = 0; i < res.size() && (int32_t)i < max_out; ++i) out[i] = res[i];
+    if (n_out) *n_out = (int32_t)res.size();
     return QIEO_OK;
 }
 

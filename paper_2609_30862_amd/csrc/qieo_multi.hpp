@@ -29,8 +29,7 @@ public:
 
 private:
     char* base_ = nullptr;
-    qieo_dev_ctx ctx_{};
-    bool has_alloc_ = false;
+    DevMem mem_;
     OffsetAllocator book_;            // which byte ranges of the pool are in use
 };
 
@@ -62,7 +61,9 @@ struct ShapeClass {
 
 class Engine {
 public:
-    explicit Engine(hipStream_t s) : stream_(s) {}
+    // ctx: the caller's allocator (and stream) for the engine's own tables,
+    // or NULL for hipMalloc
+    Engine(hipStream_t s, const qieo_dev_ctx* ctx) : stream_(s) { mem_.set(ctx); }
     ~Engine();
 
     // Membership.  add() uploads items and initialises the state on the
@@ -100,6 +101,14 @@ public:
     // last launch (device_desc() is valid only after this).
     int ensure_built() { return dirty_ ? rebuild() : QIEO_OK; }
 
+    // Times candidate work shapes for every launch class of the current
+    // membership (gens generations each, every candidate from the same state:
+    // the members' arenas are saved first and restored after each candidate
+    // and at the end, so the batch's own trajectory does not move), records
+    // the fastest per class in the tuning database and rebuilds the classes
+    // with them.  out receives one entry per class.
+    int tune_classes(int gens, std::vector<qieo_class_tune>* out);
+
 private:
     int rebuild();               // descriptors and tile tables after membership change
     bool capture(int nmax);
@@ -107,6 +116,7 @@ private:
     void invalidate_graph();
 
     hipStream_t stream_;
+    DevMem mem_;
     std::vector<Member> members_;
     bool dirty_ = true;
     InstDev* d_desc_ = nullptr;

@@ -30,6 +30,24 @@ int hip_fail(hipError_t e, const char* what)
     return set_error(QIEO_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+void* DevMem::alloc(size_t bytes) const
+{
+    if (custom) return ctx.alloc(bytes, ctx.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void DevMem::release(void* p) const
+{
+    if (!p) return;
+    if (custom) ctx.free(p, ctx.user);
+    else (void)hipFree(p);
+}
+
 // ---------------------------------------------------------------------------
 // Device arena
 // ---------------------------------------------------------------------------
@@ -107,8 +125,7 @@ struct qieo_inst {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    qieo_dev_ctx ctx{};
-    bool has_alloc = false;
+    DevMem mem;                  // the caller's allocator, or hipMalloc
     char* arena = nullptr;
     ArenaLayout L{};
     InstDev d{};
@@ -139,24 +156,6 @@ struct qieo_inst {
     double total_ms[kStages] = {0, 0, 0, 0, 0};
 };
 
-static void* dev_alloc(qieo_inst* h, size_t bytes)
-{
-    if (h->has_alloc) return h->ctx.alloc(bytes, h->ctx.user);
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    return p;
-}
-
-static void dev_free(qieo_inst* h, void* p)
-{
-    if (!p) return;
-    if (h->has_alloc) h->ctx.free(p, h->ctx.user);
-    else (void)hipFree(p);
-}
-
 static void inst_release(qieo_inst* h)
 {
     if (!h) return;
@@ -165,8 +164,8 @@ static void inst_release(qieo_inst* h)
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     if (h->h_fit) (void)hipHostFree(h->h_fit);
     if (h->h_key) (void)hipHostFree(h->h_key);
-    dev_free(h, h->arena);
-    dev_free(h, h->d_desc);
+    h->mem.release(h->arena);
+    h->mem.release(h->d_desc);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -212,10 +211,7 @@ static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity
     qieo_inst* h = new (std::nothrow) qieo_inst();
     if (!h) return set_error(QIEO_ENOMEM, "host allocation failed");
     (void)hipGetDevice(&h->device);
-    if (ctx) {
-        h->ctx = *ctx;
-        h->has_alloc = ctx->alloc != nullptr;
-    }
+    h->mem.set(ctx);
     hipError_t e;
     if (ctx && ctx->stream) {
         h->stream = (hipStream_t)ctx->stream;
@@ -234,8 +230,8 @@ static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity
     h->items_hash = items_fnv1a(items, n_items);
     h->f64 = f64;
     arena_layout(n_items, n_pop, &h->L, f64 ? 8 : 4);
-    h->arena = (char*)dev_alloc(h, h->L.total);
-    h->d_desc = (InstDev*)dev_alloc(h, sizeof(InstDev));
+    h->arena = (char*)h->mem.alloc(h->L.total);
+    h->d_desc = h->arena ? (InstDev*)h->mem.alloc(sizeof(InstDev)) : nullptr;
     if (!h->arena || !h->d_desc) {
         inst_release(h);
         return set_error(QIEO_ENOMEM, "device allocation of %zu bytes failed", h->L.total);
@@ -572,6 +568,7 @@ struct TempDev {
     void* p = nullptr;
     explicit TempDev(size_t n)
     {
+        if (n == 0) return;
         if (hipMalloc(&p, n) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
@@ -583,8 +580,11 @@ struct TempDev {
     }
 };
 
-int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
-              uint32_t* bits, size_t n_words)
+// The best-so-far record and, if bits is not NULL, its alleles unpacked on
+// the device into `staging` (device memory of ceil(ng / 32) words; NULL: a
+// temporary allocation) and copied to the host.
+static int read_best_via(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
+                         uint32_t* bits, size_t n_words, uint32_t* staging)
 {
     const size_t need = ((size_t)d.ng + 31) / 32;
     if (bits && n_words < need)
@@ -606,15 +606,22 @@ int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* ou
     out->generation = (int64_t)(((uint64_t)(uint32_t)rec[5] << 32) | (uint32_t)rec[4]);
     out->chromosome = rec[6];
     if (!bits) return QIEO_OK;
-    TempDev tmp(need * sizeof(uint32_t));
-    if (!tmp.p) return set_error(QIEO_ENOMEM, "device allocation failed");
-    if ((e = launch_bits_unpack(d.best_bits, d.ng, (uint32_t*)tmp.p, s)) != hipSuccess)
+    TempDev tmp(staging ? 0 : need * sizeof(uint32_t));
+    uint32_t* dst = staging ? staging : (uint32_t*)tmp.p;
+    if (!dst) return set_error(QIEO_ENOMEM, "device allocation failed");
+    if ((e = launch_bits_unpack(d.best_bits, d.ng, dst, s)) != hipSuccess)
         return hip_fail(e, "bits unpack kernel");
-    if ((e = hipMemcpyAsync(bits, tmp.p, need * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
+    if ((e = hipMemcpyAsync(bits, dst, need * sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(bits)");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return QIEO_OK;
+}
+
+int read_best(const InstDev& d, int32_t capacity, hipStream_t s, qieo_result* out,
+              uint32_t* bits, size_t n_words)
+{
+    return read_best_via(d, capacity, s, out, bits, n_words, nullptr);
 }
 
 int read_generations(const InstDev& d, hipStream_t s, int64_t* t)

@@ -253,7 +253,7 @@ extern "C" int qieo_server_create(const qieo_server_cfg* cfg, const qieo_dev_ctx
         server_release(s);
         return rc;
     }
-    s->eng = new (std::nothrow) Engine(s->stream);
+    s->eng = new (std::nothrow) Engine(s->stream, ctx);
     if (!s->eng) {
         server_release(s);
         return set_error(QIEO_ENOMEM, "host allocation failed");

@@ -3,10 +3,20 @@
 // The generation kernel's speed depends on rows per workgroup R, wavefronts
 // per workgroup S and the variant flags, never its results.  The tuner times
 // every candidate on a scratch population of the caller's shape (its own
-// arena, the caller's item tables copied device to device, the caller's
-// trajectory untouched), picks the fastest, and records it under the shape's
-// bucket (log2 of rows, log2 of 256-gene chunks per row).  qieo_create
-// consults the database before falling back to the built-in rule.
+// arena; the caller's trajectory untouched), picks the fastest, and records
+// it under the shape's bucket (log2 of rows, log2 of 256-gene chunks per
+// row).  qieo_create consults the database before falling back to the
+// built-in rule.  Every candidate starts from the same state (a device copy
+// of the scratch arena taken after two warm-up generations) and runs the
+// same generations, so each does the same work: later candidates are not
+// timed on a more converged population, whose rows tied with the elite skip
+// the rotation.  Candidates are timed twice, in opposite orders, and keep
+// the faster time.
+//
+// The same database holds batch launch classes (shape class, log2 of the
+// class's rows, log2 of its longest row in chunks), filled by
+// qieo_batch_autotune and consulted when a batch or server engine builds
+// its classes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +26,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/qieo.h"
@@ -30,8 +41,12 @@ struct Entry {
     double ms;
 };
 
+// key: {kind, a, b, c}: kind 0 = single instance {log2 rows, log2 chunks, 0};
+// kind 1 = batch class {class, log2 rows, log2 longest row in chunks}
+using Key = std::tuple<int, int, int, int>;
+
 std::mutex g_db_mu;
-std::map<std::pair<int, int>, Entry> g_db;
+std::map<Key, Entry> g_db;
 
 int ilog2(int64_t x)
 {
@@ -43,14 +58,19 @@ int ilog2(int64_t x)
     return r;
 }
 
-std::pair<int, int> bucket(int32_t np, int32_t nchunk) { return {ilog2(np), ilog2(nchunk)}; }
+Key instance_key(int32_t np, int32_t nchunk) { return Key{0, ilog2(np), ilog2(nchunk), 0}; }
+
+Key class_key(int cls, int64_t rows, int32_t max_nchunk)
+{
+    return Key{1, cls, ilog2(rows), ilog2(max_nchunk)};
+}
 
 }  // namespace
 
 bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
 {
     std::lock_guard<std::mutex> lk(g_db_mu);
-    auto it = g_db.find(bucket(np, nchunk));
+    auto it = g_db.find(instance_key(np, nchunk));
     if (it == g_db.end()) return false;
     *R = it->second.R;
     *S = std::min(it->second.S, std::max(1, (int)nchunk));
@@ -60,8 +80,35 @@ bool tuned_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags)
 
 bool tuned_class(int cls, int64_t rows, int32_t max_nchunk, int* R, int* S, int* flags)
 {
-    (void)cls; (void)rows; (void)max_nchunk; (void)R; (void)S; (void)flags;
-    return false;
+    std::lock_guard<std::mutex> lk(g_db_mu);
+    auto it = g_db.find(class_key(cls, rows, max_nchunk));
+    if (it == g_db.end()) return false;
+    *R = it->second.R;
+    *S = it->second.S;
+    *flags = it->second.flags;
+    return true;
+}
+
+void record_class(int cls, int64_t rows, int32_t max_nchunk, int R, int S, int flags, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_db_mu);
+    g_db[class_key(cls, rows, max_nchunk)] = Entry{R, S, flags, ms};
+}
+
+// Items like the workloads' correlated ones: weights uniform in [1, 100]
+// (a 64-bit LCG), value = weight + 10, capacity half the weight sum.
+void synthetic_items(int32_t n, std::vector<qieo_item>* items, int32_t* capacity)
+{
+    items->resize((size_t)n);
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    int64_t sum = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        const int32_t w = 1 + (int32_t)((x >> 33) % 100);
+        (*items)[(size_t)i] = qieo_item{w + 10, w};
+        sum += w;
+    }
+    *capacity = (int32_t)(sum / 2);
 }
 
 }  // namespace qieo
@@ -83,15 +130,14 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
     if (rc) return rc;
     std::vector<qieo_item> synth;
     if (!items) {
-        // timing does not depend on the item values: a unit-weight instance
-        synth.assign((size_t)n_items, qieo_item{1, 1});
+        synthetic_items(n_items, &synth, &capacity);
         items = synth.data();
-        capacity = n_items / 2;
     }
     if ((rc = validate_problem(items, n_items, capacity, n_pop))) return rc;
     ArenaLayout L;
     arena_layout(n_items, n_pop, &L);
     char* arena = nullptr;
+    char* backup = nullptr;
     InstDev* d_desc = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -101,6 +147,7 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (arena) (void)hipFree(arena);
+        if (backup) (void)hipFree(backup);
         if (d_desc) (void)hipFree(d_desc);
         if (s) (void)hipStreamDestroy(s);
     };
@@ -111,10 +158,11 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
         return rc;
     }
     if (hipMalloc((void**)&arena, L.total) != hipSuccess ||
+        hipMalloc((void**)&backup, L.total) != hipSuccess ||
         hipMalloc((void**)&d_desc, sizeof(InstDev)) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
-        return set_error(QIEO_ENOMEM, "scratch population of %zu bytes does not fit", L.total);
+        return set_error(QIEO_ENOMEM, "scratch population of 2 x %zu bytes does not fit", L.total);
     }
     InstDev d = bind_arena(arena, L, n_items, n_pop, capacity, 0x7475ull);
     std::vector<int32_t> staging;
@@ -133,55 +181,70 @@ extern "C" int qieo_autotune(int32_t n_items, int32_t n_pop, const qieo_item* it
     for (int R : {1, 2, 4})
         for (int S : {2, 4, 8, 16}) {
             if (S > std::max(2, L.nchunk) && S != 2) continue;
-            for (int f = 0; f < kFlagSegments; ++f) cand.push_back(Entry{R, S, f, 0.0});
+            for (int f = 0; f < kFlagSegments; ++f) cand.push_back(Entry{R, S, f, 1e300});
         }
     // segment order: the work shape does not apply, only the cache hints
     for (int f : {0, kFlagNontemporal, kFlagNontemporalLoads, kFlagNontemporal | kFlagNontemporalLoads})
-        cand.push_back(Entry{1, kSegWaves32, kFlagSegments | f, 0.0});
-    // one generation of warm-up (generation 0 reads beta only), then trials
-    auto run = [&](const Entry& c, int gens, double* ms) -> int {
+        cand.push_back(Entry{1, kSegWaves32, kFlagSegments | f, 1e300});
+    // gens launches of candidate c from generation tbase
+    auto launch = [&](const Entry& c, int gens) -> hipError_t {
         const int blocks = (n_pop + c.R - 1) / c.R;
-        hipError_t ee = hipEventRecord(e0, s);
+        hipError_t ee = hipSuccess;
         for (int k = 0; k < gens && ee == hipSuccess; ++k)
             ee = (c.flags & kFlagSegments)
-                     ? launch_segments(d_desc, n_pop, L.nchunk, L.part_nseg, c.flags, k, gens, false, s)
+                     ? launch_segments(d_desc, n_pop, L.nchunk, L.part_nseg, c.flags, k, gens,
+                                       false, s)
                      : launch_generation(d_desc, nullptr, blocks, c.R, c.S, c.flags, k, nullptr,
                                          gens, s);
-        if (ee == hipSuccess) ee = launch_finish(d_desc, 1, nullptr, gens, nullptr, s);
+        return ee;
+    };
+    // two warm-up generations, then the state every candidate starts from
+    e = launch(cand[0], 2);
+    if (e == hipSuccess) e = launch_finish(d_desc, 1, nullptr, 2, nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(backup, arena, L.total, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "tuning warm-up");
+        cleanup();
+        return rc;
+    }
+    auto time_one = [&](Entry& c) -> int {
+        hipError_t ee = hipMemcpyAsync(arena, backup, L.total, hipMemcpyDeviceToDevice, s);
+        if (ee == hipSuccess) ee = hipEventRecord(e0, s);
+        if (ee == hipSuccess) ee = launch(c, trial_generations);
         if (ee == hipSuccess) ee = hipEventRecord(e1, s);
         if (ee == hipSuccess) ee = hipEventSynchronize(e1);
         float f = 0.f;
         if (ee == hipSuccess) ee = hipEventElapsedTime(&f, e0, e1);
         if (ee != hipSuccess) return hip_fail(ee, "tuning launch");
-        *ms = f;
+        c.ms = std::min(c.ms, (double)f / trial_generations);
         return QIEO_OK;
     };
-    double tmp;
-    if ((rc = run(cand[0], 1, &tmp))) {
-        cleanup();
-        return rc;
-    }
-    Entry best{0, 0, 0, 1e300};
-    for (auto& c : cand) {
-        if ((rc = run(c, trial_generations, &c.ms))) {
-            cleanup();
-            return rc;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t j = 0; j < cand.size(); ++j) {
+            Entry& c = cand[pass == 0 ? j : cand.size() - 1 - j];
+            if ((rc = time_one(c))) {
+                cleanup();
+                return rc;
+            }
         }
-        c.ms /= trial_generations;
-        if (c.ms < best.ms) best = c;
     }
     cleanup();
+    Entry best{0, 0, 0, 1e300};
+    double worst = 0.0;
+    for (auto& c : cand) {
+        if (c.ms < best.ms) best = c;
+        worst = std::max(worst, c.ms);
+    }
     {
         std::lock_guard<std::mutex> lk(g_db_mu);
-        g_db[bucket(n_pop, L.nchunk)] = best;
+        g_db[instance_key(n_pop, L.nchunk)] = best;
     }
     if (out) {
         out->rows_per_block = best.R;
         out->waves_per_block = best.S;
         out->flags = best.flags;
         out->ms_per_generation = best.ms;
-        double worst = 0.0;
-        for (auto& c : cand) worst = std::max(worst, c.ms);
         out->worst_ms_per_generation = worst;
         out->candidates = (int32_t)cand.size();
     }
@@ -198,10 +261,18 @@ extern "C" int qieo_tune_db_save(const char* path)
     std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
     bool first = true;
     for (auto& kv : g_db) {
-        std::fprintf(f, "%s\n  {\"np_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, \"S\": %d, "
-                        "\"flags\": %d, \"ms\": %.6f}",
-                     first ? "" : ",", kv.first.first, kv.first.second, kv.second.R, kv.second.S,
-                     kv.second.flags, kv.second.ms);
+        int kind, a, b, c;
+        std::tie(kind, a, b, c) = kv.first;
+        if (kind == 0)
+            std::fprintf(f, "%s\n  {\"np_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, \"S\": %d, "
+                            "\"flags\": %d, \"ms\": %.6f}",
+                         first ? "" : ",", a, b, kv.second.R, kv.second.S, kv.second.flags,
+                         kv.second.ms);
+        else
+            std::fprintf(f, "%s\n  {\"class\": %d, \"rows_log2\": %d, \"nchunk_log2\": %d, "
+                            "\"R\": %d, \"S\": %d, \"flags\": %d, \"ms\": %.6f}",
+                         first ? "" : ",", a, b, c, kv.second.R, kv.second.S, kv.second.flags,
+                         kv.second.ms);
         first = false;
     }
     std::fprintf(f, "\n]}\n");
@@ -218,17 +289,29 @@ extern "C" int qieo_tune_db_load(const char* path)
     if (!f) return set_error(QIEO_EINVAL, "cannot read %s", path);
     char line[512];
     int n = 0;
-    std::map<std::pair<int, int>, Entry> loaded;
+    std::map<Key, Entry> loaded;
     while (std::fgets(line, sizeof line, f)) {
-        int a, b, R, S, fl;
+        int a, b, c = 0, R, S, fl;
         double ms;
-        const char* p = std::strstr(line, "\"np_log2\"");
-        if (!p) continue;
-        if (std::sscanf(p, "\"np_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, \"S\": %d, "
-                           "\"flags\": %d, \"ms\": %lf", &a, &b, &R, &S, &fl, &ms) != 6)
+        Key key;
+        const char* p;
+        if ((p = std::strstr(line, "\"np_log2\""))) {
+            if (std::sscanf(p, "\"np_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, \"S\": %d, "
+                               "\"flags\": %d, \"ms\": %lf", &a, &b, &R, &S, &fl, &ms) != 6)
+                continue;
+            key = Key{0, a, b, 0};
+        } else if ((p = std::strstr(line, "\"class\""))) {
+            if (std::sscanf(p, "\"class\": %d, \"rows_log2\": %d, \"nchunk_log2\": %d, \"R\": %d, "
+                               "\"S\": %d, \"flags\": %d, \"ms\": %lf",
+                            &a, &b, &c, &R, &S, &fl, &ms) != 7)
+                continue;
+            if (a < 0 || a >= kClasses) continue;
+            key = Key{1, a, b, c};
+        } else {
             continue;
+        }
         if ((R != 1 && R != 2 && R != 4) || S < 1 || S > 16 || fl < 0 || fl > kFlagAll) continue;
-        loaded[{a, b}] = Entry{R, S, fl, ms};
+        loaded[key] = Entry{R, S, fl, ms};
         ++n;
     }
     std::fclose(f);

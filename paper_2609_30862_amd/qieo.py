@@ -75,6 +75,16 @@ class qieo_tune_result(ctypes.Structure):
                 ("worst_ms_per_generation", ctypes.c_double)]
 
 
+class qieo_class_tune(ctypes.Structure):
+    _fields_ = [("shape_class", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("max_chunks", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("default_rows_per_block", ctypes.c_int32),
+                ("default_waves_per_block", ctypes.c_int32), ("default_flags", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("ms_per_generation", ctypes.c_double),
+                ("default_ms_per_generation", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -82,6 +92,31 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class qieo_dev_ctx(ctypes.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p)]
+
+
+class DeviceContext:
+    """A caller's device allocator and stream for a handle (qieo_dev_ctx).
+
+    alloc(nbytes) -> device pointer as an int (0 when it cannot allocate) and
+    free(ptr) replace hipMalloc / hipFree for the handle's device memory
+    (both or neither); stream is a hipStream_t (int) on which the handle
+    orders all its work, or None.  The object keeps the C callbacks alive
+    and must outlive every handle created with it."""
+
+    def __init__(self, alloc=None, free=None, stream: int | None = None):
+        if (alloc is None) != (free is None):
+            raise ValueError("alloc and free go together")
+        self._alloc = ALLOC_FN(lambda n, user: alloc(int(n)) or None) if alloc else ALLOC_FN(0)
+        self._free = FREE_FN(lambda p, user: free(int(p))) if free else FREE_FN(0)
+        self.struct = qieo_dev_ctx(self._alloc, self._free, None,
+                                   ctypes.c_void_p(stream) if stream else None)
+
+
+def _ctx_ref(ctx: DeviceContext | None, stream: int | None):
+    """(reference to a qieo_dev_ctx or None, object to keep alive)."""
+    if ctx is None and stream is not None:
+        ctx = DeviceContext(stream=stream)
+    return (ctypes.byref(ctx.struct) if ctx is not None else None), ctx
 
 
 def _load():
@@ -186,6 +221,9 @@ def _load():
     L.qieo_batch_set_persistent.argtypes = [H, i32]
     L.qieo_batch_set_segment_order.restype = ctypes.c_int
     L.qieo_batch_set_segment_order.argtypes = [H, i32]
+    L.qieo_batch_autotune.restype = ctypes.c_int
+    L.qieo_batch_autotune.argtypes = [H, ctypes.c_int32, ctypes.POINTER(qieo_class_tune),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.qieo_batch_set_graph.restype = ctypes.c_int
     L.qieo_batch_set_graph.argtypes = [H, i32]
     L.qieo_batch_destroy.restype = None
@@ -274,23 +312,20 @@ def qieo_tune_db_clear():
 
 
 def qieo_create(items: np.ndarray, n_items: int, capacity: int, n_pop: int, seed: int,
-                stream: int | None = None, precision: int = 32):
+                stream: int | None = None, precision: int = 32,
+                ctx: DeviceContext | None = None):
     """items: int32 array [n_items, 2] of (profit, weight).  Returns a handle."""
     h = ctypes.c_void_p()
+    ref, _ = _ctx_ref(ctx, stream)
     if precision == 64:
-        ctx = None
-        if stream is not None:
-            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
-                                            ctypes.c_void_p(stream)))
-        rc = lib.qieo_create_f64(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1), ctx,
+        rc = lib.qieo_create_f64(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1), ref,
                                  ctypes.byref(h))
-    elif stream is None:
+    elif ref is None:
         rc = lib.qieo_create(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1),
                              ctypes.byref(h))
     else:
-        ctx = qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None, ctypes.c_void_p(stream))
         rc = lib.qieo_create_ex(_ptr(items), n_items, capacity, n_pop, seed & (2**64 - 1),
-                                ctypes.byref(ctx), ctypes.byref(h))
+                                ref, ctypes.byref(h))
     _check(rc, "qieo_create")
     return h
 
@@ -348,15 +383,17 @@ class Instance:
     """One resident QIEO population (owner of a libqieo handle)."""
 
     def __init__(self, values, weights, capacity: int, n_pop: int, seed: int,
-                 stream: int | None = None, precision: int = 32):
+                 stream: int | None = None, precision: int = 32,
+                 ctx: DeviceContext | None = None):
         self.items = items_array(values, weights)
         self.n_items = int(self.items.shape[0])
         self.n_pop = int(n_pop)
         self.capacity = int(capacity)
         self.seed = int(seed)
         self.precision = int(precision)
+        self._ctx = ctx
         self._h = qieo_create(self.items, self.n_items, self.capacity, self.n_pop, self.seed,
-                              stream, self.precision)
+                              stream, self.precision, ctx)
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -502,7 +539,7 @@ def _export(fn, n_items, n_pop, row0, n_rows, amplitudes, alleles, where):
 class Batch:
     """Many resident populations advanced together (qieo_batch_*)."""
 
-    def __init__(self, problems, stream: int | None = None):
+    def __init__(self, problems, stream: int | None = None, ctx: DeviceContext | None = None):
         """problems: iterable of (values, weights, capacity, n_pop, seed)."""
         self._items = []
         arr = (qieo_problem * len(problems))()
@@ -514,11 +551,8 @@ class Batch:
                                   int(seed) & (2**64 - 1))
             self.shapes.append((int(n_pop), int(it.shape[0]), int(cap)))
         h = ctypes.c_void_p()
-        ctx = None
-        if stream is not None:
-            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
-                                            ctypes.c_void_p(stream)))
-        _check(lib.qieo_batch_create(arr, len(problems), ctx, ctypes.byref(h)),
+        ref, self._ctx = _ctx_ref(ctx, stream)
+        _check(lib.qieo_batch_create(arr, len(problems), ref, ctypes.byref(h)),
                "qieo_batch_create")
         self._h = h
         self.n = len(problems)
@@ -577,6 +611,16 @@ class Batch:
     def set_graph(self, enabled: bool):
         _check(lib.qieo_batch_set_graph(self._h, int(bool(enabled))), "qieo_batch_set_graph")
 
+    def autotune(self, trial_generations: int = 5) -> list:
+        """qieo_batch_autotune: the tuned shape of every launch class (dicts)."""
+        out = (qieo_class_tune * 8)()
+        n = ctypes.c_int32()
+        _check(lib.qieo_batch_autotune(self._h, int(trial_generations), out, 8, ctypes.byref(n)),
+               "qieo_batch_autotune")
+        return [{name: getattr(out[k], name) for name, _ in qieo_class_tune._fields_}
+                for k in range(min(n.value, 8))]
+
+
     def set_convergence(self, window: int):
         _check(lib.qieo_batch_set_convergence(self._h, int(window)), "qieo_batch_set_convergence")
 
@@ -602,15 +646,13 @@ class Server:
     """Continuous-batching request server (qieo_server_*)."""
 
     def __init__(self, hbm_budget_bytes: int, max_resident: int = 0, gens_per_iter: int = 0,
-                 convergence_window: int = 0, stream: int | None = None):
+                 convergence_window: int = 0, stream: int | None = None,
+                 ctx: DeviceContext | None = None):
         cfg = qieo_server_cfg(int(hbm_budget_bytes), int(max_resident), int(gens_per_iter),
                               int(convergence_window))
         h = ctypes.c_void_p()
-        ctx = None
-        if stream is not None:
-            ctx = ctypes.byref(qieo_dev_ctx(ALLOC_FN(0), FREE_FN(0), None,
-                                            ctypes.c_void_p(stream)))
-        _check(lib.qieo_server_create(ctypes.byref(cfg), ctx, ctypes.byref(h)),
+        ref, self._ctx = _ctx_ref(ctx, stream)
+        _check(lib.qieo_server_create(ctypes.byref(cfg), ref, ctypes.byref(h)),
                "qieo_server_create")
         self._h = h
         self._n_items = {}

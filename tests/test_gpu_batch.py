@@ -162,3 +162,44 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     seg.close()
     seg32.close()
     row.close()
+
+
+def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_mod):
+    """Class tuning runs candidates on the batch itself and restores its
+    state: after tuning (and with the tuned shapes afterwards) every member
+    follows the same trajectory as an untuned batch and as the oracle."""
+    insts = _ragged_instances()
+    probs = _problems(insts)
+    ref = qieo.Batch(probs)
+    b = qieo.Batch(probs)
+    n = len(insts)
+    gens = [k % 4 + 1 for k in range(n)]
+    ref.step(gens)
+    b.step(gens)
+    try:
+        classes = b.autotune(3)
+        say("tuned classes: %s" % [(c["shape_class"], c["rows_per_block"], c["waves_per_block"],
+                                    c["flags"], round(c["ms_per_generation"], 4)) for c in classes])
+        assert classes and all(c["candidates"] >= 24 for c in classes)
+        assert len({c["shape_class"] for c in classes}) == len(classes)
+        for k in range(n):                      # tuning left the state as it was
+            a, c = ref.export_rows(k), b.export_rows(k)
+            for key in ("alpha", "beta", "alleles", "fitness"):
+                assert np.array_equal(a[key], c[key]), (k, key)
+        for g in ([3] * n, [5] * n, [5] * n):    # tuned shapes from here on, then a replay
+            ref.step(g)
+            b.step(g)
+        for k in range(n):
+            a, c = ref.export_rows(k), b.export_rows(k)
+            for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+                assert np.array_equal(a[key], c[key]), (k, key)
+        for k in (0, 6, 13):
+            i = insts[k]
+            o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+            o.run(gens[k] + 13)
+            assert_state_equal(View(b, k), o, label="tuned batch member %d" % k)
+    finally:
+        qieo.qieo_tune_db_clear()
+        ref.close()
+        b.close()
+

@@ -1,22 +1,82 @@
 """Pins of the oracle's binary64 variant (the paper's precision, Sec. V)."""
 import math
+import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
 
 import workloads
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-def test_binary64_constants_are_the_correctly_rounded_values(oracle_mod):
-    # correctly rounded binary64 values of cos(pi/100), sin(pi/100), 1/sqrt(2)
-    # (computed to 60 digits with Machin's pi and Taylor series); libm agrees
-    # on the first two
-    assert float.fromhex("0x1.ffbf52e9d1086p-1") == math.cos(0.01 * math.pi)
-    assert float.fromhex("0x1.015122df75860p-5") == math.sin(0.01 * math.pi)
-    from fractions import Fraction
-    x = Fraction(float.fromhex("0x1.6a09e667f3bcdp-1"))
-    half_ulp = Fraction(1, 2 ** 54)            # ulp of [0.5, 1) is 2^-53
-    assert (x - half_ulp) ** 2 < Fraction(1, 2) < (x + half_ulp) ** 2
+
+def _pi(digits):
+    """pi to `digits` decimals by Machin's formula, pi = 16 atan(1/5) - 4 atan(1/239),
+    in integer fixed point (truncation error below 10^-(digits - 5))."""
+    scale = 10 ** (digits + 10)
+
+    def atan_inv(n):
+        term = scale // n
+        total, k, sign = 0, 1, 1
+        while term:
+            total += sign * (term // k)
+            term //= n * n
+            k += 2
+            sign = -sign
+        return total
+
+    return Fraction(16 * atan_inv(5) - 4 * atan_inv(239), scale)
+
+
+def _cos_sin(x, terms=40):
+    """cos x and sin x by their Taylor series, exactly in rationals (|x| < 0.1:
+    the first omitted term is below 10^-100)."""
+    c, s_, term = Fraction(0), Fraction(0), Fraction(1)
+    for k in range(2 * terms):
+        if k % 2 == 0:
+            c += term if (k // 2) % 2 == 0 else -term
+        else:
+            s_ += term if (k // 2) % 2 == 0 else -term
+        term = term * x / (k + 1)
+    return c, s_
+
+
+def _correctly_rounded(value, x, precision_bits, margin=Fraction(1, 10 ** 80)):
+    """x is the float of `precision_bits` significand bits nearest `value`
+    (strictly within half an ulp, by more than the error of `value`)."""
+    _, e = math.frexp(x)                    # x = m 2^e, 0.5 <= m < 1
+    half_ulp = Fraction(2) ** (e - precision_bits - 1)
+    return abs(Fraction(x) - value) + margin < half_ulp
+
+
+def test_gate_constants_are_the_correctly_rounded_values():
+    """The oracle's rotation constants, binary32 and binary64, are the values
+    of cos(pi/100), sin(pi/100) and 1/sqrt(2) rounded to nearest in their
+    precision, checked against 90-digit values of the functions (pi from
+    Machin's formula, cos and sin from their Taylor series, 1/sqrt(2) by
+    squaring): a half-ulp test with rationals, no libm involved."""
+    import re
+    src = open(os.path.join(ROOT, "oracle", "qieo_oracle.c")).read()
+    const = dict(re.findall(r"#define (ROT_C|ROT_S|AMP0|ROT_C64|ROT_S64|AMP0_64)\s+(\S+)", src))
+    assert set(const) == {"ROT_C", "ROT_S", "AMP0", "ROT_C64", "ROT_S64", "AMP0_64"}
+    f32 = {k: float.fromhex(v.rstrip("f")) for k, v in const.items() if not k.endswith("64")}
+    f64 = {k[:-3] if k.endswith("_64") else k[:-2]: float.fromhex(v)
+           for k, v in const.items() if k.endswith("64")}
+    for v in f32.values():                   # exactly representable in binary32
+        assert float(np.float32(v)) == v
+    c, s_ = _cos_sin(_pi(90) / 100)
+    assert abs(c * c + s_ * s_ - 1) < Fraction(1, 10 ** 85)
+    for name, x, bits in (("cos", f32["ROT_C"], 24), ("sin", f32["ROT_S"], 24),
+                          ("cos", f64["ROT_C"], 53), ("sin", f64["ROT_S"], 53)):
+        assert _correctly_rounded(c if name == "cos" else s_, x, bits), (name, bits, x.hex())
+    # 1/sqrt(2): x is the nearest float iff (x -+ half ulp)^2 bracket 1/2
+    for x, bits in ((f32["AMP0"], 24), (f64["AMP0"], 53)):
+        _, e = math.frexp(x)
+        h = Fraction(2) ** (e - bits - 1)
+        assert (Fraction(x) - h) ** 2 < Fraction(1, 2) < (Fraction(x) + h) ** 2, bits
+    # the constants move angles by 0.01 pi: atan2(S, C) within an ulp of pi/100
+    assert abs(math.atan2(f64["ROT_S"], f64["ROT_C"]) - math.pi / 100) < 1e-17
 
 
 def test_f64_closed_form_angle_tracking(oracle_mod):

@@ -57,6 +57,11 @@ __device__ __forceinline__ void philox_round(uint32_t& x0, uint32_t& x1, uint32_
 __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1)
 {
+    // The round keys are two scalar adds each; left loop-invariant, the
+    // compiler would keep all twenty in scalar registers across a kernel's
+    // chunk loop (and spill them once registers are tight), so the key is
+    // passed through an empty asm here, which makes each call derive its own.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         philox_round(c0, c1, c2, c3, k0, k1);
@@ -64,6 +69,15 @@ __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         k1 += 0xBB67AE85u;
     }
     return Draw4{c0, c1, c2, c3};
+}
+
+// Keeps a chunk's draws where they are computed: an empty asm that uses
+// them, so the compiler issues the Philox arithmetic before the code that
+// follows (the rotation, which first waits for the allele masks' scalar
+// loads) instead of sinking it down to the observation that reads it.
+__device__ __forceinline__ void pin_draws(const Draw4& d)
+{
+    asm volatile("" ::"v"(d.r0), "v"(d.r1), "v"(d.r2), "v"(d.r3));
 }
 
 // Observation of one qubit: 1 iff the 24-bit uniform of r lies below beta^2
@@ -265,6 +279,53 @@ __device__ __forceinline__ void cip_gene(T& a, T& b, uint64_t rot, uint64_t tgt)
     const T b2 = b1 * g;
     a = sel(mv, a, a2);
     b = sel(mv, b, b2);
+}
+
+// CIP on a lane's four genes (slot j of the chunk in component j): the same
+// gate as cip_gene, arranged so that one chunk is one straight run of code.
+// The sign logic of all four genes comes first; the pole test (a moving lane
+// with a zero product) is one branch for the whole chunk, almost never
+// taken; then the four rotations.  A wave whose masks are all zero (a row
+// that does not rotate) computes the rotations and keeps the old values.
+template <typename V4, typename T>
+__device__ __forceinline__ void cip_chunk(V4& a4, V4& b4, const uint64_t rot[4],
+                                          const uint64_t tgt[4])
+{
+    constexpr T kC = Gate<T>::c, kS = Gate<T>::s;
+    T a[4] = {a4.x, a4.y, a4.z, a4.w};
+    T b[4] = {b4.x, b4.y, b4.z, b4.w};
+    T sd[4];
+    uint64_t mv[4];
+    uint64_t zero = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const T p = a[j] * b[j];
+        const uint64_t pos = ballot(p > (T)0), neg = ballot(p < (T)0);
+        sd[j] = sel((pos & ~tgt[j]) | (neg & tgt[j]), kS, -kS);
+        mv[j] = rot[j];
+        zero |= rot[j] & ~(pos | neg);
+    }
+    if (zero != 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mv[j] &= ~ballot(sel(tgt[j], b[j], a[j]) == (T)0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const T ca = kC * a[j];
+        const T sb = sd[j] * b[j];
+        const T a1 = ca - sb;
+        const T sa = sd[j] * a[j];
+        const T cb = kC * b[j];
+        const T b1 = sa + cb;
+        const T aa = a1 * a1;
+        const T bb = b1 * b1;
+        const T n = aa + bb;
+        const T g = fma_((T)-0.5, n, (T)1.5);
+        a[j] = sel(mv[j], a[j], a1 * g);
+        b[j] = sel(mv[j], b[j], b1 * g);
+    }
+    a4 = V4{a[0], a[1], a[2], a[3]};
+    b4 = V4{b[0], b[1], b[2], b[3]};
 }
 
 // The alleles of one 256-gene chunk, four 64-bit wave masks (slot j of every

@@ -256,6 +256,8 @@ generation_kernel(const InstDev* __restrict__ insts,
     // a row's last chunk) read the slack after the plane or the next row;
     // their alleles are masked to 0 and their stores skipped.
     V4 nb[R], na[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { nb[r] = V4{}; na[r] = V4{}; }
     auto load_chunk = [&](int chx) {
         const uint32_t qx = (uint32_t)chx * (kChunk / 4) + lane;
 #pragma unroll
@@ -293,8 +295,10 @@ generation_kernel(const InstDev* __restrict__ insts,
             v4 = gload((const i32x4*)I.v, q);
             w4 = gload((const i32x4*)I.w, q);
         }
+        // the elite's alleles of t-1 (at generation 0, nothing rotates and
+        // the words read are the zeroed slot)
         uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0;
-        if (kCip && pending) {
+        if (kCip) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(brow + ch * kWordsPerChunk);
             bm0 = load_mask(bw); bm1 = load_mask(bw + 1);
             bm2 = load_mask(bw + 2); bm3 = load_mask(bw + 3);
@@ -306,37 +310,40 @@ generation_kernel(const InstDev* __restrict__ insts,
             V4 b4 = cb[r];
             V4 a4 = ca[r];
             // the row's stored alleles of t-1 (scalar loads, in flight while
-            // the draws below are computed)
-            uint64_t xm0 = 0, xm1 = 0, xm2 = 0, xm3 = 0;
-            if (rot[r] && !RC) {
+            // the draws below are computed; read for every row, so that the
+            // chunk's arithmetic is one straight run of code)
+            uint64_t xm[4] = {0, 0, 0, 0};
+            if (kCip && !RC) {
                 const uint64_t* xw = reinterpret_cast<const uint64_t*>(
                     xprev + (size_t)c * wpr + ch * kWordsPerChunk);
-                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
-                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xm[j] = load_mask(xw + j);
             }
             // the draws of generation t depend on no loaded value
             Draw4 d{0u, 0u, 0u, 0u};
-            if (kQip) d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
-            if (rot[r]) {
+            if (kQip) {
+                d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+                pin_draws(d);
+            }
+            if (kCip) {
                 if (RC) {
                     // The stored beta is the one generation t-1 observed (its
                     // rotation is still pending), so the same draw against it
                     // gives back the alleles of t-1 bit for bit.
                     const Draw4 dp = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u,
                                                    I.seed_lo, I.seed_hi);
-                    xm0 = ballot(observe(dp.r0, b4.x)) & actm;
-                    xm1 = ballot(observe(dp.r1, b4.y)) & actm;
-                    xm2 = ballot(observe(dp.r2, b4.z)) & actm;
-                    xm3 = ballot(observe(dp.r3, b4.w)) & actm;
+                    xm[0] = ballot(observe(dp.r0, b4.x)) & actm;
+                    xm[1] = ballot(observe(dp.r1, b4.y)) & actm;
+                    xm[2] = ballot(observe(dp.r2, b4.z)) & actm;
+                    xm[3] = ballot(observe(dp.r3, b4.w)) & actm;
                 }
-                T a0 = a4.x, a1 = a4.y, a2 = a4.z, a3 = a4.w;
-                T b0 = b4.x, b1 = b4.y, b2 = b4.z, b3 = b4.w;
-                cip_gene(a0, b0, xm0 ^ bm0, bm0);
-                cip_gene(a1, b1, xm1 ^ bm1, bm1);
-                cip_gene(a2, b2, xm2 ^ bm2, bm2);
-                cip_gene(a3, b3, xm3 ^ bm3, bm3);
-                a4 = V4{a0, a1, a2, a3};
-                b4 = V4{b0, b1, b2, b3};
+                // genes that move: the row scores below the elite and the
+                // allele differs from the elite's
+                const uint64_t rowm = rot[r] ? ~0ull : 0ull;
+                const uint64_t tg[4] = {bm0, bm1, bm2, bm3};
+                const uint64_t mv[4] = {(xm[0] ^ bm0) & rowm, (xm[1] ^ bm1) & rowm,
+                                        (xm[2] ^ bm2) & rowm, (xm[3] ^ bm3) & rowm};
+                cip_chunk<V4, T>(a4, b4, mv, tg);
             }
             uint64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
             if (kQip) {
@@ -483,6 +490,8 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
 
     // every load of the wave first
     V4 a4[CPW], b4[CPW];
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) { a4[u] = V4{}; b4[u] = V4{}; }
     f64x2 la[CPW][2], lb[CPW][2];
 #pragma unroll
     for (int u = 0; u < CPW; ++u) {
@@ -513,22 +522,31 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * lane;
         const uint64_t actm = ballot(g0 < (uint32_t)I.pitch);
         const uint32_t q = g0 >> 2;
-        // the elite's and the row's own alleles of t-1 (scalar loads, in
-        // flight while the draws are computed)
-        uint64_t bm0 = 0, bm1 = 0, bm2 = 0, bm3 = 0, xm0 = 0, xm1 = 0, xm2 = 0, xm3 = 0;
-        if (rot) {
+        // Binary32 runs the chunk as one straight run: the elite's and the
+        // row's own alleles of t-1 are read whether or not the row rotates
+        // (scalar loads, in flight while the draws are computed) and a
+        // non-rotating row's gate masks are zero.  Binary64 is bound by its
+        // amplitude traffic; there a uniform branch skips the masks and the
+        // gates of a row that keeps its amplitudes.
+        constexpr bool kStraight = !kStage;
+        uint64_t bm[4] = {0, 0, 0, 0}, xm[4] = {0, 0, 0, 0};
+        if (kStraight || rot) {
             const uint64_t* bw = reinterpret_cast<const uint64_t*>(erow + ch * kWordsPerChunk);
-            bm0 = load_mask(bw); bm1 = load_mask(bw + 1);
-            bm2 = load_mask(bw + 2); bm3 = load_mask(bw + 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bm[j] = load_mask(bw + j);
             if (!RC) {
                 const uint64_t* xw = reinterpret_cast<const uint64_t*>(orow + ch * kWordsPerChunk);
-                xm0 = load_mask(xw); xm1 = load_mask(xw + 1);
-                xm2 = load_mask(xw + 2); xm3 = load_mask(xw + 3);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xm[j] = load_mask(xw + j);
             }
         }
         const i32x4 v4 = gload((const i32x4*)I.v, q);
         const i32x4 w4 = gload((const i32x4*)I.w, q);
-        const Draw4 d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+        Draw4 d;
+        if constexpr (kStraight) {
+            d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
+            pin_draws(d);
+        }
         if constexpr (kStage) {
             T* sa = stage[wave][0];
             T* sb = stage[wave][1];
@@ -544,26 +562,24 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
             __builtin_amdgcn_wave_barrier();
         }
         V4 bb = b4[u], aa = a4[u];
-        if (rot) {
-            if (RC) {
+        if (kStraight || rot) {
+            if (RC && pending) {
                 // the stored beta is the one generation t-1 observed, so its
                 // draws give back that generation's alleles bit for bit
                 const Draw4 dp = philox4x32_10(q, (uint32_t)c, (uint32_t)(t - 1), 0u, I.seed_lo,
                                                I.seed_hi);
-                xm0 = ballot(observe(dp.r0, bb.x)) & actm;
-                xm1 = ballot(observe(dp.r1, bb.y)) & actm;
-                xm2 = ballot(observe(dp.r2, bb.z)) & actm;
-                xm3 = ballot(observe(dp.r3, bb.w)) & actm;
+                xm[0] = ballot(observe(dp.r0, bb.x)) & actm;
+                xm[1] = ballot(observe(dp.r1, bb.y)) & actm;
+                xm[2] = ballot(observe(dp.r2, bb.z)) & actm;
+                xm[3] = ballot(observe(dp.r3, bb.w)) & actm;
             }
-            T a0 = aa.x, a1 = aa.y, a2 = aa.z, a3 = aa.w;
-            T b0 = bb.x, b1 = bb.y, b2 = bb.z, b3 = bb.w;
-            cip_gene(a0, b0, xm0 ^ bm0, bm0);
-            cip_gene(a1, b1, xm1 ^ bm1, bm1);
-            cip_gene(a2, b2, xm2 ^ bm2, bm2);
-            cip_gene(a3, b3, xm3 ^ bm3, bm3);
-            aa = V4{a0, a1, a2, a3};
-            bb = V4{b0, b1, b2, b3};
+            const uint64_t rowm = rot ? ~0ull : 0ull;
+            const uint64_t mv[4] = {(xm[0] ^ bm[0]) & rowm, (xm[1] ^ bm[1]) & rowm,
+                                    (xm[2] ^ bm[2]) & rowm, (xm[3] ^ bm[3]) & rowm};
+            cip_chunk<V4, T>(aa, bb, mv, bm);
         }
+        if constexpr (!kStraight)
+            d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
         const uint64_t m0 = ballot(observe(d.r0, bb.x)) & actm;
         const uint64_t m1 = ballot(observe(d.r1, bb.y)) & actm;
         const uint64_t m2 = ballot(observe(d.r2, bb.z)) & actm;

@@ -569,7 +569,11 @@ int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
         const Cand* dflt = nullptr;
         for (const Cand& c : cand) {
             if (c.ms < best->ms) best = &c;
-            if (c.R == def.R && c.S == def.S && c.flags == def.flags) dflt = &c;
+            // a segment-order launch ignores the row shape: its flags name it
+            const bool same = (def.flags & kFlagSegments)
+                                  ? c.flags == def.flags
+                                  : c.R == def.R && c.S == def.S && c.flags == def.flags;
+            if (same) dflt = &c;
         }
         record_class(def.cls, def.rows, def.max_nchunk, best->R, best->S, best->flags, best->ms);
         qieo_class_tune r{};

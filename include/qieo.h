@@ -131,6 +131,21 @@ int qieo_sync(qieo_inst *h);
 int qieo_best(qieo_inst *h, qieo_result *out, uint32_t *bits_or_null,
               size_t n_words);
 
+/* qieo_best for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it.  Same arguments and results as qieo_best; it calls no
+ * hipMalloc, hipFree or other allocating routine (on success it allocates no
+ * host memory either).  The best string is unpacked on the device into a static
+ * staging buffer of the library (QIEO_BEST_NOALLOC_MAX_ITEMS genes, 1 MiB,
+ * one per device, held until the process ends) and copied from there into
+ * bits_or_null.  Every call on a device shares that buffer: calls that
+ * overlap on one device (from different threads, or with streams not
+ * ordered against each other) race and must be serialised by the caller.
+ * With bits_or_null != NULL, an instance of more than
+ * QIEO_BEST_NOALLOC_MAX_ITEMS items gives QIEO_EINVAL (use qieo_best). */
+#define QIEO_BEST_NOALLOC_MAX_ITEMS (1 << 23)
+int qieo_best_noalloc(qieo_inst *h, qieo_result *out, uint32_t *bits_or_null, size_t n_words);
+
 /* Number of generations run so far (waits for queued work). */
 int qieo_generations(qieo_inst *h, int64_t *out);
 

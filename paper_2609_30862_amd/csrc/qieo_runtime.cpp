@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -742,6 +743,61 @@ extern "C" int qieo_best(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t 
     clear_error();
     if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
     return read_best(h->d, h->capacity, h->stream, out, bits, n_words);
+}
+
+// ---------------------------------------------------------------------------
+// qieo_best without allocation.  The unpacked best string goes through a
+// file-scope device array (one copy per device, for the process's life).
+// Host code never passes `scratch` itself to a kernel or a copy: its name is
+// a host-side stand-in; the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchWords = QIEO_BEST_NOALLOC_MAX_ITEMS / 32;   // 1 MiB
+static_assert(QIEO_BEST_NOALLOC_MAX_ITEMS % 32 == 0, "whole words");
+__device__ __align__(256) uint32_t scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (made current by the caller).
+int scratch_on(int dev, uint32_t** out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(QIEO_EDEVICE, "device %d out of range for the static buffer", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        }
+        g_scratch_ptr[dev] = (uint32_t*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QIEO_OK;
+}
+}  // namespace
+
+extern "C" int qieo_best_noalloc(qieo_inst* h, qieo_result* out, uint32_t* bits, size_t n_words)
+{
+    clear_error();
+    if (!h || !out) return set_error(QIEO_EINVAL, "NULL argument");
+    if (bits && (size_t)h->ng > (size_t)QIEO_BEST_NOALLOC_MAX_ITEMS)
+        return set_error(QIEO_EINVAL, "%d items exceed the static staging of %d items", h->ng,
+                         QIEO_BEST_NOALLOC_MAX_ITEMS);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != h->device && (e = hipSetDevice(h->device)) != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    uint32_t* staging = nullptr;
+    int rc = bits ? scratch_on(h->device, &staging) : QIEO_OK;
+    if (rc == QIEO_OK) rc = read_best_via(h->d, h->capacity, h->stream, out, bits, n_words, staging);
+    if (cur != h->device) (void)hipSetDevice(cur);
+    return rc;
 }
 
 extern "C" int qieo_export_rows(qieo_inst* h, int32_t row0, int32_t n_rows, float* alpha,

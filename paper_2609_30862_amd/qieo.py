@@ -24,6 +24,9 @@ QIEO_EDEVICE = -4
 QIEO_EAGAIN = -5
 QIEO_ESTATE = -6
 
+# qieo_best_noalloc: largest instance (items) its static staging holds
+QIEO_BEST_NOALLOC_MAX_ITEMS = 1 << 23
+
 PIPELINE_FUSED = 0
 PIPELINE_UNFUSED = 1
 PIPELINE_UNFUSED_FE_DE = 2
@@ -151,6 +154,8 @@ def _load():
     L.qieo_sync.argtypes = [H]
     L.qieo_best.restype = ctypes.c_int
     L.qieo_best.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
+    L.qieo_best_noalloc.restype = ctypes.c_int
+    L.qieo_best_noalloc.argtypes = [H, ctypes.POINTER(qieo_result), P, ctypes.c_size_t]
     L.qieo_generations.restype = ctypes.c_int
     L.qieo_generations.argtypes = [H, ctypes.POINTER(i64)]
     L.qieo_autotune.restype = ctypes.c_int
@@ -349,6 +354,17 @@ def qieo_best(h, n_items: int | None = None):
         bits = np.zeros((n_items + 31) // 32, dtype=np.uint32)
     _check(lib.qieo_best(h, ctypes.byref(r), _ptr(bits), 0 if bits is None else bits.size),
            "qieo_best")
+    return r, bits
+
+
+def qieo_best_noalloc(h, n_items: int | None = None):
+    """qieo_best through the library's static staging buffer (no allocation)."""
+    r = qieo_result()
+    bits = None
+    if n_items is not None:
+        bits = np.zeros((n_items + 31) // 32, dtype=np.uint32)
+    _check(lib.qieo_best_noalloc(h, ctypes.byref(r), _ptr(bits),
+                                 0 if bits is None else bits.size), "qieo_best_noalloc")
     return r, bits
 
 

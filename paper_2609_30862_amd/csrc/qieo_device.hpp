@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qieo_layout.hpp"
+
 namespace qieo {
 
 // ---------------------------------------------------------------------------
@@ -329,18 +331,36 @@ __device__ __forceinline__ void cip_chunk(V4& a4, V4& b4, const uint64_t rot[4],
 }
 
 // The alleles of one 256-gene chunk, four 64-bit wave masks (slot j of every
-// lane), stored as eight words by lane 0 in two 16-byte stores.
+// lane), stored as eight words: lane l < 8 holds word l (half l & 1 of mask
+// l >> 1), written into its lane from the scalar registers, so the chunk's
+// 32 bytes go out in one store instruction.  Lanes 8..63 of the result are
+// not used.
+template <int L>
+__device__ __forceinline__ void write_lane(uint32_t& w, uint32_t v)
+{
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(w) : "s"(v), "n"(L));
+}
+
+__device__ __forceinline__ uint32_t chunk_word(uint64_t m0, uint64_t m1, uint64_t m2,
+                                               uint64_t m3)
+{
+    uint32_t w = 0u;
+    write_lane<0>(w, (uint32_t)uniform_mask(m0));
+    write_lane<1>(w, (uint32_t)(uniform_mask(m0) >> 32));
+    write_lane<2>(w, (uint32_t)uniform_mask(m1));
+    write_lane<3>(w, (uint32_t)(uniform_mask(m1) >> 32));
+    write_lane<4>(w, (uint32_t)uniform_mask(m2));
+    write_lane<5>(w, (uint32_t)(uniform_mask(m2) >> 32));
+    write_lane<6>(w, (uint32_t)uniform_mask(m3));
+    write_lane<7>(w, (uint32_t)(uniform_mask(m3) >> 32));
+    return w;
+}
+
 __device__ __forceinline__ void store_chunk_words(uint32_t* dst, uint64_t m0, uint64_t m1,
                                                   uint64_t m2, uint64_t m3, int lane)
 {
-    if (lane == 0) {
-        const i32x4 lo = {(int)(uint32_t)m0, (int)(uint32_t)(m0 >> 32), (int)(uint32_t)m1,
-                          (int)(uint32_t)(m1 >> 32)};
-        const i32x4 hi = {(int)(uint32_t)m2, (int)(uint32_t)(m2 >> 32), (int)(uint32_t)m3,
-                          (int)(uint32_t)(m3 >> 32)};
-        gstore((i32x4*)dst, 0u, lo);
-        gstore((i32x4*)dst, 1u, hi);
-    }
+    const uint32_t word = chunk_word(m0, m1, m2, m3);
+    if (lane < kWordsPerChunk) gstore(dst, (uint32_t)lane, word);
 }
 
 // Evaluation's per-lane sum of eq. (1) over the lane's four genes: the items

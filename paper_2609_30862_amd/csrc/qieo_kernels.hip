@@ -38,6 +38,7 @@
 #include <mutex>
 
 #include "qieo_device.hpp"
+#include "qieo_elite.hpp"
 #include "qieo_host.hpp"
 #include "qieo_kernels.hpp"
 
@@ -48,59 +49,6 @@ namespace {
 // Wave sums and maxima stay in registers (DPP lane moves); the result is
 // wave-uniform.  Integer sums do not depend on the order of combination.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_sum_dpp(v); }
-
-__device__ __forceinline__ int32_t key_fitness(unsigned long long key)
-{
-    return (int32_t)((uint32_t)(key >> 32) ^ 0x80000000u);
-}
-
-__device__ __forceinline__ int32_t key_row(unsigned long long key)
-{
-    return (int32_t)(~(uint32_t)key);
-}
-
-__device__ __forceinline__ unsigned long long make_key(int32_t f, int32_t row)
-{
-    return ((unsigned long long)((uint32_t)f ^ 0x80000000u) << 32) |
-           (unsigned long long)(~(uint32_t)row);
-}
-
-// Offers a row's key to the generation's elite slot.  Device-scope atomics
-// on one address serialise at the memory side (about 12 ns per wave
-// instruction on MI355X: 4096 rows cost 48 us), so the slot is read first
-// and the atomic issued only by a key that can still win; the slot only
-// grows during a generation, so a key not above a value once read is never
-// the maximum and skipping it leaves the result unchanged.
-__device__ __forceinline__ void offer_key(unsigned long long* slot, unsigned long long key)
-{
-    const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-    if (key > cur) atomicMax(slot, key);
-}
-
-// Best-so-far update for generation tg whose elite is (e, fe).  Executed by
-// one whole wavefront (the only writer of the record in this launch), after
-// the generation tg launch has completed.
-__device__ void best_update(const InstDev& I, int64_t tg, int32_t e, int32_t fe,
-                            const uint32_t* __restrict__ xg, int lane)
-{
-    const int has = I.best[0];
-    const int32_t bf = I.best[1];
-    if (has && !(fe > bf)) return;
-    const int wpr = I.nchunk * kWordsPerChunk;
-    const uint32_t* src = xg + (size_t)e * wpr;
-    for (int i = lane; i < wpr; i += 64) I.best_bits[i] = src[i];
-    if (lane == 0) {
-        const int slot = (int)(tg & 1) * I.np + e;
-        I.best[1] = fe;
-        I.best[2] = I.prof[slot];
-        I.best[3] = I.wt[slot];
-        I.best[4] = (int32_t)(uint32_t)(uint64_t)tg;
-        I.best[5] = (int32_t)(uint32_t)((uint64_t)tg >> 32);
-        I.best[6] = e;
-        I.best[0] = 1;
-    }
-}
 
 // Opens generation t of instance I for one workgroup.  Termination test
 // (convergence window): decided by every workgroup from values earlier

@@ -28,9 +28,14 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, 8.0 TB/s
 AMPLITUDES_PER_GENE_UPDATE = 4
 KERNEL_SOURCES = ["paper_2609_30862_amd/csrc/qieo_kernels.hip",
                   "paper_2609_30862_amd/csrc/qieo_device.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_elite.hpp",
                   "paper_2609_30862_amd/csrc/qieo_kernels.hpp",
                   "paper_2609_30862_amd/csrc/qieo_layout.hpp"]
 PROFILE = "profiles/generation_kernel_np4096_ng200000.md"
+# kernels of the whole-call paths (qieo_get_call_path 1, 2, 3)
+PATH_KERNELS = {1: "resident_kernel (one launch per call)",
+                2: "persistent_kernel (one launch per call)",
+                3: "onchip_kernel (one cooperative launch per call)"}
 
 
 def log(msg):
@@ -606,6 +611,7 @@ def main():
         g.sync()
         torch.cuda.synchronize()
         launches, kern_ms = g.kernel_time(reset=True)
+        path = g.call_path()
         g.set_timing(False)
         g.close()
         # per generation: the events enclose each generation's launches, or
@@ -616,7 +622,6 @@ def main():
             % (rep, wall, wall / args.steps * 1e3, avg_ms, launches,
                bytes_per_launch / (avg_ms * 1e-3) / 1e9, best.fitness, best.generation))
         runs.append((wall, avg_ms))
-        one_launch = launches == 1 and args.steps > 1     # the single-workgroup path
 
     # the median run by wall time, and the median kernel average
     wall = sorted(w for w, _ in runs)[len(runs) // 2]
@@ -669,9 +674,11 @@ def main():
                      # counters were taken with one work shape and variant
                      "traffic": measured_traffic(inst.n_pop, inst.n_items, shape,
                                                  args.precision),
-                     "kernel": ("segment_kernel + segment_fe_kernel" if shape[2] & 16
-                                else "resident_kernel (one launch per call)" if one_launch
-                                else "generation_kernel"), "kernel_avg_ms": avg_ms,
+                     "kernel": PATH_KERNELS.get(path, "generation_kernel")
+                               if path != qieo.PATH_LAUNCHES
+                               else ("segment_kernel + segment_fe_kernel" if shape[2] & 16
+                                     else "generation_kernel"),
+                     "kernel_avg_ms": avg_ms,
                      # algorithmic bytes of the timed generations' average
                      # launch (rotating rows 4 amplitudes per gene, others 1)
                      "bytes_per_launch": bytes_exact,

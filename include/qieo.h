@@ -338,15 +338,42 @@ int qieo_server_get_stats(qieo_server *s, qieo_server_stats *out);
 /* Stops the worker after its current iteration and frees everything. */
 void qieo_server_destroy(qieo_server *s);
 
-/* Persistent path for small populations: one single-workgroup launch runs all
- * generations of a qieo_step call, block barriers replacing launch
- * boundaries.  mode 0: never; 1 (default): for tiny populations, where it is
- * faster than launches: the whole state (amplitudes, allele words, item
- * tables, fitness) fits in one workgroup's LDS, which holds it for the call,
- * and n_pop * ceil(n_items / 256) <= 16; 2: whenever the state fits in LDS,
- * else from global memory when n_pop <= 2048.  Results are identical in every
- * mode. */
+/* Whole-call launches (binary32, fused pipeline).  One launch runs all
+ * generations of a qieo_step call, barriers replacing launch boundaries:
+ *  - single workgroup: the whole state (amplitudes, allele words, item
+ *    tables, fitness) in one workgroup's LDS, or read from global memory;
+ *  - on-chip grid: one cooperative launch, one workgroup per compute unit,
+ *    the amplitude planes held in registers for the call and written back
+ *    at its end, a grid barrier per generation (Sec. III-B's loop, with
+ *    DetermineElite's result final at each barrier).  It takes populations
+ *    of up to 16 x 10 (row, 256-gene chunk) items per compute unit whose
+ *    item tables fit in LDS, e.g. 1024 x 10,000 on 256 compute units, and
+ *    no convergence window.
+ * mode 0: never (per-generation launches); 1 (default): the single
+ * workgroup from LDS for tiny populations (n_pop * ceil(n_items / 256) <=
+ * 16), the on-chip grid for calls of >= 4 generations of populations it
+ * takes; 2: a single workgroup whenever the state fits in LDS, else from
+ * global memory when n_pop <= 2048; 3: the on-chip grid for every call it
+ * takes.  A population or call a mode does not take runs as mode 0.
+ * Results are identical in every mode.  An on-chip grid barrier that waits
+ * longer than its bound (qieo_set_barrier_timeout, default one second) ends
+ * the launch; qieo_sync then reports QIEO_EDEVICE and the instance's state
+ * is undefined. */
 int qieo_set_persistent(qieo_inst *h, int32_t mode);
+/* How the last qieo_step[_async] call ran: QIEO_PATH_LAUNCHES (a launch
+ * per generation, or per step of the unfused pipelines), QIEO_PATH_LDS (one
+ * single-workgroup launch from LDS), QIEO_PATH_GLOBAL (one single-workgroup
+ * launch from global memory), QIEO_PATH_ONCHIP (one on-chip grid launch);
+ * -1 before the first call. */
+#define QIEO_PATH_LAUNCHES 0
+#define QIEO_PATH_LDS 1
+#define QIEO_PATH_GLOBAL 2
+#define QIEO_PATH_ONCHIP 3
+int qieo_get_call_path(qieo_inst *h, int32_t *path);
+/* Bound on one grid-barrier wait of the on-chip loop, in microseconds of the
+ * device's wall clock (a watchdog: a generation takes tens of microseconds);
+ * [0, 3600 s], default 1 s. */
+int qieo_set_barrier_timeout(qieo_inst *h, int64_t microseconds);
 
 /* 1 (default): a qieo_step call of n >= 2 generations on the fused
  * per-generation path that repeats the previous call (same n, work shape and

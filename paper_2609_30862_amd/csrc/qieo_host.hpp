@@ -31,7 +31,7 @@ const char* last_error();
 struct ArenaLayout {
     int32_t pitch, nchunk;
     int32_t part_nseg;
-    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv, part;
+    size_t alpha, beta, xbits, v, w, fit, prof, wt, ekey, best, best_bits, tbase, conv, sync, part;
     size_t zero_from;
     size_t total;
 };
@@ -56,6 +56,30 @@ int variant_flags(int R, int S, int64_t nchunk, int64_t plane_bytes);
 void pick_tile(int32_t np, int32_t nchunk, int* R, int* S, int* flags, int elem_bytes = 4);
 // LDS bytes of the single-workgroup resident loop for one population.
 size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk);
+
+// ---- on-chip loop --------------------------------------------------------
+// One cooperative launch runs every generation of a call with the amplitude
+// planes held in registers: one workgroup of kOnchipWaves waves per CU,
+// workgroup b owning rows [b*R, b*R + R) whole, wave w holding the
+// workgroup's (row, chunk) items w*K .. w*K + K - 1 in row-major order, at
+// 8 registers per item (a lane's four genes of alpha and beta).
+constexpr int kOnchipWaves = 16;
+// Shortest call the default mode runs this way.
+constexpr int kOnchipMinGens = 4;
+constexpr int kOnchipVariants = 5;
+constexpr int kOnchipK[kOnchipVariants] = {2, 4, 6, 8, 10};   // compiled items per wave
+struct OnchipPlan {
+    int R = 0;          // rows per workgroup
+    int blocks = 0;     // workgroups, at most one per CU
+    int K = 0;          // items per wave: a compiled variant
+    size_t lds = 0;     // dynamic LDS bytes per workgroup
+};
+// Item tables, the workgroup's own allele words of two generations, the
+// elite's words, and per-row fitness and sums.
+size_t onchip_lds_bytes(int R, int32_t nchunk);
+// False when the population does not fit: more items per wave than the
+// largest variant, or more LDS than lds_limit.
+bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out);
 
 // Segment numbering constants of one segment-order launch of n_seg
 // workgroups on a device of `xcds` XCDs; nseg_row > 0 for an untiled launch

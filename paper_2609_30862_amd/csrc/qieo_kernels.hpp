@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qieo_host.hpp"
 #include "qieo_layout.hpp"
 
 namespace qieo {
@@ -58,6 +59,18 @@ hipError_t launch_resident(const InstDev* dI, const uint32_t* ids, int n_blocks,
 hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_blocks,
                              int waves_per_block, const int32_t* gens_arr, int gens_all,
                              hipStream_t s);
+// On-chip loop (qieo_onchip.hip): one cooperative launch of p.blocks
+// workgroups runs all gens generations of instance 0 with its planes in
+// registers (p from onchip_plan); a small launch before it clears the
+// barrier block.  The call's last generation's bookkeeping is left to
+// launch_finish.  A barrier wait longer than spin_ticks (device wall-clock
+// ticks) raises the abort flag sync[1] and ends the launch early.
+// onchip_limits: the dynamic LDS every variant may use and the CUs of the
+// current device, both 0 where the loop cannot run (no cooperative launch, or
+// a variant whose registers do not allow one workgroup per CU).
+void onchip_limits(size_t* lds_limit, int* n_cu);
+hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64_t spin_ticks,
+                         hipStream_t s);
 // End of a call for n_inst instances: the last generation's best-so-far
 // update, the generation counter, convergence; status (may be NULL): per
 // instance {generations completed, converged flag}.

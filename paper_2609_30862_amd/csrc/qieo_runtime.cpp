@@ -70,6 +70,7 @@ InstDev bind_arena(char* base, const ArenaLayout& L, int32_t ng, int32_t np, int
     d.tbase = reinterpret_cast<int64_t*>(base + L.tbase);
     d.conv = reinterpret_cast<int32_t*>(base + L.conv);
     d.part = reinterpret_cast<uint32_t*>(base + L.part);
+    d.sync = reinterpret_cast<uint32_t*>(base + L.sync);
     d.np = np;
     d.ng = ng;
     d.pitch = L.pitch;
@@ -139,7 +140,10 @@ struct qieo_inst {
     int R = 1, S = 1, flags = 0;
     int pipeline = QIEO_PIPELINE_FUSED;
     bool f64 = false;            // binary64 amplitudes
-    int persistent = 1;          // 0 never, 1 (default) when the state fits LDS, 2 whenever rows fit
+    int persistent = 1;          // see qieo_set_persistent
+    bool onchip_check = false;   // an on-chip launch is queued: qieo_sync reads its abort flag
+    int32_t last_path = -1;      // QIEO_PATH_* of the last step call
+    int64_t barrier_us = 1000000;    // bound on one on-chip grid-barrier wait
     bool use_graph = true;       // replay a captured graph of a call's launches
     hipGraphExec_t graph = nullptr;
     int32_t graph_n = -1;        // generations the cached graph runs
@@ -287,6 +291,19 @@ extern "C" int qieo_create(const qieo_item* items, int32_t n_items, int32_t capa
     return create_impl(items, n_items, capacity, n_pop, seed, nullptr, false, out);
 }
 
+// Bound on one grid-barrier wait of the on-chip loop, in ticks of the
+// device's wall clock.
+static int64_t onchip_spin_ticks(int device, int64_t microseconds)
+{
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        khz <= 0) {
+        (void)hipGetLastError();
+        khz = 100000;
+    }
+    return (int64_t)khz * microseconds / 1000;
+}
+
 static int timed_event_pair(qieo_inst* h, int stage, hipEvent_t* a, hipEvent_t* b)
 {
     while (h->ev.size() < 2 * (h->ev_used + 1)) {
@@ -394,6 +411,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
     hipError_t e;
     const int blocks = (h->np + h->R - 1) / h->R;
     if (h->f64) {
+        h->last_path = QIEO_PATH_LAUNCHES;
         for (int32_t k = 0; k < n; ++k) {
             hipEvent_t a = nullptr, b = nullptr;
             if (h->timing) {
@@ -413,6 +431,38 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
             return hip_fail(e, "finish kernel");
         h->t += n;
         return QIEO_OK;
+    }
+    // populations whose planes fit the chip's registers: the whole call in
+    // one cooperative launch that holds them there (mode 1 from
+    // kOnchipMinGens generations on, where the planes' one load and one store
+    // per call cost less than the per-generation launches' traffic; mode 3
+    // for every call).  Not with a convergence window.
+    if (h->pipeline == QIEO_PIPELINE_FUSED && h->window == 0 &&
+        (h->persistent == 3 || (h->persistent == 1 && n >= kOnchipMinGens &&
+                                (int64_t)h->np * h->L.nchunk > 16))) {
+        OnchipPlan p;
+        size_t lim = 0;
+        int ncu = 0;
+        onchip_limits(&lim, &ncu);
+        if (ncu > 0 && onchip_plan(h->np, h->L.nchunk, ncu, lim, &p)) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (h->timing) {
+                int rc = timed_event_pair(h, 0, &a, &b);
+                if (rc) return rc;
+                (void)hipEventRecord(a, h->stream);
+            }
+            if ((e = launch_onchip(h->d_desc, p, n, onchip_spin_ticks(h->device, h->barrier_us),
+                                   h->stream)) !=
+                hipSuccess)
+                return hip_fail(e, "on-chip kernel");
+            h->onchip_check = true;
+            h->last_path = QIEO_PATH_ONCHIP;
+            if (h->timing) (void)hipEventRecord(b, h->stream);
+            if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
+                return hip_fail(e, "finish kernel");
+            h->t += n;
+            return QIEO_OK;
+        }
     }
     // small populations: the whole call in one single-workgroup launch, from
     // LDS when the whole state fits there.  Mode 1 takes it only where it
@@ -435,12 +485,14 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         e = fits_lds ? launch_resident(h->d_desc, nullptr, 1, waves, lds, nullptr, n, h->stream)
                      : launch_persistent(h->d_desc, nullptr, 1, waves, nullptr, n, h->stream);
         if (e != hipSuccess) return hip_fail(e, "persistent kernel");
+        h->last_path = fits_lds ? QIEO_PATH_LDS : QIEO_PATH_GLOBAL;
         if (h->timing) (void)hipEventRecord(b, h->stream);
         if ((e = launch_finish(h->d_desc, 1, nullptr, n, nullptr, h->stream)) != hipSuccess)
             return hip_fail(e, "finish kernel");
         h->t += n;
         return QIEO_OK;
     }
+    h->last_path = QIEO_PATH_LAUNCHES;
     // fused per-generation launches: replay one captured graph per call.  A
     // call is captured once it repeats (same generation count, same shape and
     // variant as the previous call): capturing a one-off call costs more than
@@ -512,6 +564,16 @@ extern "C" int qieo_sync(qieo_inst* h)
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (h->onchip_check) {
+        h->onchip_check = false;
+        uint32_t abort_flag = 0;
+        if ((e = copy_on(&abort_flag, h->d.sync + 1, sizeof abort_flag, hipMemcpyDeviceToHost,
+                         h->stream)) != hipSuccess)
+            return hip_fail(e, "copy(on-chip abort flag)");
+        if (abort_flag)
+            return set_error(QIEO_EDEVICE, "on-chip loop: a grid barrier wait ran past its bound; "
+                                           "the instance's state is undefined");
+    }
     if (h->timing) return collect_timing(h);
     return QIEO_OK;
 }
@@ -870,6 +932,25 @@ extern "C" int qieo_get_tile(qieo_inst* h, int32_t* rows_per_block, int32_t* wav
     return QIEO_OK;
 }
 
+extern "C" int qieo_set_barrier_timeout(qieo_inst* h, int64_t microseconds)
+{
+    clear_error();
+    if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
+    if (microseconds < 0 || microseconds > 3600LL * 1000000)
+        return set_error(QIEO_EINVAL, "timeout must be in [0, 3600 s] (got %lld us)",
+                         (long long)microseconds);
+    h->barrier_us = microseconds;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_get_call_path(qieo_inst* h, int32_t* path)
+{
+    clear_error();
+    if (!h || !path) return set_error(QIEO_EINVAL, "NULL argument");
+    *path = h->last_path;
+    return QIEO_OK;
+}
+
 extern "C" int qieo_set_timing(qieo_inst* h, int enabled)
 {
     clear_error();
@@ -922,7 +1003,8 @@ extern "C" int qieo_set_persistent(qieo_inst* h, int32_t mode)
 {
     clear_error();
     if (!h) return set_error(QIEO_EINVAL, "handle is NULL");
-    if (mode < 0 || mode > 2) return set_error(QIEO_EINVAL, "mode must be 0, 1 or 2 (got %d)", mode);
+    if (mode < 0 || mode > 3)
+        return set_error(QIEO_EINVAL, "mode must be 0, 1, 2 or 3 (got %d)", mode);
     if (h->f64 && mode != 0)
         return set_error(QIEO_ESTATE, "binary64 instances use per-generation launches");
     h->persistent = mode;

@@ -27,6 +27,11 @@ QIEO_ESTATE = -6
 # qieo_best_noalloc: largest instance (items) its static staging holds
 QIEO_BEST_NOALLOC_MAX_ITEMS = 1 << 23
 
+PATH_LAUNCHES = 0
+PATH_LDS = 1
+PATH_GLOBAL = 2
+PATH_ONCHIP = 3
+
 PIPELINE_FUSED = 0
 PIPELINE_UNFUSED = 1
 PIPELINE_UNFUSED_FE_DE = 2
@@ -170,6 +175,10 @@ def _load():
     L.qieo_set_graph.argtypes = [H, i32]
     L.qieo_set_persistent.restype = ctypes.c_int
     L.qieo_set_persistent.argtypes = [H, i32]
+    L.qieo_get_call_path.restype = ctypes.c_int
+    L.qieo_get_call_path.argtypes = [H, ctypes.POINTER(i32)]
+    L.qieo_set_barrier_timeout.restype = ctypes.c_int
+    L.qieo_set_barrier_timeout.argtypes = [H, i64]
     L.qieo_set_pipeline.restype = ctypes.c_int
     L.qieo_set_pipeline.argtypes = [H, i32]
     L.qieo_stage_time.restype = ctypes.c_int
@@ -496,6 +505,16 @@ class Instance:
 
     def set_persistent(self, mode: int):
         _check(lib.qieo_set_persistent(self._h, int(mode)), "qieo_set_persistent")
+
+    def set_barrier_timeout(self, microseconds: int):
+        _check(lib.qieo_set_barrier_timeout(self._h, int(microseconds)),
+               "qieo_set_barrier_timeout")
+
+    def call_path(self) -> int:
+        """PATH_* of the last step call (-1 before the first)."""
+        p = ctypes.c_int32()
+        _check(lib.qieo_get_call_path(self._h, ctypes.byref(p)), "qieo_get_call_path")
+        return p.value
 
     def set_pipeline(self, pipeline: int):
         _check(lib.qieo_set_pipeline(self._h, int(pipeline)), "qieo_set_pipeline")

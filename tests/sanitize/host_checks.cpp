@@ -65,6 +65,7 @@ static void check_arena()
                 {L.best_bits, wpr * 4, "best_bits"},
                 {L.tbase, 8, "tbase"},
                 {L.conv, 256, "conv"},
+                {L.sync, 64, "sync"},
                 {L.part, (size_t)L.part_nseg * np * 8, "part"}};
             size_t end = 0;
             for (const B& b : blocks) {
@@ -475,6 +476,49 @@ static void check_validation()
     }
 }
 
+// ---------------------------------------------------------------------------
+// On-chip loop planning: rows per workgroup, items per wave, LDS
+// ---------------------------------------------------------------------------
+static void check_onchip_plan()
+{
+    const size_t lim = 160 * 1024 - 256;
+    OnchipPlan p;
+    // 1024 x 10,000 on 256 CUs: 4 rows of 40 chunks per workgroup, 10 items a wave
+    CHECK(onchip_plan(1024, 40, 256, lim, &p), "medium workload");
+    CHECK(p.R == 4 && p.blocks == 256 && p.K == 10 && p.lds == onchip_lds_bytes(4, 40),
+          "R %d blocks %d K %d", p.R, p.blocks, p.K);
+    // every accepted shape: whole rows per workgroup, the grid covers the rows
+    // once, every workgroup's items fit its waves, a compiled K, LDS in bounds
+    for (int32_t np = 1; np <= 5000; np += 37) {
+        for (int32_t nchunk = 1; nchunk <= 200; nchunk += 7) {
+            OnchipPlan q;
+            if (!onchip_plan(np, nchunk, 256, lim, &q)) {
+                const int64_t R = (np + 255) / 256;
+                CHECK((R * nchunk + kOnchipWaves - 1) / kOnchipWaves > kOnchipK[kOnchipVariants - 1] ||
+                          onchip_lds_bytes((int)R, nchunk) > lim,
+                      "%d x %d refused without cause", np, nchunk);
+                continue;
+            }
+            CHECK(q.blocks >= 1 && q.blocks <= 256 && (int64_t)q.blocks * q.R >= np &&
+                      (int64_t)(q.blocks - 1) * q.R < np,
+                  "%d x %d: %d blocks of %d rows", np, nchunk, q.blocks, q.R);
+            CHECK((int64_t)q.R * nchunk <= (int64_t)kOnchipWaves * q.K, "items per wave");
+            bool compiled = false;
+            for (int k : kOnchipK) compiled = compiled || k == q.K;
+            CHECK(compiled, "K %d", q.K);
+            CHECK(q.lds <= lim && q.lds % 16 == 0 &&
+                      q.lds >= (2 * (size_t)nchunk * kChunk + 2 * (size_t)q.R * nchunk * 8) * 4,
+                  "lds %zu", q.lds);
+        }
+    }
+    // beyond the register budget or the LDS: refused
+    CHECK(!onchip_plan(4096, 20, 256, lim, &p), "16 rows x 20 chunks per CU");
+    CHECK(!onchip_plan(50, 79, 256, lim, &p), "item tables of 79 chunks exceed LDS");
+    CHECK(onchip_plan(50, 47, 256, lim, &p) && p.blocks == 50 && p.K == 4, "50 x 47");
+    CHECK(!onchip_plan(1024, 40, 0, lim, &p) && !onchip_plan(1024, 40, 256, 0, &p),
+          "no device support");
+}
+
 int main()
 {
     check_arena();
@@ -484,6 +528,7 @@ int main()
     check_plan_batch();
     check_snapshots();
     check_validation();
+    check_onchip_plan();
     std::printf("host checks passed: %d\n", g_checks);
     return 0;
 }

@@ -1,0 +1,158 @@
+"""The on-chip grid loop (qieo_set_persistent mode 3, and mode 1's choice for
+calls of >= 4 generations): one cooperative launch per call, amplitudes in
+registers, a grid barrier per generation.  Against the oracle at the medium
+workload and on shapes that exercise its item split (rows per workgroup,
+items per wave, waves whose items span rows, waves with no item, rows
+shorter than a chunk, a ragged last workgroup), and across calls that mix it
+with per-generation launches, exports and checkpoints."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_common import assert_state_equal, say
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def qieo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2609_30862_amd import qieo as q
+    return q
+
+
+def _pair(qieo, oracle_mod, inst, mode=3):
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_persistent(mode)
+    o = oracle_mod.Oracle(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed,
+                          threads=THREADS)
+    return g, o
+
+
+def _step_path(g, n):
+    """Steps n generations; returns the path the call took and the number of
+    launches the library timed for it (one for a whole-call launch)."""
+    g.set_timing(True)
+    g.kernel_time(reset=True)
+    g.step(n)
+    launches, _ = g.kernel_time(reset=True)
+    g.set_timing(False)
+    return g.call_path(), launches
+
+
+def test_medium_workload_every_call_length(qieo, oracle_mod):
+    """1024 x 10,000 (seed 1): calls of 1, 2, 7 and 40 generations, the
+    whole state against the oracle after each; every call is one launch."""
+    inst = workloads.medium_instance()
+    g, o = _pair(qieo, oracle_mod, inst)
+    for n in (1, 2, 7, 40):
+        assert _step_path(g, n) == (qieo.PATH_ONCHIP, 1), "call of %d generations" % n
+        o.run(n)
+        assert_state_equal(g, o, label="medium after %d generations" % o.t)
+        say("  medium: %d generations equal the oracle" % o.t)
+    g.close()
+
+
+@pytest.mark.parametrize("ng,n_pop", [
+    (3000, 1000),     # 12 chunks, 4 rows per workgroup, last workgroup ragged
+    (700, 2000),      # 3 chunks: a wave's items span rows
+    (60, 4000),       # one 64-gene chunk per row, 16 rows per workgroup
+    (9000, 300),      # 2 rows per workgroup, 36 chunks
+    (12000, 50),      # fewer rows than compute units, 47 chunks a row
+    (100, 5),         # five workgroups of one item each
+])
+def test_item_split_shapes(qieo, oracle_mod, ng, n_pop):
+    inst = workloads.random_instance(ng, n_pop, seed=400 + ng % 97)
+    g, o = _pair(qieo, oracle_mod, inst)
+    for n in (1, 5, 12):
+        path = _step_path(g, n)
+        o.run(n)
+        assert path == (qieo.PATH_ONCHIP, 1), "%d x %d: call of %d ran as %s" % (n_pop, ng, n, path)
+        assert_state_equal(g, o, label="%d x %d after %d" % (n_pop, ng, o.t))
+    say("  %d x %d: 18 generations in three calls equal the oracle" % (n_pop, ng))
+    g.close()
+
+
+def test_mixed_with_per_generation_launches_and_exports(qieo, oracle_mod):
+    """On-chip calls interleaved with per-generation calls (mode 0), the
+    default mode, exports in between, and a checkpoint resumed into a fresh
+    handle that continues with per-generation launches."""
+    inst = workloads.random_instance(5000, 700, seed=431)
+    g, o = _pair(qieo, oracle_mod, inst)
+    plan = [(3, 6), (0, 5), (3, 1), (1, 9), (0, 2), (3, 11)]
+    for mode, n in plan:
+        g.set_persistent(mode)
+        g.step(n)
+        assert g.call_path() == (qieo.PATH_LAUNCHES if mode == 0 else qieo.PATH_ONCHIP)
+        o.run(n)
+        assert_state_equal(g, o, label="mode %d, after %d" % (mode, o.t))
+    snap = g.export_state()
+    h = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    h.import_state(snap)
+    h.set_persistent(0)
+    g.set_persistent(3)
+    for n in (4, 7):
+        g.step(n)
+        h.step(n)
+        o.run(n)
+    assert_state_equal(g, o, label="on-chip after resume point")
+    assert_state_equal(h, o, label="resumed handle")
+    say("  %d generations across modes, exports and a checkpoint" % o.t)
+    g.close()
+    h.close()
+
+
+def test_default_mode_takes_it_for_calls_of_four_or_more(qieo, oracle_mod):
+    inst = workloads.random_instance(10000, 1024, seed=432)
+    g, o = _pair(qieo, oracle_mod, inst, mode=1)
+    assert _step_path(g, 3) == (qieo.PATH_LAUNCHES, 3)     # below the threshold
+    assert _step_path(g, 4) == (qieo.PATH_ONCHIP, 1)
+    o.run(7)
+    assert_state_equal(g, o, label="default mode")
+    g.close()
+
+
+def test_populations_it_does_not_take_run_per_generation(qieo, oracle_mod):
+    """Mode 3 on a population beyond its register budget (4096 x 5000:
+    16 rows of 20 chunks per compute unit) and with a convergence window:
+    per-generation launches, same results as the oracle."""
+    inst = workloads.random_instance(5000, 4096, seed=433)
+    g, o = _pair(qieo, oracle_mod, inst)
+    assert _step_path(g, 5) == (qieo.PATH_LAUNCHES, 5)
+    o.run(5)
+    assert_state_equal(g, o, label="4096 x 5000, mode 3")
+    g.close()
+    inst = workloads.random_instance(2000, 300, seed=434)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_convergence(3)
+    g.set_persistent(3)
+    assert _step_path(g, 6) == (qieo.PATH_LAUNCHES, 6)
+    g.close()
+
+
+def test_barrier_timeout_ends_the_launch_and_is_reported(qieo):
+    """A zero bound on the grid-barrier wait: the workgroups give up at the
+    first barrier that is not already complete, every one of them leaves
+    the launch, and qieo_sync reports QIEO_EDEVICE.  A fresh instance on the
+    same device runs normally afterwards."""
+    inst = workloads.random_instance(3000, 1000, seed=435)
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_persistent(3)
+    g.set_barrier_timeout(0)
+    with pytest.raises(qieo.QieoError) as ei:
+        g.step(50)
+    assert ei.value.code == qieo.QIEO_EDEVICE and "barrier" in str(ei.value)
+    g.close()
+    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    g.set_persistent(3)
+    g.step(5)
+    assert g.call_path() == qieo.PATH_ONCHIP and g.generations == 5
+    g.close()
+    with pytest.raises(qieo.QieoError):
+        qieo.Instance(inst.values, inst.weights, inst.capacity, 1, 1).set_barrier_timeout(-1)

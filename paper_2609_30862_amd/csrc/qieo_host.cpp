@@ -60,7 +60,8 @@ size_t arena_layout(int32_t ng, int32_t np, ArenaLayout* L, int elem)
     L->best_bits = take(wpr * sizeof(uint32_t));
     L->tbase = take(sizeof(int64_t));
     L->conv = take(64 * sizeof(int32_t));
-    L->sync = take(16 * sizeof(uint32_t));
+    L->sync = take(16 * sizeof(uint32_t) +
+                   2 * (size_t)std::min(np, (int32_t)kOnchipMaxBlocks) * sizeof(uint64_t));
     // the segment sums: the last block, so a launch with shorter segments
     // than this sizing would write past the arena's end (segments_fit)
     L->part_nseg = (int32_t)seg_count(nchunk, kSegChunksMin);
@@ -186,13 +187,14 @@ size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk)
 size_t onchip_lds_bytes(int R, int32_t nchunk)
 {
     const size_t wpr = (size_t)nchunk * kWordsPerChunk;
-    const size_t words = 2 * (size_t)nchunk * kChunk + 2 * (size_t)R * wpr + wpr + 4 * (size_t)R;
+    const size_t words = 2 * (size_t)nchunk * kChunk + 2 * (size_t)R * wpr + wpr + 8 * (size_t)R;
     return (words * sizeof(uint32_t) + 15) / 16 * 16;
 }
 
 bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out)
 {
-    if (np < 1 || nchunk < 1 || n_cu < 1) return false;
+    // rows travel in 16 bits of the workgroups' keys
+    if (np < 1 || np > 65536 || nchunk < 1 || n_cu < 1 || n_cu > kOnchipMaxBlocks) return false;
     const int64_t R = (np + (int64_t)n_cu - 1) / n_cu;
     const int64_t need = (R * nchunk + kOnchipWaves - 1) / kOnchipWaves;
     int K = 0;

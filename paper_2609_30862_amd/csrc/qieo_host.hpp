@@ -75,7 +75,8 @@ struct OnchipPlan {
     size_t lds = 0;     // dynamic LDS bytes per workgroup
 };
 // Item tables, the workgroup's own allele words of two generations, the
-// elite's words, and per-row fitness and sums.
+// elite's words, and per row the fitness, profit and weight of two
+// generations and the running sums.
 size_t onchip_lds_bytes(int R, int32_t nchunk);
 // False when the population does not fit: more items per wave than the
 // largest variant, or more LDS than lds_limit.

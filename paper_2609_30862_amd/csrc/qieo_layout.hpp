@@ -35,8 +35,10 @@ constexpr int kWordsPerChunk = 8;
 //   conv        : int32[64]               convergence test: [0] converged flag,
 //                 [1..2] generation it converged at (lo, hi), [3] window
 //                 (0 = off), [8..40) elite fitness of generation g in slot g%32
-//   sync        : uint32[16]              on-chip loop: grid-barrier arrival
-//                 counter [0] and abort flag [1], cleared before each launch
+//   sync        : uint32[16] + uint64[2][min(np, kOnchipMaxBlocks)]  on-chip
+//                 loop: abort flag [1], then for generations of either
+//                 parity each workgroup's tagged best key (all cleared
+//                 before each launch)
 // Padding genes (ng <= i < pitch) hold alpha = 1, beta = 0, v = w = 0: they
 // are never observed as 1 and never rotate.  Each amplitude plane is followed
 // by kChunk floats of zeroed slack and v, w hold nchunk*kChunk entries, so a
@@ -56,7 +58,7 @@ struct InstDev {
     int64_t* tbase;
     int32_t* conv;
     uint32_t* part;              // [np][nseg] (profit, weight) partial sums, segment path
-    uint32_t* sync;              // on-chip loop's barrier counter and abort flag
+    uint32_t* sync;              // on-chip loop's abort flag and workgroup keys
     int32_t np, ng, pitch, nchunk;
     int32_t capacity;
     uint32_t seed_lo, seed_hi;
@@ -96,6 +98,8 @@ constexpr int kStepAll = kStepCip | kStepQip | kStepFe | kStepDe;
 // timing slots: fused generation, CIP, QIP, Evaluation, DetermineElite
 constexpr int kStages = 5;
 constexpr int kConvRing = 32;      // longest convergence window
+// On-chip loop: most workgroups (one per CU) a launch may have.
+constexpr int kOnchipMaxBlocks = 1024;
 // Single-workgroup loop from global memory: rows it can hold sums for in LDS.
 constexpr int kPersistentMaxRows = 2048;
 

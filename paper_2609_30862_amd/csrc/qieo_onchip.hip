@@ -10,9 +10,9 @@
 // 8K registers of amplitudes.  A generation is the fused one of the
 // per-generation kernels, gene for gene the same arithmetic (so the same
 // bits): CIP(t-1) toward the elite of t-1, QIP(t), Evaluation's sums of
-// eq. (1) closed per row inside the workgroup, and the row's key offered to
-// the elite slot of t.  A grid barrier then ends the generation; after it
-// the elite of t is final everywhere.
+// eq. (1) closed per row inside the workgroup, and the workgroup's best key
+// published.  The next generation starts in each workgroup once every
+// workgroup's key is in (a grid barrier); their maximum is the elite of t.
 //
 // Item tables, the workgroup's own allele words of t-1 and t, and the elite's
 // words of t-1 are read from LDS.  Allele words, fitness slots, elite keys
@@ -22,13 +22,20 @@
 // once, at the end.  The call therefore leaves the state the per-generation
 // launches would leave, and the next call (of any kind) continues from it.
 //
-// Grid barrier: an arrival counter in the instance's arena (cleared by a
-// small launch before this one).  Each workgroup waits for its own stores,
-// then one thread adds its arrival with release semantics at device scope
-// (the XCD's L2 writes back what the workgroup wrote) and spins on the
-// counter; once it reaches the generation's target, an acquire at device
-// scope drops stale lines before anyone reads other workgroups' data.  The
-// wait is bounded in time: past the bound the waiting workgroup raises the
+// Grid barrier and DetermineElite in one step: at the end of generation k
+// each workgroup stores its best key, tagged with k, into its slot of a
+// per-launch array (release at device scope: the XCD's L2 writes back what
+// the workgroup wrote first), and at the start of generation k + 1 one
+// thread per workgroup slot polls that slot until it carries the tag.  When
+// every slot has it, the workgroup holds every workgroup's key and takes
+// their maximum: the elite of k.  So no workgroup waits for a counter and
+// then reads the keys, and DetermineElite needs no atomics on one address
+// except in the call's last generation, whose key goes to the elite slot
+// the way the per-generation launches leave it.  Data other workgroups wrote
+// (the elite's allele words) is read with device-scope loads, which see the
+// written-back values.  The best-so-far record is followed by every
+// workgroup alike and written by the one that owns the new best row, from
+// its LDS.  Waits are bounded in time: past the bound a thread raises the
 // abort flag, every workgroup that sees it leaves, and the host reports the
 // call as failed (the state is then undefined).
 #include <mutex>
@@ -56,42 +63,97 @@ __device__ __forceinline__ void lds_masks(const uint32_t* p, int lane, uint64_t 
     }
 }
 
-// Ends a generation for the whole grid.  Returns false if the wait ran past
-// its bound or another workgroup gave up (every thread gets the same answer).
-__device__ __forceinline__ bool grid_barrier(uint32_t* sync, uint32_t target, int64_t spin_ticks,
-                                             int* s_flag)
+// A workgroup key in a slot: fitness (sign flipped), the row's complement
+// in 16 bits (rows < 2^16), and the generation tag (1 .. 65535) in the low
+// 16 bits.  Ordered like the elite key: larger fitness, then lower row.
+__device__ __forceinline__ unsigned long long slot_key(int32_t f, int32_t row)
 {
-    // this wave's stores (allele words, fitness, best record) have reached
-    // the L2 before the workgroup's arrival can be counted
+    return ((unsigned long long)((uint32_t)f ^ 0x80000000u) << 32) |
+           ((unsigned long long)(~(uint32_t)row & 0xffffu) << 16);
+}
+
+__device__ __forceinline__ uint32_t slot_tag(int k) { return (uint32_t)(k % 65535) + 1u; }
+
+// Ends generation k for the workgroup: its best key (max over wkey[], one
+// per wave) goes to *slot with the tag of k, after the workgroup's stores.
+__device__ __forceinline__ void publish_key(unsigned long long* slot, const unsigned long long* wkey,
+                                            int k)
+{
+    // every wave's stores (allele words, fitness, best record) have reached
+    // the L2 before the key is stored
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int bad = 0;
+        unsigned long long m = 0ull;
+        for (int w = 0; w < kOnchipWaves; ++w) m = wkey[w] > m ? wkey[w] : m;
+        __hip_atomic_store(slot, m | slot_tag(k), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Waits until every workgroup has published its key of generation k and
+// returns their maximum (tag removed) in every thread, or false if a wait
+// ran past its bound or another workgroup gave up.
+__device__ __forceinline__ bool gather_keys(const unsigned long long* slots, int nb, int k,
+                                            uint32_t* abort_flag, int64_t spin_ticks,
+                                            unsigned long long* wkey, int* s_flag,
+                                            unsigned long long* key)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) *s_flag = 0;
+    __syncthreads();
+    unsigned long long m = 0ull;
+    if (tid < nb) {
+        const uint32_t tag = slot_tag(k);
         const int64_t start = wall_clock64();
-        while ((int32_t)(__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
-                         target) < 0) {
-            if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                bad = 1;
+        for (uint32_t it = 0;; ++it) {
+            const unsigned long long v = __hip_atomic_load(slots + tid, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(v & 0xffffu) == tag) {
+                m = v & ~0xffffull;
+                break;
+            }
+            if ((it & 7u) == 7u &&
+                __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                *s_flag = 1;
                 break;
             }
             if (wall_clock64() - start > spin_ticks) {
-                __hip_atomic_store(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bad = 1;
+                __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *s_flag = 1;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *s_flag = bad;
     }
+    m = wave_max_u64_dpp(m);
+    if ((tid & 63) == 0) wkey[tid >> 6] = m;
     __syncthreads();
+    unsigned long long r = 0ull;
+    for (int w = 0; w < kOnchipWaves; ++w) r = wkey[w] > r ? wkey[w] : r;
+    *key = r;
     return *s_flag == 0;
 }
 
-__global__ void onchip_reset_kernel(const InstDev* __restrict__ insts)
+template <typename T>
+__device__ __forceinline__ T load_dev(const T* p)
 {
-    if (threadIdx.x < 2) insts[0].sync[threadIdx.x] = 0u;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_dev(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Clears the abort flag and both generations' key slots of the launch.
+__global__ void onchip_reset_kernel(const InstDev* __restrict__ insts, int nb)
+{
+    const InstDev I = insts[0];
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < 2) I.sync[i] = 0u;
+    unsigned long long* slots = reinterpret_cast<unsigned long long*>(I.sync + 16);
+    if (i < 2 * nb) slots[i] = 0ull;
 }
 
 template <int K>
@@ -101,6 +163,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
 {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ int s_flag;
+    __shared__ unsigned long long s_wkey[kOnchipWaves];
     const InstDev I = insts[0];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -114,9 +177,16 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
     uint32_t* sX = reinterpret_cast<uint32_t*>(sWt + nchunk * kChunk);   // [2][R][wpr] by parity
     uint32_t* sE = sX + 2 * R * wpr;                                     // [wpr] elite of t-1
     int32_t* sF = reinterpret_cast<int32_t*>(sE + wpr);                  // [2][R] fitness by parity
-    uint32_t* sSum = reinterpret_cast<uint32_t*>(sF + 2 * R);            // [R][2] profit, weight
+    int32_t* sPW = sF + 2 * R;                                           // [2][R][2] profit, weight
+    uint32_t* sSum = reinterpret_cast<uint32_t*>(sPW + 4 * R);           // [R][2] running sums
+    unsigned long long* slots = reinterpret_cast<unsigned long long*>(I.sync + 16);  // [2][grid]
+    const int nb = (int)gridDim.x;
 
     const int64_t t0 = sload(I.tbase);
+    // the best-so-far record as the previous launch left it; every
+    // workgroup follows it the same way
+    int has_best = __builtin_amdgcn_readfirstlane(I.best[0]);
+    int32_t best_f = __builtin_amdgcn_readfirstlane(I.best[1]);
     // item tables, and the rows' allele words and fitness of t0 - 1 (for
     // t0 = 0 the zeroed slot 1, which nothing uses: no row rotates at 0)
     for (int i = tid; i < nchunk * kChunk; i += nthr) {
@@ -127,7 +197,11 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
         const int pp = (int)((t0 - 1) & 1);
         const uint32_t* src = I.xbits + ((size_t)pp * np + row0) * wpr;
         for (int i = tid; i < nrows * wpr; i += nthr) sX[pp * R * wpr + i] = src[i];
-        if (tid < nrows) sF[pp * R + tid] = I.fit[pp * np + row0 + tid];
+        if (tid < nrows) {
+            sF[pp * R + tid] = I.fit[pp * np + row0 + tid];
+            sPW[(pp * R + tid) * 2] = I.prof[pp * np + row0 + tid];
+            sPW[(pp * R + tid) * 2 + 1] = I.wt[pp * np + row0 + tid];
+        }
         if (tid < 2 * R) sSum[tid] = 0u;
     }
 
@@ -159,30 +233,55 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
         const int64_t t = t0 + k;
         const int par = (int)(t & 1);
         const bool pending = t > 0;
-        int32_t e_prev = 0, fe_prev = 0;
-        if (pending) {
-            // final: written by the previous launch, or before the last barrier
-            const unsigned long long key = __hip_atomic_load(I.ekey + (t - 1) % 3, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-            e_prev = __builtin_amdgcn_readfirstlane(key_row(key));
-            fe_prev = __builtin_amdgcn_readfirstlane(key_fitness(key));
-        }
-        const uint32_t* xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
-        uint32_t* xcur = I.xbits + (size_t)par * np * wpr;
-        // the previous generation's bookkeeping, as the first workgroup of a
-        // per-generation launch does it (no convergence window here)
-        if (blockIdx.x == 0 && wave == 0) {
-            if (pending) best_update(I, t - 1, e_prev, fe_prev, xprev, lane);
-            if (lane == 0)
-                __hip_atomic_store(I.ekey + (t + 1) % 3, 0ull, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (pending)
-            for (int i = tid; i < wpr; i += nthr) sE[i] = xprev[(size_t)e_prev * wpr + i];
-        __syncthreads();
-
         const uint32_t* sXp = sX + (par ^ 1) * R * wpr;
         uint32_t* sXc = sX + par * R * wpr;
+        const uint32_t* xprev = I.xbits + (size_t)(par ^ 1) * np * wpr;
+        uint32_t* xcur = I.xbits + (size_t)par * np * wpr;
+        // DetermineElite of t-1: the previous launch's elite slot, or the
+        // maximum of the workgroups' keys of generation k - 1, gathered as
+        // they are published (the grid barrier)
+        int32_t e_prev = 0, fe_prev = 0;
+        if (pending) {
+            unsigned long long key;
+            if (k == 0) {
+                key = load_dev(I.ekey + (t - 1) % 3);
+            } else {
+                unsigned long long sk;
+                if (!gather_keys(slots + (size_t)((k - 1) & 1) * nb, nb, k - 1, I.sync + 1,
+                                 spin_ticks, s_wkey, &s_flag, &sk))
+                    return;
+                key = make_key((int32_t)((uint32_t)(sk >> 32) ^ 0x80000000u),
+                               (int32_t)(~(uint32_t)(sk >> 16) & 0xffffu));
+            }
+            e_prev = __builtin_amdgcn_readfirstlane(key_row(key));
+            fe_prev = __builtin_amdgcn_readfirstlane(key_fitness(key));
+            // the elite ring as the per-generation launches leave it
+            if (blockIdx.x == 0 && tid == 0 && k > 0) store_dev(I.ekey + (t - 1) % 3, key);
+        }
+        if (blockIdx.x == 0 && tid == 0) store_dev(I.ekey + (t + 1) % 3, 0ull);
+        // best-so-far record of t-1, written by the workgroup owning the row
+        if (pending && (!has_best || fe_prev > best_f)) {
+            has_best = 1;
+            best_f = fe_prev;
+            const int re = e_prev - row0;
+            if (re >= 0 && re < nrows) {
+                for (int i = tid; i < wpr; i += nthr) store_dev(I.best_bits + i, sXp[re * wpr + i]);
+                if (tid == 0) {
+                    const int64_t tg = t - 1;
+                    store_dev(I.best + 1, fe_prev);
+                    store_dev(I.best + 2, sPW[((par ^ 1) * R + re) * 2]);
+                    store_dev(I.best + 3, sPW[((par ^ 1) * R + re) * 2 + 1]);
+                    store_dev(I.best + 4, (int32_t)(uint32_t)(uint64_t)tg);
+                    store_dev(I.best + 5, (int32_t)(uint32_t)((uint64_t)tg >> 32));
+                    store_dev(I.best + 6, e_prev);
+                    store_dev(I.best + 0, 1);
+                }
+            }
+        }
+        if (pending)
+            for (int i = tid; i < wpr; i += nthr) sE[i] = load_dev(xprev + (size_t)e_prev * wpr + i);
+        __syncthreads();
+
         uint32_t accP = 0u, accW = 0u;
         // the item coordinates pass through an empty asm, so nothing derived
         // from them is computed once and held across the generation loop
@@ -246,19 +345,30 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             if (row_end) { ch = 0; ++r; } else { ++ch; }
         }
         __syncthreads();
-        // Evaluation closes per row; DetermineElite offers the row's key
+        // Evaluation closes per row; DetermineElite takes the workgroup's
+        // best key (the call's last generation offers every row's key to
+        // the elite slot, as the per-generation launches do)
+        const bool last = k + 1 == gens;
+        unsigned long long rkey = 0ull;
         if (tid < nrows) {
             const int32_t Pi = (int32_t)sSum[2 * tid], Wi = (int32_t)sSum[2 * tid + 1];
             sSum[2 * tid] = 0u;
             sSum[2 * tid + 1] = 0u;
             const int32_t f = (Wi <= I.capacity) ? Pi : -(Wi - I.capacity);
             sF[par * R + tid] = f;
+            sPW[(par * R + tid) * 2] = Pi;
+            sPW[(par * R + tid) * 2 + 1] = Wi;
             const int c = row0 + tid;
             const int slot = par * np + c;
             I.fit[slot] = f;
             I.prof[slot] = Pi;
             I.wt[slot] = Wi;
-            offer_key(&I.ekey[t % 3], make_key(f, c));
+            if (last) offer_key(&I.ekey[t % 3], make_key(f, c));
+            rkey = slot_key(f, c);
+        }
+        if (!last) {
+            rkey = wave_max_u64_dpp(rkey);
+            if (lane == 0) s_wkey[wave] = rkey;
         }
         if (k + 1 == gens) {
             // the planes as the per-generation launches leave them (rotation
@@ -278,7 +388,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             }
             break;      // the launch boundary ends the last generation
         }
-        if (!grid_barrier(I.sync, (uint32_t)(k + 1) * gridDim.x, spin_ticks, &s_flag)) return;
+        publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, k);
     }
 }
 
@@ -348,7 +458,8 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
     onchip_limits(&lim, &ncu);
     const OnchipFn f = onchip_fn(p.K);
     if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(onchip_reset_kernel, dim3(1), dim3(64), 0, s, dI);
+    hipLaunchKernelGGL(onchip_reset_kernel, dim3((unsigned)((2 * p.blocks + 255) / 256)), dim3(256),
+                       0, s, dI, p.blocks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const InstDev* a0 = dI;

@@ -65,7 +65,7 @@ static void check_arena()
                 {L.best_bits, wpr * 4, "best_bits"},
                 {L.tbase, 8, "tbase"},
                 {L.conv, 256, "conv"},
-                {L.sync, 64, "sync"},
+                {L.sync, 64 + 16 * (size_t)std::min(np, (int32_t)kOnchipMaxBlocks), "sync"},
                 {L.part, (size_t)L.part_nseg * np * 8, "part"}};
             size_t end = 0;
             for (const B& b : blocks) {

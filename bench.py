@@ -32,6 +32,16 @@ KERNEL_SOURCES = ["paper_2609_30862_amd/csrc/qieo_kernels.hip",
                   "paper_2609_30862_amd/csrc/qieo_kernels.hpp",
                   "paper_2609_30862_amd/csrc/qieo_layout.hpp"]
 PROFILE = "profiles/generation_kernel_np4096_ng200000.md"
+# the on-chip loop's sources and its instruction-count summary
+ONCHIP_SOURCES = ["paper_2609_30862_amd/csrc/qieo_onchip.hip",
+                  "paper_2609_30862_amd/csrc/qieo_device.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_elite.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_host.hpp",
+                  "paper_2609_30862_amd/csrc/qieo_layout.hpp"]
+ONCHIP_PROFILE = "profiles/onchip_kernel_np1024_ng10000.md"
+# vector ALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one non-packed instruction per lane and cycle), in G lane-instructions/s
+VALU_PEAK_G = 256 * 4 * 16 * 2.4
 # kernels of the whole-call paths (qieo_get_call_path 1, 2, 3)
 PATH_KERNELS = {1: "resident_kernel (one launch per call)",
                 2: "persistent_kernel (one launch per call)",
@@ -42,19 +52,37 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_code_digest(read=None) -> str:
+def kernel_code_digest(read=None, sources=None) -> str:
     """sha256 of the kernel sources' code: each line with its // comment and
     surrounding blanks removed, empty lines dropped (comments do not change
     what the counters measured).  read(path) -> text, default: the tree."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (sources or KERNEL_SOURCES):
         text = read(f) if read else open(os.path.join(ROOT, f)).read()
         for line in text.splitlines():
             code = line.split("//", 1)[0].strip()
             if code:
                 h.update(code.encode() + b"\n")
     return h.hexdigest()
+
+
+def onchip_valu_per_generation(n_pop: int, n_items: int):
+    """Vector ALU instructions (per wave, summed over the grid) of one
+    generation of the on-chip loop, from the committed rocprofv3 summary, if
+    it was taken on this workload with the current on-chip code; else None."""
+    if (n_pop, n_items) != (1024, 10_000):
+        return None
+    keys = ("valu_insts_per_generation", "onchip_code_sha256")
+    try:
+        text = open(os.path.join(ROOT, ONCHIP_PROFILE)).read()
+        fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                   if line.strip().startswith(tuple(k + ":" for k in keys)))
+        if fig.get("onchip_code_sha256") != kernel_code_digest(sources=ONCHIP_SOURCES):
+            return None
+        return float(fig["valu_insts_per_generation"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def measured_traffic(n_pop: int, n_items: int, shape=None, precision: int = 64):
@@ -636,6 +664,15 @@ def main():
     log("rotating rows in the timed generations: %d of %d (%.5f)"
         % (sum(rot), inst.n_pop * args.steps, rot_frac))
     achieved = bytes_exact / (avg_ms * 1e-3) / 1e9
+    # the on-chip loop keeps the planes in registers: bound by vector ALU
+    # issue, measured by its instruction count (rocprofv3 SQ_INSTS_VALU)
+    valu = onchip_valu_per_generation(inst.n_pop, inst.n_items)
+    valu_rate = None if valu is None else valu * 64 / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "alu", "achieved": valu_rate, "peak": VALU_PEAK_G,
+                "unit": "G VALU lane-instructions/s",
+                "frac": None if valu_rate is None else valu_rate / VALU_PEAK_G,
+                "traffic": None, "kernel": PATH_KERNELS[3], "kernel_avg_ms": avg_ms,
+                "valu_insts_per_generation": valu}
 
     out = {
         "metric": "gene-updates/s",
@@ -669,7 +706,8 @@ def main():
         "rotating_rows": {"fraction": rot_frac, "rows": sum(rot),
                           "of": inst.n_pop * args.steps,
                           "min_per_generation": min(rot), "max_per_generation": max(rot)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": roofline if path == qieo.PATH_ONCHIP else
+                    {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      # counters were taken with one work shape and variant
                      "traffic": measured_traffic(inst.n_pop, inst.n_items, shape,
@@ -684,6 +722,9 @@ def main():
                      "bytes_per_launch": bytes_exact,
                      "bytes_per_launch_all_rows_rotating": bytes_per_launch},
     }
+    if path == qieo.PATH_ONCHIP:
+        out["note"] = ("on-chip loop: the planes stay in registers for the call, so "
+                       "hbm_frac_algorithmic is what the per-generation path would need")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on %d rows x %d generations" % (args.cpu_rows, args.cpu_gens))
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows, args.cpu_gens,

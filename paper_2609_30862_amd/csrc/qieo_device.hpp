@@ -56,6 +56,29 @@ __device__ __forceinline__ void philox_round(uint32_t& x0, uint32_t& x1, uint32_
     x0 = y0; x1 = y1; x2 = y2; x3 = y3;
 }
 
+// a ^ b ^ k in one instruction (gfx950's three-input bitwise operation,
+// truth table 0x96), for per-lane a, b and a wave-uniform k
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t k, uint32_t b)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "s"(k), "v"(b));
+    return r;
+}
+
+// A round whose four words are all per-lane: the same arithmetic as
+// philox_round, each word's two XORs in one instruction.
+__device__ __forceinline__ void philox_round_lanes(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                                   uint32_t& x3, uint32_t k0, uint32_t k1)
+{
+    const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = xor3((uint32_t)(pb >> 32), k0, x1);
+    const uint32_t y1 = (uint32_t)pb;
+    const uint32_t y2 = xor3((uint32_t)(pa >> 32), k1, x3);
+    const uint32_t y3 = (uint32_t)pa;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+}
+
 __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, uint32_t k0, uint32_t k1)
 {
@@ -64,9 +87,13 @@ __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     // chunk loop (and spill them once registers are tight), so the key is
     // passed through an empty asm here, which makes each call derive its own.
     asm volatile("" : "+s"(k0), "+s"(k1));
+    // Rounds 0 and 1 still have uniform words (only counter word 0 is
+    // per-lane at the start), which the compiler keeps scalar; from round 2
+    // on every word is per-lane.
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        philox_round(c0, c1, c2, c3, k0, k1);
+        if (r < 2) philox_round(c0, c1, c2, c3, k0, k1);
+        else philox_round_lanes(c0, c1, c2, c3, k0, k1);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

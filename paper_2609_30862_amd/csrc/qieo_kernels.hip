@@ -488,8 +488,15 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
                 for (int j = 0; j < 4; ++j) xm[j] = load_mask(xw + j);
             }
         }
-        const i32x4 v4 = gload((const i32x4*)I.v, q);
-        const i32x4 w4 = gload((const i32x4*)I.w, q);
+        // Item tables (cache hits): binary32 issues them here, so that they
+        // arrive during the draws; binary64 after the observation (issued
+        // here, the wait for its amplitudes before the LDS staging would wait
+        // for them too, and held through the chunk they cost occupancy).
+        i32x4 v4 = {0, 0, 0, 0}, w4 = {0, 0, 0, 0};
+        if constexpr (kStraight) {
+            v4 = gload((const i32x4*)I.v, q);
+            w4 = gload((const i32x4*)I.w, q);
+        }
         Draw4 d;
         if constexpr (kStraight) {
             d = philox4x32_10(q, (uint32_t)c, (uint32_t)t, 0u, I.seed_lo, I.seed_hi);
@@ -533,6 +540,11 @@ __global__ __launch_bounds__(64 * SW) void segment_kernel(const InstDev* __restr
         const uint64_t m2 = ballot(observe(d.r2, bb.z)) & actm;
         const uint64_t m3 = ballot(observe(d.r3, bb.w)) & actm;
         store_chunk_words(xcur + (size_t)c * wpr + ch * kWordsPerChunk, m0, m1, m2, m3, lane);
+        if constexpr (!kStraight) {
+            v4 = gload((const i32x4*)I.v, q);
+            w4 = gload((const i32x4*)I.w, q);
+            asm volatile("" ::"v"(v4), "v"(w4));     // both loads in flight together
+        }
         accP += masked_sum4(m0, m1, m2, m3, v4);
         accW += masked_sum4(m0, m1, m2, m3, w4);
         if constexpr (kStage) {

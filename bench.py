@@ -471,20 +471,22 @@ def bench_fractions(args):
 def bench_launch(args):
     """Small and medium single instances, where launch overhead matters: time
     per generation with one launch per generation, with graph replay of the
-    whole call, with the single-workgroup loop from LDS where the state fits
-    (persistent mode 1; per-generation launches otherwise), and with the
-    single-workgroup loop from global memory (mode 2, where LDS is too small)."""
+    whole call, in the default mode (1), with the single-workgroup loop
+    (mode 2: from LDS where the state fits, else from global memory) and
+    with the on-chip grid loop (mode 3; per-generation launches where the
+    population does not fit it)."""
     import torch
     import workloads
     from paper_2609_30862_amd import qieo
 
     shapes = [(16, 100), (32, 500), (64, 100), (64, 1000), (128, 500), (24, 5000), (256, 500),
-              (64, 4000), (256, 2000), (1024, 10_000)]
+              (64, 4000), (256, 2000), (32, 12_000), (128, 8000), (256, 8000), (512, 5000),
+              (1024, 2000), (4096, 1000), (2048, 3000), (1024, 10_000)]
     for (np_, ng) in shapes:
         inst = workloads.random_instance(ng, np_, seed=ng + np_)
         cell = {"n_pop": np_, "n_items": ng}
         for name, graph, pers in (("launches", 0, 0), ("graph", 1, 0), ("persistent", 0, 1),
-                                  ("persistent_any", 0, 2)):
+                                  ("persistent_any", 0, 2), ("onchip", 0, 3)):
             g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
             g.set_graph(graph)
             g.set_persistent(pers)
@@ -495,9 +497,10 @@ def bench_launch(args):
             g.step(500)
             cell[name] = (time.perf_counter() - t0) / 500 * 1e6
             g.close()
-        log("Np=%5d Ng=%6d  us/generation: launches %.2f  graph %.2f  persistent (LDS) %.2f  "
-            "persistent (any) %.2f" % (np_, ng, cell["launches"], cell["graph"], cell["persistent"],
-                                       cell["persistent_any"]))
+        log("Np=%5d Ng=%6d  us/generation: launches %.2f  graph %.2f  default mode %.2f  "
+            "single workgroup %.2f  on-chip %.2f"
+            % (np_, ng, cell["launches"], cell["graph"], cell["persistent"],
+               cell["persistent_any"], cell["onchip"]))
         print(json.dumps(cell), flush=True)
 
 

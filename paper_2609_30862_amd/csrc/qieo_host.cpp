@@ -191,6 +191,11 @@ size_t onchip_lds_bytes(int R, int32_t nchunk)
     return (words * sizeof(uint32_t) + 15) / 16 * 16;
 }
 
+bool onchip_worth(int32_t np, int32_t nchunk)
+{
+    return (int64_t)np * nchunk >= 4096 || nchunk >= 20;
+}
+
 bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out)
 {
     // rows travel in 16 bits of the workgroups' keys

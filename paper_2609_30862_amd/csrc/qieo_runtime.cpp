@@ -435,11 +435,12 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
     // populations whose planes fit the chip's registers: the whole call in
     // one cooperative launch that holds them there (mode 1 from
     // kOnchipMinGens generations on, where the planes' one load and one store
-    // per call cost less than the per-generation launches' traffic; mode 3
-    // for every call).  Not with a convergence window.
+    // per call cost less than the per-generation launches' traffic, for
+    // populations large enough to pay for its synchronisation; mode 3 for
+    // every call).  Not with a convergence window.
     if (h->pipeline == QIEO_PIPELINE_FUSED && h->window == 0 &&
         (h->persistent == 3 || (h->persistent == 1 && n >= kOnchipMinGens &&
-                                (int64_t)h->np * h->L.nchunk > 16))) {
+                                onchip_worth(h->np, h->L.nchunk)))) {
         OnchipPlan p;
         size_t lim = 0;
         int ncu = 0;

@@ -347,8 +347,9 @@ void qieo_server_destroy(qieo_server *s);
  *    at its end, a grid barrier per generation (Sec. III-B's loop, with
  *    DetermineElite's result final at each barrier).  It takes populations
  *    of up to 16 x 10 (row, 256-gene chunk) items per compute unit whose
- *    item tables fit in LDS, e.g. 1024 x 10,000 on 256 compute units, and
- *    no convergence window.
+ *    item tables fit in LDS, e.g. 1024 x 10,000 on 256 compute units,
+ *    with or without a convergence window (each workgroup makes the window
+ *    test on the elites it gathers; all stop at the same generation).
  * mode 0: never (per-generation launches); 1 (default): the single
  * workgroup from LDS for tiny populations (n_pop * ceil(n_items / 256) <=
  * 16), the on-chip grid for calls of >= 4 generations of populations it

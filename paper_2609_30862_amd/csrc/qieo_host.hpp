@@ -80,6 +80,8 @@ struct OnchipPlan {
     int blocks = 0;     // workgroups, at most one per CU
     int K = 0;          // items per wave: a compiled variant
     size_t lds = 0;     // dynamic LDS bytes per workgroup
+    bool conv = false;  // the variant that makes the convergence-window test
+                        // (set by the caller: the instance has a window)
 };
 // Item tables, the workgroup's own allele words of two generations, the
 // elite's words, and per row the fitness, profit and weight of two

@@ -63,9 +63,10 @@ hipError_t launch_persistent(const InstDev* dI, const uint32_t* ids, int n_block
 // workgroups runs all gens generations of instance 0 with its planes in
 // registers (p from onchip_plan); a small launch before it clears the
 // abort flag and the workgroups' key slots.  The call's last generation's
-// bookkeeping is left to launch_finish.  A barrier wait longer than
-// spin_ticks (device wall-clock ticks) raises the abort flag sync[1] and ends
-// the launch early.
+// bookkeeping is left to launch_finish.  p.conv selects the variant that
+// makes the convergence-window test (the other one assumes window 0).  A
+// barrier wait longer than spin_ticks (device wall-clock ticks) raises the
+// abort flag sync[1] and ends the launch early.
 // onchip_limits: the dynamic LDS every variant may use and the CUs of the
 // current device, both 0 where the loop cannot run (no cooperative launch, or
 // a variant whose registers do not allow one workgroup per CU).

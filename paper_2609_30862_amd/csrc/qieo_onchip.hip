@@ -38,6 +38,14 @@
 // its LDS.  Waits are bounded in time: past the bound a thread raises the
 // abort flag, every workgroup that sees it leaves, and the host reports the
 // call as failed (the state is then undefined).
+//
+// Convergence window (Sec. IV-A): every workgroup knows every elite fitness
+// of the call, so each counts the run of equal values that ends at the
+// latest elite (seeded from the fitness ring at the start of the call) and
+// all of them stop at the same generation: the one after the elite that
+// completes a run of window equal values.  That generation does not run;
+// the first workgroup records the stop the way the per-generation launches
+// do, and the planes are written back as they stand.
 #include <mutex>
 
 #include "qieo_device.hpp"
@@ -156,7 +164,27 @@ __global__ void onchip_reset_kernel(const InstDev* __restrict__ insts, int nb)
     if (i < 2 * nb) slots[i] = 0ull;
 }
 
+// The planes of the wave's K items back to global memory, from registers.
 template <int K>
+__device__ __forceinline__ void store_planes(const InstDev& I, const f32x4 (&A)[K],
+                                             const f32x4 (&B)[K], int row0, int r, int ch,
+                                             int lane, int first, int n_items)
+{
+    const int pitch = I.pitch, nchunk = I.nchunk;
+    asm volatile("" : "+s"(r), "+s"(ch), "+v"(lane));
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const uint32_t g0 = (uint32_t)(ch * kChunk) + 4u * (uint32_t)lane;
+        if (first + u < n_items && g0 < (uint32_t)pitch) {
+            const size_t base = (size_t)(row0 + r) * pitch;
+            gstore((f32x4*)(I.alpha + base), g0 >> 2, A[u]);
+            gstore((f32x4*)(I.beta + base), g0 >> 2, B[u]);
+        }
+        if (++ch == nchunk) { ch = 0; ++r; }
+    }
+}
+
+template <int K, bool CONV>
 __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev* __restrict__ insts,
                                                                   int R, int gens,
                                                                   int64_t spin_ticks)
@@ -183,6 +211,21 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
     const int nb = (int)gridDim.x;
 
     const int64_t t0 = sload(I.tbase);
+    // CONV: the instance has a convergence window (the launch without it
+    // keeps none of the test's state in registers)
+    const int window = CONV ? sload(I.conv + 3) : 0;
+    if (CONV && sload(I.conv) != 0) return;         // converged in an earlier call
+    // run of equal elite fitness values ending at generation t0 - 1 (counted
+    // as far back as the ring reaches, which covers any window)
+    int run = 0;
+    int32_t run_fe = 0;
+    if (CONV && t0 > 0) {
+        const int lim = (int)min<int64_t>(t0, kConvRing);
+        run_fe = sload(I.conv + 8 + (int)((t0 - 1) & (kConvRing - 1)));
+        run = 1;
+        while (run < lim && sload(I.conv + 8 + (int)((t0 - 1 - run) & (kConvRing - 1))) == run_fe)
+            ++run;
+    }
     // the best-so-far record as the previous launch left it; every
     // workgroup follows it the same way
     int has_best = __builtin_amdgcn_readfirstlane(I.best[0]);
@@ -229,7 +272,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
     }
     __syncthreads();
 
-    for (int k = 0; k < gens; ++k) {
+    for (int k = 0; CONV || k < gens; ++k) {
         const int64_t t = t0 + k;
         const int par = (int)(t & 1);
         const bool pending = t > 0;
@@ -239,9 +282,11 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
         uint32_t* xcur = I.xbits + (size_t)par * np * wpr;
         // DetermineElite of t-1: the previous launch's elite slot, or the
         // maximum of the workgroups' keys of generation k - 1, gathered as
-        // they are published (the grid barrier)
+        // they are published (the grid barrier).  k == gens (the window's
+        // variant only): the call's generations are done.
+        const bool done = CONV && k == gens;
         int32_t e_prev = 0, fe_prev = 0;
-        if (pending) {
+        if (pending && !done) {
             unsigned long long key;
             if (k == 0) {
                 key = load_dev(I.ekey + (t - 1) % 3);
@@ -258,9 +303,25 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             // the elite ring as the per-generation launches leave it
             if (blockIdx.x == 0 && tid == 0 && k > 0) store_dev(I.ekey + (t - 1) % 3, key);
         }
-        if (blockIdx.x == 0 && tid == 0) store_dev(I.ekey + (t + 1) % 3, 0ull);
+        // termination test on the elite of t-1 (for k = 0 the previous
+        // call's finish already made it)
+        bool stop = false;
+        if (CONV && pending && k > 0 && !done) {
+            run = (run > 0 && fe_prev == run_fe) ? run + 1 : 1;
+            run_fe = fe_prev;
+            stop = run >= window;
+            if (blockIdx.x == 0 && tid == 0) {
+                store_dev(I.conv + 8 + (int)((t - 1) & (kConvRing - 1)), fe_prev);
+                if (stop) {
+                    store_dev(I.conv + 1, (int32_t)(uint32_t)(uint64_t)(t - 1));
+                    store_dev(I.conv + 2, (int32_t)(uint32_t)((uint64_t)(t - 1) >> 32));
+                    store_dev(I.conv + 0, 1);
+                }
+            }
+        }
+        if (blockIdx.x == 0 && tid == 0 && !done && !stop) store_dev(I.ekey + (t + 1) % 3, 0ull);
         // best-so-far record of t-1, written by the workgroup owning the row
-        if (pending && (!has_best || fe_prev > best_f)) {
+        if (pending && !done && (!has_best || fe_prev > best_f)) {
             has_best = 1;
             best_f = fe_prev;
             const int re = e_prev - row0;
@@ -277,6 +338,14 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
                     store_dev(I.best + 0, 1);
                 }
             }
+        }
+        if (done || stop) {
+            // the planes as generation t-1 left them (its rotation pending),
+            // as the per-generation launches leave them; written from one
+            // place inside the loop, so the amplitude registers are neither
+            // live past it nor copied for a second exit
+            store_planes<K>(I, A, B, row0, r_first, ch_first, lane, first, n_items);
+            break;
         }
         if (pending)
             for (int i = tid; i < wpr; i += nthr) sE[i] = load_dev(xprev + (size_t)e_prev * wpr + i);
@@ -370,41 +439,34 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             rkey = wave_max_u64_dpp(rkey);
             if (lane == 0) s_wkey[wave] = rkey;
         }
-        if (k + 1 == gens) {
-            // the planes as the per-generation launches leave them (rotation
-            // of the last generation pending); written inside the loop, so
-            // the amplitude registers are not live past it
-            int rw = r_first, cw = ch_first, lw = lane;
-            asm volatile("" : "+s"(rw), "+s"(cw), "+v"(lw));
-#pragma unroll
-            for (int u = 0; u < K; ++u) {
-                const uint32_t g0 = (uint32_t)(cw * kChunk) + 4u * (uint32_t)lw;
-                if (first + u < n_items && g0 < (uint32_t)pitch) {
-                    const size_t base = (size_t)(row0 + rw) * pitch;
-                    gstore((f32x4*)(I.alpha + base), g0 >> 2, A[u]);
-                    gstore((f32x4*)(I.beta + base), g0 >> 2, B[u]);
-                }
-                if (++cw == nchunk) { cw = 0; ++rw; }
-            }
-            break;      // the launch boundary ends the last generation
+        if (!CONV && last) {
+            // the same write-back, at the end of the last generation (the
+            // register allocation of the variant without the window test
+            // holds the amplitudes in fewer registers this way)
+            store_planes<K>(I, A, B, row0, r_first, ch_first, lane, first, n_items);
+            break;
         }
-        publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, k);
+        // the launch boundary ends the last generation
+        if (!last) publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, k);
     }
 }
 
 typedef void (*OnchipFn)(const InstDev*, int, int, int64_t);
 
+template <bool CONV>
 OnchipFn onchip_fn(int K)
 {
     switch (K) {
-        case 2: return onchip_kernel<2>;
-        case 4: return onchip_kernel<4>;
-        case 6: return onchip_kernel<6>;
-        case 8: return onchip_kernel<8>;
-        case 10: return onchip_kernel<10>;
+        case 2: return onchip_kernel<2, CONV>;
+        case 4: return onchip_kernel<4, CONV>;
+        case 6: return onchip_kernel<6, CONV>;
+        case 8: return onchip_kernel<8, CONV>;
+        case 10: return onchip_kernel<10, CONV>;
         default: return nullptr;
     }
 }
+
+OnchipFn onchip_fn(int K, bool conv) { return conv ? onchip_fn<true>(K) : onchip_fn<false>(K); }
 
 }  // namespace
 
@@ -430,16 +492,18 @@ void onchip_limits(size_t* lds_limit, int* n_cu)
         }
         constexpr size_t kStatic = 256;           // the kernel's own __shared__ variables
         const size_t want = (size_t)smem > kStatic ? (size_t)smem - kStatic : 0;
-        for (int K : kOnchipK) {
-            const void* f = reinterpret_cast<const void*>(onchip_fn(K));
-            int blocks = 0;
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) !=
-                    hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64 * kOnchipWaves,
-                                                             want) != hipSuccess ||
-                blocks < 1) {
-                (void)hipGetLastError();
-                return;
+        for (bool conv : {false, true}) {
+            for (int K : kOnchipK) {
+                const void* f = reinterpret_cast<const void*>(onchip_fn(K, conv));
+                int blocks = 0;
+                if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)want) != hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64 * kOnchipWaves,
+                                                                 want) != hipSuccess ||
+                    blocks < 1) {
+                    (void)hipGetLastError();
+                    return;
+                }
             }
         }
         lim = want;
@@ -456,7 +520,7 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
     size_t lim = 0;
     int ncu = 0;
     onchip_limits(&lim, &ncu);
-    const OnchipFn f = onchip_fn(p.K);
+    const OnchipFn f = onchip_fn(p.K, p.conv);
     if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
     hipLaunchKernelGGL(onchip_reset_kernel, dim3((unsigned)((2 * p.blocks + 255) / 256)), dim3(256),
                        0, s, dI, p.blocks);

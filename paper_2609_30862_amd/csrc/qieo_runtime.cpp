@@ -437,8 +437,8 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
     // kOnchipMinGens generations on, where the planes' one load and one store
     // per call cost less than the per-generation launches' traffic, for
     // populations large enough to pay for its synchronisation; mode 3 for
-    // every call).  Not with a convergence window.
-    if (h->pipeline == QIEO_PIPELINE_FUSED && h->window == 0 &&
+    // every call), with or without a convergence window.
+    if (h->pipeline == QIEO_PIPELINE_FUSED &&
         (h->persistent == 3 || (h->persistent == 1 && n >= kOnchipMinGens &&
                                 onchip_worth(h->np, h->L.nchunk)))) {
         OnchipPlan p;
@@ -452,6 +452,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
                 if (rc) return rc;
                 (void)hipEventRecord(a, h->stream);
             }
+            p.conv = h->window > 0;
             if ((e = launch_onchip(h->d_desc, p, n, onchip_spin_ticks(h->device, h->barrier_us),
                                    h->stream)) !=
                 hipSuccess)

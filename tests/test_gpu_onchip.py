@@ -3,8 +3,9 @@ calls of >= 4 generations): one cooperative launch per call, amplitudes in
 registers, a grid barrier per generation.  Against the oracle at the medium
 workload and on shapes that exercise its item split (rows per workgroup,
 items per wave, waves whose items span rows, waves with no item, rows
-shorter than a chunk, a ragged last workgroup), and across calls that mix it
-with per-generation launches, exports and checkpoints."""
+shorter than a chunk, a ragged last workgroup), across calls that mix it
+with per-generation launches, exports and checkpoints, and with a
+convergence window."""
 import os
 
 import numpy as np
@@ -120,19 +121,48 @@ def test_default_mode_takes_it_for_calls_of_four_or_more(qieo, oracle_mod):
 
 def test_populations_it_does_not_take_run_per_generation(qieo, oracle_mod):
     """Mode 3 on a population beyond its register budget (4096 x 5000:
-    16 rows of 20 chunks per compute unit) and with a convergence window:
-    per-generation launches, same results as the oracle."""
+    16 rows of 20 chunks per compute unit): per-generation launches, same
+    results as the oracle."""
     inst = workloads.random_instance(5000, 4096, seed=433)
     g, o = _pair(qieo, oracle_mod, inst)
     assert _step_path(g, 5) == (qieo.PATH_LAUNCHES, 5)
     o.run(5)
     assert_state_equal(g, o, label="4096 x 5000, mode 3")
     g.close()
-    inst = workloads.random_instance(2000, 300, seed=434)
-    g = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
-    g.set_convergence(3)
-    g.set_persistent(3)
-    assert _step_path(g, 6) == (qieo.PATH_LAUNCHES, 6)
+
+
+# (n_items, n_pop, seed, window, calls, mode): where the oracle stops is
+# noted per case; the calls put the stop mid-call, at a call's last
+# generation (found by the finish, the next call then runs nothing), and
+# after a run of equal elites that began in an earlier call (the run is
+# seeded from the fitness ring).
+@pytest.mark.parametrize("ng,n_pop,seed,window,calls,mode", [
+    (3000, 1000, 441, 2, [10, 30, 40], 3),     # stops after 67, in the third call
+    (3000, 1000, 441, 2, [10, 30, 40], 1),     # the same calls in the default mode
+    (700, 2000, 442, 3, [1, 50, 200], 3),      # 136
+    (9000, 300, 443, 2, [13, 5], 3),           # 13: the first call's finish
+    (500, 600, 447, 3, [40, 30], 3),           # 42: the run began in the first call
+    (256, 1024, 448, 3, [100, 100], 3),        # 136
+    (256, 1024, 448, 1, [5, 5], 3),            # window 1: every elite completes it
+    (60, 4000, 446, 8, [4, 4, 100], 3),        # 65
+    (12000, 50, 445, 2, [7, 50], 3),           # 23
+])
+def test_convergence_window_stops_with_the_oracle(qieo, oracle_mod, ng, n_pop, seed, window,
+                                                  calls, mode):
+    inst = workloads.random_instance(ng, n_pop, seed=seed)
+    g, o = _pair(qieo, oracle_mod, inst, mode=mode)
+    g.set_convergence(window)
+    n = o.run_until_converged(sum(calls), window)
+    assert o.converged(window), "the case is meant to converge"
+    for c in calls:
+        assert _step_path(g, c) == (qieo.PATH_ONCHIP, 1), "call of %d" % c
+    conv, at = g.converged()
+    assert (g.generations, conv, at) == (n, 1, n - 1)
+    assert_state_equal(g, o, label="%d x %d, window %d" % (n_pop, ng, window))
+    g.step(6)                                  # nothing runs after convergence
+    assert g.call_path() == qieo.PATH_ONCHIP and g.generations == n
+    assert_state_equal(g, o, label="%d x %d, window %d, after" % (n_pop, ng, window))
+    say("  %d x %d, window %d: stops after %d generations with the oracle" % (n_pop, ng, window, n))
     g.close()
 
 

@@ -87,9 +87,9 @@ __device__ __forceinline__ Draw4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     // chunk loop (and spill them once registers are tight), so the key is
     // passed through an empty asm here, which makes each call derive its own.
     asm volatile("" : "+s"(k0), "+s"(k1));
-    // Rounds 0 and 1 still have uniform words (only counter word 0 is
-    // per-lane at the start), which the compiler keeps scalar; from round 2
-    // on every word is per-lane.
+    // The first two Philox rounds still have uniform words (only counter
+    // word 0 is per-lane at the start), which the compiler keeps scalar;
+    // from the third on every word is per-lane.
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r < 2) philox_round(c0, c1, c2, c3, k0, k1);

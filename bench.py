@@ -537,7 +537,11 @@ def main():
                          "fractions: per-step costs of the fused and unfused pipelines; "
                          "launch: launch-bound small instances; stream: HBM reference rates "
                          "on the large workload's planes")
-    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--config", type=int, choices=[1, 2, 3, 4, 5], default=None,
+                    help="the five workloads by number: 1 small, 2 medium, 3 large, 4 batch, "
+                         "5 serve (all 20,000 requests unless --requests is given)")
+    ap.add_argument("--requests", type=int, default=None,
+                    help="serve: number of requests (default 2000; 20,000 with --config 5)")
     ap.add_argument("--rate", type=float, default=500.0, help="serve: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=128.0, help="serve: HBM budget")
     ap.add_argument("--max-resident", type=int, default=0, help="serve: resident cap (0 = none)")
@@ -549,6 +553,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
+    if args.config is not None:
+        args.workload = {1: "small", 2: "medium", 3: "large", 4: "batch", 5: "serve"}[args.config]
+    if args.requests is None:
+        args.requests = 20_000 if args.config == 5 else 2000
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: libqieo runs each population on one GPU "

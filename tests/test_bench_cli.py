@@ -31,3 +31,18 @@ def test_profile_figures_parse():
         assert os.path.exists(os.path.join(ROOT, f)), f
     json.dumps({"traffic": [bench.measured_traffic(4096, 200_000, precision=p)
                             for p in (32, 64)]})
+
+
+def test_config_numbers_name_the_workloads():
+    """--config 1..5 selects the five workloads; --gpus 2 is still refused
+    first, so this runs without a GPU."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "--config" in r.stdout
+    for c in ("1", "5"):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", c,
+                            "--gpus", "2"], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2 and "one GPU" in r.stderr
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", "6"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr

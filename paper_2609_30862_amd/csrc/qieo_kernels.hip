@@ -828,11 +828,15 @@ __global__ __launch_bounds__(1024) void persistent_kernel(const InstDev* __restr
             const unsigned long long key = make_key(f, c);
             best = key > best ? key : best;
         }
-        best = wave_max_u64_dpp(best);
-        if (lane == 0) skey[wave] = best;
+        // only the waves that closed rows hold keys
+        const int nw = (min(np, (int)blockDim.x) + 63) >> 6;
+        if (wave < nw) {
+            best = wave_max_u64_dpp(best);
+            if (lane == 0) skey[wave] = best;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 1; w < S; ++w) best = skey[w] > best ? skey[w] : best;
+            for (int w = 1; w < nw; ++w) best = skey[w] > best ? skey[w] : best;
             I.ekey[t % 3] = best;
         }
         __syncthreads();
@@ -870,6 +874,9 @@ __global__ __launch_bounds__(1024) void resident_kernel(const InstDev* __restric
     const int np = I.np, pitch = I.pitch, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
     const int plane = np * pitch;
     const int items = np * nchunk;
+    // waves that close rows (thread c closes row c, c < np): only their
+    // keys enter DetermineElite's block max
+    const int nw = (min(np, nthr) + 63) >> 6;
 
     float* sA = reinterpret_cast<float*>(lds);
     float* sB = sA + plane;
@@ -1048,12 +1055,14 @@ __global__ __launch_bounds__(1024) void resident_kernel(const InstDev* __restric
             const unsigned long long key = make_key(f, c);
             best = key > best ? key : best;
         }
-        best = wave_max_u64_dpp(best);
-        if (lane == 0) skey[wave] = best;
+        if (wave < nw) {
+            best = wave_max_u64_dpp(best);
+            if (lane == 0) skey[wave] = best;
+        }
         __syncthreads();
         elite_before = elite;
         elite = skey[0];
-        for (int w = 1; w < S; ++w) elite = skey[w] > elite ? skey[w] : elite;
+        for (int w = 1; w < nw; ++w) elite = skey[w] > elite ? skey[w] : elite;
     }
     __syncthreads();
 

@@ -186,3 +186,29 @@ def test_barrier_timeout_ends_the_launch_and_is_reported(qieo):
     g.close()
     with pytest.raises(qieo.QieoError):
         qieo.Instance(inst.values, inst.weights, inst.capacity, 1, 1).set_barrier_timeout(-1)
+
+
+def test_convergence_across_a_checkpoint(qieo, oracle_mod):
+    """A run of equal elites that spans a checkpoint: the state exported
+    after generation 40 (window 3, the oracle stops after 42) is imported
+    into a fresh handle, whose on-chip call seeds its run from the restored
+    fitness ring and stops where the oracle does; the original handle,
+    continued with per-generation launches, stops there too."""
+    inst = workloads.random_instance(500, 600, seed=447)
+    g, o = _pair(qieo, oracle_mod, inst)
+    g.set_convergence(3)
+    n = o.run_until_converged(100, 3)
+    assert (n, o.converged(3)) == (42, True)
+    assert _step_path(g, 40) == (qieo.PATH_ONCHIP, 1)
+    snap = g.export_state()
+    h = qieo.Instance(inst.values, inst.weights, inst.capacity, inst.n_pop, inst.seed)
+    h.import_state(snap)
+    h.set_persistent(3)
+    assert _step_path(h, 30) == (qieo.PATH_ONCHIP, 1)
+    g.set_persistent(0)
+    assert _step_path(g, 30)[0] == qieo.PATH_LAUNCHES
+    for x, label in ((h, "imported, on-chip"), (g, "original, launches")):
+        assert (x.generations,) + tuple(x.converged()) == (n, 1, n - 1), label
+        assert_state_equal(x, o, label=label)
+    g.close()
+    h.close()

@@ -24,9 +24,11 @@
 //
 // Grid barrier and DetermineElite in one step: at the end of generation k
 // each workgroup stores its best key, tagged with k, into its slot of a
-// per-launch array (release at device scope: the XCD's L2 writes back what
-// the workgroup wrote first), and at the start of generation k + 1 one
-// thread per workgroup slot polls that slot until it carries the tag.  When
+// per-launch array, once its own stores have completed (the allele words,
+// the only data other workgroups read during the launch, are stored at
+// device scope, so completed means visible on every XCD), and at the start
+// of generation k + 1 one thread per workgroup slot polls that slot until
+// it carries the tag.  When
 // every slot has it, the workgroup holds every workgroup's key and takes
 // their maximum: the elite of k.  So no workgroup waits for a counter and
 // then reads the keys, and DetermineElite needs no atomics on one address
@@ -87,14 +89,19 @@ __device__ __forceinline__ uint32_t slot_tag(int k) { return (uint32_t)(k % 6553
 __device__ __forceinline__ void publish_key(unsigned long long* slot, const unsigned long long* wkey,
                                             int k)
 {
-    // every wave's stores (allele words, fitness, best record) have reached
-    // the L2 before the key is stored
+    // Every wave's stores have completed before the key is stored.  What
+    // other workgroups read in this launch (the allele words, through
+    // device-scope loads) was written with device-scope stores, which are
+    // complete only once they are visible to every XCD; so the key needs no
+    // release, whose write-back of the XCD's whole L2 (fitness slots and the
+    // like, which no other workgroup reads before the launch ends) measured
+    // about 1.4 us a generation.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = 0ull;
         for (int w = 0; w < kOnchipWaves; ++w) m = wkey[w] > m ? wkey[w] : m;
-        __hip_atomic_store(slot, m | slot_tag(k), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slot, m | slot_tag(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -130,7 +137,8 @@ __device__ __forceinline__ bool gather_keys(const unsigned long long* slots, int
                 *s_flag = 1;
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            // no sleep between polls: each waits a memory round trip anyway,
+            // and a pause only delays the sight of the key
         }
     }
     m = wave_max_u64_dpp(m);
@@ -392,7 +400,8 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             const uint64_t m3 = ballot(observe(d.r3, B[u].w)) & actm;
             const uint32_t word = chunk_word(m0, m1, m2, m3);
             if (valid && lane < kWordsPerChunk) {
-                gstore(xcur + (size_t)c * wpr + ch * kWordsPerChunk, (uint32_t)lane, word);
+                // device scope: the elite's words are read by every workgroup
+                store_dev(xcur + (size_t)c * wpr + ch * kWordsPerChunk + lane, word);
                 sXc[rv * wpr + ch * kWordsPerChunk + lane] = word;
             }
             // the item tables hold nchunk * 256 entries: g0 is inside

@@ -258,12 +258,16 @@ def bench_batch(args):
     loops = {}
     done_at = {}                # per-instance completion time in the loop, from its start
     same = 0
-    for mode in (() if args.skip_loop else ("graph", "launches")):
+    # the loop in the library's default mode (whole-call launches where they
+    # pay, graph capture on or off), and the plain per-generation launch loop
+    for mode in (() if args.skip_loop else ("graph", "launches", "per_generation_launches")):
         wall_loop = 0.0
         done_at[mode] = []
         for k, i in enumerate(insts):
             g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
             g.set_graph(mode == "graph")
+            if mode == "per_generation_launches":
+                g.set_persistent(0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             g.step(gens)
@@ -284,6 +288,7 @@ def bench_batch(args):
         print(json.dumps(out), flush=True)
         return
     log("identical best records %d/%d" % (same, len(insts)))
+    wall_launch_loop = loops.pop("per_generation_launches")
     wall_loop = min(loops.values())
     # per-instance latency from the start: the batched call returns every
     # result when it ends; the loop finishes instance k after the calls of
@@ -306,6 +311,9 @@ def bench_batch(args):
                               "variants_seconds": loops},
         "batch_variants_seconds": variants,
         "speedup_vs_loop": wall_loop / wall_batch,
+        "per_generation_launch_loop": {"value": genes * gens / wall_launch_loop,
+                                       "seconds": wall_launch_loop},
+        "speedup_vs_per_generation_launch_loop": wall_launch_loop / wall_batch,
         "latency_s": latency,
         "identical_best": "%d/%d" % (same, len(insts)),
         "tuned_classes": tuned,
@@ -377,6 +385,20 @@ def bench_serve(args):
     loop_rate = sum(work[:m]) / loop_s
     log("per-instance loop on %d requests: %.2f s, %.4g gene-updates/s, identical %d/%d"
         % (m, loop_s, loop_rate, same, m))
+    # the same requests as a plain per-generation launch loop (mode 0)
+    launch_s = 0.0
+    for k in range(m):
+        i = reqs[k].instance
+        g = qieo.Instance(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        g.set_persistent(0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        g.step(i.generations)
+        launch_s += time.perf_counter() - ts
+        g.close()
+    launch_rate = sum(work[:m]) / launch_s
+    log("per-generation launch loop on %d requests: %.2f s, %.4g gene-updates/s"
+        % (m, launch_s, launch_rate))
     out = {
         "metric": "gene-updates/s", "value": served, "unit": "gene-updates/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
@@ -390,6 +412,8 @@ def bench_serve(args):
         "per_instance_loop": {"requests": m, "value": loop_rate, "seconds": loop_s,
                               "identical_best": "%d/%d" % (same, m)},
         "speedup_vs_loop": served / loop_rate,
+        "per_generation_launch_loop": {"requests": m, "value": launch_rate, "seconds": launch_s},
+        "speedup_vs_per_generation_launch_loop": served / launch_rate,
     }
     print(json.dumps(out), flush=True)
 
@@ -481,7 +505,10 @@ def bench_launch(args):
 
     shapes = [(16, 100), (32, 500), (64, 100), (64, 1000), (128, 500), (24, 5000), (256, 500),
               (64, 4000), (256, 2000), (32, 12_000), (128, 8000), (256, 8000), (512, 5000),
-              (1024, 2000), (4096, 1000), (2048, 3000), (1024, 10_000)]
+              (1024, 2000), (4096, 1000), (2048, 3000), (1024, 10_000),
+              # around the default mode's on-chip threshold: 256 to 2048 (row, chunk) items
+              (256, 200), (512, 100), (96, 1300), (128, 1000), (1024, 200), (512, 400),
+              (2048, 100), (64, 8000)]
     for (np_, ng) in shapes:
         inst = workloads.random_instance(ng, np_, seed=ng + np_)
         cell = {"n_pop": np_, "n_items": ng}

@@ -353,8 +353,9 @@ void qieo_server_destroy(qieo_server *s);
  * mode 0: never (per-generation launches); 1 (default): the single
  * workgroup from LDS for tiny populations (n_pop * ceil(n_items / 256) <=
  * 16), the on-chip grid for calls of >= 4 generations of populations it
- * takes that have n_pop * ceil(n_items / 256) >= 4096 or n_items > 4864
- * (rows of 20 chunks), where it measured faster than launches; 2: a
+ * takes that have n_pop >= 256, n_pop * ceil(n_items / 256) >= 1024 or
+ * n_items > 4864 (rows of 20 chunks), where it measured faster than
+ * launches; 2: a
  * single workgroup whenever the state fits in LDS, else from
  * global memory when n_pop <= 2048; 3: the on-chip grid for every call it
  * takes.  A population or call a mode does not take runs as mode 0.

@@ -193,7 +193,7 @@ size_t onchip_lds_bytes(int R, int32_t nchunk)
 
 bool onchip_worth(int32_t np, int32_t nchunk)
 {
-    return (int64_t)np * nchunk >= 4096 || nchunk >= 20;
+    return np >= 256 || (int64_t)np * nchunk >= 1024 || nchunk >= 20;
 }
 
 bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out)

@@ -67,11 +67,12 @@ constexpr int kOnchipWaves = 16;
 // Shortest call the default mode runs this way.
 constexpr int kOnchipMinGens = 4;
 // Populations the default mode runs this way: a generation of the loop costs
-// about 6 us of synchronisation however small the population, while a
-// per-generation launch costs 4-5 us for small ones, so the loop pays from
-// about 4096 (row, chunk) items, or from rows of 20 chunks, whose launches
-// walk long chains of chunks per wave (measured over 17 shapes from 16 x 100
-// to 4096 x 1000).
+// about 6 us however small the population (its synchronisation), while a
+// per-generation launch costs 4.5-5.5 us for populations of up to ~128 rows
+// and grows with the rows (6.2 us at 256, 9.5 at 512, 15 at 1024 rows of one
+// chunk), so the loop pays from 256 rows, from 1024 (row, chunk) items, or
+// from rows of 20 chunks, whose launches walk long chains of chunks per wave
+// (measured over 25 shapes from 16 x 100 to 4096 x 1000).
 bool onchip_worth(int32_t np, int32_t nchunk);
 constexpr int kOnchipVariants = 5;
 constexpr int kOnchipK[kOnchipVariants] = {2, 4, 6, 8, 10};   // compiled items per wave

@@ -517,10 +517,11 @@ static void check_onchip_plan()
     CHECK(onchip_plan(50, 47, 256, lim, &p) && p.blocks == 50 && p.K == 4, "50 x 47");
     CHECK(!onchip_plan(1024, 40, 0, lim, &p) && !onchip_plan(1024, 40, 256, 0, &p),
           "no device support");
-    // the default mode's choice: enough items, or long rows
+    // the default mode's choice: many rows, enough items, or long rows
     CHECK(onchip_worth(1024, 40) && onchip_worth(128, 32) && onchip_worth(24, 20) &&
-              onchip_worth(4096, 4) && !onchip_worth(256, 8) && !onchip_worth(64, 16) &&
-              !onchip_worth(16, 1) && !onchip_worth(2047, 2),
+              onchip_worth(4096, 4) && onchip_worth(256, 1) && onchip_worth(64, 16) &&
+              onchip_worth(128, 8) && !onchip_worth(128, 4) && !onchip_worth(96, 6) &&
+              !onchip_worth(255, 4) && !onchip_worth(16, 1) && !onchip_worth(64, 15),
           "onchip_worth");
 }
 

@@ -119,6 +119,25 @@ def test_default_mode_takes_it_for_calls_of_four_or_more(qieo, oracle_mod):
     g.close()
 
 
+@pytest.mark.parametrize("ng,n_pop,onchip", [
+    (200, 256, True),      # 256 rows of one chunk
+    (4000, 64, True),      # 1024 (row, chunk) items
+    (5000, 24, True),      # rows of 20 chunks
+    (1000, 128, False),    # 512 items, 128 rows: per-generation launches
+    (1300, 96, False),     # 576 items
+])
+def test_default_mode_rule(qieo, oracle_mod, ng, n_pop, onchip):
+    """Mode 1 takes the loop from 256 rows, 1024 items or rows of 20 chunks
+    (calls of >= 4 generations); both sides of the rule equal the oracle."""
+    inst = workloads.random_instance(ng, n_pop, seed=450 + ng % 31)
+    g, o = _pair(qieo, oracle_mod, inst, mode=1)
+    path, _ = _step_path(g, 6)
+    assert path == (qieo.PATH_ONCHIP if onchip else qieo.PATH_LAUNCHES), (n_pop, ng, path)
+    o.run(6)
+    assert_state_equal(g, o, label="default mode %d x %d" % (n_pop, ng))
+    g.close()
+
+
 def test_populations_it_does_not_take_run_per_generation(qieo, oracle_mod):
     """Mode 3 on a population beyond its register budget (4096 x 5000:
     16 rows of 20 chunks per compute unit): per-generation launches, same

@@ -87,7 +87,7 @@ __device__ __forceinline__ uint32_t slot_tag(int k) { return (uint32_t)(k % 6553
 // Ends generation k for the workgroup: its best key (max over wkey[], one
 // per wave) goes to *slot with the tag of k, after the workgroup's stores.
 __device__ __forceinline__ void publish_key(unsigned long long* slot, const unsigned long long* wkey,
-                                            int k)
+                                            int nw, int k)
 {
     // Every wave's stores have completed before the key is stored.  What
     // other workgroups read in this launch (the allele words, through
@@ -100,7 +100,7 @@ __device__ __forceinline__ void publish_key(unsigned long long* slot, const unsi
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = 0ull;
-        for (int w = 0; w < kOnchipWaves; ++w) m = wkey[w] > m ? wkey[w] : m;
+        for (int w = 0; w < nw; ++w) m = wkey[w] > m ? wkey[w] : m;
         __hip_atomic_store(slot, m | slot_tag(k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -141,11 +141,15 @@ __device__ __forceinline__ bool gather_keys(const unsigned long long* slots, int
             // and a pause only delays the sight of the key
         }
     }
-    m = wave_max_u64_dpp(m);
-    if ((tid & 63) == 0) wkey[tid >> 6] = m;
+    // only the polling waves hold keys: they reduce, the rest wait
+    const int nwp = (nb + 63) >> 6;
+    if ((tid >> 6) < nwp) {
+        m = wave_max_u64_dpp(m);
+        if ((tid & 63) == 0) wkey[tid >> 6] = m;
+    }
     __syncthreads();
     unsigned long long r = 0ull;
-    for (int w = 0; w < kOnchipWaves; ++w) r = wkey[w] > r ? wkey[w] : r;
+    for (int w = 0; w < nwp; ++w) r = wkey[w] > r ? wkey[w] : r;
     *key = r;
     return *s_flag == 0;
 }
@@ -444,7 +448,9 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             if (last) offer_key(&I.ekey[t % 3], make_key(f, c));
             rkey = slot_key(f, c);
         }
-        if (!last) {
+        // thread c closes row c: only the waves up to the last row hold keys
+        const int nwr = (nrows + 63) >> 6;
+        if (!last && wave < nwr) {
             rkey = wave_max_u64_dpp(rkey);
             if (lane == 0) s_wkey[wave] = rkey;
         }
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             break;
         }
         // the launch boundary ends the last generation
-        if (!last) publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, k);
+        if (!last) publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, nwr, k);
     }
 }
 

@@ -48,6 +48,7 @@
 // completes a run of window equal values.  That generation does not run;
 // the first workgroup records the stop the way the per-generation launches
 // do, and the planes are written back as they stand.
+#include <map>
 #include <mutex>
 
 #include "qieo_device.hpp"
@@ -528,6 +529,30 @@ void onchip_limits(size_t* lds_limit, int* n_cu)
     *n_cu = cus;
 }
 
+namespace {
+
+// The on-chip launches of this library on one device run one after another,
+// whatever their streams: two grids that each hold one workgroup on every
+// CU could otherwise split the CUs between them and wait for each other at
+// their barriers (until the bound ends both).  Each launch waits for the
+// event the previous one recorded and records its own.  A stream under
+// graph capture is not chained (a captured wait on an event recorded
+// outside the capture is not allowed).
+struct CoopChain {
+    std::mutex m;
+    hipEvent_t last = nullptr;
+};
+
+CoopChain& coop_chain(int device)
+{
+    static std::mutex mm;
+    static std::map<int, CoopChain> chains;
+    std::lock_guard<std::mutex> g(mm);
+    return chains[device];          // std::map nodes do not move
+}
+
+}  // namespace
+
 hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64_t spin_ticks,
                          hipStream_t s)
 {
@@ -537,16 +562,32 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
     onchip_limits(&lim, &ncu);
     const OnchipFn f = onchip_fn(p.K, p.conv);
     if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return e;
+    const bool chain = cap == hipStreamCaptureStatusNone;
+    CoopChain& c = coop_chain(dev);
+    std::lock_guard<std::mutex> g(c.m);
+    if (chain) {
+        if (!c.last && (e = hipEventCreateWithFlags(&c.last, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        // an event never recorded completes at once
+        if ((e = hipStreamWaitEvent(s, c.last, 0)) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(onchip_reset_kernel, dim3((unsigned)((2 * p.blocks + 255) / 256)), dim3(256),
                        0, s, dI, p.blocks);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const InstDev* a0 = dI;
     int a1 = p.R, a2 = gens;
     int64_t a3 = spin_ticks;
     void* args[] = {&a0, &a1, &a2, &a3};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3((unsigned)p.blocks),
-                                      dim3(64 * kOnchipWaves), args, (unsigned)p.lds, s);
+    if ((e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3((unsigned)p.blocks),
+                                        dim3(64 * kOnchipWaves), args, (unsigned)p.lds, s)) !=
+        hipSuccess)
+        return e;
+    return chain ? hipEventRecord(c.last, s) : hipSuccess;
 }
 
 }  // namespace qieo

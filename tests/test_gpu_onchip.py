@@ -231,3 +231,27 @@ def test_convergence_across_a_checkpoint(qieo, oracle_mod):
         assert_state_equal(x, o, label=label)
     g.close()
     h.close()
+
+
+def test_concurrent_instances_on_their_own_streams(qieo, oracle_mod):
+    """Three instances, each on its own stream, whose calls take the on-chip
+    loop and are enqueued back to back before any is waited for: every
+    cooperative launch completes (a grid that could not be co-resident
+    would end at the barrier bound with QIEO_EDEVICE, not hang), and each
+    instance equals its oracle."""
+    insts = [workloads.random_instance(3000, 512, seed=460 + k) for k in range(3)]
+    gs, os_ = [], []
+    for inst in insts:
+        g, o = _pair(qieo, oracle_mod, inst, mode=3)
+        g.set_barrier_timeout(5_000_000)
+        gs.append(g)
+        os_.append(o)
+    for _ in range(3):
+        for g in gs:
+            g.step_async(7)
+    for g, o in zip(gs, os_):
+        g.sync()
+        assert g.call_path() == qieo.PATH_ONCHIP
+        o.run(21)
+        assert_state_equal(g, o, label="concurrent instance")
+        g.close()

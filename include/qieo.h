@@ -359,7 +359,9 @@ void qieo_server_destroy(qieo_server *s);
  * single workgroup whenever the state fits in LDS, else from
  * global memory when n_pop <= 2048; 3: the on-chip grid for every call it
  * takes.  A population or call a mode does not take runs as mode 0.
- * Results are identical in every mode.  An on-chip grid barrier that waits
+ * Results are identical in every mode.  On-chip launches of different
+ * instances on one device run one after another, whatever their streams
+ * (each grid holds every CU).  An on-chip grid barrier that waits
  * longer than its bound (qieo_set_barrier_timeout, default one second) ends
  * the launch; qieo_sync then reports QIEO_EDEVICE and the instance's state
  * is undefined. */

@@ -228,32 +228,45 @@ def bench_batch(args):
                    c["default_ms_per_generation"]))
         log("class tuning took %.1f s" % (time.perf_counter() - t0))
     variants = {}
-    for name, pers, seg in (("no_persistent", False, 1), ("persistent_small", True, 1),
-                            ("segment_order_32_chunk_rows_only", True, 2),
-                            ("row_order_long_rows", True, 0)):
+    onchip_launches = None
+    # one call per variant, each on a fresh batch; "default" is the library's
+    # default mode (members of rows under 8 chunks in batched on-chip
+    # launches, tiny members LDS-resident, rows of 8+ chunks in segment order)
+    for name, pers, seg, onchip in (("no_onchip_no_persistent", False, 1, False),
+                                    ("no_onchip", True, 1, False),
+                                    ("default", True, 1, True),
+                                    ("onchip_no_persistent", False, 1, True),
+                                    ("segment_order_32_chunk_rows_only", True, 2, True),
+                                    ("row_order_long_rows", True, 0, True)):
         b = qieo.Batch(probs)
         b.set_persistent(pers)
         b.set_segment_order(seg)
+        b.set_onchip(onchip)
+        n_onchip = b.onchip_launches()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(gens)
         variants[name] = time.perf_counter() - t0
-        best_batch = [b.best(k) for k in range(len(insts))]
+        if name == "default":
+            best_batch = [b.best(k) for k in range(len(insts))]
+            onchip_launches = n_onchip
         b.close()
-        log("batched (%s): %.3f s" % (name, variants[name]))
-    wall_batch = min(variants[k] for k in ("no_persistent", "persistent_small"))
+        log("batched (%s, %d on-chip launches): %.3f s" % (name, n_onchip, variants[name]))
+    wall_batch = variants["default"]
 
-    # replay of the same call on a batch whose graph is already captured (a
-    # call is captured when it repeats)
-    b = qieo.Batch(probs)
-    b.step(gens)
-    b.step(gens)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(gens)
-    variants["replay_captured"] = time.perf_counter() - t0
-    b.close()
-    log("batched, replay of a captured graph: %.3f s" % variants["replay_captured"])
+    # the third call of a batch: without the on-chip loop a repeated call is
+    # replayed from its captured graph; with it, launched directly
+    for name, onchip in (("replay_captured_no_onchip", False), ("third_call_default", True)):
+        b = qieo.Batch(probs)
+        b.set_onchip(onchip)
+        b.step(gens)
+        b.step(gens)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(gens)
+        variants[name] = time.perf_counter() - t0
+        b.close()
+        log("batched, third call (%s): %.3f s" % (name, variants[name]))
 
     loops = {}
     done_at = {}                # per-instance completion time in the loop, from its start
@@ -284,7 +297,7 @@ def bench_batch(args):
     if args.skip_loop:
         out = {"workload": "batch", "batch_variants_seconds": variants,
                "value": genes * gens / wall_batch, "unit": "gene-updates/s",
-               "tuned_classes": tuned}
+               "onchip_launches": onchip_launches, "tuned_classes": tuned}
         print(json.dumps(out), flush=True)
         return
     log("identical best records %d/%d" % (same, len(insts)))
@@ -310,6 +323,7 @@ def bench_batch(args):
         "per_instance_loop": {"value": genes * gens / wall_loop, "seconds": wall_loop,
                               "variants_seconds": loops},
         "batch_variants_seconds": variants,
+        "onchip_launches": onchip_launches,
         "speedup_vs_loop": wall_loop / wall_batch,
         "per_generation_launch_loop": {"value": genes * gens / wall_launch_loop,
                                        "seconds": wall_launch_loop},

@@ -290,6 +290,30 @@ int qieo_batch_set_persistent(qieo_batch *b, int32_t enabled);
  * for every member.  Other values give QIEO_EINVAL.  Ignored while
  * qieo_batch_set_tile forces a shape.  Results are identical. */
 int qieo_batch_set_segment_order(qieo_batch *b, int32_t mode);
+/* 1 (default): every member that fits runs every generation of a call
+ * inside cooperative launches with its amplitude planes held in registers,
+ * the on-chip loop of qieo_set_persistent mode 3 extended to many members:
+ * each member on workgroups of whole rows (rows of up to 160 chunks of 256
+ * genes), its workgroups waiting only for each other at the end of each
+ * generation (Sec. III-B's loop: DetermineElite over the member's rows
+ * before its CIP), at most one workgroup per CU, so a batch of more rows
+ * than that takes several such launches one after another; they run before
+ * the call's other launches, alone on the device.  The members it cannot
+ * place (longer rows, too many rows for one launch) keep the per-generation
+ * launches (LDS-resident, segment or row order as set above).  Taken only
+ * while no member has a convergence window and no shape is forced, and not
+ * with graph capture (such a call is launched directly).  0: every member
+ * per-generation launches.  Results are identical.  A barrier wait past its
+ * bound (qieo_batch_set_barrier_timeout) makes the call fail with
+ * QIEO_EDEVICE when the batch is synchronised, its members' state then
+ * undefined. */
+int qieo_batch_set_onchip(qieo_batch *b, int32_t enabled);
+/* On-chip launches (see qieo_batch_set_onchip) one call of the current
+ * membership makes (0 if none); plans the batch if membership changed. */
+int qieo_batch_onchip_launches(qieo_batch *b, int32_t *n);
+/* Bound on one barrier wait of the batched on-chip loop, in microseconds
+ * (default one second); QIEO_EINVAL if negative. */
+int qieo_batch_set_barrier_timeout(qieo_batch *b, int64_t microseconds);
 void qieo_batch_destroy(qieo_batch *b);
 
 /* ---- server: continuous batching of solve requests ----------------------- */

@@ -334,18 +334,116 @@ int class_of(int32_t nchunk)
     return 4;
 }
 
+void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size_t>& ids,
+                 const PlanOptions& opt, std::vector<OnchipLaunch>* out, std::vector<size_t>* rest)
+{
+    out->clear();
+    rest->clear();
+    struct Place {
+        size_t id;
+        int32_t R, nb;
+        size_t lds;
+    };
+    std::vector<std::vector<Place>> by_variant(kOnchipVariants);
+    for (size_t i : ids) {
+        const MemberShape& m = members[i];
+        int best = -1;
+        double best_cost = 0.0;
+        Place pick{};
+        for (int v = 0; v < kOnchipVariants && opt.onchip_blocks > 0; ++v) {
+            if (!(opt.onchip_variants & (1u << v))) continue;
+            const int K = kOnchipK[v];
+            const int64_t cap = (int64_t)kOnchipWaves * K;    // items a workgroup holds
+            if (m.np < 1 || m.np > 65536 || m.nchunk < 1 || m.nchunk > cap) continue;
+            int64_t R = std::min<int64_t>(m.np, cap / m.nchunk);
+            int64_t nb = (m.np + R - 1) / R;
+            R = (m.np + nb - 1) / nb;                         // balanced: same nb, fewer rows
+            nb = (m.np + R - 1) / R;
+            const size_t lds = onchip_lds_bytes((int)R, m.nchunk);
+            if (nb > opt.onchip_blocks || lds > opt.onchip_lds_limit) continue;
+            // the member's share of a launch's generation: its workgroups
+            // times the cost of one workgroup-generation of variant K
+            const double cost = (double)nb * (6.0 + 1.1 * K);
+            if (best < 0 || cost < best_cost) {
+                best = v;
+                best_cost = cost;
+                pick = Place{i, (int32_t)R, (int32_t)nb, lds};
+            }
+        }
+        if (best < 0) rest->push_back(i);
+        else by_variant[best].push_back(pick);
+    }
+    // per variant (largest K first), first fit by decreasing workgroup count
+    for (int v = kOnchipVariants - 1; v >= 0; --v) {
+        std::vector<Place>& placed = by_variant[v];
+        if (placed.empty()) continue;
+        std::stable_sort(placed.begin(), placed.end(),
+                         [](const Place& a, const Place& b) { return a.nb > b.nb; });
+        std::vector<int64_t> used;
+        std::vector<std::vector<size_t>> bins;
+        for (size_t p = 0; p < placed.size(); ++p) {
+            size_t b = 0;
+            while (b < used.size() && used[b] + placed[p].nb > opt.onchip_blocks) ++b;
+            if (b == used.size()) {
+                used.push_back(0);
+                bins.emplace_back();
+            }
+            used[b] += placed[p].nb;
+            bins[b].push_back(p);
+        }
+        for (auto& bin : bins) {
+            OnchipLaunch L;
+            L.K = kOnchipK[v];
+            // members in index order inside a launch
+            std::sort(bin.begin(), bin.end(),
+                      [&](size_t a, size_t b) { return placed[a].id < placed[b].id; });
+            for (size_t p : bin) {
+                const Place& q = placed[p];
+                const int32_t np = members[q.id].np;
+                for (int32_t b = 0; b < q.nb; ++b) {
+                    OnchipTile t{};
+                    t.inst = (uint32_t)q.id;
+                    t.row0 = b * q.R;
+                    t.nrows = std::min(q.R, np - t.row0);
+                    t.R = q.R;
+                    t.blk = b;
+                    t.nb = q.nb;
+                    L.tiles.push_back(t);
+                }
+                L.lds = std::max(L.lds, q.lds);
+            }
+            out->push_back(std::move(L));
+        }
+    }
+}
+
 int plan_batch(const std::vector<MemberShape>& members, const PlanOptions& opt, BatchPlan* out)
 {
     out->resident.clear();
     out->resident_lds = 0;
+    out->onchip.clear();
     out->classes.clear();
     const size_t n = members.size();
     if (n > (size_t)UINT32_MAX) return set_error(QIEO_EINVAL, "too many members (%zu)", n);
 
-    // members whose whole state fits in one workgroup's LDS run the call
-    // there (one workgroup each); the rest are grouped by shape class
+    // The batched on-chip loop takes every member it can place (not under a
+    // forced shape): its workgroups hold their members' planes in registers
+    // for the whole call, at about 6e11 gene-updates/s for the chip (vector
+    // ALU bound) against about 3.7e11 streamed from HBM at 16 B a gene.
+    std::vector<size_t> rest;
+    {
+        std::vector<size_t> all(n);
+        for (size_t i = 0; i < n; ++i) all[i] = i;
+        if (opt.onchip_blocks > 0 && opt.force_R == 0)
+            plan_onchip(members, all, opt, &out->onchip, &rest);
+        else
+            rest = std::move(all);
+    }
+    // of the others, members whose whole state fits in one workgroup's LDS
+    // run the call there (one workgroup each); the rest are grouped by shape
+    // class
     std::vector<std::vector<size_t>> groups(kClasses);
-    for (size_t i = 0; i < n; ++i) {
+    for (size_t i : rest) {
         const MemberShape& m = members[i];
         const size_t lds = resident_lds_bytes(m.np, m.pitch, m.nchunk);
         if (opt.use_persistent && lds <= opt.lds_limit) {
@@ -359,10 +457,11 @@ int plan_batch(const std::vector<MemberShape>& members, const PlanOptions& opt, 
     std::stable_sort(out->resident.begin(), out->resident.end(), [&](uint32_t a, uint32_t b) {
         return (int64_t)members[a].np * members[a].pitch > (int64_t)members[b].np * members[b].pitch;
     });
-    // amplitude bytes one generation of the whole batch streams (the classes
-    // run side by side, so they share the caches)
+    // amplitude bytes one generation of the batch streams, on-chip members
+    // aside (the classes run side by side, so they share the caches)
     int64_t plane_bytes = 0;
-    for (auto& m : members) plane_bytes += (int64_t)m.np * m.pitch * 2 * (int64_t)sizeof(float);
+    for (size_t i : rest)
+        plane_bytes += (int64_t)members[i].np * members[i].pitch * 2 * (int64_t)sizeof(float);
     // A batch that streams from HBM runs the rows of 8 or more chunks in
     // segment order, all in one table (one launch pair per generation), when
     // that table stays within kMaxSegTiles; else only the >= 32-chunk class

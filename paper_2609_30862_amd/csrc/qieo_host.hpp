@@ -139,6 +139,13 @@ struct MemberShape {
 struct PlanOptions {
     bool use_persistent = true;   // LDS-resident members as single workgroups
     size_t lds_limit = 0;         // dynamic LDS the resident kernel may take
+    // Batched on-chip loop for every member it can place (before the
+    // LDS-resident set and the classes): workgroups per launch (the
+    // device's CUs; 0 = off), the dynamic LDS a workgroup may take, and the
+    // usable compiled variants (bit v: kOnchipK[v]).
+    int onchip_blocks = 0;
+    size_t onchip_lds_limit = 0;
+    unsigned onchip_variants = 0;
     bool use_segments = true;     // long rows in segment order when the batch streams
     bool merge_segments = true;   // rows of 8+ chunks in one segment table
     int force_R = 0, force_S = 0, force_flags = 0;   // every class, when force_R > 0
@@ -160,11 +167,33 @@ struct ClassPlan {
     std::vector<Tile> tiles, fe_tiles;
 };
 
+// One cooperative launch of the batched on-chip loop: every generation of
+// the call for the members its tiles cover, one workgroup per tile.
+struct OnchipLaunch {
+    int K = 0;                        // compiled items per wave
+    size_t lds = 0;                   // dynamic LDS per workgroup (the largest tile's need)
+    std::vector<OnchipTile> tiles;
+};
+
 struct BatchPlan {
     std::vector<uint32_t> resident;   // members run by the LDS-resident kernel, largest first
     size_t resident_lds = 0;          // its dynamic LDS (the largest member's need)
+    std::vector<OnchipLaunch> onchip; // batched on-chip launches, run one after another
     std::vector<ClassPlan> classes;   // smallest rows first
 };
+
+// Places members (indices into `members`) on batched on-chip launches.
+// Each member takes the usable variant K that costs it least, counted as
+// its workgroups times the measured cost of a workgroup-generation (about 6
+// us of synchronisation plus 1.1 us per item a wave holds): at variant K it
+// runs on b workgroups of R = ceil(np / b) whole rows, b the fewest whose
+// kOnchipWaves * K items hold its rows.  The members of each variant are
+// packed first-fit by decreasing b into launches of at most
+// opt.onchip_blocks workgroups.  Members no variant can place (a row longer
+// than the largest variant holds, more workgroups than a launch has, more
+// LDS than the limit, more than 65536 rows) are returned in *rest.
+void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size_t>& ids,
+                 const PlanOptions& opt, std::vector<OnchipLaunch>* out, std::vector<size_t>* rest);
 
 // Groups members into the resident set and the shape classes and builds
 // every tile table.  QIEO_EINVAL if a table would not fit a launch or a

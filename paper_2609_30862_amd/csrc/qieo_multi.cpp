@@ -66,6 +66,8 @@ Engine::~Engine()
         mem_.release(c.d_tiles);
         mem_.release(c.d_fe_tiles);
     }
+    for (auto& o : onchip_) mem_.release(o.d_tiles);
+    mem_.release(d_abort_);
     mem_.release(d_desc_);
     mem_.release(d_gens_);
     mem_.release(d_status_);
@@ -147,6 +149,10 @@ int Engine::rebuild()
         mem_.release(c.d_fe_tiles);
     }
     classes_.clear();
+    for (auto& o : onchip_) mem_.release(o.d_tiles);
+    onchip_.clear();
+    mem_.release(d_abort_);
+    d_abort_ = nullptr;
     const size_t n = members_.size();
     hipError_t e;
     // copies from the local host vectors below may still be in flight when a
@@ -213,6 +219,7 @@ int Engine::rebuild()
     opt.force_S = force_S_;
     opt.force_flags = force_flags_;
     opt.tuned = use_tuned_ ? tuned_class : nullptr;
+    set_onchip_options(&opt);
     BatchPlan plan;
     int rc = plan_batch(shapes, opt, &plan);
     if (rc) {
@@ -238,6 +245,20 @@ int Engine::rebuild()
     }
     if (!fork_ && (e = hipEventCreateWithFlags(&fork_, hipEventDisableTiming)) != hipSuccess)
         return rebuild_fail(e, "hipEventCreate");
+    if (!plan.onchip.empty()) {
+        if (!(d_abort_ = (uint32_t*)mem_.alloc(plan.onchip.size() * sizeof(uint32_t))))
+            return rebuild_nomem("on-chip abort words");
+        for (OnchipLaunch& L : plan.onchip) {
+            // owned by onchip_ from here on (freed at the next rebuild)
+            onchip_.push_back(OnchipRun{L.K, L.lds, (int)L.tiles.size(), nullptr});
+            OnchipRun& o = onchip_.back();
+            if (!(o.d_tiles = (OnchipTile*)mem_.alloc(L.tiles.size() * sizeof(OnchipTile))))
+                return rebuild_nomem("on-chip tiles");
+            if ((e = hipMemcpyAsync(o.d_tiles, L.tiles.data(), L.tiles.size() * sizeof(OnchipTile),
+                                    hipMemcpyHostToDevice, stream_)) != hipSuccess)
+                return rebuild_fail(e, "hipMemcpyAsync(on-chip tiles)");
+        }
+    }
     for (ClassPlan& cp : plan.classes) {
         ShapeClass sc;
         sc.cls = cp.cls;
@@ -292,6 +313,19 @@ int Engine::rebuild()
 int Engine::enqueue(int nmax)
 {
     hipError_t e;
+    // the batched on-chip launches first, alone on the device: a cooperative
+    // launch holds its workgroups' CUs for the whole call, so nothing of this
+    // call runs beside it
+    if (!onchip_.empty()) {
+        const int64_t ticks = onchip_spin_ticks(device_of_stream(), barrier_us_);
+        for (size_t j = 0; j < onchip_.size(); ++j) {
+            const OnchipRun& o = onchip_[j];
+            if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.lds, d_gens_, 0,
+                                         d_abort_ + j, ticks, stream_)) != hipSuccess)
+                return hip_fail(e, "batched on-chip kernel");
+        }
+        onchip_check_ = true;
+    }
     const size_t nc = classes_.size();
     const bool forked = !pids_.empty() || nc > 1;
     if (forked && (e = hipEventRecord(fork_, stream_)) != hipSuccess) return hip_fail(e, "fork");
@@ -389,7 +423,9 @@ int Engine::run(const int32_t* gens)
     const bool repeat = prev_n_ == nmax;
     prev_n_ = nmax;
     bool done = false;
-    if (use_graph_ && (graph_n_ == nmax || (repeat && capture(nmax)))) {
+    // a cooperative launch is not captured: a batch with on-chip launches
+    // enqueues its calls directly
+    if (use_graph_ && onchip_.empty() && (graph_n_ == nmax || (repeat && capture(nmax)))) {
         if ((e = hipGraphLaunch(graph_, stream_)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         done = true;
     }
@@ -412,7 +448,52 @@ int Engine::sync()
 {
     hipError_t e = hipStreamSynchronize(stream_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return check_onchip_abort();
+}
+
+// After the stream has drained: fails if a batched on-chip launch queued
+// since the last check gave up on a barrier wait.
+int Engine::check_onchip_abort()
+{
+    if (!onchip_check_) return QIEO_OK;
+    onchip_check_ = false;
+    std::vector<uint32_t> flags(onchip_.size(), 0u);
+    hipError_t e;
+    if (!flags.empty() &&
+        (e = copy_on(flags.data(), d_abort_, flags.size() * sizeof(uint32_t),
+                     hipMemcpyDeviceToHost, stream_)) != hipSuccess)
+        return hip_fail(e, "copy(on-chip abort words)");
+    for (uint32_t f : flags)
+        if (f)
+            return set_error(QIEO_EDEVICE, "batched on-chip loop: a barrier wait ran past its "
+                                           "bound; the state of its members is undefined");
     return QIEO_OK;
+}
+
+// Device the engine's stream belongs to.
+int Engine::device_of_stream() const
+{
+    int dev = 0;
+    if (hipStreamGetDevice(stream_, &dev) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGetDevice(&dev);
+    }
+    return dev;
+}
+
+void Engine::set_onchip_options(PlanOptions* opt) const
+{
+    // the batched loop has no convergence test: a batch with a window keeps
+    // the per-generation launches
+    bool windows = false;
+    for (const Member& m : members_) windows = windows || m.window > 0;
+    if (!use_onchip_ || windows) return;
+    size_t lim = 0;
+    int ncu = 0;
+    onchip_limits(&lim, &ncu);
+    opt->onchip_blocks = ncu;
+    opt->onchip_lds_limit = lim;
+    opt->onchip_variants = ncu > 0 ? onchip_multi_variants() : 0u;
 }
 
 int Engine::refresh_status()
@@ -422,6 +503,8 @@ int Engine::refresh_status()
     std::vector<int64_t> st(2 * n);
     hipError_t e = hipStreamSynchronize(stream_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int rc = check_onchip_abort();
+    if (rc) return rc;
     if ((e = copy_on(st.data(), d_status_, st.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
                      stream_)) != hipSuccess)
         return hip_fail(e, "copy(status)");
@@ -453,6 +536,7 @@ int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
     opt.lds_limit = use_persistent_ ? resident_lds_limit() : 0;
     opt.use_segments = use_segments_;
     opt.merge_segments = merge_segments_;
+    set_onchip_options(&opt);
     BatchPlan plan;
     if ((rc = plan_batch(shapes, opt, &plan))) return rc;
     // every member's state, saved once, restored before each candidate and
@@ -608,6 +692,8 @@ int Engine::set_window_all(int32_t window)
         if (rc) return rc;
         m.window = window;
     }
+    // the batched on-chip loop runs only without windows
+    if (use_onchip_) dirty_ = true;
     return QIEO_OK;
 }
 
@@ -678,6 +764,7 @@ extern "C" int qieo_batch_create(const qieo_problem* probs, int32_t n, const qie
         batch_release(b);
         return set_error(QIEO_ENOMEM, "host allocation failed");
     }
+    b->eng->set_use_onchip(true);
     for (int32_t i = 0; i < n; ++i) {
         if ((rc = b->eng->add(b->pool, probs[i].items, probs[i].n_items, probs[i].capacity,
                               probs[i].n_pop, probs[i].seed, (uint64_t)i, 0))) {
@@ -822,6 +909,35 @@ extern "C" int qieo_batch_set_segment_order(qieo_batch* b, int32_t enabled)
     if (enabled < 0 || enabled > 2)
         return set_error(QIEO_EINVAL, "segment order mode must be 0, 1 or 2 (got %d)", enabled);
     b->eng->set_use_segments(enabled);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_set_onchip(qieo_batch* b, int32_t enabled)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    b->eng->set_use_onchip(enabled != 0);
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_onchip_launches(qieo_batch* b, int32_t* n)
+{
+    clear_error();
+    if (!b || !n) return set_error(QIEO_EINVAL, "NULL argument");
+    int rc = b->eng->ensure_built();
+    if (rc) return rc;
+    *n = (int32_t)b->eng->onchip_launches();
+    return QIEO_OK;
+}
+
+extern "C" int qieo_batch_set_barrier_timeout(qieo_batch* b, int64_t microseconds)
+{
+    clear_error();
+    if (!b) return set_error(QIEO_EINVAL, "batch is NULL");
+    if (microseconds < 0)
+        return set_error(QIEO_EINVAL, "barrier timeout must be >= 0 (got %lld)",
+                         (long long)microseconds);
+    b->eng->set_barrier_us(microseconds);
     return QIEO_OK;
 }
 

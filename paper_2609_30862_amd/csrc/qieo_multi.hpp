@@ -89,6 +89,13 @@ public:
     void force_shape(int R, int S, int flags);
     void set_use_graph(bool on) { use_graph_ = on; invalidate_graph(); }
     void set_use_persistent(bool on) { use_persistent_ = on; dirty_ = true; }
+    // Batched on-chip loop for members of rows under 32 chunks (off by default)
+    void set_use_onchip(bool on) { use_onchip_ = on; dirty_ = true; }
+    bool use_onchip() const { return use_onchip_; }
+    // On-chip launches the current plan makes per call (after ensure_built)
+    size_t onchip_launches() const { return onchip_.size(); }
+    // Bound on one on-chip barrier wait, in microseconds
+    void set_barrier_us(int64_t us) { barrier_us_ = us; }
     // mode 0: row order everywhere; 1: segment order for rows of >= 8 chunks
     // of a streaming batch; 2: only for rows of >= 32 chunks
     void set_use_segments(int mode)
@@ -133,6 +140,22 @@ private:
     uint32_t* d_pids_ = nullptr;
     hipStream_t side_ = nullptr;
     hipEvent_t fork_ = nullptr, join_ = nullptr;
+    // batched on-chip launches (run first, on the main stream, before the
+    // fork: each takes one workgroup on every CU it uses for the whole call)
+    struct OnchipRun {
+        int K = 0;
+        size_t lds = 0;
+        int n_tiles = 0;
+        OnchipTile* d_tiles = nullptr;
+    };
+    std::vector<OnchipRun> onchip_;
+    uint32_t* d_abort_ = nullptr;    // one abort word per on-chip launch
+    bool onchip_check_ = false;      // launches queued since the abort words were read
+    int check_onchip_abort();
+    int device_of_stream() const;
+    void set_onchip_options(PlanOptions* opt) const;
+    bool use_onchip_ = false;
+    int64_t barrier_us_ = 1000000;
     // shape classes after the first run on streams of their own
     std::vector<hipStream_t> cstreams_;
     std::vector<hipEvent_t> cjoin_;

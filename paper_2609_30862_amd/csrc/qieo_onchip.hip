@@ -197,20 +197,21 @@ __device__ __forceinline__ void store_planes(const InstDev& I, const f32x4 (&A)[
     }
 }
 
+// The loop of one workgroup: rows [row0, row0 + nrows) of instance I, LDS
+// laid out for R rows, workgroup blk of the nb that run the instance, gens
+// generations; abort_flag is the launch's abort word.
 template <int K, bool CONV>
-__global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev* __restrict__ insts,
-                                                                  int R, int gens,
-                                                                  int64_t spin_ticks)
+__device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, const int nrows,
+                                            const int R, const int blk, const int nb,
+                                            const int gens, uint32_t* abort_flag,
+                                            int64_t spin_ticks)
 {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ int s_flag;
     __shared__ unsigned long long s_wkey[kOnchipWaves];
-    const InstDev I = insts[0];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int np = I.np, pitch = I.pitch, nchunk = I.nchunk, wpr = nchunk * kWordsPerChunk;
-    const int row0 = (int)blockIdx.x * R;
-    const int nrows = min(R, np - row0);            // >= 1: the grid is ceil(np / R)
     const int n_items = nrows * nchunk;
 
     int32_t* sV = reinterpret_cast<int32_t*>(lds);                     // [nchunk * 256]
@@ -220,8 +221,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
     int32_t* sF = reinterpret_cast<int32_t*>(sE + wpr);                  // [2][R] fitness by parity
     int32_t* sPW = sF + 2 * R;                                           // [2][R][2] profit, weight
     uint32_t* sSum = reinterpret_cast<uint32_t*>(sPW + 4 * R);           // [R][2] running sums
-    unsigned long long* slots = reinterpret_cast<unsigned long long*>(I.sync + 16);  // [2][grid]
-    const int nb = (int)gridDim.x;
+    unsigned long long* slots = reinterpret_cast<unsigned long long*>(I.sync + 16);  // [2][nb]
 
     const int64_t t0 = sload(I.tbase);
     // CONV: the instance has a convergence window (the launch without it
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
                 key = load_dev(I.ekey + (t - 1) % 3);
             } else {
                 unsigned long long sk;
-                if (!gather_keys(slots + (size_t)((k - 1) & 1) * nb, nb, k - 1, I.sync + 1,
+                if (!gather_keys(slots + (size_t)((k - 1) & 1) * nb, nb, k - 1, abort_flag,
                                  spin_ticks, s_wkey, &s_flag, &sk))
                     return;
                 key = make_key((int32_t)((uint32_t)(sk >> 32) ^ 0x80000000u),
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             e_prev = __builtin_amdgcn_readfirstlane(key_row(key));
             fe_prev = __builtin_amdgcn_readfirstlane(key_fitness(key));
             // the elite ring as the per-generation launches leave it
-            if (blockIdx.x == 0 && tid == 0 && k > 0) store_dev(I.ekey + (t - 1) % 3, key);
+            if (blk == 0 && tid == 0 && k > 0) store_dev(I.ekey + (t - 1) % 3, key);
         }
         // termination test on the elite of t-1 (for k = 0 the previous
         // call's finish already made it)
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             run = (run > 0 && fe_prev == run_fe) ? run + 1 : 1;
             run_fe = fe_prev;
             stop = run >= window;
-            if (blockIdx.x == 0 && tid == 0) {
+            if (blk == 0 && tid == 0) {
                 store_dev(I.conv + 8 + (int)((t - 1) & (kConvRing - 1)), fe_prev);
                 if (stop) {
                     store_dev(I.conv + 1, (int32_t)(uint32_t)(uint64_t)(t - 1));
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
                 }
             }
         }
-        if (blockIdx.x == 0 && tid == 0 && !done && !stop) store_dev(I.ekey + (t + 1) % 3, 0ull);
+        if (blk == 0 && tid == 0 && !done && !stop) store_dev(I.ekey + (t + 1) % 3, 0ull);
         // best-so-far record of t-1, written by the workgroup owning the row
         if (pending && !done && (!has_best || fe_prev > best_f)) {
             has_best = 1;
@@ -463,7 +463,52 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
             break;
         }
         // the launch boundary ends the last generation
-        if (!last) publish_key(slots + (size_t)(k & 1) * nb + blockIdx.x, s_wkey, nwr, k);
+        if (!last) publish_key(slots + (size_t)(k & 1) * nb + blk, s_wkey, nwr, k);
+    }
+}
+
+template <int K, bool CONV>
+__global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev* __restrict__ insts,
+                                                                  int R, int gens,
+                                                                  int64_t spin_ticks)
+{
+    const InstDev I = insts[0];
+    const int row0 = (int)blockIdx.x * R;
+    // nrows >= 1: the grid is ceil(np / R)
+    onchip_body<K, CONV>(I, row0, min(R, I.np - row0), R, (int)blockIdx.x, (int)gridDim.x, gens,
+                         I.sync + 1, spin_ticks);
+}
+
+// Batched form: workgroup b runs tiles[b] (whole rows of one member) for
+// that member's gens_arr entry (gens_all when gens_arr is NULL); the
+// workgroups of one member wait only for each other.  No convergence window.
+template <int K>
+__global__ __launch_bounds__(64 * kOnchipWaves) void onchip_multi_kernel(
+    const InstDev* __restrict__ insts, const OnchipTile* __restrict__ tiles,
+    const int32_t* __restrict__ gens_arr, int gens_all, uint32_t* abort_flag,
+    int64_t spin_ticks)
+{
+    const OnchipTile T = tiles[blockIdx.x];
+    const int gens = gens_arr ? gens_arr[T.inst] : gens_all;
+    // every workgroup of the member leaves here alike
+    if (gens <= 0) return;
+    const InstDev I = insts[T.inst];
+    onchip_body<K, false>(I, T.row0, T.nrows, T.R, T.blk, T.nb, gens, abort_flag, spin_ticks);
+}
+
+// Clears the launch's abort word and, for each tile, its workgroup's key
+// slots of both parities in its member's arena.
+__global__ void onchip_multi_reset_kernel(const InstDev* __restrict__ insts,
+                                          const OnchipTile* __restrict__ tiles, int n_tiles,
+                                          uint32_t* abort_flag)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i == 0) *abort_flag = 0u;
+    if (i < n_tiles) {
+        const OnchipTile T = tiles[i];
+        unsigned long long* slots = reinterpret_cast<unsigned long long*>(insts[T.inst].sync + 16);
+        slots[T.blk] = 0ull;
+        slots[T.nb + T.blk] = 0ull;
     }
 }
 
@@ -483,6 +528,21 @@ OnchipFn onchip_fn(int K)
 }
 
 OnchipFn onchip_fn(int K, bool conv) { return conv ? onchip_fn<true>(K) : onchip_fn<false>(K); }
+
+typedef void (*OnchipMultiFn)(const InstDev*, const OnchipTile*, const int32_t*, int, uint32_t*,
+                              int64_t);
+
+OnchipMultiFn onchip_multi_fn(int K)
+{
+    switch (K) {
+        case 2: return onchip_multi_kernel<2>;
+        case 4: return onchip_multi_kernel<4>;
+        case 6: return onchip_multi_kernel<6>;
+        case 8: return onchip_multi_kernel<8>;
+        case 10: return onchip_multi_kernel<10>;
+        default: return nullptr;
+    }
+}
 
 }  // namespace
 
@@ -529,6 +589,43 @@ void onchip_limits(size_t* lds_limit, int* n_cu)
     *n_cu = cus;
 }
 
+int64_t onchip_spin_ticks(int device, int64_t microseconds)
+{
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+        khz <= 0) {
+        (void)hipGetLastError();
+        khz = 100000;
+    }
+    return (int64_t)khz * microseconds / 1000;
+}
+
+unsigned onchip_multi_variants()
+{
+    static std::once_flag once;
+    static unsigned mask = 0;
+    std::call_once(once, [] {
+        size_t lim = 0;
+        int ncu = 0;
+        onchip_limits(&lim, &ncu);
+        if (ncu == 0) return;
+        for (int v = 0; v < kOnchipVariants; ++v) {
+            const void* f = reinterpret_cast<const void*>(onchip_multi_fn(kOnchipK[v]));
+            int blocks = 0;
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+                    hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64 * kOnchipWaves, lim) !=
+                    hipSuccess ||
+                blocks < 1) {
+                (void)hipGetLastError();
+                continue;
+            }
+            mask |= 1u << v;
+        }
+    });
+    return mask;
+}
+
 namespace {
 
 // The on-chip launches of this library on one device run one after another,
@@ -551,17 +648,12 @@ CoopChain& coop_chain(int device)
     return chains[device];          // std::map nodes do not move
 }
 
-}  // namespace
-
-hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64_t spin_ticks,
-                         hipStream_t s)
+// Enqueues reset() and then the cooperative launch on s, after the device's
+// previous on-chip launch (see CoopChain).
+template <typename Reset>
+hipError_t chained_coop_launch(const void* f, unsigned blocks, void** args, size_t lds,
+                               hipStream_t s, Reset reset)
 {
-    if (gens <= 0) return hipSuccess;
-    size_t lim = 0;
-    int ncu = 0;
-    onchip_limits(&lim, &ncu);
-    const OnchipFn f = onchip_fn(p.K, p.conv);
-    if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -576,18 +668,63 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
         // an event never recorded completes at once
         if ((e = hipStreamWaitEvent(s, c.last, 0)) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(onchip_reset_kernel, dim3((unsigned)((2 * p.blocks + 255) / 256)), dim3(256),
-                       0, s, dI, p.blocks);
+    reset();
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipLaunchCooperativeKernel(f, dim3(blocks), dim3(64 * kOnchipWaves), args,
+                                        (unsigned)lds, s)) != hipSuccess)
+        return e;
+    return chain ? hipEventRecord(c.last, s) : hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64_t spin_ticks,
+                         hipStream_t s)
+{
+    if (gens <= 0) return hipSuccess;
+    size_t lim = 0;
+    int ncu = 0;
+    onchip_limits(&lim, &ncu);
+    const OnchipFn f = onchip_fn(p.K, p.conv);
+    if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
     const InstDev* a0 = dI;
     int a1 = p.R, a2 = gens;
     int64_t a3 = spin_ticks;
     void* args[] = {&a0, &a1, &a2, &a3};
-    if ((e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(f), dim3((unsigned)p.blocks),
-                                        dim3(64 * kOnchipWaves), args, (unsigned)p.lds, s)) !=
-        hipSuccess)
-        return e;
-    return chain ? hipEventRecord(c.last, s) : hipSuccess;
+    return chained_coop_launch(reinterpret_cast<const void*>(f), (unsigned)p.blocks, args, p.lds, s,
+                               [&] {
+                                   hipLaunchKernelGGL(onchip_reset_kernel,
+                                                      dim3((unsigned)((2 * p.blocks + 255) / 256)),
+                                                      dim3(256), 0, s, dI, p.blocks);
+                               });
+}
+
+hipError_t launch_onchip_multi(const InstDev* dI, const OnchipTile* tiles, int n_tiles, int K,
+                               size_t lds, const int32_t* gens_arr, int gens_all,
+                               uint32_t* abort_flag, int64_t spin_ticks, hipStream_t s)
+{
+    size_t lim = 0;
+    int ncu = 0;
+    onchip_limits(&lim, &ncu);
+    int v = 0;
+    while (v < kOnchipVariants && kOnchipK[v] != K) ++v;
+    if (v == kOnchipVariants || !(onchip_multi_variants() & (1u << v)) || n_tiles < 1 ||
+        n_tiles > ncu || lds > lim || !abort_flag)
+        return hipErrorInvalidValue;
+    const InstDev* a0 = dI;
+    const OnchipTile* a1 = tiles;
+    const int32_t* a2 = gens_arr;
+    int a3 = gens_all;
+    uint32_t* a4 = abort_flag;
+    int64_t a5 = spin_ticks;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
+    return chained_coop_launch(reinterpret_cast<const void*>(onchip_multi_fn(K)),
+                               (unsigned)n_tiles, args, lds, s, [&] {
+                                   hipLaunchKernelGGL(onchip_multi_reset_kernel,
+                                                      dim3((unsigned)((n_tiles + 255) / 256)),
+                                                      dim3(256), 0, s, dI, tiles, n_tiles,
+                                                      abort_flag);
+                               });
 }
 
 }  // namespace qieo

@@ -291,19 +291,6 @@ extern "C" int qieo_create(const qieo_item* items, int32_t n_items, int32_t capa
     return create_impl(items, n_items, capacity, n_pop, seed, nullptr, false, out);
 }
 
-// Bound on one grid-barrier wait of the on-chip loop, in ticks of the
-// device's wall clock.
-static int64_t onchip_spin_ticks(int device, int64_t microseconds)
-{
-    int khz = 0;
-    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
-        khz <= 0) {
-        (void)hipGetLastError();
-        khz = 100000;
-    }
-    return (int64_t)khz * microseconds / 1000;
-}
-
 static int timed_event_pair(qieo_inst* h, int stage, hipEvent_t* a, hipEvent_t* b)
 {
     while (h->ev.size() < 2 * (h->ev_used + 1)) {

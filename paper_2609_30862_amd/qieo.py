@@ -235,6 +235,12 @@ def _load():
     L.qieo_batch_set_persistent.argtypes = [H, i32]
     L.qieo_batch_set_segment_order.restype = ctypes.c_int
     L.qieo_batch_set_segment_order.argtypes = [H, i32]
+    L.qieo_batch_set_onchip.restype = ctypes.c_int
+    L.qieo_batch_set_onchip.argtypes = [H, i32]
+    L.qieo_batch_onchip_launches.restype = ctypes.c_int
+    L.qieo_batch_onchip_launches.argtypes = [H, ctypes.POINTER(i32)]
+    L.qieo_batch_set_barrier_timeout.restype = ctypes.c_int
+    L.qieo_batch_set_barrier_timeout.argtypes = [H, i64]
     L.qieo_batch_autotune.restype = ctypes.c_int
     L.qieo_batch_autotune.argtypes = [H, ctypes.c_int32, ctypes.POINTER(qieo_class_tune),
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
@@ -669,6 +675,21 @@ class Batch:
         only; 0 / False: row order for every member."""
         _check(lib.qieo_batch_set_segment_order(self._h, int(mode)),
                "qieo_batch_set_segment_order")
+
+    def set_onchip(self, enabled: bool):
+        """True (default): members of rows under 32 chunks that would run in
+        row order run each call inside batched on-chip launches."""
+        _check(lib.qieo_batch_set_onchip(self._h, int(bool(enabled))), "qieo_batch_set_onchip")
+
+    def onchip_launches(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib.qieo_batch_onchip_launches(self._h, ctypes.byref(n)),
+               "qieo_batch_onchip_launches")
+        return int(n.value)
+
+    def set_barrier_timeout(self, microseconds: int):
+        _check(lib.qieo_batch_set_barrier_timeout(self._h, int(microseconds)),
+               "qieo_batch_set_barrier_timeout")
 
     def converged(self, i: int):
         c, g = ctypes.c_int32(), ctypes.c_int64()

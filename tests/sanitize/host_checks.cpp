@@ -261,6 +261,13 @@ static void check_plan_batch()
         opt.merge_segments = round % 3 != 2;
         if (round % 7 == 3) { opt.force_R = 4; opt.force_S = 8; opt.force_flags = 3; }
         if (round % 7 == 5) opt.tuned = tuned_stub;
+        if (round % 2 == 1) {
+            // batched on-chip loop: a full device, or a small one that forces
+            // several launches and leaves members with too many rows out
+            opt.onchip_blocks = round % 4 == 1 ? 256 : 24;
+            opt.onchip_lds_limit = round % 8 == 3 ? 6 * 1024 : 160 * 1024 - 256;
+            opt.onchip_variants = round % 3 == 0 ? 0x1fu : 0x06u;
+        }
         BatchPlan plan;
         CHECK(plan_batch(ms, opt, &plan) == QIEO_OK, "plan failed: %s", last_error());
         int64_t plane_bytes = 0;
@@ -282,6 +289,44 @@ static void check_plan_batch()
             where[id] = 100;
             for (auto& r : rows[id]) r = 1;
             for (auto& r : fe[id]) r = 1;
+        }
+        CHECK((opt.onchip_blocks > 0 && opt.force_R == 0) || plan.onchip.empty(),
+              "on-chip launches while off or under a forced shape");
+        for (const OnchipLaunch& L : plan.onchip) {
+            int v = 0;
+            while (v < kOnchipVariants && kOnchipK[v] != L.K) ++v;
+            CHECK(v < kOnchipVariants && (opt.onchip_variants >> v & 1u), "variant K %d", L.K);
+            CHECK(!L.tiles.empty() && (int)L.tiles.size() <= opt.onchip_blocks,
+                  "%zu workgroups in a launch of at most %d", L.tiles.size(), opt.onchip_blocks);
+            size_t lds = 0;
+            std::map<uint32_t, std::vector<int>> blk_seen;
+            for (const OnchipTile& t : L.tiles) {
+                CHECK(t.inst < (uint32_t)n, "on-chip tile member");
+                const MemberShape& m = ms[t.inst];
+                CHECK(m.np <= 65536, "member %u: %d rows on-chip", t.inst, m.np);
+                CHECK(t.nb >= 1 && t.nb <= opt.onchip_blocks && t.blk >= 0 && t.blk < t.nb,
+                      "workgroup %d of %d", t.blk, t.nb);
+                CHECK(t.R >= 1 && (int64_t)t.R * m.nchunk <= (int64_t)kOnchipWaves * L.K,
+                      "R %d x %d chunks beyond %d items", t.R, m.nchunk, kOnchipWaves * L.K);
+                CHECK(t.row0 == t.blk * t.R && t.nrows == std::min(t.R, m.np - t.row0) &&
+                          t.nrows >= 1,
+                      "rows %d + %d of member %u", t.row0, t.nrows, t.inst);
+                CHECK((int64_t)t.nb == ((int64_t)m.np + t.R - 1) / t.R, "nb %d", t.nb);
+                auto& seen = blk_seen[t.inst];
+                if (seen.empty()) {
+                    CHECK(where[t.inst] == -1, "member %u in two on-chip launches", t.inst);
+                    seen.assign(t.nb, 0);
+                    where[t.inst] = 200;
+                }
+                CHECK((int)seen.size() == t.nb && ++seen[t.blk] == 1, "workgroup %d repeated", t.blk);
+                for (int32_t r = t.row0; r < t.row0 + t.nrows; ++r) {
+                    rows[t.inst][r]++;
+                    fe[t.inst][r]++;
+                }
+                lds = std::max(lds, onchip_lds_bytes(t.R, m.nchunk));
+            }
+            CHECK(L.lds == lds && lds <= opt.onchip_lds_limit, "launch LDS %zu (tiles %zu)", L.lds,
+                  lds);
         }
         int prev_cls = -1;
         for (const ClassPlan& c : plan.classes) {
@@ -337,7 +382,8 @@ static void check_plan_batch()
         }
         for (int i = 0; i < n; ++i) {
             CHECK(where[i] != -1, "member %d in no launch", i);
-            if (where[i] != 100 && where[i] != kClasses - 1 && where[i] != kClasses - 2)
+            if (where[i] != 100 && where[i] != 200 && where[i] != kClasses - 1 &&
+                where[i] != kClasses - 2)
                 CHECK(where[i] == class_of(ms[i].nchunk), "member %d in class %d, nchunk %d", i,
                       where[i], ms[i].nchunk);
             for (int r = 0; r < ms[i].np; ++r) {

@@ -51,6 +51,9 @@ def _problems(insts):
 def test_batch_matches_oracle_with_uneven_generation_counts(qieo, oracle_mod):
     insts = _ragged_instances()
     b = qieo.Batch(_problems(insts))
+    # the members of rows under 8 chunks that are not LDS-resident run in
+    # the batched on-chip loop
+    assert b.onchip_launches() >= 1
     orcs = [oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
     n = len(insts)
     # calls 2 and 3 repeat call 1's longest count: captured, then replayed
@@ -66,8 +69,8 @@ def test_batch_matches_oracle_with_uneven_generation_counts(qieo, oracle_mod):
                 assert_state_equal(View(b, k), o, label="batch call %d inst %d" % (call, k))
 
 
-@pytest.mark.parametrize("mode", ["no-graph", "no-persistent", "no-graph-no-persistent", "R1S1",
-                                  "R2S4f3", "R4S16f1"])
+@pytest.mark.parametrize("mode", ["no-graph", "no-persistent", "no-graph-no-persistent", "no-onchip",
+                                  "no-onchip-no-persistent", "R1S1", "R2S4f3", "R4S16f1"])
 def test_batch_modes_are_identical(qieo, mode):
     insts = _ragged_instances()
     ref = qieo.Batch(_problems(insts))
@@ -77,6 +80,9 @@ def test_batch_modes_are_identical(qieo, mode):
             alt.set_graph(False)
         if "persistent" in mode:
             alt.set_persistent(False)
+        if "onchip" in mode:
+            alt.set_onchip(False)
+            assert alt.onchip_launches() == 0
     else:
         R, S = int(mode[1]), int(mode[3:].split("f")[0])
         f = int(mode.split("f")[1]) if "f" in mode else 0
@@ -127,11 +133,19 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     planes = sum(i.n_pop * ((i.n_items + 63) // 64 * 64) * 8 for i in insts)
     assert planes > 256 << 20
     say("batch of %d, %.0f MB of planes" % (len(insts), planes / 2 ** 20))
+    # the per-generation launch paths (the default takes the on-chip loop
+    # for every member it can place; compared here too)
     seg = qieo.Batch(_problems(insts))
+    seg.set_onchip(False)
     seg32 = qieo.Batch(_problems(insts))
+    seg32.set_onchip(False)
     seg32.set_segment_order(2)
     row = qieo.Batch(_problems(insts))
+    row.set_onchip(False)
     row.set_segment_order(False)
+    onc = qieo.Batch(_problems(insts))
+    say("on-chip launches of the default batch: %d" % onc.onchip_launches())
+    assert onc.onchip_launches() >= 1
     with pytest.raises(qieo.QieoError) as ei:
         row.set_segment_order(3)
     assert ei.value.code == qieo.QIEO_EINVAL
@@ -139,13 +153,14 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     done = [0] * n
     for gens in ([3] * n, [k % 5 for k in range(n)], [k % 5 for k in range(n)],
                  [(k + 2) % 5 for k in range(n)]):
-        for b in (seg, seg32, row):
+        for b in (seg, seg32, row, onc):
             b.step(gens)
         done = [d + g for d, g in zip(done, gens)]
     for k in range(n):
         c = row.export_rows(k)
         rc = row.best(k)
-        for other, label in ((seg, "rows of 8+ chunks"), (seg32, "rows of 32+ chunks")):
+        for other, label in ((seg, "rows of 8+ chunks"), (seg32, "rows of 32+ chunks"),
+                             (onc, "default (on-chip)")):
             a = other.export_rows(k)
             for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
                 assert np.array_equal(a[key], c[key]), (label, k, key)
@@ -162,6 +177,7 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     seg.close()
     seg32.close()
     row.close()
+    onc.close()
 
 
 def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_mod):
@@ -203,3 +219,88 @@ def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_
         ref.close()
         b.close()
 
+
+
+def _many_mid_sized(n=40):
+    """Members of 6-chunk rows and 256 rows: about ten on-chip workgroups
+    each, more than one launch holds on a 256-CU device."""
+    return [workloads.random_instance(1500 - 7 * k, 256 - (k % 5), seed=3000 + k, wmax=20 + k)
+            for k in range(n)]
+
+
+def test_onchip_over_several_launches(qieo, oracle_mod):
+    """A batch whose on-chip members need more workgroups than one launch
+    has: several launches, one after another, each member on one of them.
+    Every member equals the per-generation launch path bit for bit over
+    calls of uneven counts (switching between the two paths from call to
+    call), and sampled members equal the oracle."""
+    insts = _many_mid_sized()
+    n = len(insts)
+    on = qieo.Batch(_problems(insts))
+    off = qieo.Batch(_problems(insts))
+    off.set_onchip(False)
+    n_launch = on.onchip_launches()
+    say("on-chip launches: %d for %d members" % (n_launch, n))
+    assert n_launch >= 2 and off.onchip_launches() == 0
+    sample = [0, n // 2, n - 1]
+    orcs = {k: oracle_mod.Oracle(insts[k].values, insts[k].weights, insts[k].capacity,
+                                 insts[k].n_pop, insts[k].seed) for k in sample}
+    calls = [[5] * n, [k % 4 for k in range(n)], [0] * n, [(3 * k) % 7 for k in range(n)]]
+    for call, gens in enumerate(calls):
+        # the third call on the on-chip batch runs without the loop, the
+        # fourth with it again: the two paths leave the same state
+        on.set_onchip(call != 2)
+        say("call %d" % call)
+        on.step(gens)
+        off.step(gens)
+        for k in sample:
+            orcs[k].run(gens[k])
+    for k in range(n):
+        a, c = on.export_rows(k), off.export_rows(k)
+        for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+            assert np.array_equal(a[key], c[key]), (k, key)
+        assert a["elite"] == c["elite"]
+        ra, rc = on.best(k), off.best(k)
+        assert (ra.fitness, ra.generation, ra.chromosome) == (rc.fitness, rc.generation,
+                                                               rc.chromosome)
+        assert on.generations(k) == off.generations(k) == sum(g[k] for g in calls)
+    for k in sample:
+        assert_state_equal(View(on, k), orcs[k], label="on-chip member %d" % k)
+
+
+def test_onchip_not_taken_with_convergence_window(qieo, oracle_mod):
+    """The batched loop makes no convergence test: with a window the batch
+    keeps the per-generation launches, and still follows the oracle."""
+    # LDS-resident members and the three that take the on-chip loop
+    insts = [_ragged_instances()[k] for k in (0, 3, 8, 11, 13)]
+    b = qieo.Batch(_problems(insts))
+    assert b.onchip_launches() >= 1
+    b.set_convergence(4)
+    assert b.onchip_launches() == 0
+    b.step(40)
+    for k, i in enumerate(insts):
+        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        o.run_until_converged(40, 4)
+        assert b.generations(k) == o.t
+        assert_state_equal(View(b, k), o, label="windowed member %d" % k)
+
+
+def test_onchip_barrier_timeout_is_reported(qieo):
+    """A zero bound on the barrier wait: a workgroup that finds a key of its
+    member missing gives up, raises the launch's abort word, and the others
+    leave at their next wait; the call reports QIEO_EDEVICE at the sync
+    (every wait is bounded, so the launch always ends)."""
+    insts = _many_mid_sized(4)
+    b = qieo.Batch(_problems(insts))
+    assert b.onchip_launches() == 1
+    b.set_barrier_timeout(0)
+    with pytest.raises(qieo.QieoError) as ei:
+        b.step(200)
+    assert ei.value.code == qieo.QIEO_EDEVICE and "barrier" in str(ei.value)
+    with pytest.raises(qieo.QieoError):
+        b.set_barrier_timeout(-1)
+    b.close()
+    # a new batch on the same device runs normally
+    c = qieo.Batch(_problems(insts))
+    c.step(3)
+    assert all(c.generations(k) == 3 for k in range(len(insts)))

@@ -137,6 +137,7 @@ def test_batch_of_512_every_instance(qieo, oracle_mod):
     say("batch of %d instances x %d generations, oracle on %d workers"
         % (len(insts), gens, THREADS))
     b = qieo.Batch([(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts])
+    say("  on-chip launches per call: %d" % b.onchip_launches())
     b.step(gens)
 
     def run(k):

@@ -351,6 +351,7 @@ def bench_serve(args):
         % (len(reqs), args.rate, sum(work), args.budget_gb, args.max_resident,
            args.gens_per_iter))
     srv = qieo.Server(int(args.budget_gb * (1 << 30)), args.max_resident, args.gens_per_iter)
+    srv.set_onchip(not args.no_onchip)
     torch.cuda.synchronize()
     tickets = []
     t0 = time.perf_counter()
@@ -419,7 +420,8 @@ def bench_serve(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "qieo-knapsack serving, %d Poisson requests at %.0f/s, "
                                "%.0f GB budget" % (len(reqs), args.rate, args.budget_gb),
-                   "max_resident": args.max_resident, "gens_per_iter": args.gens_per_iter},
+                   "max_resident": args.max_resident, "gens_per_iter": args.gens_per_iter,
+                   "onchip": not args.no_onchip},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
         "server": {k: st[k] for k in ("iterations", "peak_resident", "peak_pool_used", "failed")},
@@ -589,6 +591,8 @@ def main():
     ap.add_argument("--gens-per-iter", type=int, default=25, help="serve: generations/iteration")
     ap.add_argument("--loop-sample", type=int, default=200,
                     help="serve: requests re-run one by one for the per-instance loop baseline")
+    ap.add_argument("--no-onchip", action="store_true",
+                    help="serve: residents in per-generation launches only (no batched on-chip loop)")
     ap.add_argument("--skip-loop", action="store_true",
                     help="batch: time the batched calls only (no per-instance loop)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

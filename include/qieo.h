@@ -348,6 +348,12 @@ int qieo_server_create(const qieo_server_cfg *cfg, const qieo_dev_ctx *ctx, qieo
  * identifies it.  Its result is bit-identical to qieo_create + qieo_step(n_gen)
  * + qieo_best on the same inputs, whatever else is resident. */
 int qieo_server_submit(qieo_server *s, const qieo_problem *p, int32_t n_gen, uint64_t *ticket);
+/* 1 (default): the residents' generations run in batched on-chip launches
+ * wherever they fit (see qieo_batch_set_onchip; not with a convergence
+ * window), the rest in per-generation launches; 0: per-generation launches
+ * only.  Takes effect at the worker's next iteration.  Results are
+ * identical. */
+int qieo_server_set_onchip(qieo_server *s, int32_t enabled);
 /* QIEO_EAGAIN while the request is queued or running; otherwise its result
  * (or its failure code, e.g. QIEO_ENOMEM when its population can never fit
  * the budget).  latency_ns = completion - submission, steady clock. */

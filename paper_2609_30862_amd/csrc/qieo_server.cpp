@@ -64,6 +64,7 @@ struct qieo_server {
     std::unordered_map<uint64_t, Request*> all;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool onchip = true;                // batched on-chip loop (the worker applies it)
     int worker_error = QIEO_OK;
     std::string worker_msg;
 
@@ -79,12 +80,18 @@ static void server_loop(qieo_server* s)
 {
     (void)hipSetDevice(s->device);
     std::vector<int32_t> gens;
+    bool onchip = !s->onchip;          // applied below on the first pass
     for (;;) {
         std::vector<Request*> to_admit;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->resident.empty(); });
             if (s->stop) return;
+            // the engine is the worker's alone: a change of mode reaches it here
+            if (s->onchip != onchip) {
+                onchip = s->onchip;
+                s->eng->set_use_onchip(onchip);
+            }
             // admission in arrival order, limited by the resident cap; memory is
             // checked below, where the allocation itself is attempted
             size_t cap = s->cfg.max_resident > 0 ? (size_t)s->cfg.max_resident : (size_t)-1;
@@ -265,6 +272,15 @@ extern "C" int qieo_server_create(const qieo_server_cfg* cfg, const qieo_dev_ctx
     s->eng->set_use_segments(2);
     s->worker = std::thread(server_loop, s);
     *out = s;
+    return QIEO_OK;
+}
+
+extern "C" int qieo_server_set_onchip(qieo_server* s, int32_t enabled)
+{
+    clear_error();
+    if (!s) return set_error(QIEO_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->onchip = enabled != 0;
     return QIEO_OK;
 }
 

@@ -235,6 +235,8 @@ def _load():
     L.qieo_batch_set_persistent.argtypes = [H, i32]
     L.qieo_batch_set_segment_order.restype = ctypes.c_int
     L.qieo_batch_set_segment_order.argtypes = [H, i32]
+    L.qieo_server_set_onchip.restype = ctypes.c_int
+    L.qieo_server_set_onchip.argtypes = [H, i32]
     L.qieo_batch_set_onchip.restype = ctypes.c_int
     L.qieo_batch_set_onchip.argtypes = [H, i32]
     L.qieo_batch_onchip_launches.restype = ctypes.c_int
@@ -724,6 +726,11 @@ class Server:
 
     def __del__(self):
         self.close()
+
+    def set_onchip(self, enabled: bool):
+        """True (default): residents run in batched on-chip launches where
+        they fit; False: per-generation launches only."""
+        _check(lib.qieo_server_set_onchip(self._h, int(bool(enabled))), "qieo_server_set_onchip")
 
     def submit(self, values, weights, capacity: int, n_pop: int, seed: int, n_gen: int) -> int:
         it = items_array(values, weights)

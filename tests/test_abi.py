@@ -83,6 +83,7 @@ def test_null_handles_are_rejected():
     assert L.qieo_set_kernel_flags(None, 0) == qieo.QIEO_EINVAL
     assert L.qieo_batch_set_segment_order(None, 1) == qieo.QIEO_EINVAL
     assert L.qieo_batch_set_onchip(None, 1) == qieo.QIEO_EINVAL
+    assert L.qieo_server_set_onchip(None, 1) == qieo.QIEO_EINVAL
     assert L.qieo_batch_set_barrier_timeout(None, 1) == qieo.QIEO_EINVAL
     n32 = ctypes.c_int32(0)
     assert L.qieo_batch_onchip_launches(None, ctypes.byref(n32)) == qieo.QIEO_EINVAL

@@ -50,12 +50,16 @@ def _check_against_oracle(oracle_mod, inst, gens, res):
     assert np.array_equal(res.alleles(inst.n_items), ob.bits)
 
 
-def test_server_continuous_batching_matches_oracle(qieo, oracle_mod):
+@pytest.mark.parametrize("onchip", [True, False])
+def test_server_continuous_batching_matches_oracle(qieo, oracle_mod, onchip):
+    """With the residents in batched on-chip launches (the default) and in
+    per-generation launches only."""
     reqs = _requests(24, 5000)
     sizes = sorted(footprint(i.n_items, i.n_pop) for i, _ in reqs)
     budget = sizes[-1] + sizes[-2] + sizes[-3]          # room for about three at a time
-    say("server budget %d bytes for %d requests" % (budget, len(reqs)))
+    say("server budget %d bytes for %d requests, on-chip %s" % (budget, len(reqs), onchip))
     s = qieo.Server(budget, max_resident=0, gens_per_iter=7)
+    s.set_onchip(onchip)
     tickets = [s.submit(i.values, i.weights, i.capacity, i.n_pop, i.seed, g) for i, g in reqs]
     results = [s.wait(t) for t in tickets]
     st = s.stats()

@@ -34,6 +34,7 @@ KERNEL_SOURCES = ["paper_2609_30862_amd/csrc/qieo_kernels.hip",
 PROFILE = "profiles/generation_kernel_np4096_ng200000.md"
 # the on-chip loop's sources and its instruction-count summary
 ONCHIP_SOURCES = ["paper_2609_30862_amd/csrc/qieo_onchip.hip",
+                  "paper_2609_30862_amd/csrc/qieo_onchip.hpp",
                   "paper_2609_30862_amd/csrc/qieo_device.hpp",
                   "paper_2609_30862_amd/csrc/qieo_elite.hpp",
                   "paper_2609_30862_amd/csrc/qieo_host.hpp",
@@ -229,15 +230,24 @@ def bench_batch(args):
         log("class tuning took %.1f s" % (time.perf_counter() - t0))
     variants = {}
     onchip_launches = None
+    # untimed: two generations of the whole batch load every kernel variant
+    # the timed calls use
+    b = qieo.Batch(probs)
+    b.step(2)
+    b.close()
     # one call per variant, each on a fresh batch; "default" is the library's
-    # default mode (members of rows under 8 chunks in batched on-chip
-    # launches, tiny members LDS-resident, rows of 8+ chunks in segment order)
-    for name, pers, seg, onchip in (("no_onchip_no_persistent", False, 1, False),
-                                    ("no_onchip", True, 1, False),
-                                    ("default", True, 1, True),
-                                    ("onchip_no_persistent", False, 1, True),
-                                    ("segment_order_32_chunk_rows_only", True, 2, True),
-                                    ("row_order_long_rows", True, 0, True)):
+    # default mode (every member that fits in batched on-chip launches, the
+    # others LDS-resident or in per-generation launches, rows of 8+ chunks in
+    # segment order)
+    all_variants = (("default", True, 1, True),
+                    ("no_onchip", True, 1, False),
+                    ("no_onchip_no_persistent", False, 1, False),
+                    ("no_onchip_segment_order_32_chunk_rows_only", True, 2, False),
+                    ("no_onchip_row_order_long_rows", True, 0, False))
+    for name, pers, seg, onchip in all_variants:
+        if name != "default" and args.batch_variants != "all" and \
+                name not in args.batch_variants.split(","):
+            continue
         b = qieo.Batch(probs)
         b.set_persistent(pers)
         b.set_segment_order(seg)
@@ -257,6 +267,8 @@ def bench_batch(args):
     # the third call of a batch: without the on-chip loop a repeated call is
     # replayed from its captured graph; with it, launched directly
     for name, onchip in (("replay_captured_no_onchip", False), ("third_call_default", True)):
+        if args.batch_variants != "all" and name not in args.batch_variants.split(","):
+            continue
         b = qieo.Batch(probs)
         b.set_onchip(onchip)
         b.step(gens)
@@ -591,6 +603,11 @@ def main():
     ap.add_argument("--gens-per-iter", type=int, default=25, help="serve: generations/iteration")
     ap.add_argument("--loop-sample", type=int, default=200,
                     help="serve: requests re-run one by one for the per-instance loop baseline")
+    ap.add_argument("--batch-variants", default="all",
+                    help="batch: comma-separated variants to time (default, no_onchip, "
+                         "no_onchip_no_persistent, no_onchip_segment_order_32_chunk_rows_only, "
+                         "no_onchip_row_order_long_rows, replay_captured_no_onchip, "
+                         "third_call_default) or all; default is always timed")
     ap.add_argument("--no-onchip", action="store_true",
                     help="serve: residents in per-generation launches only (no batched on-chip loop)")
     ap.add_argument("--skip-loop", action="store_true",

@@ -167,6 +167,16 @@ struct ClassPlan {
     std::vector<Tile> tiles, fe_tiles;
 };
 
+// One workgroup of a batched on-chip launch: rows [row0, row0 + nrows) of
+// member inst, which the launch runs on nb workgroups (blk = this one's
+// index among them) of up to R rows each.
+struct OnchipTile {
+    uint32_t inst;
+    int32_t row0, nrows, R;
+    int32_t blk, nb;
+    int32_t pad[2];
+};
+
 // One cooperative launch of the batched on-chip loop: every generation of
 // the call for the members its tiles cover, one workgroup per tile.
 struct OnchipLaunch {

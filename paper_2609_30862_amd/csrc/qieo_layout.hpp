@@ -70,16 +70,6 @@ struct Tile {
     uint32_t row0;
 };
 
-// One workgroup of a batched on-chip launch: rows [row0, row0 + nrows) of
-// member inst, which the launch runs on nb workgroups (blk = this one's
-// index among them) of up to R rows each.
-struct OnchipTile {
-    uint32_t inst;
-    int32_t row0, nrows, R;
-    int32_t blk, nb;
-    int32_t pad[2];
-};
-
 // Kernel variant bits ("flags"): bit 0 = prefetch the next chunk's
 // amplitudes while computing the current one; bit 1 = non-temporal amplitude
 // stores; bit 2 = non-temporal amplitude loads; bit 3 = re-derive the

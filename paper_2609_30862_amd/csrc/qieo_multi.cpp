@@ -7,6 +7,7 @@
 // of 512.  The launches of a whole call (n generations x classes, plus the
 // finishing step) are captured once into a HIP graph and replayed.
 #include "qieo_multi.hpp"
+#include "qieo_onchip.hpp"
 
 #include <algorithm>
 #include <cstring>

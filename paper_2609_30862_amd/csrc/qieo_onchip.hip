@@ -55,6 +55,7 @@
 #include "qieo_elite.hpp"
 #include "qieo_host.hpp"
 #include "qieo_kernels.hpp"
+#include "qieo_onchip.hpp"
 
 namespace qieo {
 

@@ -18,6 +18,7 @@
 #include "../../include/qieo.h"
 #include "qieo_internal.hpp"
 #include "qieo_kernels.hpp"
+#include "qieo_onchip.hpp"
 
 using namespace qieo;
 

@@ -300,9 +300,11 @@ int qieo_batch_set_segment_order(qieo_batch *b, int32_t mode);
  * than that takes several such launches one after another; they run before
  * the call's other launches, alone on the device.  The members it cannot
  * place (longer rows, too many rows for one launch) keep the per-generation
- * launches (LDS-resident, segment or row order as set above).  Taken only
- * while no member has a convergence window and no shape is forced, and not
- * with graph capture (such a call is launched directly).  0: every member
+ * launches (LDS-resident, segment or row order as set above).  Members with
+ * a convergence window (qieo_batch_set_convergence) run in launches of their
+ * own that make the window test (every workgroup of a member stops at the
+ * generation the per-generation launches would).  Not taken while a shape
+ * is forced, nor with graph capture (such a call is launched directly).  0: every member
  * per-generation launches.  Results are identical.  A barrier wait past its
  * bound (qieo_batch_set_barrier_timeout) makes the call fail with
  * QIEO_EDEVICE when the batch is synchronised, its members' state then
@@ -349,10 +351,9 @@ int qieo_server_create(const qieo_server_cfg *cfg, const qieo_dev_ctx *ctx, qieo
  * + qieo_best on the same inputs, whatever else is resident. */
 int qieo_server_submit(qieo_server *s, const qieo_problem *p, int32_t n_gen, uint64_t *ticket);
 /* 1 (default): the residents' generations run in batched on-chip launches
- * wherever they fit (see qieo_batch_set_onchip; not with a convergence
- * window), the rest in per-generation launches; 0: per-generation launches
- * only.  Takes effect at the worker's next iteration.  Results are
- * identical. */
+ * wherever they fit (see qieo_batch_set_onchip), the rest in per-generation
+ * launches; 0: per-generation launches only.  Takes effect at the worker's
+ * next iteration.  Results are identical. */
 int qieo_server_set_onchip(qieo_server *s, int32_t enabled);
 /* QIEO_EAGAIN while the request is queued or running; otherwise its result
  * (or its failure code, e.g. QIEO_ENOMEM when its population can never fit

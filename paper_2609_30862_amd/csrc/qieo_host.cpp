@@ -344,7 +344,8 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
         int32_t R, nb;
         size_t lds;
     };
-    std::vector<std::vector<Place>> by_variant(kOnchipVariants);
+    // [variant][has a window]
+    std::vector<std::vector<Place>> by_variant(2 * kOnchipVariants);
     for (size_t i : ids) {
         const MemberShape& m = members[i];
         int best = -1;
@@ -371,11 +372,13 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
             }
         }
         if (best < 0) rest->push_back(i);
-        else by_variant[best].push_back(pick);
+        else by_variant[2 * best + (m.conv ? 1 : 0)].push_back(pick);
     }
-    // per variant (largest K first), first fit by decreasing workgroup count
-    for (int v = kOnchipVariants - 1; v >= 0; --v) {
-        std::vector<Place>& placed = by_variant[v];
+    // per variant (largest K first) and window test, first fit by decreasing
+    // workgroup count
+    for (int vc = 2 * kOnchipVariants - 1; vc >= 0; --vc) {
+        const int v = vc / 2;
+        std::vector<Place>& placed = by_variant[vc];
         if (placed.empty()) continue;
         std::stable_sort(placed.begin(), placed.end(),
                          [](const Place& a, const Place& b) { return a.nb > b.nb; });
@@ -394,6 +397,7 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
         for (auto& bin : bins) {
             OnchipLaunch L;
             L.K = kOnchipK[v];
+            L.conv = (vc & 1) != 0;
             // members in index order inside a launch
             std::sort(bin.begin(), bin.end(),
                       [&](size_t a, size_t b) { return placed[a].id < placed[b].id; });

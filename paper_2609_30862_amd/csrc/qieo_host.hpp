@@ -134,6 +134,7 @@ struct MemberShape {
     int32_t np = 0, pitch = 0, nchunk = 0;
     int32_t part_nseg = 0;        // from the member's arena layout
     uint64_t addr = 0;            // arena address (segment tiles go in address order)
+    bool conv = false;            // has a convergence window
 };
 
 struct PlanOptions {
@@ -181,6 +182,7 @@ struct OnchipTile {
 // the call for the members its tiles cover, one workgroup per tile.
 struct OnchipLaunch {
     int K = 0;                        // compiled items per wave
+    bool conv = false;                // the variant with the window test (its members have windows)
     size_t lds = 0;                   // dynamic LDS per workgroup (the largest tile's need)
     std::vector<OnchipTile> tiles;
 };
@@ -197,9 +199,9 @@ struct BatchPlan {
 // its workgroups times the measured cost of a workgroup-generation (about 6
 // us of synchronisation plus 1.1 us per item a wave holds): at variant K it
 // runs on b workgroups of R = ceil(np / b) whole rows, b the fewest whose
-// kOnchipWaves * K items hold its rows.  The members of each variant are
-// packed first-fit by decreasing b into launches of at most
-// opt.onchip_blocks workgroups.  Members no variant can place (a row longer
+// kOnchipWaves * K items hold its rows.  The members of each variant, those
+// with a convergence window apart from those without, are packed first-fit
+// by decreasing b into launches of at most opt.onchip_blocks workgroups.  Members no variant can place (a row longer
 // than the largest variant holds, more workgroups than a launch has, more
 // LDS than the limit, more than 65536 rows) are returned in *rest.
 void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size_t>& ids,

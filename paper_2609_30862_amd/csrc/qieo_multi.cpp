@@ -210,6 +210,7 @@ int Engine::rebuild()
         shapes[i].nchunk = m.L.nchunk;
         shapes[i].part_nseg = m.L.part_nseg;
         shapes[i].addr = (uint64_t)(uintptr_t)m.arena;
+        shapes[i].conv = m.window > 0;
     }
     PlanOptions opt;
     opt.use_persistent = use_persistent_;
@@ -251,7 +252,7 @@ int Engine::rebuild()
             return rebuild_nomem("on-chip abort words");
         for (OnchipLaunch& L : plan.onchip) {
             // owned by onchip_ from here on (freed at the next rebuild)
-            onchip_.push_back(OnchipRun{L.K, L.lds, (int)L.tiles.size(), nullptr});
+            onchip_.push_back(OnchipRun{L.K, L.conv, L.lds, (int)L.tiles.size(), nullptr});
             OnchipRun& o = onchip_.back();
             if (!(o.d_tiles = (OnchipTile*)mem_.alloc(L.tiles.size() * sizeof(OnchipTile))))
                 return rebuild_nomem("on-chip tiles");
@@ -321,8 +322,8 @@ int Engine::enqueue(int nmax)
         const int64_t ticks = onchip_spin_ticks(device_of_stream(), barrier_us_);
         for (size_t j = 0; j < onchip_.size(); ++j) {
             const OnchipRun& o = onchip_[j];
-            if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.lds, d_gens_, 0,
-                                         d_abort_ + j, ticks, stream_)) != hipSuccess)
+            if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.conv, o.lds, d_gens_,
+                                         0, d_abort_ + j, ticks, stream_)) != hipSuccess)
                 return hip_fail(e, "batched on-chip kernel");
         }
         onchip_check_ = true;
@@ -484,11 +485,7 @@ int Engine::device_of_stream() const
 
 void Engine::set_onchip_options(PlanOptions* opt) const
 {
-    // the batched loop has no convergence test: a batch with a window keeps
-    // the per-generation launches
-    bool windows = false;
-    for (const Member& m : members_) windows = windows || m.window > 0;
-    if (!use_onchip_ || windows) return;
+    if (!use_onchip_) return;
     size_t lim = 0;
     int ncu = 0;
     onchip_limits(&lim, &ncu);
@@ -530,7 +527,7 @@ int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
     for (size_t i = 0; i < n; ++i) {
         const Member& m = members_[i];
         shapes[i] = MemberShape{m.np, m.L.pitch, m.L.nchunk, m.L.part_nseg,
-                                (uint64_t)(uintptr_t)m.arena};
+                                (uint64_t)(uintptr_t)m.arena, m.window > 0};
     }
     PlanOptions opt;
     opt.use_persistent = use_persistent_;
@@ -693,7 +690,7 @@ int Engine::set_window_all(int32_t window)
         if (rc) return rc;
         m.window = window;
     }
-    // the batched on-chip loop runs only without windows
+    // the batched on-chip launches are planned by window
     if (use_onchip_) dirty_ = true;
     return QIEO_OK;
 }

@@ -144,6 +144,7 @@ private:
     // fork: each takes one workgroup on every CU it uses for the whole call)
     struct OnchipRun {
         int K = 0;
+        bool conv = false;
         size_t lds = 0;
         int n_tiles = 0;
         OnchipTile* d_tiles = nullptr;

@@ -482,8 +482,9 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
 
 // Batched form: workgroup b runs tiles[b] (whole rows of one member) for
 // that member's gens_arr entry (gens_all when gens_arr is NULL); the
-// workgroups of one member wait only for each other.  No convergence window.
-template <int K>
+// workgroups of one member wait only for each other.  CONV: every member of
+// the launch has a convergence window.
+template <int K, bool CONV>
 __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_multi_kernel(
     const InstDev* __restrict__ insts, const OnchipTile* __restrict__ tiles,
     const int32_t* __restrict__ gens_arr, int gens_all, uint32_t* abort_flag,
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_multi_kernel(
     // every workgroup of the member leaves here alike
     if (gens <= 0) return;
     const InstDev I = insts[T.inst];
-    onchip_body<K, false>(I, T.row0, T.nrows, T.R, T.blk, T.nb, gens, abort_flag, spin_ticks);
+    onchip_body<K, CONV>(I, T.row0, T.nrows, T.R, T.blk, T.nb, gens, abort_flag, spin_ticks);
 }
 
 // Clears the launch's abort word and, for each tile, its workgroup's key
@@ -533,16 +534,22 @@ OnchipFn onchip_fn(int K, bool conv) { return conv ? onchip_fn<true>(K) : onchip
 typedef void (*OnchipMultiFn)(const InstDev*, const OnchipTile*, const int32_t*, int, uint32_t*,
                               int64_t);
 
+template <bool CONV>
 OnchipMultiFn onchip_multi_fn(int K)
 {
     switch (K) {
-        case 2: return onchip_multi_kernel<2>;
-        case 4: return onchip_multi_kernel<4>;
-        case 6: return onchip_multi_kernel<6>;
-        case 8: return onchip_multi_kernel<8>;
-        case 10: return onchip_multi_kernel<10>;
+        case 2: return onchip_multi_kernel<2, CONV>;
+        case 4: return onchip_multi_kernel<4, CONV>;
+        case 6: return onchip_multi_kernel<6, CONV>;
+        case 8: return onchip_multi_kernel<8, CONV>;
+        case 10: return onchip_multi_kernel<10, CONV>;
         default: return nullptr;
     }
+}
+
+OnchipMultiFn onchip_multi_fn(int K, bool conv)
+{
+    return conv ? onchip_multi_fn<true>(K) : onchip_multi_fn<false>(K);
 }
 
 }  // namespace
@@ -611,17 +618,20 @@ unsigned onchip_multi_variants()
         onchip_limits(&lim, &ncu);
         if (ncu == 0) return;
         for (int v = 0; v < kOnchipVariants; ++v) {
-            const void* f = reinterpret_cast<const void*>(onchip_multi_fn(kOnchipK[v]));
-            int blocks = 0;
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
-                    hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64 * kOnchipWaves, lim) !=
-                    hipSuccess ||
-                blocks < 1) {
-                (void)hipGetLastError();
-                continue;
+            bool ok = true;
+            for (bool conv : {false, true}) {
+                const void* f = reinterpret_cast<const void*>(onchip_multi_fn(kOnchipK[v], conv));
+                int blocks = 0;
+                if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+                        hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64 * kOnchipWaves,
+                                                                 lim) != hipSuccess ||
+                    blocks < 1) {
+                    (void)hipGetLastError();
+                    ok = false;
+                }
             }
-            mask |= 1u << v;
+            if (ok) mask |= 1u << v;
         }
     });
     return mask;
@@ -701,7 +711,7 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
 }
 
 hipError_t launch_onchip_multi(const InstDev* dI, const OnchipTile* tiles, int n_tiles, int K,
-                               size_t lds, const int32_t* gens_arr, int gens_all,
+                               bool conv, size_t lds, const int32_t* gens_arr, int gens_all,
                                uint32_t* abort_flag, int64_t spin_ticks, hipStream_t s)
 {
     size_t lim = 0;
@@ -719,7 +729,7 @@ hipError_t launch_onchip_multi(const InstDev* dI, const OnchipTile* tiles, int n
     uint32_t* a4 = abort_flag;
     int64_t a5 = spin_ticks;
     void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
-    return chained_coop_launch(reinterpret_cast<const void*>(onchip_multi_fn(K)),
+    return chained_coop_launch(reinterpret_cast<const void*>(onchip_multi_fn(K, conv)),
                                (unsigned)n_tiles, args, lds, s, [&] {
                                    hipLaunchKernelGGL(onchip_multi_reset_kernel,
                                                       dim3((unsigned)((n_tiles + 255) / 256)),

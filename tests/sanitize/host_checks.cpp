@@ -251,6 +251,7 @@ static void check_plan_batch()
             ms[i].nchunk = L.nchunk;
             ms[i].part_nseg = L.part_nseg;
             ms[i].addr = addr + (uint64_t)(rng() % 1000) * 4096;   // not in member order
+            ms[i].conv = rng() % 3 == 0;
             addr += L.total + (1 << 20);
             ngs[i] = ng;
         }
@@ -303,6 +304,8 @@ static void check_plan_batch()
             for (const OnchipTile& t : L.tiles) {
                 CHECK(t.inst < (uint32_t)n, "on-chip tile member");
                 const MemberShape& m = ms[t.inst];
+                CHECK(m.conv == L.conv, "member %u (window %d) in a launch with window test %d",
+                      t.inst, (int)m.conv, (int)L.conv);
                 CHECK(m.np <= 65536, "member %u: %d rows on-chip", t.inst, m.np);
                 CHECK(t.nb >= 1 && t.nb <= opt.onchip_blocks && t.blk >= 0 && t.blk < t.nb,
                       "workgroup %d of %d", t.blk, t.nb);

@@ -268,21 +268,33 @@ def test_onchip_over_several_launches(qieo, oracle_mod):
         assert_state_equal(View(on, k), orcs[k], label="on-chip member %d" % k)
 
 
-def test_onchip_not_taken_with_convergence_window(qieo, oracle_mod):
-    """The batched loop makes no convergence test: with a window the batch
-    keeps the per-generation launches, and still follows the oracle."""
-    # LDS-resident members and the three that take the on-chip loop
-    insts = [_ragged_instances()[k] for k in (0, 3, 8, 11, 13)]
-    b = qieo.Batch(_problems(insts))
-    assert b.onchip_launches() >= 1
-    b.set_convergence(4)
-    assert b.onchip_launches() == 0
-    b.step(40)
-    for k, i in enumerate(insts):
-        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
-        o.run_until_converged(40, 4)
-        assert b.generations(k) == o.t
-        assert_state_equal(View(b, k), o, label="windowed member %d" % k)
+def test_onchip_with_convergence_window(qieo, oracle_mod):
+    """Members with a convergence window run in on-chip launches of their
+    own that make the window test: each member stops where the oracle does,
+    across calls, as the per-generation launches do."""
+    # LDS-sized members and three that need several workgroups each
+    insts = [_ragged_instances()[k] for k in (0, 3, 8, 11, 13)] + _many_mid_sized(3)
+    on = qieo.Batch(_problems(insts))
+    off = qieo.Batch(_problems(insts))
+    off.set_onchip(False)
+    for b in (on, off):
+        b.set_convergence(4)
+    assert on.onchip_launches() >= 1 and off.onchip_launches() == 0
+    orcs = [oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed) for i in insts]
+    for call, g in enumerate((7, 13, 40, 40)):
+        say("window call %d: %d generations" % (call, g))
+        on.step(g)
+        off.step(g)
+        for k, o in enumerate(orcs):
+            o.run_until_converged(g, 4)
+            assert on.generations(k) == off.generations(k) == o.t, (call, k)
+            assert on.converged(k)[0] == off.converged(k)[0] == o.converged(4), (call, k)
+    for k, o in enumerate(orcs):
+        assert_state_equal(View(on, k), o, label="windowed member %d" % k)
+        a, c = on.export_rows(k), off.export_rows(k)
+        for key in ("alpha", "beta", "alleles", "fitness"):
+            assert np.array_equal(a[key], c[key]), (k, key)
+    say("converged: %s" % [on.converged(k)[0] for k in range(len(insts))])
 
 
 def test_onchip_barrier_timeout_is_reported(qieo):

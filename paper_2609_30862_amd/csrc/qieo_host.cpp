@@ -334,90 +334,152 @@ int class_of(int32_t nchunk)
     return 4;
 }
 
+namespace {
+
+struct OnchipPlace {
+    size_t id;
+    int32_t R, nb;
+    size_t lds;
+};
+
+// Member m on workgroups of variant v: false if it does not fit.
+bool onchip_fit(const MemberShape& m, size_t id, int v, const PlanOptions& opt, OnchipPlace* out)
+{
+    const int K = kOnchipK[v];
+    const int64_t cap = (int64_t)kOnchipWaves * K;          // items a workgroup holds
+    if (m.np < 1 || m.np > 65536 || m.nchunk < 1 || m.nchunk > cap) return false;
+    int64_t R = std::min<int64_t>(m.np, cap / m.nchunk);
+    int64_t nb = (m.np + R - 1) / R;
+    R = (m.np + nb - 1) / nb;                               // balanced: same nb, fewer rows
+    nb = (m.np + R - 1) / R;
+    const size_t lds = onchip_lds_bytes((int)R, m.nchunk);
+    if (nb > opt.onchip_blocks || lds > opt.onchip_lds_limit) return false;
+    *out = OnchipPlace{id, (int32_t)R, (int32_t)nb, lds};
+    return true;
+}
+
+// Measured cost of one generation of a launch of variant v, in us.
+double onchip_launch_cost(int v) { return 6.0 + 1.1 * kOnchipK[v]; }
+
+}  // namespace
+
 void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size_t>& ids,
                  const PlanOptions& opt, std::vector<OnchipLaunch>* out, std::vector<size_t>* rest)
 {
     out->clear();
     rest->clear();
-    struct Place {
-        size_t id;
-        int32_t R, nb;
-        size_t lds;
-    };
     // [variant][has a window]
-    std::vector<std::vector<Place>> by_variant(2 * kOnchipVariants);
+    std::vector<std::vector<OnchipPlace>> by_variant(2 * kOnchipVariants);
     for (size_t i : ids) {
         const MemberShape& m = members[i];
         int best = -1;
         double best_cost = 0.0;
-        Place pick{};
+        OnchipPlace pick{};
         for (int v = 0; v < kOnchipVariants && opt.onchip_blocks > 0; ++v) {
             if (!(opt.onchip_variants & (1u << v))) continue;
-            const int K = kOnchipK[v];
-            const int64_t cap = (int64_t)kOnchipWaves * K;    // items a workgroup holds
-            if (m.np < 1 || m.np > 65536 || m.nchunk < 1 || m.nchunk > cap) continue;
-            int64_t R = std::min<int64_t>(m.np, cap / m.nchunk);
-            int64_t nb = (m.np + R - 1) / R;
-            R = (m.np + nb - 1) / nb;                         // balanced: same nb, fewer rows
-            nb = (m.np + R - 1) / R;
-            const size_t lds = onchip_lds_bytes((int)R, m.nchunk);
-            if (nb > opt.onchip_blocks || lds > opt.onchip_lds_limit) continue;
+            OnchipPlace q;
+            if (!onchip_fit(m, i, v, opt, &q)) continue;
             // the member's share of a launch's generation: its workgroups
             // times the cost of one workgroup-generation of variant K
-            const double cost = (double)nb * (6.0 + 1.1 * K);
+            const double cost = (double)q.nb * onchip_launch_cost(v);
             if (best < 0 || cost < best_cost) {
                 best = v;
                 best_cost = cost;
-                pick = Place{i, (int32_t)R, (int32_t)nb, lds};
+                pick = q;
             }
         }
         if (best < 0) rest->push_back(i);
         else by_variant[2 * best + (m.conv ? 1 : 0)].push_back(pick);
     }
-    // per variant (largest K first) and window test, first fit by decreasing
-    // workgroup count
+    // per variant and window test, first fit by decreasing workgroup count
+    struct Bin {
+        int v;
+        bool conv;
+        int64_t used;
+        std::vector<OnchipPlace> items;
+    };
+    std::vector<Bin> bins;
     for (int vc = 2 * kOnchipVariants - 1; vc >= 0; --vc) {
-        const int v = vc / 2;
-        std::vector<Place>& placed = by_variant[vc];
+        std::vector<OnchipPlace>& placed = by_variant[vc];
         if (placed.empty()) continue;
         std::stable_sort(placed.begin(), placed.end(),
-                         [](const Place& a, const Place& b) { return a.nb > b.nb; });
-        std::vector<int64_t> used;
-        std::vector<std::vector<size_t>> bins;
-        for (size_t p = 0; p < placed.size(); ++p) {
-            size_t b = 0;
-            while (b < used.size() && used[b] + placed[p].nb > opt.onchip_blocks) ++b;
-            if (b == used.size()) {
-                used.push_back(0);
-                bins.emplace_back();
-            }
-            used[b] += placed[p].nb;
-            bins[b].push_back(p);
+                         [](const OnchipPlace& a, const OnchipPlace& b) { return a.nb > b.nb; });
+        const size_t first = bins.size();
+        for (const OnchipPlace& q : placed) {
+            size_t b = first;
+            while (b < bins.size() && bins[b].used + q.nb > opt.onchip_blocks) ++b;
+            if (b == bins.size()) bins.push_back(Bin{vc / 2, (vc & 1) != 0, 0, {}});
+            bins[b].used += q.nb;
+            bins[b].items.push_back(q);
         }
-        for (auto& bin : bins) {
-            OnchipLaunch L;
-            L.K = kOnchipK[v];
-            L.conv = (vc & 1) != 0;
-            // members in index order inside a launch
-            std::sort(bin.begin(), bin.end(),
-                      [&](size_t a, size_t b) { return placed[a].id < placed[b].id; });
-            for (size_t p : bin) {
-                const Place& q = placed[p];
-                const int32_t np = members[q.id].np;
-                for (int32_t b = 0; b < q.nb; ++b) {
-                    OnchipTile t{};
-                    t.inst = (uint32_t)q.id;
-                    t.row0 = b * q.R;
-                    t.nrows = std::min(q.R, np - t.row0);
-                    t.R = q.R;
-                    t.blk = b;
-                    t.nb = q.nb;
-                    L.tiles.push_back(t);
+    }
+    // A launch costs the same per generation however few of its workgroups
+    // are used, so a launch whose members all fit the spare workgroups of
+    // launches of a larger variant (same window test) is emptied into them:
+    // cheapest launches first, each member first-fit into the largest
+    // variants first, all or nothing.
+    std::vector<size_t> order(bins.size());
+    for (size_t b = 0; b < bins.size(); ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return bins[a].v < bins[b].v; });
+    std::vector<bool> gone(bins.size(), false);
+    for (size_t src : order) {
+        std::vector<int64_t> used(bins.size());
+        for (size_t b = 0; b < bins.size(); ++b) used[b] = bins[b].used;
+        std::vector<std::pair<size_t, OnchipPlace>> moves;
+        bool all = true;
+        for (const OnchipPlace& q : bins[src].items) {
+            bool placed = false;
+            for (size_t dst = 0; dst < bins.size() && !placed; ++dst) {
+                if (gone[dst] || dst == src || bins[dst].conv != bins[src].conv ||
+                    bins[dst].v <= bins[src].v)
+                    continue;
+                OnchipPlace r;
+                if (onchip_fit(members[q.id], q.id, bins[dst].v, opt, &r) &&
+                    used[dst] + r.nb <= opt.onchip_blocks) {
+                    used[dst] += r.nb;
+                    moves.emplace_back(dst, r);
+                    placed = true;
                 }
-                L.lds = std::max(L.lds, q.lds);
             }
-            out->push_back(std::move(L));
+            if (!placed) {
+                all = false;
+                break;
+            }
         }
+        if (!all) continue;
+        for (auto& mv : moves) {
+            bins[mv.first].used += mv.second.nb;
+            bins[mv.first].items.push_back(mv.second);
+        }
+        bins[src].items.clear();
+        bins[src].used = 0;
+        gone[src] = true;
+    }
+    for (size_t b = 0; b < bins.size(); ++b) {
+        if (gone[b]) continue;
+        Bin& bin = bins[b];
+        OnchipLaunch L;
+        L.K = kOnchipK[bin.v];
+        L.conv = bin.conv;
+        // members in index order inside a launch
+        std::sort(bin.items.begin(), bin.items.end(),
+                  [](const OnchipPlace& a, const OnchipPlace& c) { return a.id < c.id; });
+        for (const OnchipPlace& q : bin.items) {
+            const int32_t np = members[q.id].np;
+            for (int32_t w = 0; w < q.nb; ++w) {
+                OnchipTile t{};
+                t.inst = (uint32_t)q.id;
+                t.row0 = w * q.R;
+                t.nrows = std::min(q.R, np - t.row0);
+                t.R = q.R;
+                t.blk = w;
+                t.nb = q.nb;
+                L.tiles.push_back(t);
+            }
+            L.lds = std::max(L.lds, q.lds);
+        }
+        out->push_back(std::move(L));
     }
 }
 

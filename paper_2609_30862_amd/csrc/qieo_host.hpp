@@ -201,7 +201,10 @@ struct BatchPlan {
 // runs on b workgroups of R = ceil(np / b) whole rows, b the fewest whose
 // kOnchipWaves * K items hold its rows.  The members of each variant, those
 // with a convergence window apart from those without, are packed first-fit
-// by decreasing b into launches of at most opt.onchip_blocks workgroups.  Members no variant can place (a row longer
+// by decreasing b into launches of at most opt.onchip_blocks workgroups;
+// then each launch whose members all fit the spare workgroups of launches
+// of a larger variant (their b recomputed there) is emptied into them,
+// cheapest launches first.  Members no variant can place (a row longer
 // than the largest variant holds, more workgroups than a launch has, more
 // LDS than the limit, more than 65536 rows) are returned in *rest.
 void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size_t>& ids,

@@ -221,6 +221,13 @@ def bench_batch(args):
         tuned = b.autotune(args.autotune)
         b.close()
         for c in tuned:
+            if c["shape_class"] == -1:
+                log("tuned on-chip variants: subset 0x%x, %d launches, %.4f ms/generation "
+                    "(default subset 0x%x, %d launches: %.4f), %d subsets timed"
+                    % (c["flags"], c["rows_per_block"], c["ms_per_generation"], c["default_flags"],
+                       c["default_rows_per_block"], c["default_ms_per_generation"],
+                       c["candidates"]))
+                continue
             log("tuned class %d (%d rows, <= %d chunks): R %d S %d bits %d, %.4f ms/generation "
                 "(default R %d S %d bits %d: %.4f)"
                 % (c["shape_class"], c["rows"], c["max_chunks"], c["rows_per_block"],

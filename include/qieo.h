@@ -480,7 +480,21 @@ typedef struct qieo_class_tune {
  * max_out entries, *n_out (may be NULL) the number of classes.  Needs device
  * memory for a copy of the members' state (QIEO_ENOMEM otherwise);
  * trial_generations outside [1, 1000] gives QIEO_EINVAL.  Results of later
- * calls are unchanged (work shapes never change results). */
+ * calls are unchanged (work shapes never change results).
+ * A batch with on-chip launches (qieo_batch_set_onchip) also gets its
+ * items-per-wave variants tuned: every subset of the usable variants
+ * K = 2, 4, 6, 8, 10 that holds the largest is planned for the members
+ * the current plan places on-chip and timed with all its launches for
+ * trial_generations generations from the same state (twice, in opposite
+ * orders); the fastest subset is kept for this batch's later calls,
+ * recorded in the tuning database as class -1 (bucket: log2 of all the
+ * batch's rows, log2 of its longest row; later batches and servers in the
+ * bucket use it) and reported as an entry with shape_class -1:
+ * rows and max_chunks of the on-chip members, flags = the chosen subset
+ * (bit v: K = 2v + 2), rows_per_block = its launches per call,
+ * waves_per_block = 16, the default_* fields the same for the subset in
+ * use before, candidates = subsets timed, ms_per_generation for all the
+ * launches together. */
 int qieo_batch_autotune(qieo_batch *b, int32_t trial_generations, qieo_class_tune *out,
                         int32_t max_out, int32_t *n_out);
 /* Tuning database as JSON (one entry per line, single-instance buckets and

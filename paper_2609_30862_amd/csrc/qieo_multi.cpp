@@ -10,6 +10,7 @@
 #include "qieo_onchip.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <new>
 
@@ -483,15 +484,35 @@ int Engine::device_of_stream() const
     return dev;
 }
 
+// Rows of all members and the longest row in chunks: the tuning database's
+// bucket for a batch's on-chip variant subset.
+void Engine::batch_signature(int64_t* rows, int32_t* max_nchunk) const
+{
+    *rows = 0;
+    *max_nchunk = 0;
+    for (const Member& m : members_) {
+        *rows += m.np;
+        *max_nchunk = std::max(*max_nchunk, m.L.nchunk);
+    }
+}
+
 void Engine::set_onchip_options(PlanOptions* opt) const
 {
     if (!use_onchip_) return;
     size_t lim = 0;
     int ncu = 0;
     onchip_limits(&lim, &ncu);
+    // the subset tuned on this batch, else one tuned on a batch of the same
+    // bucket, else every usable variant
+    unsigned mask = onchip_mask_;
+    int R = 0, S = 0, F = 0;
+    int64_t rows = 0;
+    int32_t maxc = 0;
+    batch_signature(&rows, &maxc);
+    if (!mask && use_tuned_ && tuned_class(-1, rows, maxc, &R, &S, &F)) mask = (unsigned)F;
     opt->onchip_blocks = ncu;
     opt->onchip_lds_limit = lim;
-    opt->onchip_variants = ncu > 0 ? onchip_multi_variants() : 0u;
+    opt->onchip_variants = ncu > 0 ? onchip_multi_variants() & (mask ? mask : ~0u) : 0u;
 }
 
 int Engine::refresh_status()
@@ -513,13 +534,144 @@ int Engine::refresh_status()
     return QIEO_OK;
 }
 
+// The batched on-chip launches' variant subset, timed on the batch itself:
+// every subset of the usable variants that holds the largest one (so every
+// member the current plan places stays placeable), planned for the members
+// the current plan places, each run for gens generations of all its
+// launches from the saved state, twice in opposite orders, the faster time
+// counting.  The fastest subset is kept for this batch (onchip_mask_) and
+// reported as an entry with shape_class -1.
+int Engine::tune_onchip(int gens, const std::vector<MemberShape>& shapes, const PlanOptions& opt,
+                        const BatchPlan& plan,
+                        const std::function<hipError_t(const std::vector<uint32_t>&)>& restore,
+                        std::vector<void*>& temps, hipEvent_t e0, hipEvent_t e1,
+                        std::vector<qieo_class_tune>* out)
+{
+    std::vector<uint32_t> ids;
+    {
+        std::vector<bool> seen(members_.size(), false);
+        for (const OnchipLaunch& L : plan.onchip)
+            for (const OnchipTile& t : L.tiles)
+                if (!seen[t.inst]) {
+                    seen[t.inst] = true;
+                    ids.push_back(t.inst);
+                }
+        std::sort(ids.begin(), ids.end());
+    }
+    std::vector<size_t> cand_ids(ids.begin(), ids.end());
+    const unsigned usable = onchip_multi_variants();
+    int top = -1;
+    for (int v = 0; v < kOnchipVariants; ++v)
+        if (usable & (1u << v)) top = v;
+    if (top < 0) return QIEO_OK;
+    struct Cand {
+        unsigned mask;
+        std::vector<OnchipLaunch> launches;
+        std::vector<OnchipTile*> d_tiles;
+        double ms;
+    };
+    std::vector<Cand> cand;
+    size_t max_launches = 0;
+    int64_t rows = 0;
+    int32_t max_chunks = 0;
+    for (uint32_t i : ids) {
+        rows += members_[i].np;
+        max_chunks = std::max(max_chunks, members_[i].L.nchunk);
+    }
+    for (unsigned m = 1; m < (1u << kOnchipVariants); ++m) {
+        if ((m & usable) != m || !(m & (1u << top))) continue;
+        PlanOptions o = opt;
+        o.onchip_variants = m;
+        Cand c{m, {}, {}, 1e300};
+        std::vector<size_t> rest;
+        plan_onchip(shapes, cand_ids, o, &c.launches, &rest);
+        if (!rest.empty() || c.launches.empty()) continue;
+        for (const OnchipLaunch& L : c.launches) {
+            OnchipTile* d = (OnchipTile*)mem_.alloc(L.tiles.size() * sizeof(OnchipTile));
+            if (!d) return set_error(QIEO_ENOMEM, "device allocation of tuning tiles failed");
+            temps.push_back(d);
+            const hipError_t ee = hipMemcpyAsync(d, L.tiles.data(), L.tiles.size() * sizeof(OnchipTile),
+                                                 hipMemcpyHostToDevice, stream_);
+            if (ee != hipSuccess) return hip_fail(ee, "hipMemcpyAsync(tiles)");
+            c.d_tiles.push_back(d);
+        }
+        max_launches = std::max(max_launches, c.launches.size());
+        cand.push_back(std::move(c));
+    }
+    if (cand.empty()) return QIEO_OK;
+    uint32_t* d_abort = (uint32_t*)mem_.alloc(max_launches * sizeof(uint32_t));
+    if (!d_abort) return set_error(QIEO_ENOMEM, "device allocation of tuning abort words failed");
+    temps.push_back(d_abort);
+    // the tile tables above are local host vectors: their copies complete here
+    hipError_t e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const int64_t ticks = onchip_spin_ticks(device_of_stream(), barrier_us_);
+    auto time_one = [&](Cand& c) {
+        hipError_t ee = restore(ids);
+        if (ee == hipSuccess) ee = hipEventRecord(e0, stream_);
+        for (size_t j = 0; j < c.launches.size() && ee == hipSuccess; ++j)
+            ee = launch_onchip_multi(d_desc_, c.d_tiles[j], (int)c.launches[j].tiles.size(),
+                                     c.launches[j].K, c.launches[j].conv, c.launches[j].lds,
+                                     d_gens_, 0, d_abort + j, ticks, stream_);
+        if (ee == hipSuccess) ee = hipEventRecord(e1, stream_);
+        if (ee == hipSuccess) ee = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (ee == hipSuccess) ee = hipEventElapsedTime(&ms, e0, e1);
+        if (ee != hipSuccess) return hip_fail(ee, "tuning launch");
+        std::vector<uint32_t> flags(c.launches.size(), 0u);
+        if ((ee = copy_on(flags.data(), d_abort, flags.size() * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, stream_)) != hipSuccess)
+            return hip_fail(ee, "copy(on-chip abort words)");
+        for (uint32_t f : flags)
+            if (f)
+                return set_error(QIEO_EDEVICE, "batched on-chip loop: a barrier wait ran past "
+                                               "its bound while tuning");
+        c.ms = std::min(c.ms, (double)ms / gens);
+        return QIEO_OK;
+    };
+    int rc;
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t j = 0; j < cand.size(); ++j)
+            if ((rc = time_one(cand[pass == 0 ? j : cand.size() - 1 - j]))) return rc;
+    const unsigned dflt_mask = opt.onchip_variants;
+    const Cand* best = &cand[0];
+    const Cand* dflt = nullptr;
+    for (const Cand& c : cand) {
+        if (c.ms < best->ms) best = &c;
+        if (c.mask == dflt_mask) dflt = &c;
+    }
+    onchip_mask_ = best->mask;
+    {
+        int64_t all_rows = 0;
+        int32_t all_max = 0;
+        batch_signature(&all_rows, &all_max);
+        record_class(-1, all_rows, all_max, (int)best->launches.size(), kOnchipWaves,
+                     (int)best->mask, best->ms);
+    }
+    qieo_class_tune r{};
+    r.shape_class = -1;
+    r.rows = (int32_t)std::min<int64_t>(rows, INT32_MAX);
+    r.max_chunks = max_chunks;
+    r.rows_per_block = (int32_t)best->launches.size();
+    r.waves_per_block = kOnchipWaves;
+    r.flags = (int32_t)best->mask;
+    r.default_rows_per_block = (int32_t)plan.onchip.size();
+    r.default_waves_per_block = kOnchipWaves;
+    r.default_flags = (int32_t)dflt_mask;
+    r.candidates = (int32_t)cand.size();
+    r.ms_per_generation = best->ms;
+    r.default_ms_per_generation = dflt ? dflt->ms : -1.0;
+    out->push_back(r);
+    return QIEO_OK;
+}
+
 int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
 {
     out->clear();
     int rc = ensure_built();
     if (rc) return rc;
     const size_t n = members_.size();
-    if (n == 0 || classes_.empty()) return QIEO_OK;
+    if (n == 0 || (classes_.empty() && onchip_.empty())) return QIEO_OK;
     hipError_t e = hipStreamSynchronize(stream_);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     // the built-in rule's classes (the shapes a tuned entry replaces)
@@ -580,6 +732,9 @@ int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
                                              hipMemcpyHostToDevice, stream_);
         return ee == hipSuccess ? QIEO_OK : hip_fail(ee, "hipMemcpyAsync(tiles)");
     };
+    if (!plan.onchip.empty() && (rc = tune_onchip(gens, shapes, opt, plan, restore, temps, e0, e1,
+                                                  out)))
+        return done(rc);
     for (const ClassPlan& def : plan.classes) {
         // the class's members, longest rows first (as the planner orders them)
         std::vector<uint32_t> ids;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -153,7 +154,14 @@ private:
     uint32_t* d_abort_ = nullptr;    // one abort word per on-chip launch
     bool onchip_check_ = false;      // launches queued since the abort words were read
     int check_onchip_abort();
+    int tune_onchip(int gens, const std::vector<MemberShape>& shapes, const PlanOptions& opt,
+                    const BatchPlan& plan,
+                    const std::function<hipError_t(const std::vector<uint32_t>&)>& restore,
+                    std::vector<void*>& temps, hipEvent_t e0, hipEvent_t e1,
+                    std::vector<qieo_class_tune>* out);
+    unsigned onchip_mask_ = 0;       // variant subset the tuner chose (0: every usable one)
     int device_of_stream() const;
+    void batch_signature(int64_t* rows, int32_t* max_nchunk) const;
     void set_onchip_options(PlanOptions* opt) const;
     bool use_onchip_ = false;
     int64_t barrier_us_ = 1000000;

@@ -42,7 +42,9 @@ struct Entry {
 };
 
 // key: {kind, a, b, c}: kind 0 = single instance {log2 rows, log2 chunks, 0};
-// kind 1 = batch class {class, log2 rows, log2 longest row in chunks}
+// kind 1 = batch class {class, log2 rows, log2 longest row in chunks}, class
+// -1 = a batch's on-chip variant subset {-1, log2 of all its rows, log2 of
+// its longest row} with R = launches, S = waves, flags = the subset
 using Key = std::tuple<int, int, int, int>;
 
 std::mutex g_db_mu;
@@ -305,8 +307,16 @@ extern "C" int qieo_tune_db_load(const char* path)
                                "\"S\": %d, \"flags\": %d, \"ms\": %lf",
                             &a, &b, &c, &R, &S, &fl, &ms) != 7)
                 continue;
-            if (a < 0 || a >= kClasses) continue;
+            if (a < -1 || a >= kClasses) continue;
             key = Key{1, a, b, c};
+            // class -1: a batch's on-chip variant subset (R = its launches,
+            // S = waves per workgroup, flags = the subset)
+            if (a == -1) {
+                if (R < 1 || S != kOnchipWaves || fl < 1 || fl >= (1 << kOnchipVariants)) continue;
+                loaded[key] = Entry{R, S, fl, ms};
+                ++n;
+                continue;
+            }
         } else {
             continue;
         }

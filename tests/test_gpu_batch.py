@@ -180,7 +180,7 @@ def test_long_rows_in_segment_order(qieo, oracle_mod):
     onc.close()
 
 
-def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_mod):
+def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_mod, tmp_path):
     """Class tuning runs candidates on the batch itself and restores its
     state: after tuning (and with the tuned shapes afterwards) every member
     follows the same trajectory as an untuned batch and as the oracle."""
@@ -196,8 +196,22 @@ def test_batch_autotune_keeps_the_trajectory_and_uses_tuned_shapes(qieo, oracle_
         classes = b.autotune(3)
         say("tuned classes: %s" % [(c["shape_class"], c["rows_per_block"], c["waves_per_block"],
                                     c["flags"], round(c["ms_per_generation"], 4)) for c in classes])
-        assert classes and all(c["candidates"] >= 24 for c in classes)
+        assert classes and all(c["candidates"] >= 24 for c in classes if c["shape_class"] >= 0)
         assert len({c["shape_class"] for c in classes}) == len(classes)
+        # the batched on-chip launches: the variant subset (bit v: K = 2v + 2)
+        # timed on the batch, the largest variant always in it
+        onc = [c for c in classes if c["shape_class"] == -1]
+        assert len(onc) == 1 and onc[0]["candidates"] >= 1 and onc[0]["flags"] & 0x10
+        assert onc[0]["rows_per_block"] >= 1 and onc[0]["ms_per_generation"] > 0
+        # the database holds every entry (the on-chip subset as class -1),
+        # and a new batch of the same bucket plans with the tuned subset
+        path = str(tmp_path / "tune.json")
+        qieo.qieo_tune_db_save(path)
+        qieo.qieo_tune_db_clear()
+        assert qieo.qieo_tune_db_load(path) == len(classes)
+        fresh = qieo.Batch(probs)
+        assert fresh.onchip_launches() == onc[0]["rows_per_block"]
+        fresh.close()
         for k in range(n):                      # tuning left the state as it was
             a, c = ref.export_rows(k), b.export_rows(k)
             for key in ("alpha", "beta", "alleles", "fitness"):

@@ -146,6 +146,11 @@ int Engine::rebuild()
         const hipError_t se = hipStreamSynchronize(stream_);
         if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
     }
+    // the abort words of a call not yet synchronised are read before they go
+    {
+        const int rc0 = check_onchip_abort();
+        if (rc0) return rc0;
+    }
     for (auto& c : classes_) {
         mem_.release(c.d_tiles);
         mem_.release(c.d_fe_tiles);

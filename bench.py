@@ -40,6 +40,7 @@ ONCHIP_SOURCES = ["paper_2609_30862_amd/csrc/qieo_onchip.hip",
                   "paper_2609_30862_amd/csrc/qieo_host.hpp",
                   "paper_2609_30862_amd/csrc/qieo_layout.hpp"]
 ONCHIP_PROFILE = "profiles/onchip_kernel_np1024_ng10000.md"
+BATCH_PROFILE = "profiles/batch_512_ragged.md"
 # vector ALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (one non-packed instruction per lane and cycle), in G lane-instructions/s
 VALU_PEAK_G = 256 * 4 * 16 * 2.4
@@ -82,6 +83,25 @@ def onchip_valu_per_generation(n_pop: int, n_items: int):
         if fig.get("onchip_code_sha256") != kernel_code_digest(sources=ONCHIP_SOURCES):
             return None
         return float(fig["valu_insts_per_generation"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def batch_valu_per_call(onchip_launches: int):
+    """Vector ALU instructions (per wave, summed over the grids) of the
+    512-instance batch's on-chip launches in one 500-generation call, from
+    the committed rocprofv3 summary, if it was taken with the current
+    on-chip code and the same number of on-chip launches; else None."""
+    keys = ("batch_valu_insts_per_call", "batch_onchip_launches", "onchip_code_sha256")
+    try:
+        text = open(os.path.join(ROOT, BATCH_PROFILE)).read()
+        fig = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                   if line.strip().startswith(tuple(k + ":" for k in keys)))
+        if fig.get("onchip_code_sha256") != kernel_code_digest(sources=ONCHIP_SOURCES):
+            return None
+        if int(fig["batch_onchip_launches"]) != onchip_launches:
+            return None
+        return float(fig["batch_valu_insts_per_call"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -313,8 +333,19 @@ def bench_batch(args):
             g.close()
         loops[mode] = wall_loop
         log("per-instance loop (%s): %.3f s" % (mode, wall_loop))
+    # the on-chip launches keep the planes in registers: bound by vector ALU
+    # issue, measured by their instruction count (rocprofv3 SQ_INSTS_VALU);
+    # the call's whole wall time, the left-out members' launches included
+    valu = batch_valu_per_call(onchip_launches or 0) if gens == 500 else None
+    valu_rate = None if valu is None else valu * 64 / wall_batch / 1e9
+    roofline = {"bound": "alu", "achieved": valu_rate, "peak": VALU_PEAK_G,
+                "unit": "G VALU lane-instructions/s",
+                "frac": None if valu_rate is None else valu_rate / VALU_PEAK_G,
+                "traffic": None,
+                "kernel": "onchip_multi_kernel (%s on-chip launches per call)" % onchip_launches,
+                "valu_insts_per_call": valu}
     if args.skip_loop:
-        out = {"workload": "batch", "batch_variants_seconds": variants,
+        out = {"workload": "batch", "batch_variants_seconds": variants, "roofline": roofline,
                "value": genes * gens / wall_batch, "unit": "gene-updates/s",
                "onchip_launches": onchip_launches, "tuned_classes": tuned}
         print(json.dumps(out), flush=True)
@@ -343,6 +374,7 @@ def bench_batch(args):
                               "variants_seconds": loops},
         "batch_variants_seconds": variants,
         "onchip_launches": onchip_launches,
+        "roofline": roofline,
         "speedup_vs_loop": wall_loop / wall_batch,
         "per_generation_launch_loop": {"value": genes * gens / wall_launch_loop,
                                        "seconds": wall_launch_loop},

@@ -293,8 +293,10 @@ int qieo_batch_set_segment_order(qieo_batch *b, int32_t mode);
 /* 1 (default): every member that fits runs every generation of a call
  * inside cooperative launches with its amplitude planes held in registers,
  * the on-chip loop of qieo_set_persistent mode 3 extended to many members:
- * each member on workgroups of whole rows (rows of up to 160 chunks of 256
- * genes), its workgroups waiting only for each other at the end of each
+ * each member on workgroups of whole rows (rows of up to 76 chunks of 256
+ * genes: the member's item tables and two generations of its rows' allele
+ * words must fit a workgroup's LDS), its workgroups waiting only for each
+ * other at the end of each
  * generation (Sec. III-B's loop: DetermineElite over the member's rows
  * before its CIP), at most one workgroup per CU, so a batch of more rows
  * than that takes several such launches one after another; they run before

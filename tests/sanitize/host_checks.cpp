@@ -574,6 +574,75 @@ static void check_onchip_plan()
           "onchip_worth");
 }
 
+// The batched on-chip planner's choices on hand-built members (the sizes
+// worked out by hand from its rule): A = 256 rows of 70 chunks takes
+// K = 10 (2 rows a workgroup, 128 workgroups, 154,624 B of LDS: 128 x 17
+// us against 256 x 14.8 at K = 8); C = 256 rows of 7 chunks K = 10 (22
+// rows, 12 workgroups: 12 x 17 against 15 x 14.8 at K = 8); B = 32 rows of
+// 1 chunk K = 2 (one workgroup), whose launch is then emptied into a
+// K = 10 launch with room.  Rows of 77 or more chunks need more than the
+// 160 KB of LDS (item tables alone 2 KB a chunk) and are left out.
+static void check_onchip_choices()
+{
+    std::vector<MemberShape> ms(3);
+    const int32_t np[3] = {256, 32, 256}, nchunk[3] = {70, 1, 7};
+    for (int i = 0; i < 3; ++i) {
+        ms[i].np = np[i];
+        ms[i].nchunk = nchunk[i];
+        ms[i].pitch = nchunk[i] * kChunk;
+    }
+    PlanOptions opt;
+    opt.onchip_blocks = 256;
+    opt.onchip_lds_limit = 160 * 1024 - 256;
+    opt.onchip_variants = 0x1fu;
+    std::vector<OnchipLaunch> L;
+    std::vector<size_t> rest;
+    plan_onchip(ms, {0, 1, 2}, opt, &L, &rest);
+    CHECK(rest.empty() && L.size() == 1 && L[0].K == 10 && L[0].tiles.size() == 141,
+          "one K = 10 launch of 141 workgroups (got %zu launches, %zu left)", L.size(),
+          rest.size());
+    std::map<uint32_t, std::pair<int, int>> shape;    // member -> (R, nb)
+    for (const OnchipTile& t : L[0].tiles) shape[t.inst] = {t.R, t.nb};
+    CHECK(shape[0] == std::make_pair(2, 128) && shape[1] == std::make_pair(32, 1) &&
+              shape[2] == std::make_pair(22, 12),
+          "rows per workgroup and workgroups per member");
+    // 130 workgroups a launch: A alone, C in a second K = 10 launch, B's
+    // K = 2 launch emptied into A's (128 + 1 <= 130)
+    opt.onchip_blocks = 130;
+    plan_onchip(ms, {0, 1, 2}, opt, &L, &rest);
+    CHECK(rest.empty() && L.size() == 2 && L[0].K == 10 && L[1].K == 10,
+          "two K = 10 launches (got %zu)", L.size());
+    size_t sizes[2] = {L[0].tiles.size(), L[1].tiles.size()};
+    std::sort(sizes, sizes + 2);
+    CHECK(sizes[0] == 12 && sizes[1] == 129, "launches of 12 and 129 workgroups (%zu, %zu)",
+          sizes[0], sizes[1]);
+    // K = 2 alone: A's rows do not fit a workgroup of 32 items, C takes one
+    // row of 7 chunks ... 4 rows (28 items) a workgroup
+    opt.onchip_blocks = 256;
+    opt.onchip_variants = 0x01u;
+    plan_onchip(ms, {0, 1, 2}, opt, &L, &rest);
+    CHECK(rest.size() == 1 && rest[0] == 0, "the 70-chunk member left out at K = 2");
+    // a row of 77 chunks fits no workgroup's LDS
+    opt.onchip_variants = 0x1fu;
+    std::vector<MemberShape> wide(1);
+    wide[0].np = 8;
+    wide[0].nchunk = 77;
+    wide[0].pitch = 77 * kChunk;
+    plan_onchip(wide, {0}, opt, &L, &rest);
+    CHECK(L.empty() && rest.size() == 1, "a 77-chunk row placed");
+    wide[0].nchunk = 76;
+    wide[0].pitch = 76 * kChunk;
+    plan_onchip(wide, {0}, opt, &L, &rest);
+    CHECK(L.size() == 1 && rest.empty(), "a 76-chunk row left out");
+    // windows apart: B with a window goes to a launch of its own
+    opt.onchip_variants = 0x1fu;
+    ms[1].conv = true;
+    plan_onchip(ms, {0, 1, 2}, opt, &L, &rest);
+    CHECK(L.size() == 2, "a window-testing launch apart (%zu launches)", L.size());
+    for (const OnchipLaunch& x : L)
+        for (const OnchipTile& t : x.tiles) CHECK(ms[t.inst].conv == x.conv, "window test mixed");
+}
+
 int main()
 {
     check_arena();
@@ -584,6 +653,7 @@ int main()
     check_snapshots();
     check_validation();
     check_onchip_plan();
+    check_onchip_choices();
     std::printf("host checks passed: %d\n", g_checks);
     return 0;
 }

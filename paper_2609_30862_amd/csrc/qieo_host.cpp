@@ -184,11 +184,21 @@ size_t resident_lds_bytes(int32_t np, int32_t pitch, int32_t nchunk)
     return words * sizeof(uint32_t);
 }
 
-size_t onchip_lds_bytes(int R, int32_t nchunk)
+size_t onchip_lds_bytes(int R, int32_t nchunk, bool packed)
 {
     const size_t wpr = (size_t)nchunk * kWordsPerChunk;
-    const size_t words = 2 * (size_t)nchunk * kChunk + 2 * (size_t)R * wpr + wpr + 8 * (size_t)R;
+    const size_t words = (packed ? 1 : 2) * (size_t)nchunk * kChunk + 2 * (size_t)R * wpr + wpr +
+                         8 * (size_t)R;
     return (words * sizeof(uint32_t) + 15) / 16 * 16;
+}
+
+bool items_packable(const qieo_item* items, int32_t n)
+{
+    for (int32_t i = 0; i < n; ++i)
+        if (items[i].profit < 0 || items[i].profit > kPackedItemMax || items[i].weight < 0 ||
+            items[i].weight > kPackedItemMax)
+            return false;
+    return true;
 }
 
 bool onchip_worth(int32_t np, int32_t nchunk)
@@ -196,7 +206,8 @@ bool onchip_worth(int32_t np, int32_t nchunk)
     return np >= 256 || (int64_t)np * nchunk >= 1024 || nchunk >= 20;
 }
 
-bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out)
+bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out,
+                 bool packed)
 {
     // rows travel in 16 bits of the workgroups' keys
     if (np < 1 || np > 65536 || nchunk < 1 || n_cu < 1 || n_cu > kOnchipMaxBlocks) return false;
@@ -206,8 +217,9 @@ bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipP
     for (int k : kOnchipK)
         if (k >= need) { K = k; break; }
     if (K == 0) return false;
-    const size_t lds = onchip_lds_bytes((int)R, nchunk);
+    const size_t lds = onchip_lds_bytes((int)R, nchunk, packed);
     if (lds > lds_limit) return false;
+    out->packed = packed;
     out->R = (int)R;
     out->blocks = (int)((np + R - 1) / R);
     out->K = K;
@@ -352,7 +364,7 @@ bool onchip_fit(const MemberShape& m, size_t id, int v, const PlanOptions& opt, 
     int64_t nb = (m.np + R - 1) / R;
     R = (m.np + nb - 1) / nb;                               // balanced: same nb, fewer rows
     nb = (m.np + R - 1) / R;
-    const size_t lds = onchip_lds_bytes((int)R, m.nchunk);
+    const size_t lds = onchip_lds_bytes((int)R, m.nchunk, m.packed);
     if (nb > opt.onchip_blocks || lds > opt.onchip_lds_limit) return false;
     *out = OnchipPlace{id, (int32_t)R, (int32_t)nb, lds};
     return true;
@@ -368,8 +380,8 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
 {
     out->clear();
     rest->clear();
-    // [variant][has a window]
-    std::vector<std::vector<OnchipPlace>> by_variant(2 * kOnchipVariants);
+    // [variant][has a window][packed item tables]
+    std::vector<std::vector<OnchipPlace>> by_variant(4 * kOnchipVariants);
     for (size_t i : ids) {
         const MemberShape& m = members[i];
         int best = -1;
@@ -389,17 +401,17 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
             }
         }
         if (best < 0) rest->push_back(i);
-        else by_variant[2 * best + (m.conv ? 1 : 0)].push_back(pick);
+        else by_variant[4 * best + (m.conv ? 2 : 0) + (m.packed ? 1 : 0)].push_back(pick);
     }
     // per variant and window test, first fit by decreasing workgroup count
     struct Bin {
         int v;
-        bool conv;
+        bool conv, packed;
         int64_t used;
         std::vector<OnchipPlace> items;
     };
     std::vector<Bin> bins;
-    for (int vc = 2 * kOnchipVariants - 1; vc >= 0; --vc) {
+    for (int vc = 4 * kOnchipVariants - 1; vc >= 0; --vc) {
         std::vector<OnchipPlace>& placed = by_variant[vc];
         if (placed.empty()) continue;
         std::stable_sort(placed.begin(), placed.end(),
@@ -408,7 +420,7 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
         for (const OnchipPlace& q : placed) {
             size_t b = first;
             while (b < bins.size() && bins[b].used + q.nb > opt.onchip_blocks) ++b;
-            if (b == bins.size()) bins.push_back(Bin{vc / 2, (vc & 1) != 0, 0, {}});
+            if (b == bins.size()) bins.push_back(Bin{vc / 4, (vc & 2) != 0, (vc & 1) != 0, 0, {}});
             bins[b].used += q.nb;
             bins[b].items.push_back(q);
         }
@@ -432,7 +444,7 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
             bool placed = false;
             for (size_t dst = 0; dst < bins.size() && !placed; ++dst) {
                 if (gone[dst] || dst == src || bins[dst].conv != bins[src].conv ||
-                    bins[dst].v <= bins[src].v)
+                    bins[dst].packed != bins[src].packed || bins[dst].v <= bins[src].v)
                     continue;
                 OnchipPlace r;
                 if (onchip_fit(members[q.id], q.id, bins[dst].v, opt, &r) &&
@@ -462,6 +474,7 @@ void plan_onchip(const std::vector<MemberShape>& members, const std::vector<size
         OnchipLaunch L;
         L.K = kOnchipK[bin.v];
         L.conv = bin.conv;
+        L.packed = bin.packed;
         // members in index order inside a launch
         std::sort(bin.items.begin(), bin.items.end(),
                   [](const OnchipPlace& a, const OnchipPlace& c) { return a.id < c.id; });

@@ -77,6 +77,7 @@ bool onchip_worth(int32_t np, int32_t nchunk);
 constexpr int kOnchipVariants = 5;
 constexpr int kOnchipK[kOnchipVariants] = {2, 4, 6, 8, 10};   // compiled items per wave
 struct OnchipPlan {
+    bool packed = false;  // packed item tables (items_packable)
     int R = 0;          // rows per workgroup
     int blocks = 0;     // workgroups, at most one per CU
     int K = 0;          // items per wave: a compiled variant
@@ -84,13 +85,20 @@ struct OnchipPlan {
     bool conv = false;  // the variant that makes the convergence-window test
                         // (set by the caller: the instance has a window)
 };
-// Item tables, the workgroup's own allele words of two generations, the
-// elite's words, and per row the fitness, profit and weight of two
-// generations and the running sums.
-size_t onchip_lds_bytes(int R, int32_t nchunk);
+// Item tables (one word per item when packed, else two), the workgroup's
+// own allele words of two generations, the elite's words, and per row the
+// fitness, profit and weight of two generations and the running sums.
+size_t onchip_lds_bytes(int R, int32_t nchunk, bool packed = false);
+// Packed item tables: every profit and weight of an instance in [0,
+// kPackedItemMax] lets the on-chip loops keep one LDS word per item,
+// profit | weight << 16; a lane's sum over its four genes then stays below
+// 2^16 in each half, so one masked sum gives both exactly.
+constexpr int32_t kPackedItemMax = (1 << 14) - 1;
+bool items_packable(const qieo_item* items, int32_t n);
 // False when the population does not fit: more items per wave than the
 // largest variant, or more LDS than lds_limit.
-bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out);
+bool onchip_plan(int32_t np, int32_t nchunk, int n_cu, size_t lds_limit, OnchipPlan* out,
+                 bool packed = false);
 
 // Segment numbering constants of one segment-order launch of n_seg
 // workgroups on a device of `xcds` XCDs; nseg_row > 0 for an untiled launch
@@ -135,6 +143,7 @@ struct MemberShape {
     int32_t part_nseg = 0;        // from the member's arena layout
     uint64_t addr = 0;            // arena address (segment tiles go in address order)
     bool conv = false;            // has a convergence window
+    bool packed = false;          // items_packable
 };
 
 struct PlanOptions {
@@ -183,6 +192,7 @@ struct OnchipTile {
 struct OnchipLaunch {
     int K = 0;                        // compiled items per wave
     bool conv = false;                // the variant with the window test (its members have windows)
+    bool packed = false;              // the variant with packed item tables (its members' items fit)
     size_t lds = 0;                   // dynamic LDS per workgroup (the largest tile's need)
     std::vector<OnchipTile> tiles;
 };
@@ -200,7 +210,8 @@ struct BatchPlan {
 // us of synchronisation plus 1.1 us per item a wave holds): at variant K it
 // runs on b workgroups of R = ceil(np / b) whole rows, b the fewest whose
 // kOnchipWaves * K items hold its rows.  The members of each variant, those
-// with a convergence window apart from those without, are packed first-fit
+// with a convergence window apart from those without and those with packed
+// item tables apart from the others, are packed first-fit
 // by decreasing b into launches of at most opt.onchip_blocks workgroups;
 // then each launch whose members all fit the spare workgroups of launches
 // of a larger variant (their b recomputed there) is emptied into them,

@@ -97,6 +97,7 @@ int Engine::add(DevicePool& pool, const qieo_item* items, int32_t n_items, int32
     m.d = bind_arena(m.arena, m.L, n_items, n_pop, capacity, seed);
     m.ng = n_items;
     m.np = n_pop;
+    m.packed = items_packable(items, n_items);
     m.capacity = capacity;
     m.seed = seed;
     m.id = id;
@@ -217,6 +218,7 @@ int Engine::rebuild()
         shapes[i].part_nseg = m.L.part_nseg;
         shapes[i].addr = (uint64_t)(uintptr_t)m.arena;
         shapes[i].conv = m.window > 0;
+        shapes[i].packed = m.packed;
     }
     PlanOptions opt;
     opt.use_persistent = use_persistent_;
@@ -258,7 +260,7 @@ int Engine::rebuild()
             return rebuild_nomem("on-chip abort words");
         for (OnchipLaunch& L : plan.onchip) {
             // owned by onchip_ from here on (freed at the next rebuild)
-            onchip_.push_back(OnchipRun{L.K, L.conv, L.lds, (int)L.tiles.size(), nullptr});
+            onchip_.push_back(OnchipRun{L.K, L.conv, L.packed, L.lds, (int)L.tiles.size(), nullptr});
             OnchipRun& o = onchip_.back();
             if (!(o.d_tiles = (OnchipTile*)mem_.alloc(L.tiles.size() * sizeof(OnchipTile))))
                 return rebuild_nomem("on-chip tiles");
@@ -328,8 +330,8 @@ int Engine::enqueue(int nmax)
         const int64_t ticks = onchip_spin_ticks(device_of_stream(), barrier_us_);
         for (size_t j = 0; j < onchip_.size(); ++j) {
             const OnchipRun& o = onchip_[j];
-            if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.conv, o.lds, d_gens_,
-                                         0, d_abort_ + j, ticks, stream_)) != hipSuccess)
+            if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.conv, o.packed, o.lds,
+                                         d_gens_, 0, d_abort_ + j, ticks, stream_)) != hipSuccess)
                 return hip_fail(e, "batched on-chip kernel");
         }
         onchip_check_ = true;
@@ -616,8 +618,8 @@ int Engine::tune_onchip(int gens, const std::vector<MemberShape>& shapes, const 
         if (ee == hipSuccess) ee = hipEventRecord(e0, stream_);
         for (size_t j = 0; j < c.launches.size() && ee == hipSuccess; ++j)
             ee = launch_onchip_multi(d_desc_, c.d_tiles[j], (int)c.launches[j].tiles.size(),
-                                     c.launches[j].K, c.launches[j].conv, c.launches[j].lds,
-                                     d_gens_, 0, d_abort + j, ticks, stream_);
+                                     c.launches[j].K, c.launches[j].conv, c.launches[j].packed,
+                                     c.launches[j].lds, d_gens_, 0, d_abort + j, ticks, stream_);
         if (ee == hipSuccess) ee = hipEventRecord(e1, stream_);
         if (ee == hipSuccess) ee = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -684,7 +686,7 @@ int Engine::tune_classes(int gens, std::vector<qieo_class_tune>* out)
     for (size_t i = 0; i < n; ++i) {
         const Member& m = members_[i];
         shapes[i] = MemberShape{m.np, m.L.pitch, m.L.nchunk, m.L.part_nseg,
-                                (uint64_t)(uintptr_t)m.arena, m.window > 0};
+                                (uint64_t)(uintptr_t)m.arena, m.window > 0, m.packed};
     }
     PlanOptions opt;
     opt.use_persistent = use_persistent_;

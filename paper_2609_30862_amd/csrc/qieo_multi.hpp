@@ -45,6 +45,7 @@ struct Member {
     uint64_t id = 0;      // caller's identifier
     int32_t window = 0;   // convergence window (0 = fixed budget)
     bool converged = false;
+    bool packed = false;  // profits and weights fit the on-chip loops' packed item tables
 };
 
 // Work shape of one launch class.
@@ -146,6 +147,7 @@ private:
     struct OnchipRun {
         int K = 0;
         bool conv = false;
+        bool packed = false;
         size_t lds = 0;
         int n_tiles = 0;
         OnchipTile* d_tiles = nullptr;

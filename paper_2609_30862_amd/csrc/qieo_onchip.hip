@@ -200,8 +200,12 @@ __device__ __forceinline__ void store_planes(const InstDev& I, const f32x4 (&A)[
 
 // The loop of one workgroup: rows [row0, row0 + nrows) of instance I, LDS
 // laid out for R rows, workgroup blk of the nb that run the instance, gens
-// generations; abort_flag is the launch's abort word.
-template <int K, bool CONV>
+// generations; abort_flag is the launch's abort word.  PACKED: every profit
+// and weight of the instance is at most kPackedItemMax, so the item tables
+// take one LDS word per item (profit | weight << 16) and Evaluation's
+// per-lane sum over four genes gives both sums at once (each half stays
+// below 2^16, no carry crosses).
+template <int K, bool CONV, bool PACKED>
 __device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, const int nrows,
                                             const int R, const int blk, const int nb,
                                             const int gens, uint32_t* abort_flag,
@@ -216,8 +220,8 @@ __device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, co
     const int n_items = nrows * nchunk;
 
     int32_t* sV = reinterpret_cast<int32_t*>(lds);                     // [nchunk * 256]
-    int32_t* sWt = sV + nchunk * kChunk;                                 // [nchunk * 256]
-    uint32_t* sX = reinterpret_cast<uint32_t*>(sWt + nchunk * kChunk);   // [2][R][wpr] by parity
+    int32_t* sWt = sV + nchunk * kChunk;                                 // [nchunk * 256], not PACKED
+    uint32_t* sX = reinterpret_cast<uint32_t*>(PACKED ? sWt : sWt + nchunk * kChunk);  // [2][R][wpr]
     uint32_t* sE = sX + 2 * R * wpr;                                     // [wpr] elite of t-1
     int32_t* sF = reinterpret_cast<int32_t*>(sE + wpr);                  // [2][R] fitness by parity
     int32_t* sPW = sF + 2 * R;                                           // [2][R][2] profit, weight
@@ -247,8 +251,12 @@ __device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, co
     // item tables, and the rows' allele words and fitness of t0 - 1 (for
     // t0 = 0 the zeroed slot 1, which nothing uses: no row rotates at 0)
     for (int i = tid; i < nchunk * kChunk; i += nthr) {
-        sV[i] = I.v[i];
-        sWt[i] = I.w[i];
+        if (PACKED) {
+            sV[i] = (int32_t)((uint32_t)I.v[i] | ((uint32_t)I.w[i] << 16));
+        } else {
+            sV[i] = I.v[i];
+            sWt[i] = I.w[i];
+        }
     }
     {
         const int pp = (int)((t0 - 1) & 1);
@@ -411,10 +419,17 @@ __device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, co
                 sXc[rv * wpr + ch * kWordsPerChunk + lane] = word;
             }
             // the item tables hold nchunk * 256 entries: g0 is inside
-            const i32x4 v4 = *reinterpret_cast<const i32x4*>(sV + g0);
-            const i32x4 w4 = *reinterpret_cast<const i32x4*>(sWt + g0);
-            accP += masked_sum4(m0, m1, m2, m3, v4);
-            accW += masked_sum4(m0, m1, m2, m3, w4);
+            if (PACKED) {
+                const i32x4 p4 = *reinterpret_cast<const i32x4*>(sV + g0);
+                const uint32_t pw = masked_sum4(m0, m1, m2, m3, p4);
+                accP += pw & 0xffffu;
+                accW += pw >> 16;
+            } else {
+                const i32x4 v4 = *reinterpret_cast<const i32x4*>(sV + g0);
+                const i32x4 w4 = *reinterpret_cast<const i32x4*>(sWt + g0);
+                accP += masked_sum4(m0, m1, m2, m3, v4);
+                accW += masked_sum4(m0, m1, m2, m3, w4);
+            }
             // the row's sums go to LDS where the wave's run of it ends
             const bool row_end = ch + 1 == nchunk;
             if (valid && (row_end || u == K - 1 || fi + u + 1 == ni)) {
@@ -468,7 +483,7 @@ __device__ __forceinline__ void onchip_body(const InstDev& I, const int row0, co
     }
 }
 
-template <int K, bool CONV>
+template <int K, bool CONV, bool PACKED>
 __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev* __restrict__ insts,
                                                                   int R, int gens,
                                                                   int64_t spin_ticks)
@@ -476,15 +491,16 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_kernel(const InstDev
     const InstDev I = insts[0];
     const int row0 = (int)blockIdx.x * R;
     // nrows >= 1: the grid is ceil(np / R)
-    onchip_body<K, CONV>(I, row0, min(R, I.np - row0), R, (int)blockIdx.x, (int)gridDim.x, gens,
-                         I.sync + 1, spin_ticks);
+    onchip_body<K, CONV, PACKED>(I, row0, min(R, I.np - row0), R, (int)blockIdx.x,
+                                 (int)gridDim.x, gens, I.sync + 1, spin_ticks);
 }
 
 // Batched form: workgroup b runs tiles[b] (whole rows of one member) for
 // that member's gens_arr entry (gens_all when gens_arr is NULL); the
 // workgroups of one member wait only for each other.  CONV: every member of
-// the launch has a convergence window.
-template <int K, bool CONV>
+// the launch has a convergence window; PACKED: every member's items fit the
+// packed tables.
+template <int K, bool CONV, bool PACKED>
 __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_multi_kernel(
     const InstDev* __restrict__ insts, const OnchipTile* __restrict__ tiles,
     const int32_t* __restrict__ gens_arr, int gens_all, uint32_t* abort_flag,
@@ -495,7 +511,8 @@ __global__ __launch_bounds__(64 * kOnchipWaves) void onchip_multi_kernel(
     // every workgroup of the member leaves here alike
     if (gens <= 0) return;
     const InstDev I = insts[T.inst];
-    onchip_body<K, CONV>(I, T.row0, T.nrows, T.R, T.blk, T.nb, gens, abort_flag, spin_ticks);
+    onchip_body<K, CONV, PACKED>(I, T.row0, T.nrows, T.R, T.blk, T.nb, gens, abort_flag,
+                                 spin_ticks);
 }
 
 // Clears the launch's abort word and, for each tile, its workgroup's key
@@ -516,40 +533,45 @@ __global__ void onchip_multi_reset_kernel(const InstDev* __restrict__ insts,
 
 typedef void (*OnchipFn)(const InstDev*, int, int, int64_t);
 
-template <bool CONV>
+template <bool CONV, bool PACKED>
 OnchipFn onchip_fn(int K)
 {
     switch (K) {
-        case 2: return onchip_kernel<2, CONV>;
-        case 4: return onchip_kernel<4, CONV>;
-        case 6: return onchip_kernel<6, CONV>;
-        case 8: return onchip_kernel<8, CONV>;
-        case 10: return onchip_kernel<10, CONV>;
+        case 2: return onchip_kernel<2, CONV, PACKED>;
+        case 4: return onchip_kernel<4, CONV, PACKED>;
+        case 6: return onchip_kernel<6, CONV, PACKED>;
+        case 8: return onchip_kernel<8, CONV, PACKED>;
+        case 10: return onchip_kernel<10, CONV, PACKED>;
         default: return nullptr;
     }
 }
 
-OnchipFn onchip_fn(int K, bool conv) { return conv ? onchip_fn<true>(K) : onchip_fn<false>(K); }
+OnchipFn onchip_fn(int K, bool conv, bool packed)
+{
+    if (packed) return conv ? onchip_fn<true, true>(K) : onchip_fn<false, true>(K);
+    return conv ? onchip_fn<true, false>(K) : onchip_fn<false, false>(K);
+}
 
 typedef void (*OnchipMultiFn)(const InstDev*, const OnchipTile*, const int32_t*, int, uint32_t*,
                               int64_t);
 
-template <bool CONV>
+template <bool CONV, bool PACKED>
 OnchipMultiFn onchip_multi_fn(int K)
 {
     switch (K) {
-        case 2: return onchip_multi_kernel<2, CONV>;
-        case 4: return onchip_multi_kernel<4, CONV>;
-        case 6: return onchip_multi_kernel<6, CONV>;
-        case 8: return onchip_multi_kernel<8, CONV>;
-        case 10: return onchip_multi_kernel<10, CONV>;
+        case 2: return onchip_multi_kernel<2, CONV, PACKED>;
+        case 4: return onchip_multi_kernel<4, CONV, PACKED>;
+        case 6: return onchip_multi_kernel<6, CONV, PACKED>;
+        case 8: return onchip_multi_kernel<8, CONV, PACKED>;
+        case 10: return onchip_multi_kernel<10, CONV, PACKED>;
         default: return nullptr;
     }
 }
 
-OnchipMultiFn onchip_multi_fn(int K, bool conv)
+OnchipMultiFn onchip_multi_fn(int K, bool conv, bool packed)
 {
-    return conv ? onchip_multi_fn<true>(K) : onchip_multi_fn<false>(K);
+    if (packed) return conv ? onchip_multi_fn<true, true>(K) : onchip_multi_fn<false, true>(K);
+    return conv ? onchip_multi_fn<true, false>(K) : onchip_multi_fn<false, false>(K);
 }
 
 }  // namespace
@@ -576,9 +598,10 @@ void onchip_limits(size_t* lds_limit, int* n_cu)
         }
         constexpr size_t kStatic = 256;           // the kernel's own __shared__ variables
         const size_t want = (size_t)smem > kStatic ? (size_t)smem - kStatic : 0;
-        for (bool conv : {false, true}) {
+        for (int cp = 0; cp < 4; ++cp) {
+            const bool conv = (cp & 1) != 0, packed = (cp & 2) != 0;
             for (int K : kOnchipK) {
-                const void* f = reinterpret_cast<const void*>(onchip_fn(K, conv));
+                const void* f = reinterpret_cast<const void*>(onchip_fn(K, conv, packed));
                 int blocks = 0;
                 if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)want) != hipSuccess ||
@@ -619,8 +642,9 @@ unsigned onchip_multi_variants()
         if (ncu == 0) return;
         for (int v = 0; v < kOnchipVariants; ++v) {
             bool ok = true;
-            for (bool conv : {false, true}) {
-                const void* f = reinterpret_cast<const void*>(onchip_multi_fn(kOnchipK[v], conv));
+            for (int cp = 0; cp < 4; ++cp) {
+                const void* f = reinterpret_cast<const void*>(
+                    onchip_multi_fn(kOnchipK[v], (cp & 1) != 0, (cp & 2) != 0));
                 int blocks = 0;
                 if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
                         hipSuccess ||
@@ -696,7 +720,7 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
     size_t lim = 0;
     int ncu = 0;
     onchip_limits(&lim, &ncu);
-    const OnchipFn f = onchip_fn(p.K, p.conv);
+    const OnchipFn f = onchip_fn(p.K, p.conv, p.packed);
     if (!f || p.R < 1 || p.blocks < 1 || p.blocks > ncu || p.lds > lim) return hipErrorInvalidValue;
     const InstDev* a0 = dI;
     int a1 = p.R, a2 = gens;
@@ -711,8 +735,9 @@ hipError_t launch_onchip(const InstDev* dI, const OnchipPlan& p, int gens, int64
 }
 
 hipError_t launch_onchip_multi(const InstDev* dI, const OnchipTile* tiles, int n_tiles, int K,
-                               bool conv, size_t lds, const int32_t* gens_arr, int gens_all,
-                               uint32_t* abort_flag, int64_t spin_ticks, hipStream_t s)
+                               bool conv, bool packed, size_t lds, const int32_t* gens_arr,
+                               int gens_all, uint32_t* abort_flag, int64_t spin_ticks,
+                               hipStream_t s)
 {
     size_t lim = 0;
     int ncu = 0;
@@ -729,7 +754,7 @@ hipError_t launch_onchip_multi(const InstDev* dI, const OnchipTile* tiles, int n
     uint32_t* a4 = abort_flag;
     int64_t a5 = spin_ticks;
     void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
-    return chained_coop_launch(reinterpret_cast<const void*>(onchip_multi_fn(K, conv)),
+    return chained_coop_launch(reinterpret_cast<const void*>(onchip_multi_fn(K, conv, packed)),
                                (unsigned)n_tiles, args, lds, s, [&] {
                                    hipLaunchKernelGGL(onchip_multi_reset_kernel,
                                                       dim3((unsigned)((n_tiles + 255) / 256)),

@@ -143,6 +143,7 @@ struct qieo_inst {
     bool f64 = false;            // binary64 amplitudes
     int persistent = 1;          // see qieo_set_persistent
     bool onchip_check = false;   // an on-chip launch is queued: qieo_sync reads its abort flag
+    bool items_packed = false;   // profits and weights fit the on-chip loop's packed item tables
     int32_t last_path = -1;      // QIEO_PATH_* of the last step call
     int64_t barrier_us = 1000000;    // bound on one on-chip grid-barrier wait
     bool use_graph = true;       // replay a captured graph of a call's launches
@@ -231,6 +232,7 @@ static int create_impl(const qieo_item* items, int32_t n_items, int32_t capacity
     }
     h->ng = n_items;
     h->np = n_pop;
+    h->items_packed = items_packable(items, n_items);
     h->capacity = capacity;
     h->seed = seed;
     h->items_hash = items_fnv1a(items, n_items);
@@ -433,7 +435,7 @@ extern "C" int qieo_step_async(qieo_inst* h, int32_t n)
         size_t lim = 0;
         int ncu = 0;
         onchip_limits(&lim, &ncu);
-        if (ncu > 0 && onchip_plan(h->np, h->L.nchunk, ncu, lim, &p)) {
+        if (ncu > 0 && onchip_plan(h->np, h->L.nchunk, ncu, lim, &p, h->items_packed)) {
             hipEvent_t a = nullptr, b = nullptr;
             if (h->timing) {
                 int rc = timed_event_pair(h, 0, &a, &b);

@@ -252,6 +252,7 @@ static void check_plan_batch()
             ms[i].part_nseg = L.part_nseg;
             ms[i].addr = addr + (uint64_t)(rng() % 1000) * 4096;   // not in member order
             ms[i].conv = rng() % 3 == 0;
+            ms[i].packed = rng() % 2 == 0;
             addr += L.total + (1 << 20);
             ngs[i] = ng;
         }
@@ -306,6 +307,8 @@ static void check_plan_batch()
                 const MemberShape& m = ms[t.inst];
                 CHECK(m.conv == L.conv, "member %u (window %d) in a launch with window test %d",
                       t.inst, (int)m.conv, (int)L.conv);
+                CHECK(m.packed == L.packed, "member %u (packed %d) in a launch with packed %d",
+                      t.inst, (int)m.packed, (int)L.packed);
                 CHECK(m.np <= 65536, "member %u: %d rows on-chip", t.inst, m.np);
                 CHECK(t.nb >= 1 && t.nb <= opt.onchip_blocks && t.blk >= 0 && t.blk < t.nb,
                       "workgroup %d of %d", t.blk, t.nb);
@@ -326,7 +329,7 @@ static void check_plan_batch()
                     rows[t.inst][r]++;
                     fe[t.inst][r]++;
                 }
-                lds = std::max(lds, onchip_lds_bytes(t.R, m.nchunk));
+                lds = std::max(lds, onchip_lds_bytes(t.R, m.nchunk, m.packed));
             }
             CHECK(L.lds == lds && lds <= opt.onchip_lds_limit, "launch LDS %zu (tiles %zu)", L.lds,
                   lds);
@@ -563,6 +566,10 @@ static void check_onchip_plan()
     // beyond the register budget or the LDS: refused
     CHECK(!onchip_plan(4096, 20, 256, lim, &p), "16 rows x 20 chunks per CU");
     CHECK(!onchip_plan(50, 79, 256, lim, &p), "item tables of 79 chunks exceed LDS");
+    // packed item tables (one word per item) make room for them
+    CHECK(onchip_plan(50, 79, 256, lim, &p, true) && p.packed && p.K == 6 &&
+              p.lds == onchip_lds_bytes(1, 79, true) && p.lds < onchip_lds_bytes(1, 79) / 2 + 8192,
+          "50 x 79, packed");
     CHECK(onchip_plan(50, 47, 256, lim, &p) && p.blocks == 50 && p.K == 4, "50 x 47");
     CHECK(!onchip_plan(1024, 40, 0, lim, &p) && !onchip_plan(1024, 40, 256, 0, &p),
           "no device support");
@@ -634,6 +641,29 @@ static void check_onchip_choices()
     wide[0].pitch = 76 * kChunk;
     plan_onchip(wide, {0}, opt, &L, &rest);
     CHECK(L.size() == 1 && rest.empty(), "a 76-chunk row left out");
+    // packed item tables (1 KB a chunk, with 12 words a chunk of allele
+    // words at one row per workgroup): rows of up to 146 chunks fit
+    wide[0].packed = true;
+    for (int nc : {77, 146}) {
+        wide[0].nchunk = nc;
+        wide[0].pitch = nc * kChunk;
+        plan_onchip(wide, {0}, opt, &L, &rest);
+        CHECK(L.size() == 1 && rest.empty() && L[0].packed, "a packed %d-chunk row left out", nc);
+    }
+    wide[0].nchunk = 147;
+    wide[0].pitch = 147 * kChunk;
+    plan_onchip(wide, {0}, opt, &L, &rest);
+    CHECK(L.empty() && rest.size() == 1, "a packed 147-chunk row placed");
+    // items_packable: both halves within [0, 2^14 - 1]
+    {
+        qieo_item it[2] = {{kPackedItemMax, kPackedItemMax}, {0, 1}};
+        CHECK(items_packable(it, 2), "items at the packed maximum refused");
+        it[1].profit = kPackedItemMax + 1;
+        CHECK(!items_packable(it, 2), "a profit of 2^14 accepted");
+        it[1].profit = 5;
+        it[1].weight = kPackedItemMax + 1;
+        CHECK(!items_packable(it, 2), "a weight of 2^14 accepted");
+    }
     // windows apart: B with a window goes to a launch of its own
     opt.onchip_variants = 0x1fu;
     ms[1].conv = true;

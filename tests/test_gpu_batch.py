@@ -282,6 +282,35 @@ def test_onchip_over_several_launches(qieo, oracle_mod):
         assert_state_equal(View(on, k), orcs[k], label="on-chip member %d" % k)
 
 
+def test_onchip_packed_and_unpacked_members(qieo, oracle_mod):
+    """Members whose profits and weights stay below 2^14 run in launches
+    with packed item tables, the others in launches with a table for each:
+    every member equals the per-generation launch path, sampled ones the
+    oracle."""
+    insts = [workloads.random_instance(ng, n_pop, seed=3500 + k, wmax=w)
+             for k, (ng, n_pop, w) in enumerate([(1500, 256, 20), (1500, 256, 30000),
+                                                 (19000, 64, 50), (19000, 64, 20000),
+                                                 (300, 40, 16378), (300, 40, 16379)])]
+    on = qieo.Batch(_problems(insts))
+    off = qieo.Batch(_problems(insts))
+    off.set_onchip(False)
+    say("on-chip launches: %d" % on.onchip_launches())
+    assert on.onchip_launches() >= 2
+    n = len(insts)
+    for gens in ([6] * n, [k % 3 + 2 for k in range(n)]):
+        on.step(gens)
+        off.step(gens)
+    for k in range(n):
+        a, c = on.export_rows(k), off.export_rows(k)
+        for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
+            assert np.array_equal(a[key], c[key]), (k, key)
+    for k in (1, 3, 4, 5):
+        i = insts[k]
+        o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
+        o.run(6 + k % 3 + 2)
+        assert_state_equal(View(on, k), o, label="member %d" % k)
+
+
 def test_onchip_with_convergence_window(qieo, oracle_mod):
     """Members with a convergence window run in on-chip launches of their
     own that make the window test: each member stops where the oracle does,

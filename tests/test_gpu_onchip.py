@@ -60,16 +60,22 @@ def test_medium_workload_every_call_length(qieo, oracle_mod):
     g.close()
 
 
-@pytest.mark.parametrize("ng,n_pop", [
-    (3000, 1000),     # 12 chunks, 4 rows per workgroup, last workgroup ragged
-    (700, 2000),      # 3 chunks: a wave's items span rows
-    (60, 4000),       # one 64-gene chunk per row, 16 rows per workgroup
-    (9000, 300),      # 2 rows per workgroup, 36 chunks
-    (12000, 50),      # fewer rows than compute units, 47 chunks a row
-    (100, 5),         # five workgroups of one item each
+@pytest.mark.parametrize("ng,n_pop,wmax", [
+    (3000, 1000, 10),     # 12 chunks, 4 rows per workgroup, last workgroup ragged
+    (700, 2000, 10),      # 3 chunks: a wave's items span rows
+    (60, 4000, 10),       # one 64-gene chunk per row, 16 rows per workgroup
+    (9000, 300, 10),      # 2 rows per workgroup, 36 chunks
+    (12000, 50, 10),      # fewer rows than compute units, 47 chunks a row
+    (100, 5, 10),         # five workgroups of one item each
+    # item values at the packed tables' limit (profits up to 2^14 - 1) and
+    # beyond it (the variant with a table for each)
+    (3000, 1000, 16378),
+    (9000, 300, 30000),
+    (12000, 50, 30000),
 ])
-def test_item_split_shapes(qieo, oracle_mod, ng, n_pop):
-    inst = workloads.random_instance(ng, n_pop, seed=400 + ng % 97)
+def test_item_split_shapes(qieo, oracle_mod, ng, n_pop, wmax):
+    inst = workloads.random_instance(ng, n_pop, seed=400 + ng % 97, wmax=wmax)
+    assert (int(inst.values.max()) <= (1 << 14) - 1) == (wmax <= 16378)
     g, o = _pair(qieo, oracle_mod, inst)
     for n in (1, 5, 12):
         path = _step_path(g, n)

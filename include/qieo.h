@@ -294,9 +294,10 @@ int qieo_batch_set_segment_order(qieo_batch *b, int32_t mode);
  * inside cooperative launches with its amplitude planes held in registers,
  * the on-chip loop of qieo_set_persistent mode 3 extended to many members:
  * each member on workgroups of whole rows (rows of up to 76 chunks of 256
- * genes: the member's item tables and two generations of its rows' allele
- * words must fit a workgroup's LDS), its workgroups waiting only for each
- * other at the end of each
+ * genes, 146 when every profit and weight is below 2^14: the member's item
+ * tables and two generations of its rows' allele words must fit a
+ * workgroup's LDS), its workgroups waiting only for each other at the end
+ * of each
  * generation (Sec. III-B's loop: DetermineElite over the member's rows
  * before its CIP), at most one workgroup per CU, so a batch of more rows
  * than that takes several such launches one after another; they run before

@@ -290,7 +290,9 @@ def test_onchip_packed_and_unpacked_members(qieo, oracle_mod):
     insts = [workloads.random_instance(ng, n_pop, seed=3500 + k, wmax=w)
              for k, (ng, n_pop, w) in enumerate([(1500, 256, 20), (1500, 256, 30000),
                                                  (19000, 64, 50), (19000, 64, 20000),
-                                                 (300, 40, 16378), (300, 40, 16379)])]
+                                                 (300, 40, 16378), (300, 40, 16379),
+                                                 # 100 chunks: on-chip only packed
+                                                 (25600, 24, 30), (25600, 24, 25000)])]
     on = qieo.Batch(_problems(insts))
     off = qieo.Batch(_problems(insts))
     off.set_onchip(False)
@@ -304,7 +306,7 @@ def test_onchip_packed_and_unpacked_members(qieo, oracle_mod):
         a, c = on.export_rows(k), off.export_rows(k)
         for key in ("alpha", "beta", "alleles", "fitness", "profit", "weight"):
             assert np.array_equal(a[key], c[key]), (k, key)
-    for k in (1, 3, 4, 5):
+    for k in (1, 3, 4, 5, 6, 7):
         i = insts[k]
         o = oracle_mod.Oracle(i.values, i.weights, i.capacity, i.n_pop, i.seed)
         o.run(6 + k % 3 + 2)

@@ -156,6 +156,23 @@ def test_populations_it_does_not_take_run_per_generation(qieo, oracle_mod):
     g.close()
 
 
+@pytest.mark.parametrize("wmax,path", [(20, "onchip"), (30000, "launches")])
+def test_long_rows_on_chip_only_with_packed_tables(qieo, oracle_mod, wmax, path):
+    """40 x 30,000 (118 chunks a row, one row a workgroup): its item tables
+    fit a workgroup's LDS only packed (items of at most 14 bits), so mode 3
+    takes the on-chip loop for small items and per-generation launches for
+    large ones; both equal the oracle."""
+    inst = workloads.random_instance(30000, 40, seed=449, wmax=wmax)
+    g, o = _pair(qieo, oracle_mod, inst)
+    want = qieo.PATH_ONCHIP if path == "onchip" else qieo.PATH_LAUNCHES
+    for n in (4, 9):
+        got = _step_path(g, n)
+        o.run(n)
+        assert got == (want, 1 if path == "onchip" else n), (wmax, n, got)
+        assert_state_equal(g, o, label="40 x 30000, items up to %d, after %d" % (wmax, o.t))
+    g.close()
+
+
 # (n_items, n_pop, seed, window, calls, mode): where the oracle stops is
 # noted per case; the calls put the stop mid-call, at a call's last
 # generation (found by the finish, the next call then runs nothing), and

@@ -328,13 +328,15 @@ int Engine::enqueue(int nmax)
     // call runs beside it
     if (!onchip_.empty()) {
         const int64_t ticks = onchip_spin_ticks(device_of_stream(), barrier_us_);
+        // set first: launches enqueued before a failing one still get their
+        // abort words read at the next sync
+        onchip_check_ = true;
         for (size_t j = 0; j < onchip_.size(); ++j) {
             const OnchipRun& o = onchip_[j];
             if ((e = launch_onchip_multi(d_desc_, o.d_tiles, o.n_tiles, o.K, o.conv, o.packed, o.lds,
                                          d_gens_, 0, d_abort_ + j, ticks, stream_)) != hipSuccess)
                 return hip_fail(e, "batched on-chip kernel");
         }
-        onchip_check_ = true;
     }
     const size_t nc = classes_.size();
     const bool forked = !pids_.empty() || nc > 1;
